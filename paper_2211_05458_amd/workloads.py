@@ -1,0 +1,406 @@
+"""Seeded synthetic workloads: meshes, fluid states and particles.
+
+This module only *describes* inputs.  It contains none of the particle method's
+arithmetic (no Lagrange mapping, no Newton, no interpolation, no tracking): meshes
+are produced by evaluating an analytic map on an integer node lattice, fluid
+states by evaluating an analytic velocity field at the analytic image of the DG
+node positions, and particles by drawing a logical cell and a point inside it.
+Both the CPU oracle and the HIP library consume exactly these arrays.
+
+Array conventions shared by every consumer
+------------------------------------------
+* ``X``      float64 ``[E][(Ng+1)^3][3]``; node index ``i + n*(j + n*k)`` with
+  ``i`` along xi^1 (fastest).  Geometry nodes are equidistant on [-1, 1].
+* ``nbr_elem``/``nbr_face`` int32 ``[E][6]``; local faces are
+  0: xi^1=-1, 1: xi^1=+1, 2: xi^2=-1, 3: xi^2=+1, 4: xi^3=-1, 5: xi^3=+1.
+* ``bc`` int8 ``[E][6]``: 0 internal, 1 open, 2 reflective, 3 periodic.
+* ``shift`` float64 ``[E][6][3]``: translation applied to a particle that
+  crosses a periodic face.
+* ``U`` float64 ``[E][5][(N+1)^3]``: conservative variables
+  (rho, rho u1, rho u2, rho u3, rho e) at the Legendre-Gauss nodes.
+* particles: ``x``, ``v`` float64 ``[Np][3]``, ``d`` float64 ``[Np]``,
+  ``elem_hint`` int32 ``[Np]``.
+
+Physical constants (fluid at rest conditions, particle material): air-like gas
+with constant viscosity, glass-like particles.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+
+KAPPA = 1.4
+MU = 1.8e-5
+RHO_F = 1.2
+P0 = 1.0e5
+RHO_P = 2500.0
+
+BC_INTERNAL, BC_OPEN, BC_REFLECT, BC_PERIODIC = 0, 1, 2, 3
+
+
+@dataclasses.dataclass
+class Mesh:
+    n_geo: int
+    X: np.ndarray          # [E][(ng)^3][3] f64
+    nbr_elem: np.ndarray   # [E][6] i32
+    nbr_face: np.ndarray   # [E][6] i32
+    bc: np.ndarray         # [E][6] i8
+    shift: np.ndarray      # [E][6][3] f64
+    h: float               # nominal element width
+    cells: tuple = ()      # logical lattice size (n1, n2, n3) when structured
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.X.shape[0])
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    N: int                 # DG degree
+    U: np.ndarray          # [E][5][(N+1)^3] f64
+    x: np.ndarray          # [Np][3]
+    v: np.ndarray          # [Np][3]
+    d: np.ndarray          # [Np]
+    elem_hint: np.ndarray  # [Np] i32
+    dt: float
+    n_steps: int
+    rk: int                # 0 = 5-stage 4th order low storage, 1 = 3-stage 3rd order
+    drag: int              # 0 = Stokes, 1 = Schiller-Naumann
+    mu: float = MU
+    kappa: float = KAPPA
+    rho_p: float = RHO_P
+    velocity: Optional[Callable] = None   # analytic field u(x) (N, 3) -> (N, 3), for tests
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.x.shape[0])
+
+
+# ----------------------------------------------------------------------------
+# integer-lattice trigonometry: sin(2*pi*num/den) with the argument reduced in
+# integers, so that periodic images of a lattice node are bitwise equal.
+# ----------------------------------------------------------------------------
+def sin2pi(num, den):
+    num = np.asarray(num, dtype=np.int64)
+    r = np.mod(num, den).astype(np.float64) / float(den)
+    return np.sin(2.0 * np.pi * r)
+
+
+def structured_mesh(cells, n_geo, node_map, periodic, wall_bc=BC_REFLECT, periods=None):
+    """Hex mesh on a logical lattice.
+
+    ``node_map(I1, I2, I3, M)`` receives integer lattice indices (broadcastable
+    int64 arrays) with ``M = (n1*Ng, n2*Ng, n3*Ng)`` and returns the physical
+    coordinates ``(..., 3)``.  Element e = i1 + n1*(i2 + n2*i3) takes the
+    lattice block starting at (i1*Ng, i2*Ng, i3*Ng); shared faces are therefore
+    bitwise identical.  ``periods[a]`` is the physical translation of a
+    periodic axis a (3-vector).
+    """
+    n1, n2, n3 = cells
+    ng = n_geo + 1
+    M = (n1 * n_geo, n2 * n_geo, n3 * n_geo)
+    I1 = np.arange(M[0] + 1, dtype=np.int64)[None, None, :]
+    I2 = np.arange(M[1] + 1, dtype=np.int64)[None, :, None]
+    I3 = np.arange(M[2] + 1, dtype=np.int64)[:, None, None]
+    L = node_map(I1, I2, I3, M)            # [M3+1][M2+1][M1+1][3]
+    loc = np.arange(ng, dtype=np.int64)
+    e1 = np.arange(n1, dtype=np.int64)
+    e2 = np.arange(n2, dtype=np.int64)
+    e3 = np.arange(n3, dtype=np.int64)
+    # (n3, n2, n1, k, j, i)
+    A1 = (e1[None, None, :, None, None, None] * n_geo + loc[None, None, None, None, None, :])
+    A2 = (e2[None, :, None, None, None, None] * n_geo + loc[None, None, None, None, :, None])
+    A3 = (e3[:, None, None, None, None, None] * n_geo + loc[None, None, None, :, None, None])
+    X = L[A3, A2, A1]                       # (n3, n2, n1, ng, ng, ng, 3)
+    E = n1 * n2 * n3
+    X = np.ascontiguousarray(X.reshape(E, ng ** 3, 3))
+
+    idx = np.arange(E, dtype=np.int64)
+    i1 = idx % n1
+    i2 = (idx // n1) % n2
+    i3 = idx // (n1 * n2)
+    nbr_elem = np.full((E, 6), -1, dtype=np.int32)
+    nbr_face = np.full((E, 6), -1, dtype=np.int32)
+    bc = np.zeros((E, 6), dtype=np.int8)
+    shift = np.zeros((E, 6, 3), dtype=np.float64)
+    cnt = (n1, n2, n3)
+    coords = [i1, i2, i3]
+    strides = (1, n1, n1 * n2)
+    for a in range(3):
+        for side in (0, 1):
+            f = 2 * a + side
+            step = -1 if side == 0 else 1
+            c = coords[a] + step
+            inside = (c >= 0) & (c < cnt[a])
+            nb = idx + step * strides[a]
+            nbr_elem[inside, f] = nb[inside]
+            nbr_face[inside, f] = 2 * a + (1 - side)
+            bc[inside, f] = BC_INTERNAL
+            out = ~inside
+            if periodic[a]:
+                wrapped = idx + (c % cnt[a] - coords[a]) * strides[a]
+                nbr_elem[out, f] = wrapped[out]
+                nbr_face[out, f] = 2 * a + (1 - side)
+                bc[out, f] = BC_PERIODIC
+                P = np.asarray(periods[a], dtype=np.float64)
+                shift[out, f, :] = -P if side == 1 else P
+            else:
+                bc[out, f] = wall_bc
+    return X, nbr_elem, nbr_face, bc, shift, L
+
+
+# ----------------------------------------------------------------------------
+# velocity fields
+# ----------------------------------------------------------------------------
+def cubic_field(rng):
+    """Each component a cubic of total degree <= 3 in (x, y, z); 20 coefficients ~U(-1,1)."""
+    exps = [(a, b, c) for a in range(4) for b in range(4) for c in range(4) if a + b + c <= 3]
+    coef = rng.uniform(-1.0, 1.0, size=(3, len(exps)))
+
+    def u(x):
+        x = np.asarray(x, dtype=np.float64)
+        out = np.zeros(x.shape[:-1] + (3,))
+        for m, (a, b, c) in enumerate(exps):
+            mono = x[..., 0] ** a * x[..., 1] ** b * x[..., 2] ** c
+            for comp in range(3):
+                out[..., comp] += coef[comp, m] * mono
+        return out
+    return u
+
+
+def fourier_field(rng, n_modes=16, kmax=4, urms=1.0):
+    """Divergence-free random Fourier field with amplitude decay |k|^(-5/3)."""
+    ks = np.array([(a, b, c) for a in range(-kmax, kmax + 1) for b in range(-kmax, kmax + 1)
+                   for c in range(-kmax, kmax + 1) if max(abs(a), abs(b), abs(c)) >= 1], dtype=np.float64)
+    pick = rng.choice(len(ks), size=n_modes, replace=False)
+    k = ks[pick]
+    rnd = rng.normal(size=(n_modes, 3))
+    sig = np.cross(k, rnd)
+    sig /= np.linalg.norm(sig, axis=1, keepdims=True)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    amp = np.linalg.norm(k, axis=1) ** (-5.0 / 3.0)
+    U0 = urms / np.sqrt(0.5 * np.sum(amp ** 2))
+
+    def u(x):
+        x = np.asarray(x, dtype=np.float64)
+        arg = 2.0 * np.pi * (x @ k.T) + phase             # (..., m)
+        return U0 * (np.cos(arg) * amp) @ sig
+    return u
+
+
+def conservative(u, rho=RHO_F, p=P0, kappa=KAPPA):
+    """(rho, rho u, rho e) from a velocity array (..., 3) at uniform rho and p."""
+    rhoe = p / (kappa - 1.0) + 0.5 * rho * np.sum(u * u, axis=-1)
+    out = np.empty(u.shape[:-1] + (5,))
+    out[..., 0] = rho
+    out[..., 1:4] = rho * u
+    out[..., 4] = rhoe
+    return out
+
+
+def gauss_nodes(n_pts):
+    """Legendre-Gauss nodes on [-1, 1] (numpy's routine; used only to place samples)."""
+    x, _ = np.polynomial.legendre.leggauss(n_pts)
+    return x
+
+
+def _dg_state(cells, N, logical_to_phys, field):
+    """Sample the analytic field at the analytic image of each element's Gauss nodes."""
+    n1, n2, n3 = cells
+    n = N + 1
+    g = gauss_nodes(n)
+    E = n1 * n2 * n3
+    idx = np.arange(E)
+    c = np.stack([idx % n1, (idx // n1) % n2, idx // (n1 * n2)], axis=1).astype(np.float64)
+    ii, jj, kk = np.meshgrid(g, g, g, indexing="ij")  # ii along xi1
+    # node order i + n(j + n k): build (k, j, i)
+    loc = np.stack([ii.transpose(2, 1, 0).ravel(), jj.transpose(2, 1, 0).ravel(),
+                    kk.transpose(2, 1, 0).ravel()], axis=1)          # (n^3, 3)
+    cnt = np.array([n1, n2, n3], dtype=np.float64)
+    U = np.empty((E, 5, n ** 3))
+    chunk = max(1, 2_000_000 // (n ** 3))
+    for s in range(0, E, chunk):
+        cs = c[s:s + chunk]
+        sl = (cs[:, None, :] + 0.5 * (loc[None, :, :] + 1.0)) / cnt   # logical coords
+        xp = logical_to_phys(sl)
+        cv = conservative(field(xp))                                     # (e, n^3, 5)
+        U[s:s + chunk] = cv.transpose(0, 2, 1)
+    return U
+
+
+def _particles(rng, cells, n_particles, logical_to_phys, field):
+    n1, n2, n3 = cells
+    E = n1 * n2 * n3
+    e = rng.integers(0, E, size=n_particles)
+    xi = rng.uniform(-1.0, 1.0, size=(n_particles, 3))
+    d = rng.lognormal(mean=-9.2, sigma=0.3, size=n_particles)
+    c = np.stack([e % n1, (e // n1) % n2, e // (n1 * n2)], axis=1).astype(np.float64)
+    sl = (c + 0.5 * (xi + 1.0)) / np.array([n1, n2, n3], dtype=np.float64)
+    x = logical_to_phys(sl)
+    v = field(x)
+    return x, v, d, e.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+# ----------------------------------------------------------------------------
+def config1(n_particles=10_000, cells=8, n_steps=100, seed=1001):
+    """Unit cube, cells^3 straight hexes, Ng=1, all faces periodic, N=3 cubic field, Stokes, 5-stage RK."""
+    rng = np.random.default_rng(seed)
+    n_geo = 1
+
+    def node_map(I1, I2, I3, M):
+        out = np.empty(np.broadcast_shapes(I1.shape, I2.shape, I3.shape) + (3,))
+        out[..., 0] = I1 / M[0]
+        out[..., 1] = I2 / M[1]
+        out[..., 2] = I3 / M[2]
+        return out
+    cc = (cells, cells, cells)
+    X, ne, nf, bc, sh, _ = structured_mesh(cc, n_geo, node_map, (True, True, True),
+                                           periods=np.eye(3))
+    mesh = Mesh(n_geo, X, ne, nf, bc, sh, h=1.0 / cells, cells=cc)
+    field = cubic_field(rng)
+    U = _dg_state(cc, 3, lambda s: s, field)
+    x, v, d, e = _particles(rng, cc, n_particles, lambda s: s, field)
+    return Workload("config1_cube%d_N3_Ng1_periodic" % cells, mesh, 3, U, x, v, d, e,
+                    dt=1e-3, n_steps=n_steps, rk=0, drag=0, velocity=field)
+
+
+def sine_map_logical(s, amp=0.05):
+    """Phi(s) = s + amp*(sin2pi s2 sin2pi s3, sin2pi s3 sin2pi s1, sin2pi s1 sin2pi s2)."""
+    S = np.sin(2.0 * np.pi * s)
+    out = s.copy()
+    out[..., 0] += amp * S[..., 1] * S[..., 2]
+    out[..., 1] += amp * S[..., 2] * S[..., 0]
+    out[..., 2] += amp * S[..., 0] * S[..., 1]
+    return out
+
+
+def sine_mesh(cells, n_geo=4, amp=0.05):
+    def node_map(I1, I2, I3, M):
+        shp = np.broadcast_shapes(I1.shape, I2.shape, I3.shape)
+        s1 = np.broadcast_to(I1 / M[0], shp)
+        s2 = np.broadcast_to(I2 / M[1], shp)
+        s3 = np.broadcast_to(I3 / M[2], shp)
+        S1 = np.broadcast_to(sin2pi(I1, M[0]), shp)
+        S2 = np.broadcast_to(sin2pi(I2, M[1]), shp)
+        S3 = np.broadcast_to(sin2pi(I3, M[2]), shp)
+        out = np.empty(shp + (3,))
+        out[..., 0] = s1 + amp * (S2 * S3)
+        out[..., 1] = s2 + amp * (S3 * S1)
+        out[..., 2] = s3 + amp * (S1 * S2)
+        return out
+    cc = (cells, cells, cells)
+    X, ne, nf, bc, sh, _ = structured_mesh(cc, n_geo, node_map, (True, False, True),
+                                           periods=np.eye(3))
+    return Mesh(n_geo, X, ne, nf, bc, sh, h=1.0 / cells, cells=cc)
+
+
+def curved_box(cells=32, N=5, n_particles=1_000_000, n_steps=500, seed=1002, name="config2",
+               n_geo=4):
+    """Sine-mapped periodic (x, z) box with curved reflective walls at logical y=0/1."""
+    rng = np.random.default_rng(seed)
+    mesh = sine_mesh(cells, n_geo)
+    cc = mesh.cells
+    field = fourier_field(rng)
+    U = _dg_state(cc, N, sine_map_logical, field)
+    x, v, d, e = _particles(rng, cc, n_particles, sine_map_logical, field)
+    return Workload("%s_sine%d_N%d_Ng%d" % (name, cells, N, n_geo), mesh, N, U, x, v, d, e,
+                    dt=1e-3, n_steps=n_steps, rk=1, drag=1, velocity=field)
+
+
+def config2(n_particles=1_000_000, cells=32, n_steps=500):
+    return curved_box(cells, 5, n_particles, n_steps, seed=1002, name="config2")
+
+
+def config3(n_particles=10_000_000, cells=64, n_steps=200):
+    return curved_box(cells, 7, n_particles, n_steps, seed=1003, name="config3")
+
+
+def config5(n_particles=20_000_000, cells=96, n_steps=100):
+    return curved_box(cells, 5, n_particles, n_steps, seed=1005, name="config5")
+
+
+# annular sector passage -----------------------------------------------------
+ANN_RH, ANN_RT, ANN_THETA, ANN_L = 1.0, 1.25, 2.0 * np.pi / 30.0, 0.5
+
+
+def annulus_logical(sl):
+    """Element logical coordinates (s, eta, q) -> physical (x, y, z)."""
+    s, eta, q = sl[..., 0], sl[..., 1], sl[..., 2]
+    r = ANN_RH + (ANN_RT - ANN_RH) * (eta + 0.04 * np.sin(np.pi * eta) * np.sin(24 * np.pi * s)
+                                      * np.sin(24 * np.pi * q))
+    th = ANN_THETA * (q - 0.5 + 0.02 * np.sin(24 * np.pi * s) * np.sin(np.pi * eta)) \
+        + 0.15 * np.sin(2 * np.pi * s)
+    out = np.empty(sl.shape)
+    out[..., 0] = r * np.cos(th)
+    out[..., 1] = r * np.sin(th)
+    out[..., 2] = ANN_L * s
+    return out
+
+
+def annulus_mesh(cells=(48, 24, 48), n_geo=6):
+    """Axial (xi1 = s) periodic, span (xi2 = eta) and pitch (xi3 = q) walls reflective."""
+    def node_map(I1, I2, I3, M):
+        shp = np.broadcast_shapes(I1.shape, I2.shape, I3.shape)
+        s = np.broadcast_to(I1 / M[0], shp)
+        eta = np.broadcast_to(I2 / M[1], shp)
+        q = np.broadcast_to(I3 / M[2], shp)
+        s24 = np.broadcast_to(sin2pi(12 * I1, M[0]), shp)      # sin(24 pi s)
+        s2 = np.broadcast_to(sin2pi(I1, M[0]), shp)            # sin(2 pi s)
+        q24 = np.broadcast_to(sin2pi(12 * I3, M[2]), shp)      # sin(24 pi q)
+        pe = np.broadcast_to(sin2pi(I2, 2 * M[1]), shp)        # sin(pi eta)
+        r = ANN_RH + (ANN_RT - ANN_RH) * (eta + 0.04 * pe * s24 * q24)
+        th = ANN_THETA * (q - 0.5 + 0.02 * s24 * pe) + 0.15 * s2
+        out = np.empty(shp + (3,))
+        out[..., 0] = r * np.cos(th)
+        out[..., 1] = r * np.sin(th)
+        out[..., 2] = ANN_L * s
+        return out
+    periods = np.array([[0.0, 0.0, ANN_L], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    X, ne, nf, bc, sh, _ = structured_mesh(cells, n_geo, node_map, (True, False, False),
+                                           periods=periods)
+    h = ANN_L / cells[0]
+    return Mesh(n_geo, X, ne, nf, bc, sh, h=h, cells=tuple(cells))
+
+
+def config4(n_particles=10_000_000, cells=(48, 24, 48), n_steps=100, seed=1004):
+    rng = np.random.default_rng(seed)
+    mesh = annulus_mesh(cells, 6)
+    field = fourier_field(rng)
+    U = _dg_state(mesh.cells, 5, annulus_logical, field)
+    x, v, d, e = _particles(rng, mesh.cells, n_particles, annulus_logical, field)
+    return Workload("config4_annulus%dx%dx%d_N5_Ng6" % tuple(cells), mesh, 5, U, x, v, d, e,
+                    dt=1e-3, n_steps=n_steps, rk=1, drag=1, velocity=field)
+
+
+# ----------------------------------------------------------------------------
+# tiny meshes for component tests
+# ----------------------------------------------------------------------------
+def single_element(n_geo, node_fn):
+    """One element whose equidistant geometry nodes are node_fn(xi (..., 3)) -> (..., 3); all faces open."""
+    ng = n_geo + 1
+    r = np.linspace(-1.0, 1.0, ng)
+    k, j, i = np.meshgrid(r, r, r, indexing="ij")
+    xi = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
+    X = np.ascontiguousarray(node_fn(xi)[None, :, :])
+    ne = np.full((1, 6), -1, np.int32)
+    nf = np.full((1, 6), -1, np.int32)
+    bc = np.full((1, 6), BC_OPEN, np.int8)
+    sh = np.zeros((1, 6, 3))
+    return Mesh(n_geo, X, ne, nf, bc, sh, h=2.0)
+
+
+def uniform_state(E, N, u, rho=RHO_F, p=P0):
+    n3 = (N + 1) ** 3
+    cv = conservative(np.asarray(u, dtype=np.float64)[None, :], rho, p)[0]
+    U = np.empty((E, 5, n3))
+    U[:, :, :] = cv[None, :, None]
+    return U
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
