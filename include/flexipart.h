@@ -1,0 +1,175 @@
+/*
+ * flexipart: MI355X (gfx950) library for the per-particle Lagrangian step of a
+ * DGSEM particle framework (Kopper et al., "A framework for high-fidelity
+ * particle tracking on massively parallel systems", arXiv 2211.05458).
+ *
+ * One call of fp_step advances every active particle through all stages of a
+ * low-storage Runge-Kutta step: reference coordinates by Newton on the curved
+ * element map (Sec. 3.2.1), tensor-product Lagrange interpolation of the DG
+ * state (eq. part_interpolation), drag (eq. dragforce, dragfactor), the stage
+ * update (Sec. 3.1/3.2.2) and physical-space tracking with face intersection,
+ * element hand-off and wall reflection (Sec. 3.2.3, 3.2.4, 2.4).
+ * fp_deposit_source projects the particle force back onto the DG nodes
+ * (Sec. 2.3, eq. theory:source).
+ *
+ * Conventions common to every entry point
+ *  - Every function returns 0 (FP_OK) on success or a negative fp_err code; a
+ *    positive return is a warning.  fp_last_error(ctx) describes the last
+ *    failure.  No C++ exception crosses this boundary.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory of the current device.  Every pointer is borrowed: the library
+ *    never frees caller memory and never keeps a host pointer past the call.
+ *    Device pointers given to fp_bind_workspace, fp_set_fluid_state and
+ *    fp_mlp_set_weights must stay valid and unmodified until they are
+ *    replaced or the context is destroyed.
+ *  - The library never allocates device memory: all device state lives in the
+ *    caller-allocated workspace (fp_workspace_size / fp_bind_workspace).
+ *  - All device work is enqueued on the stream given to fp_create, in order.
+ *    Only fp_push_particles, fp_read_particles, fp_get_stats and
+ *    fp_bind_workspace synchronise that stream.
+ *  - Element local faces: 0: xi1=-1, 1: xi1=+1, 2: xi2=-1, 3: xi2=+1,
+ *    4: xi3=-1, 5: xi3=+1.  Volume node index i + n*(j + n*k), i along xi1.
+ */
+#ifndef FLEXIPART_H
+#define FLEXIPART_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fp_ctx fp_ctx;
+
+enum fp_err {
+  FP_OK = 0,
+  FP_EINVAL = -1,   /* bad argument, size or unsupported degree */
+  FP_EMESH = -2,    /* inconsistent mesh (non-reciprocal neighbours, J <= 0) */
+  FP_EDEVICE = -3,  /* HIP runtime error */
+  FP_ESTATE = -4,   /* call out of order (e.g. step before push) */
+  FP_WDT = 1        /* warning: dt exceeds the stability bound of the drag term */
+};
+typedef enum { FP_F32 = 0, FP_F64 = 1 } fp_dtype;
+typedef enum { FP_BC_INTERNAL = 0, FP_BC_OPEN = 1, FP_BC_REFLECT = 2, FP_BC_PERIODIC = 3 } fp_bc;
+/* per-particle status (not errors) */
+enum { FP_ACTIVE = 0, FP_OPEN_EXIT = 1, FP_LOST_NEWTON = 2, FP_LOST_TRACK = 3,
+       FP_MAX_CROSS = 4, FP_REJECTED = 5 };
+
+/* Mesh of curved hexahedra (Sec. 3.1, eq. dgsem_curvedfaces): element e is the
+ * tensor-product Lagrange map of degree n_geo through X[e], and the fluid state
+ * is a tensor-product Lagrange polynomial of degree n_dg.  All pointers host. */
+typedef struct {
+  int32_t n_elem;
+  int32_t n_geo;               /* geometry degree, 1..6 (nodes equidistant on [-1,1]) */
+  const double* X;             /* [n_elem][(n_geo+1)^3][3] */
+  const int32_t* nbr_elem;     /* [n_elem][6], neighbour across each local face (-1: none) */
+  const int32_t* nbr_face;     /* [n_elem][6], the neighbour's local face */
+  const int8_t* bc;            /* [n_elem][6], fp_bc */
+  const double* periodic_shift;/* [n_elem][6][3], added to a particle crossing a periodic face */
+  int32_t n_dg;                /* DG degree N, 1..7 */
+  int32_t dg_nodes;            /* 0: Legendre-Gauss, 1: Legendre-Gauss-Lobatto */
+} fp_mesh_desc;
+
+/* Fluid and particle-material constants (Sec. 2.1, 2.2). */
+typedef struct {
+  double mu;      /* dynamic viscosity */
+  double kappa;   /* ratio of specific heats (pressure from rho e) */
+  double rho_p;   /* particle density */
+} fp_fluid_params;
+
+typedef struct {
+  int32_t rk;            /* 0: 5-stage 4th-order low-storage RK (Carpenter-Kennedy), 1: 3-stage 3rd-order (Williamson) */
+  int32_t drag;          /* 0: Stokes (f_D = 1), 1: Schiller-Naumann, 2: no drag */
+  int32_t precision;     /* 0: FP64 throughout; 1: mixed (FP32 interpolation/drag/RK, FP64 Newton tail and tracking) */
+  int32_t guess;         /* 0: the paper's initial guess; 1: learned guess on flagged elements, paper's guess as fallback */
+  int32_t sort_every;    /* counting-sort particles by element every k steps (0: never) */
+  int32_t max_newton_it; /* Newton iteration cap (50) */
+  int32_t max_crossings; /* face crossings per stage before FP_MAX_CROSS (64) */
+  int32_t pad_;
+  double gravity[3];     /* added body acceleration */
+} fp_step_opts;
+
+/* Create a context bound to a HIP stream (hipStream_t, may be NULL for the
+ * null stream) on the current device. */
+int fp_create(fp_ctx** out, void* hip_stream);
+void fp_destroy(fp_ctx* ctx);
+const char* fp_last_error(fp_ctx* ctx);
+
+/* Validate and stage a mesh (host).  Checks neighbour reciprocity; the
+ * Jacobian sign is checked at fp_bind_workspace.  FP_EINVAL / FP_EMESH. */
+int fp_init_mesh(fp_ctx* ctx, const fp_mesh_desc* desc);
+
+/* Device bytes needed for the mesh plus up to max_particles particles. */
+int fp_workspace_size(fp_ctx* ctx, int64_t max_particles, size_t* bytes);
+
+/* Bind caller-allocated device memory (>= fp_workspace_size, 256-byte
+ * aligned).  Uploads the mesh, builds the Bezier faces and their bounding
+ * boxes (Sec. 3.2.4), DG node positions and volumes, and the background mesh
+ * (Sec. 4.1.2).  Synchronises the stream. */
+int fp_bind_workspace(fp_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Borrow the DG state U (device) [n_elem][5][(n_dg+1)^3] of conservative
+ * variables (rho, rho u, rho e) in FP64 or FP32. */
+int fp_set_fluid_state(fp_ctx* ctx, const void* U_dev, fp_dtype dtype, const fp_fluid_params* params);
+
+/* Insert n particles (host arrays x[n][3], v[n][3], d[n]; elem_hint[n] or
+ * NULL) replacing any previous set.  Each is located by Newton in its hint
+ * element, else in the background-mesh candidates in element order; status_out
+ * (host, may be NULL) receives FP_ACTIVE or FP_REJECTED.  Returns the number of
+ * rejected particles (>= 0) or an error. */
+int fp_push_particles(fp_ctx* ctx, int64_t n, const double* x, const double* v, const double* d,
+                      const int32_t* elem_hint, int32_t* status_out);
+
+/* Advance all active particles by n_steps steps of size dt.  Asynchronous. */
+int fp_step(fp_ctx* ctx, double dt, int32_t n_steps, const fp_step_opts* opts);
+
+/* Add the two-way coupling source of the current particle state to S (device)
+ * [n_elem][4][(n_dg+1)^3] (3 momentum components, energy), FP64 or FP32.
+ * kind 0: nearest DOF, S = -F/V_ijk (Sec. 2.3).  kind 1: polynomial shape
+ * kernel (1-(r/R)^2)^2 of radius `radius` over all DG nodes, normalised so that
+ * sum_k S_k V_k = -F; period[3] (host, may be NULL) are the domain periods for
+ * the minimum-image distance (0: not periodic).  Asynchronous. */
+int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, double radius,
+                      const double* period, int32_t drag);
+
+/* Copy the particle state to host buffers (any may be NULL) in the order of
+ * fp_push_particles.  xi is the reference position in elem.  Synchronises. */
+int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* elem, double* xi,
+                      int32_t* wall_hits, int8_t* status);
+
+/* Counters since the last reset: out[0] Newton iterations, out[1] Newton
+ * solves, out[2] face crossings, out[3] wall hits, out[4] lost particles,
+ * out[5] learned-guess fallbacks, out[6] sorts.  Synchronises. */
+int fp_get_stats(fp_ctx* ctx, int64_t* out7);
+int fp_reset_stats(fp_ctx* ctx);
+
+/* ---- learned Newton initial guess (27-64-64-64-3 tanh MLP, FP32) --------- */
+/* Weight layout: W1[64][27] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]. */
+int64_t fp_mlp_n_weights(void);
+/* Features of n (element, point) pairs: 24 corner offsets and the point
+ * offset from the corner mean, scaled by the mean corner-edge length
+ * (device in/out: elem[n] i32, x[n][3] f64 -> feat[n][27] f32). */
+int fp_mlp_features(fp_ctx* ctx, int64_t n, const int32_t* elem_dev, const double* x_dev, float* feat_dev);
+/* Training pairs from the current particles: features and the converged
+ * Newton xi (device outputs feat[n][27], xi[n][3]); n = active particle count. */
+int fp_newton_pairs(fp_ctx* ctx, int64_t* n, float* feat_dev, float* xi_dev, int64_t capacity);
+/* Forward pass (device): out[n][3]. */
+int fp_mlp_forward(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in_dev, float* out_dev);
+/* Mean squared error loss and its gradient over n rows (device; grad[nw]). */
+int fp_mlp_loss_grad(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in_dev,
+                     const float* target_dev, float* grad_dev, float* loss_dev);
+/* One epoch of minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) in the row
+ * order given by order_dev[n]; w, m, v (device, nw each) updated in place;
+ * *t is the Adam step counter; loss_dev[n/batch] receives batch losses. */
+int fp_mlp_train_epoch(fp_ctx* ctx, float* w_dev, float* m_dev, float* v_dev, int64_t* t,
+                       const float* in_dev, const float* target_dev, const int32_t* order_dev,
+                       int64_t n, int32_t batch, float lr, float* loss_dev);
+/* Enable the learned guess with weights (device, borrowed) on elements whose
+ * geometry deviates from the trilinear corner map by > thresh * h_e. */
+int fp_mlp_set_weights(fp_ctx* ctx, const float* w_dev, double thresh);
+int fp_mlp_num_flagged(fp_ctx* ctx, int64_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,695 @@
+// C ABI of the flexipart library (see include/flexipart.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/flexipart.h"
+#include "fp_launch.h"
+
+using namespace fp;
+
+struct fp_ctx {
+  hipStream_t stream = nullptr;
+  std::string err;
+  // mesh (host staging)
+  bool mesh_ok = false;
+  int E = 0, n_geo = 0, ng = 0, N = 0, n = 0, dg_nodes = 0;
+  std::vector<double> X, shift, elo, ehi;
+  std::vector<int32_t> nbr_elem, nbr_face, bstart, blist;
+  std::vector<int8_t> bc;
+  std::vector<double> Minv;
+  double blo[3], bdx[3];
+  int bn[3];
+  double max_extent = 0.0;   // largest element box edge
+  double xgeo[kMaxNodes], cgeo[kMaxNodes], xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t cap = 0;
+  MeshView mv{};
+  Particles P[2]{};
+  int cur = 0;
+  unsigned long long* stats = nullptr;
+  int32_t *sort_count = nullptr, *sort_start = nullptr, *sort_rank = nullptr, *sort_sums = nullptr;
+  int32_t* scratch_i32 = nullptr;
+  uint8_t* mlp_flag = nullptr;
+  double* dep_buf = nullptr;   // per-particle force (4) + normalisation (1)
+  float* mlp_rows = nullptr;   // per-row activations for MLP gradients
+  float* mlp_grad = nullptr;   // gradient + loss scratch
+  // fluid
+  Fluid fl{};
+  bool fluid_ok = false;
+  // particles
+  int64_t np = 0;
+  double d_min = 0.0;
+  bool xi_dirty = false;
+  bool sorted_valid = false;
+  int64_t steps_done = 0, sorts = 0;
+  // learned guess
+  const float* mlp_w = nullptr;
+  int64_t n_flagged = 0;
+};
+
+namespace {
+
+int fail(fp_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(fp_ctx* c, hipError_t e, const char* where) {
+  return fail(c, FP_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                   \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return hip_fail(c, _e, #expr);  \
+  } while (0)
+
+// Legendre polynomial and derivative by the three-term recurrence
+void legendre_pd(int n, double x, double& P, double& dP) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { P = 1.0; dP = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  P = p1;
+  // (x^2 - 1) P_n' = n (x P_n - P_{n-1})
+  dP = (std::fabs(x) == 1.0) ? 0.5 * n * (n + 1) * std::pow(x, n + 1) : n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (n - i - 0.25) / (n + 0.5));
+    for (int it = 0; it < 60; ++it) {
+      double P, dP;
+      legendre_pd(n, z, P, dP);
+      double dz = P / dP;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double P, dP;
+    legendre_pd(n, z, P, dP);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dP * dP);
+  }
+}
+
+void gauss_lobatto(int n, double* x, double* w) {
+  int N = n - 1;
+  for (int i = 0; i <= N; ++i) {
+    double z = -std::cos(M_PI * i / N);
+    if (i > 0 && i < N)
+      for (int it = 0; it < 60; ++it) {
+        // roots of (1 - z^2) P_N'(z): Newton on q = P_{N+1} - P_{N-1}
+        double Pa, dPa, Pb, dPb;
+        legendre_pd(N + 1, z, Pa, dPa);
+        legendre_pd(N - 1, z, Pb, dPb);
+        double dz = (Pa - Pb) / (dPa - dPb);
+        z -= dz;
+        if (std::fabs(dz) < 1e-17) break;
+      }
+    x[i] = z;
+    double P, dP;
+    legendre_pd(N, z, P, dP);
+    w[i] = 2.0 / (N * (N + 1.0) * P * P);
+  }
+}
+
+void lagrange_weights(int n, const double* x, double* c) {
+  for (int i = 0; i < n; ++i) {
+    double p = 1.0;
+    for (int j = 0; j < n; ++j)
+      if (j != i) p *= (x[i] - x[j]);
+    c[i] = 1.0 / p;
+  }
+}
+
+// inverse of the Bernstein-Vandermonde matrix M_ab = B_b((s_a + 1)/2)
+std::vector<double> bernstein_vandermonde_inverse(int ng, const double* s) {
+  int D = ng - 1;
+  std::vector<double> A(ng * 2 * ng, 0.0);
+  for (int a = 0; a < ng; ++a) {
+    double t = 0.5 * (s[a] + 1.0);
+    double binom = 1.0;
+    for (int b = 0; b <= D; ++b) {
+      A[a * 2 * ng + b] = binom * std::pow(t, b) * std::pow(1.0 - t, D - b);
+      binom = binom * (D - b) / (b + 1);
+    }
+    A[a * 2 * ng + ng + a] = 1.0;
+  }
+  for (int col = 0; col < ng; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < ng; ++r)
+      if (std::fabs(A[r * 2 * ng + col]) > std::fabs(A[piv * 2 * ng + col])) piv = r;
+    for (int j = 0; j < 2 * ng; ++j) std::swap(A[col * 2 * ng + j], A[piv * 2 * ng + j]);
+    double p = A[col * 2 * ng + col];
+    for (int j = 0; j < 2 * ng; ++j) A[col * 2 * ng + j] /= p;
+    for (int r = 0; r < ng; ++r) {
+      if (r == col) continue;
+      double f = A[r * 2 * ng + col];
+      for (int j = 0; j < 2 * ng; ++j) A[r * 2 * ng + j] -= f * A[col * 2 * ng + j];
+    }
+  }
+  std::vector<double> M(ng * ng);
+  for (int i = 0; i < ng; ++i)
+    for (int j = 0; j < ng; ++j) M[i * ng + j] = A[i * 2 * ng + ng + j];
+  return M;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
+      sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, part[2], total;
+  size_t part_bytes;
+};
+
+Layout layout(const fp_ctx* c, int64_t cap) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  size_t E = c->E, ng3 = (size_t)c->ng * c->ng * c->ng, n3 = (size_t)c->n * c->n * c->n;
+  L.X = take(E * ng3 * 3 * 8);
+  L.faces = take(E * 6 * sizeof(FaceRec));
+  L.cp = take(E * 6 * c->ng * c->ng * 3 * 8);
+  L.hE = take(E * 8);
+  L.xnode = take(E * n3 * 3 * 8);
+  L.vol = take(E * n3 * 8);
+  L.elo = take(E * 3 * 8);
+  L.ehi = take(E * 3 * 8);
+  L.nbr_elem = take(E * 6 * 4);
+  L.nbr_face = take(E * 6 * 4);
+  L.bc = take(E * 6);
+  L.shift = take(E * 18 * 8);
+  L.bstart = take(c->bstart.size() * 4);
+  L.blist = take(std::max<size_t>(1, c->blist.size()) * 4);
+  L.mlp_flag = take(E);
+  L.stats = take(16 * 8);
+  L.sort_count = take((E + 1) * 4);
+  L.sort_start = take((E + 1) * 4);
+  L.sort_rank = take((size_t)std::max<int64_t>(cap, 1) * 4);
+  L.sort_sums = take(((std::max<size_t>(E + 1, cap) + 1023) / 1024 + 2) * 4);
+  L.scratch = take(64);
+  L.dep = take((size_t)std::max<int64_t>(cap, 1) * 5 * 8);
+  L.mlp_rows = take((size_t)kMlpMaxBatch * kMlpRow * 4);
+  L.mlp_grad = take((size_t)(kMlpWeights + 64) * 4);
+  size_t pc = (size_t)std::max<int64_t>(cap, 1);
+  L.part_bytes = align256(pc * 15 * 8) + align256(pc * 8) + 3 * align256(pc * 4) + align256(pc);
+  L.part[0] = take(L.part_bytes);
+  L.part[1] = take(L.part_bytes);
+  L.total = o;
+  return L;
+}
+
+Particles carve(char* base, int64_t cap) {
+  Particles P{};
+  size_t pc = (size_t)std::max<int64_t>(cap, 1);
+  P.cap = cap;
+  char* p = base;
+  P.x = (double*)p; P.v = P.x + 3 * pc; P.kx = P.v + 3 * pc; P.kv = P.kx + 3 * pc; P.xi = P.kv + 3 * pc;
+  p += align256(pc * 15 * 8);
+  P.d = (double*)p; p += align256(pc * 8);
+  P.elem = (int32_t*)p; p += align256(pc * 4);
+  P.hits = (int32_t*)p; p += align256(pc * 4);
+  P.id = (int32_t*)p; p += align256(pc * 4);
+  P.status = (int8_t*)p;
+  return P;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fp_create(fp_ctx** out, void* hip_stream) {
+  if (!out) return FP_EINVAL;
+  fp_ctx* c = new fp_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return FP_OK;
+}
+
+void fp_destroy(fp_ctx* c) { delete c; }
+
+const char* fp_last_error(fp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fp_init_mesh(fp_ctx* c, const fp_mesh_desc* d) {
+  if (!c || !d) return FP_EINVAL;
+  if (d->n_elem <= 0 || d->n_geo < 1 || d->n_geo > 6 || d->n_dg < 1 || d->n_dg > 7 || !d->X || !d->nbr_elem ||
+      !d->nbr_face || !d->bc || !d->periodic_shift)
+    return fail(c, FP_EINVAL, "fp_init_mesh: bad sizes or null arrays");
+  if (!supported(d->n_dg + 1, d->n_geo + 1))
+    return fail(c, FP_EINVAL, "fp_init_mesh: no compiled kernels for this (N, Ngeo)");
+  int E = d->n_elem;
+  // neighbour reciprocity
+  for (int e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      int nb = d->nbr_elem[e * 6 + f], nf = d->nbr_face[e * 6 + f], b = d->bc[e * 6 + f];
+      if (b < 0 || b > 3) return fail(c, FP_EMESH, "fp_init_mesh: bad boundary code");
+      if (b == FP_BC_INTERNAL || b == FP_BC_PERIODIC) {
+        if (nb < 0 || nb >= E || nf < 0 || nf > 5) return fail(c, FP_EMESH, "fp_init_mesh: bad neighbour");
+        if (d->nbr_elem[nb * 6 + nf] != e || d->nbr_face[nb * 6 + nf] != f)
+          return fail(c, FP_EMESH, "fp_init_mesh: non-reciprocal neighbour table");
+      }
+    }
+  c->E = E; c->n_geo = d->n_geo; c->ng = d->n_geo + 1; c->N = d->n_dg; c->n = d->n_dg + 1;
+  c->dg_nodes = d->dg_nodes;
+  size_t ng3 = (size_t)c->ng * c->ng * c->ng;
+  c->X.assign(d->X, d->X + (size_t)E * ng3 * 3);
+  c->nbr_elem.assign(d->nbr_elem, d->nbr_elem + E * 6);
+  c->nbr_face.assign(d->nbr_face, d->nbr_face + E * 6);
+  c->bc.assign(d->bc, d->bc + E * 6);
+  c->shift.assign(d->periodic_shift, d->periodic_shift + (size_t)E * 18);
+  for (int i = 0; i < c->ng; ++i) c->xgeo[i] = -1.0 + 2.0 * i / c->n_geo;
+  lagrange_weights(c->ng, c->xgeo, c->cgeo);
+  if (c->dg_nodes == 0) gauss_legendre(c->n, c->xdg, c->wdg);
+  else gauss_lobatto(c->n, c->xdg, c->wdg);
+  lagrange_weights(c->n, c->xdg, c->cdg);
+  c->Minv = bernstein_vandermonde_inverse(c->ng, c->xgeo);
+  // element boxes (node box padded by 5 % per axis) and the background mesh
+  c->elo.resize((size_t)E * 3);
+  c->ehi.resize((size_t)E * 3);
+  double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300}, ext = 0.0;
+  for (int e = 0; e < E; ++e) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    const double* P = c->X.data() + (size_t)e * ng3 * 3;
+    for (size_t q = 0; q < ng3; ++q)
+      for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], P[q * 3 + k]); hi[k] = std::max(hi[k], P[q * 3 + k]); }
+    double em = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double pad = 0.05 * (hi[k] - lo[k]);
+      c->elo[e * 3 + k] = lo[k] - pad;
+      c->ehi[e * 3 + k] = hi[k] + pad;
+      glo[k] = std::min(glo[k], c->elo[e * 3 + k]);
+      ghi[k] = std::max(ghi[k], c->ehi[e * 3 + k]);
+      em = std::max(em, hi[k] - lo[k]);
+    }
+    ext += em;
+    c->max_extent = std::max(c->max_extent, 1.1 * em);
+  }
+  double h = ext / E;
+  for (int k = 0; k < 3; ++k) {
+    int nb = (int)std::ceil((ghi[k] - glo[k]) / h);
+    nb = std::max(1, std::min(nb, 1024));
+    c->bn[k] = nb;
+    c->blo[k] = glo[k];
+    c->bdx[k] = (ghi[k] - glo[k]) / nb;
+    if (!(c->bdx[k] > 0.0)) c->bdx[k] = 1.0;
+  }
+  size_t ncell = (size_t)c->bn[0] * c->bn[1] * c->bn[2];
+  c->bstart.assign(ncell + 1, 0);
+  std::vector<int> lo3((size_t)E * 3), hi3((size_t)E * 3);
+  for (int e = 0; e < E; ++e)
+    for (int k = 0; k < 3; ++k) {
+      lo3[e * 3 + k] = std::max(0, (int)std::floor((c->elo[e * 3 + k] - c->blo[k]) / c->bdx[k]));
+      hi3[e * 3 + k] = std::min(c->bn[k] - 1, (int)std::floor((c->ehi[e * 3 + k] - c->blo[k]) / c->bdx[k]));
+    }
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int32_t> fill;
+    if (pass == 1) {
+      for (size_t i = 0; i < ncell; ++i) c->bstart[i + 1] += c->bstart[i];
+      c->blist.assign(c->bstart[ncell], 0);
+      fill.assign(ncell, 0);
+    }
+    for (int e = 0; e < E; ++e)
+      for (int z = lo3[e * 3 + 2]; z <= hi3[e * 3 + 2]; ++z)
+        for (int y = lo3[e * 3 + 1]; y <= hi3[e * 3 + 1]; ++y)
+          for (int x = lo3[e * 3]; x <= hi3[e * 3]; ++x) {
+            size_t cell = ((size_t)z * c->bn[1] + y) * c->bn[0] + x;
+            if (pass == 0) c->bstart[cell + 1]++;
+            else c->blist[c->bstart[cell] + fill[cell]++] = e;
+          }
+  }
+  c->mesh_ok = true;
+  c->ws = nullptr;
+  c->np = 0;
+  c->fluid_ok = false;
+  return FP_OK;
+}
+
+int fp_workspace_size(fp_ctx* c, int64_t max_particles, size_t* bytes) {
+  if (!c || !bytes || max_particles < 0) return FP_EINVAL;
+  if (!c->mesh_ok) return fail(c, FP_ESTATE, "fp_workspace_size: no mesh");
+  if (max_particles > (int64_t)INT32_MAX) return fail(c, FP_EINVAL, "fp_workspace_size: too many particles");
+  *bytes = layout(c, max_particles).total + 256;
+  return FP_OK;
+}
+
+int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
+  if (!c || !dev) return FP_EINVAL;
+  if (!c->mesh_ok) return fail(c, FP_ESTATE, "fp_bind_workspace: no mesh");
+  if (((uintptr_t)dev) & 255) return fail(c, FP_EINVAL, "fp_bind_workspace: pointer not 256-byte aligned");
+  // largest particle capacity that fits
+  int64_t lo = 0, hi = 1;
+  while (layout(c, hi).total + 256 <= bytes && hi < ((int64_t)1 << 31)) hi *= 2;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) / 2;
+    if (layout(c, mid).total + 256 <= bytes) lo = mid; else hi = mid;
+  }
+  if (layout(c, lo).total + 256 > bytes) return fail(c, FP_EINVAL, "fp_bind_workspace: too small for the mesh");
+  Layout L = layout(c, lo);
+  char* b = (char*)dev;
+  c->ws = b;
+  c->ws_bytes = bytes;
+  c->cap = lo;
+  hipStream_t s = c->stream;
+  size_t E = c->E, ng3 = (size_t)c->ng * c->ng * c->ng;
+  HIPCHK(c, hipMemcpyAsync(b + L.X, c->X.data(), E * ng3 * 3 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.elo, c->elo.data(), E * 3 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.ehi, c->ehi.data(), E * 3 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.nbr_elem, c->nbr_elem.data(), E * 6 * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.nbr_face, c->nbr_face.data(), E * 6 * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.bc, c->bc.data(), E * 6, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.shift, c->shift.data(), E * 18 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.bstart, c->bstart.data(), c->bstart.size() * 4, hipMemcpyHostToDevice, s));
+  if (!c->blist.empty())
+    HIPCHK(c, hipMemcpyAsync(b + L.blist, c->blist.data(), c->blist.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(b + L.stats, 0, 16 * 8, s));
+  HIPCHK(c, hipMemsetAsync(b + L.mlp_flag, 0, E, s));
+  MeshView& m = c->mv;
+  m = MeshView{};
+  m.E = c->E; m.ng = c->ng; m.n = c->n; m.n_geo = c->n_geo;
+  m.X = (const double*)(b + L.X);
+  m.faces = (const FaceRec*)(b + L.faces);
+  m.cp = (const double*)(b + L.cp);
+  m.hE = (const double*)(b + L.hE);
+  m.xnode = (const double*)(b + L.xnode);
+  m.vol = (const double*)(b + L.vol);
+  m.elo = (const double*)(b + L.elo);
+  m.ehi = (const double*)(b + L.ehi);
+  for (int i = 0; i < kMaxNodes; ++i) {
+    m.xgeo[i] = i < c->ng ? c->xgeo[i] : 0.0;
+    m.cgeo[i] = i < c->ng ? c->cgeo[i] : 0.0;
+    m.xdg[i] = i < c->n ? c->xdg[i] : 0.0;
+    m.cdg[i] = i < c->n ? c->cdg[i] : 0.0;
+    m.wdg[i] = i < c->n ? c->wdg[i] : 0.0;
+    m.xdgf[i] = (float)m.xdg[i];
+    m.cdgf[i] = (float)m.cdg[i];
+  }
+  for (int k = 0; k < 3; ++k) { m.blo[k] = c->blo[k]; m.bdx[k] = c->bdx[k]; m.bn[k] = c->bn[k]; }
+  m.bstart = (const int32_t*)(b + L.bstart);
+  m.blist = (const int32_t*)(b + L.blist);
+  m.mlp_flag = (const uint8_t*)(b + L.mlp_flag);
+  m.mlp_w = nullptr;
+  c->mlp_flag = (uint8_t*)(b + L.mlp_flag);
+  c->stats = (unsigned long long*)(b + L.stats);
+  c->sort_count = (int32_t*)(b + L.sort_count);
+  c->sort_start = (int32_t*)(b + L.sort_start);
+  c->sort_rank = (int32_t*)(b + L.sort_rank);
+  c->sort_sums = (int32_t*)(b + L.sort_sums);
+  c->scratch_i32 = (int32_t*)(b + L.scratch);
+  c->dep_buf = (double*)(b + L.dep);
+  c->mlp_rows = (float*)(b + L.mlp_rows);
+  c->mlp_grad = (float*)(b + L.mlp_grad);
+  c->P[0] = carve(b + L.part[0], c->cap);
+  c->P[1] = carve(b + L.part[1], c->cap);
+  c->cur = 0;
+  HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 64, s));
+  HIPCHK(c, launch_face_setup(m, m.X, (const int32_t*)(b + L.nbr_elem), (const int32_t*)(b + L.nbr_face),
+                              (const int8_t*)(b + L.bc), (const double*)(b + L.shift), c->Minv.data(),
+                              (FaceRec*)(b + L.faces), (double*)(b + L.cp), s));
+  HIPCHK(c, launch_nodes(m, (double*)(b + L.xnode), (double*)(b + L.vol), (double*)(b + L.hE), c->scratch_i32, s));
+  int32_t bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->scratch_i32, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (bad) return fail(c, FP_EMESH, "fp_bind_workspace: non-positive Jacobian at " + std::to_string(bad) + " nodes");
+  c->np = 0;
+  return FP_OK;
+}
+
+int fp_set_fluid_state(fp_ctx* c, const void* U, fp_dtype dt, const fp_fluid_params* prm) {
+  if (!c || !U || !prm) return FP_EINVAL;
+  if (!(prm->mu > 0.0) || !(prm->rho_p > 0.0)) return fail(c, FP_EINVAL, "fp_set_fluid_state: bad parameters");
+  c->fl.U = U;
+  c->fl.f32 = (dt == FP_F32);
+  c->fl.mu = prm->mu;
+  c->fl.kappa = prm->kappa;
+  c->fl.rho_p = prm->rho_p;
+  c->fluid_ok = true;
+  return FP_OK;
+}
+
+int fp_push_particles(fp_ctx* c, int64_t n, const double* x, const double* v, const double* d,
+                      const int32_t* hint, int32_t* status_out) {
+  if (!c || n < 0 || (n > 0 && (!x || !v || !d))) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_push_particles: no workspace");
+  if (n > c->cap) return fail(c, FP_EINVAL, "fp_push_particles: more particles than workspace capacity");
+  hipStream_t s = c->stream;
+  c->cur = 0;
+  Particles& P = c->P[0];
+  int64_t cap = c->cap;
+  std::vector<double> tx((size_t)n * 3), tv((size_t)n * 3);
+  double dmin = 1e300;
+  for (int64_t p = 0; p < n; ++p) {
+    for (int k = 0; k < 3; ++k) {
+      tx[k * n + p] = x[p * 3 + k];
+      tv[k * n + p] = v[p * 3 + k];
+    }
+    dmin = std::min(dmin, d[p]);
+    if (!(d[p] > 0.0)) return fail(c, FP_EINVAL, "fp_push_particles: non-positive diameter");
+  }
+  for (int k = 0; k < 3 && n > 0; ++k) {
+    HIPCHK(c, hipMemcpyAsync(P.x + k * cap, tx.data() + k * n, n * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(P.v + k * cap, tv.data() + k * n, n * 8, hipMemcpyHostToDevice, s));
+  }
+  if (n > 0) HIPCHK(c, hipMemcpyAsync(P.d, d, n * 8, hipMemcpyHostToDevice, s));
+  const int32_t* dh = nullptr;
+  if (hint && n > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->sort_rank, hint, n * 4, hipMemcpyHostToDevice, s));
+    dh = c->sort_rank;
+  }
+  HIPCHK(c, launch_locate(c->mv, P, dh, n, s));
+  std::vector<int8_t> st((size_t)std::max<int64_t>(n, 1));
+  if (n > 0) HIPCHK(c, hipMemcpyAsync(st.data(), P.status, n, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  int nrej = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    if (st[p] != FP_ACTIVE) nrej++;
+    if (status_out) status_out[p] = st[p];
+  }
+  c->np = n;
+  c->d_min = dmin;
+  c->xi_dirty = false;
+  c->steps_done = 0;
+  return nrej;
+}
+
+int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
+  if (!c || !o || n_steps < 0 || !(dt > 0.0)) return FP_EINVAL;
+  if (!c->ws || !c->fluid_ok) return fail(c, FP_ESTATE, "fp_step: workspace or fluid state missing");
+  if (o->rk < 0 || o->rk > 1 || o->drag < 0 || o->drag > 2 || o->precision < 0 || o->precision > 1)
+    return fail(c, FP_EINVAL, "fp_step: bad options");
+  if (o->precision == 0 && c->fl.f32)
+    ;  // FP64 arithmetic on an FP32 state is allowed (values widened on load)
+  // low-storage coefficients (Carpenter-Kennedy 5-stage 4th order; Williamson 3-stage 3rd order)
+  static const double A4[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+  static const double B4[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+  static const double A3[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double B3[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  const double* A = o->rk == 0 ? A4 : A3;
+  const double* B = o->rk == 0 ? B4 : B3;
+  int S = o->rk == 0 ? 5 : 3;
+  StepParams sp{};
+  sp.dt = dt;
+  for (int k = 0; k < 3; ++k) sp.gravity[k] = o->gravity[k];
+  sp.drag = o->drag;
+  sp.max_it = o->max_newton_it > 0 ? o->max_newton_it : 50;
+  sp.max_cross = o->max_crossings > 0 ? o->max_crossings : 64;
+  sp.use_mlp = (o->guess == 1 && c->mlp_w) ? 1 : 0;
+  hipStream_t s = c->stream;
+  for (int st = 0; st < n_steps; ++st) {
+    if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
+      HIPCHK(c, launch_sort(c->P[c->cur], c->P[1 - c->cur], c->np, c->E, c->sort_count, c->sort_start,
+                            c->sort_rank, c->sort_sums, s));
+      c->cur = 1 - c->cur;
+      c->sorts++;
+    }
+    for (int i = 0; i < S; ++i) {
+      sp.A = A[i];
+      sp.B = B[i];
+      HIPCHK(c, launch_stage(c->mv, c->P[c->cur], c->fl, sp, c->np, o->precision, c->stats, s));
+    }
+    c->steps_done++;
+  }
+  c->xi_dirty = true;
+  // stability of the drag term: dt * f_D / tau_p within the real-axis bound of the scheme
+  double tau_min = c->fl.rho_p * c->d_min * c->d_min / (18.0 * c->fl.mu);
+  double bound = o->rk == 0 ? 4.65 : 2.51;
+  if (o->drag != 2 && c->np > 0 && dt > bound * tau_min) {
+    c->err = "fp_step: dt exceeds the drag stability bound";
+    return FP_WDT;
+  }
+  return FP_OK;
+}
+
+int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radius, const double* period,
+                      int32_t drag) {
+  if (!c || !S || kind < 0 || kind > 1) return FP_EINVAL;
+  if (!c->ws || !c->fluid_ok) return fail(c, FP_ESTATE, "fp_deposit_source: workspace or fluid state missing");
+  if (kind == 0) {
+    HIPCHK(c, launch_deposit_nearest(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, c->stream));
+    return FP_OK;
+  }
+  if (!(radius > 0.0)) return fail(c, FP_EINVAL, "fp_deposit_source: radius must be positive");
+  double per[3] = {0, 0, 0};
+  if (period)
+    for (int k = 0; k < 3; ++k) per[k] = period[k];
+  for (int k = 0; k < 3; ++k)
+    if (per[k] > 0.0 && per[k] <= 2.0 * (radius + c->max_extent))
+      return fail(c, FP_EINVAL, "fp_deposit_source: period too short for the kernel radius");
+  // gather needs the particles bucketed by their current element
+  HIPCHK(c, launch_sort(c->P[c->cur], c->P[1 - c->cur], c->np, c->E, c->sort_count, c->sort_start, c->sort_rank,
+                        c->sort_sums, c->stream));
+  c->cur = 1 - c->cur;
+  c->sorts++;
+  HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, radius, per,
+                                 c->dep_buf, c->dep_buf, c->sort_start, c->stream));
+  return FP_OK;
+}
+
+int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* elem, double* xi,
+                      int32_t* hits, int8_t* status) {
+  if (!c) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_read_particles: no workspace");
+  hipStream_t s = c->stream;
+  int64_t n = c->np, cap = c->cap;
+  if (n_out) *n_out = n;
+  if (n == 0) return FP_OK;
+  Particles& P = c->P[c->cur];
+  if (c->xi_dirty) {
+    HIPCHK(c, launch_finalize(c->mv, P, n, c->stats, s));
+    c->xi_dirty = false;
+  }
+  std::vector<double> hx((size_t)n * 3), hv((size_t)n * 3), hxi((size_t)n * 3);
+  std::vector<int32_t> he(n), hh(n), hid(n);
+  std::vector<int8_t> hs(n);
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(c, hipMemcpyAsync(hx.data() + k * n, P.x + k * cap, n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hv.data() + k * n, P.v + k * cap, n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hxi.data() + k * n, P.xi + k * cap, n * 8, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(he.data(), P.elem, n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hh.data(), P.hits, n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hid.data(), P.id, n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hs.data(), P.status, n, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int64_t q = 0; q < n; ++q) {
+    int64_t p = hid[q];
+    if (p < 0 || p >= n) return fail(c, FP_EDEVICE, "fp_read_particles: corrupt particle ids");
+    for (int k = 0; k < 3; ++k) {
+      if (x) x[p * 3 + k] = hx[k * n + q];
+      if (v) v[p * 3 + k] = hv[k * n + q];
+      if (xi) xi[p * 3 + k] = hxi[k * n + q];
+    }
+    if (elem) elem[p] = he[q];
+    if (hits) hits[p] = hh[q];
+    if (status) status[p] = hs[q];
+  }
+  return FP_OK;
+}
+
+int fp_get_stats(fp_ctx* c, int64_t* out) {
+  if (!c || !out) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_get_stats: no workspace");
+  unsigned long long h[ST_N];
+  HIPCHK(c, hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 6; ++i) out[i] = (int64_t)h[i];
+  out[6] = c->sorts;
+  return FP_OK;
+}
+
+int fp_reset_stats(fp_ctx* c) {
+  if (!c) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_reset_stats: no workspace");
+  HIPCHK(c, hipMemsetAsync(c->stats, 0, 16 * 8, c->stream));
+  c->sorts = 0;
+  return FP_OK;
+}
+
+// ---- learned guess --------------------------------------------------------
+int64_t fp_mlp_n_weights(void) { return 64 * 27 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3; }
+
+int fp_mlp_features(fp_ctx* c, int64_t n, const int32_t* elem, const double* x, float* feat) {
+  if (!c || n < 0 || (n > 0 && (!elem || !x || !feat))) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_features: no workspace");
+  HIPCHK(c, launch_mlp_features(c->mv, n, elem, x, feat, c->stream));
+  return FP_OK;
+}
+
+int fp_newton_pairs(fp_ctx* c, int64_t* n_out, float* feat, float* xi, int64_t capacity) {
+  if (!c || !n_out || !feat || !xi) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_newton_pairs: no workspace");
+  if (capacity < c->np) return fail(c, FP_EINVAL, "fp_newton_pairs: capacity below particle count");
+  HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 4, c->stream));
+  HIPCHK(c, launch_newton_pairs(c->mv, c->P[c->cur], c->np, feat, xi, c->scratch_i32, c->stream));
+  int32_t cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->scratch_i32, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *n_out = cnt;
+  return FP_OK;
+}
+
+int fp_mlp_forward(fp_ctx* c, const float* w, int64_t n, const float* in, float* out) {
+  if (!c || !w || n < 0 || (n > 0 && (!in || !out))) return FP_EINVAL;
+  HIPCHK(c, launch_mlp_forward(w, n, in, out, c->stream));
+  return FP_OK;
+}
+
+int fp_mlp_loss_grad(fp_ctx* c, const float* w, int64_t n, const float* in, const float* target, float* grad,
+                     float* loss) {
+  if (!c || !w || n <= 0 || !in || !target || !grad || !loss) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_loss_grad: no workspace");
+  if (n > kMlpMaxBatch) return fail(c, FP_EINVAL, "fp_mlp_loss_grad: at most 8192 rows per call");
+  HIPCHK(c, launch_mlp_loss_grad(w, n, in, target, nullptr, grad, loss, c->mlp_rows, c->stream));
+  return FP_OK;
+}
+
+int fp_mlp_train_epoch(fp_ctx* c, float* w, float* m, float* v, int64_t* t, const float* in, const float* target,
+                       const int32_t* order, int64_t n, int32_t batch, float lr, float* loss) {
+  if (!c || !w || !m || !v || !t || !in || !target || !order || n <= 0 || batch <= 0) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_train_epoch: no workspace");
+  if (batch > kMlpMaxBatch) return fail(c, FP_EINVAL, "fp_mlp_train_epoch: batch above 8192");
+  int64_t nw = fp_mlp_n_weights();
+  float* grad = c->mlp_grad;
+  float* lbuf = grad + nw;
+  int64_t nb = n / batch;
+  for (int64_t bi = 0; bi < nb; ++bi) {
+    HIPCHK(c, launch_mlp_loss_grad(w, batch, in, target, order + bi * batch, grad,
+                                   loss ? loss + bi : lbuf, c->mlp_rows, c->stream));
+    (*t)++;
+    HIPCHK(c, launch_adam(w, m, v, grad, nw, *t, lr, c->stream));
+  }
+  return FP_OK;
+}
+
+int fp_mlp_set_weights(fp_ctx* c, const float* w, double thresh) {
+  if (!c) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_set_weights: no workspace");
+  c->mlp_w = w;
+  c->mv.mlp_w = w;
+  if (!w) { c->n_flagged = 0; return FP_OK; }
+  HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 4, c->stream));
+  HIPCHK(c, launch_curved_flags(c->mv, thresh, c->mlp_flag, c->scratch_i32, c->stream));
+  int32_t cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->scratch_i32, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->n_flagged = cnt;
+  return FP_OK;
+}
+
+int fp_mlp_num_flagged(fp_ctx* c, int64_t* n) {
+  if (!c || !n) return FP_EINVAL;
+  *n = c->n_flagged;
+  return FP_OK;
+}
+
+}  // extern "C"

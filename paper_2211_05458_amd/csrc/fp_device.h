@@ -1,0 +1,814 @@
+// Device building blocks of the per-particle step (gfx950).  Loop bounds are
+// compile-time node counts so that the tensor-product sums unroll into
+// straight FMA chains.
+#pragma once
+#include "fp_internal.h"
+
+namespace fp {
+
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double det3(const double J[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// ---------------------------------------------------------------------------
+// Lagrange basis l_i(x) = c_i prod_{j != i}(x - x_j), c_i = 1/prod_{j != i}(x_i - x_j)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__device__ __forceinline__ void lagrange(const T* nodes, const T* cden, T x, T* l) {
+  T dx[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) dx[j] = x - nodes[j];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T p = cden[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j != i) p *= dx[j];
+    l[i] = p;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void lagrange_d(const double* nodes, const double* cden, double x, double* l,
+                                           double* dl) {
+  double dx[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) dx[j] = x - nodes[j];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double p = 1.0, dp = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j != i) {
+        dp = dp * dx[j] + p;
+        p *= dx[j];
+      }
+    l[i] = cden[i] * p;
+    dl[i] = cden[i] * dp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// chi_e(xi) and J = d chi / d xi by sum factorisation over i, then j, then k
+// ---------------------------------------------------------------------------
+template <int NG>
+__device__ __forceinline__ void map_jac(const MeshView& m, const double* __restrict__ X, const double* xi,
+                                        double* x, double J[3][3]) {
+  double l1[NG], d1[NG], l2[NG], d2[NG], l3[NG], d3[NG];
+  lagrange_d<NG>(m.xgeo, m.cgeo, xi[0], l1, d1);
+  lagrange_d<NG>(m.xgeo, m.cgeo, xi[1], l2, d2);
+  lagrange_d<NG>(m.xgeo, m.cgeo, xi[2], l3, d3);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    x[q] = 0.0;
+    J[q][0] = J[q][1] = J[q][2] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    double a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      double s0[3] = {0, 0, 0}, s1[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        const double* P = X + ((k * NG + j) * NG + i) * 3;
+        double p0 = P[0], p1 = P[1], p2 = P[2];
+        s0[0] += p0 * l1[i]; s0[1] += p1 * l1[i]; s0[2] += p2 * l1[i];
+        s1[0] += p0 * d1[i]; s1[1] += p1 * d1[i]; s1[2] += p2 * d1[i];
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        a[q] += s0[q] * l2[j];
+        b[q] += s1[q] * l2[j];
+        c[q] += s0[q] * d2[j];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      x[q] += a[q] * l3[k];
+      J[q][0] += b[q] * l3[k];
+      J[q][1] += c[q] * l3[k];
+      J[q][2] += a[q] * d3[k];
+    }
+  }
+}
+
+// Newton for chi(xi) = x (Sec. 3.2.1): Cramer's rule, stop after an update with
+// max-norm <= 1e-10, divergence when |xi| > 2 after the third iteration.
+template <int NG>
+__device__ bool newton(const MeshView& m, int e, const double* x, double* z, int max_it, int& iters) {
+  const double* X = m.X + (size_t)e * (NG * NG * NG * 3);
+  for (int it = 1; it <= max_it; ++it) {
+    double F[3], J[3][3];
+    map_jac<NG>(m, X, z, F, J);
+    F[0] -= x[0]; F[1] -= x[1]; F[2] -= x[2];
+    double det = det3(J);
+    if (!(det != 0.0) || !isfinite(det)) { iters += it; return false; }
+    double inv = 1.0 / det;
+    // Cramer: dz_d = det(J with column d replaced by -F) / det
+    double dz0 = -(F[0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (F[1] * J[2][2] - J[1][2] * F[2]) +
+                   J[0][2] * (F[1] * J[2][1] - J[1][1] * F[2])) * inv;
+    double dz1 = -(J[0][0] * (F[1] * J[2][2] - J[1][2] * F[2]) - F[0] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                   J[0][2] * (J[1][0] * F[2] - F[1] * J[2][0])) * inv;
+    double dz2 = -(J[0][0] * (J[1][1] * F[2] - F[1] * J[2][1]) - J[0][1] * (J[1][0] * F[2] - F[1] * J[2][0]) +
+                   F[0] * (J[1][0] * J[2][1] - J[1][1] * J[2][0])) * inv;
+    z[0] += dz0; z[1] += dz1; z[2] += dz2;
+    double dmax = fmax(fabs(dz0), fmax(fabs(dz1), fabs(dz2)));
+    if (!isfinite(z[0]) || !isfinite(z[1]) || !isfinite(z[2])) { iters += it; return false; }
+    if (dmax <= kNewtonTol) { iters += it; return true; }
+    if (it >= 3 && fmax(fabs(z[0]), fmax(fabs(z[1]), fabs(z[2]))) > 2.0) { iters += it; return false; }
+  }
+  iters += max_it;
+  return false;
+}
+
+// Paper's initial guess (Sec. 3.2.1): nearest DG node (straight elements) or
+// nearest geometry node (curved), lowest index on ties.
+template <int NN, int NG>
+__device__ void guess_paper(const MeshView& m, int e, const double* x, double* g) {
+  if (NG == 2) {
+    const double* P = m.xnode + (size_t)e * (NN * NN * NN * 3);
+    int best = 0;
+    double bd = 1e300;
+    for (int q = 0; q < NN * NN * NN; ++q) {
+      double dx = P[q * 3] - x[0], dy = P[q * 3 + 1] - x[1], dz = P[q * 3 + 2] - x[2];
+      double dd = dx * dx + dy * dy + dz * dz;
+      if (dd < bd) { bd = dd; best = q; }
+    }
+    g[0] = m.xdg[best % NN];
+    g[1] = m.xdg[(best / NN) % NN];
+    g[2] = m.xdg[best / (NN * NN)];
+  } else {
+    const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
+    int best = 0;
+    double bd = 1e300;
+    for (int q = 0; q < NG * NG * NG; ++q) {
+      double dx = P[q * 3] - x[0], dy = P[q * 3 + 1] - x[1], dz = P[q * 3 + 2] - x[2];
+      double dd = dx * dx + dy * dy + dz * dz;
+      if (dd < bd) { bd = dd; best = q; }
+    }
+    g[0] = m.xgeo[best % NG];
+    g[1] = m.xgeo[(best / NG) % NG];
+    g[2] = m.xgeo[best / (NG * NG)];
+  }
+}
+
+// Third approach of Sec. 3.2.1: projection onto the directions from the node
+// mean to the node means of opposite faces.
+template <int NG>
+__device__ void guess_faces(const MeshView& m, int e, const double* x, double* g) {
+  const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
+  double c[3] = {0, 0, 0};
+  double f[6][3] = {{0}};
+  for (int k = 0; k < NG; ++k)
+    for (int j = 0; j < NG; ++j)
+      for (int i = 0; i < NG; ++i) {
+        const double* Q = P + ((k * NG + j) * NG + i) * 3;
+        for (int r = 0; r < 3; ++r) {
+          c[r] += Q[r];
+          if (i == 0) f[0][r] += Q[r];
+          if (i == NG - 1) f[1][r] += Q[r];
+          if (j == 0) f[2][r] += Q[r];
+          if (j == NG - 1) f[3][r] += Q[r];
+          if (k == 0) f[4][r] += Q[r];
+          if (k == NG - 1) f[5][r] += Q[r];
+        }
+      }
+  const double inv3 = 1.0 / (NG * NG * NG), inv2 = 1.0 / (NG * NG);
+  for (int r = 0; r < 3; ++r) c[r] *= inv3;
+  double d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+  for (int a = 0; a < 3; ++a) {
+    double sm[3], sp[3];
+    for (int r = 0; r < 3; ++r) {
+      sm[r] = f[2 * a][r] * inv2 - c[r];
+      sp[r] = f[2 * a + 1][r] * inv2 - c[r];
+    }
+    double val = 0.5 * (dot3(d, sp) / dot3(sp, sp) - dot3(d, sm) / dot3(sm, sm));
+    g[a] = fmin(1.0, fmax(-1.0, val));
+  }
+}
+
+__device__ __forceinline__ bool inside_ref(const double* xi) {
+  return fabs(xi[0]) <= 1.0 + kInsideEps && fabs(xi[1]) <= 1.0 + kInsideEps && fabs(xi[2]) <= 1.0 + kInsideEps;
+}
+
+// ---------------------------------------------------------------------------
+// learned guess: features and forward pass (FP32)
+// ---------------------------------------------------------------------------
+template <int NG>
+__device__ void mlp_features(const MeshView& m, int e, const double* x, float* feat) {
+  const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
+  constexpr int G = NG - 1;
+  double cor[8][3], ctr[3] = {0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    int i = c & 1, j = (c >> 1) & 1, k = c >> 2;
+    const double* Q = P + (((k * G) * NG + j * G) * NG + i * G) * 3;
+    for (int r = 0; r < 3; ++r) { cor[c][r] = Q[r]; ctr[r] += Q[r]; }
+  }
+  for (int r = 0; r < 3; ++r) ctr[r] *= 0.125;
+  double hs = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+      int b = a ^ (1 << bit);
+      if (b < a) continue;
+      double dx = cor[a][0] - cor[b][0], dy = cor[a][1] - cor[b][1], dz = cor[a][2] - cor[b][2];
+      hs += sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  double ih = 12.0 / hs;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    for (int r = 0; r < 3; ++r) feat[a * 3 + r] = (float)((cor[a][r] - ctr[r]) * ih);
+  for (int r = 0; r < 3; ++r) feat[24 + r] = (float)((x[r] - ctr[r]) * ih);
+}
+
+__device__ __forceinline__ float fast_tanh(float s) { return tanhf(s); }
+
+// 27-64-64-64-3 forward for one row; weights read through the scalar path
+// (uniform addresses).
+__device__ inline void mlp_forward_row(const float* __restrict__ w, const float* in, float* out) {
+  constexpr int H = 64, NI = 27;
+  const float* W1 = w;
+  const float* b1 = W1 + H * NI;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H * H;
+  const float* W4 = b3 + H;
+  const float* b4 = W4 + 3 * H;
+  float h1[H], h2[H];
+#pragma unroll 4
+  for (int o = 0; o < H; ++o) {
+    float s = b1[o];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s += W1[o * NI + i] * in[i];
+    h1[o] = fast_tanh(s);
+  }
+#pragma unroll 2
+  for (int o = 0; o < H; ++o) {
+    float s = b2[o];
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += W2[o * H + i] * h1[i];
+    h2[o] = fast_tanh(s);
+  }
+#pragma unroll 2
+  for (int o = 0; o < H; ++o) {
+    float s = b3[o];
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += W3[o * H + i] * h2[i];
+    h1[o] = fast_tanh(s);
+  }
+  for (int o = 0; o < 3; ++o) {
+    float s = b4[o];
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += W4[o * H + i] * h1[i];
+    out[o] = s;
+  }
+}
+
+// Reference coordinates of x in element e: learned guess (flagged elements),
+// then the paper's guess, then the face-barycentre guess.
+template <int NN, int NG>
+__device__ bool locate_xi(const MeshView& m, int e, const double* x, double* xi, int max_it, bool use_mlp,
+                          int& it_sum, int& calls, int& fallbacks) {
+  double g[3];
+  if (use_mlp && m.mlp_w && m.mlp_flag[e]) {
+    float feat[27], o[3];
+    mlp_features<NG>(m, e, x, feat);
+    mlp_forward_row(m.mlp_w, feat, o);
+    g[0] = o[0]; g[1] = o[1]; g[2] = o[2];
+    calls++;
+    if (newton<NG>(m, e, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+    fallbacks++;
+  }
+  guess_paper<NN, NG>(m, e, x, g);
+  calls++;
+  if (newton<NG>(m, e, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+  fallbacks++;
+  guess_faces<NG>(m, e, x, g);
+  calls++;
+  bool ok = newton<NG>(m, e, x, g, max_it, it_sum);
+  xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2];
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// interpolation of the five conservative variables (eq. part_interpolation)
+// ---------------------------------------------------------------------------
+template <int NN, typename UT>
+__device__ __forceinline__ void interp(const MeshView& m, const UT* __restrict__ U, const double* xi, double* out) {
+  double l1[NN], l2[NN], l3[NN];
+  lagrange<NN, double>(m.xdg, m.cdg, xi[0], l1);
+  lagrange<NN, double>(m.xdg, m.cdg, xi[1], l2);
+  lagrange<NN, double>(m.xdg, m.cdg, xi[2], l3);
+  constexpr int N3 = NN * NN * NN;
+#pragma unroll
+  for (int var = 0; var < 5; ++var) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+      double sk = 0.0;
+#pragma unroll
+      for (int j = 0; j < NN; ++j) {
+        double sj = 0.0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) sj += (double)U[var * N3 + (k * NN + j) * NN + i] * l1[i];
+        sk += sj * l2[j];
+      }
+      s += sk * l3[k];
+    }
+    out[var] = s;
+  }
+}
+
+// FP32 interpolation (mixed precision): FP32 basis and accumulation.
+template <int NN, typename UT>
+__device__ __forceinline__ void interp_f32(const MeshView& m, const UT* __restrict__ U, const double* xi, float* out) {
+  float l1[NN], l2[NN], l3[NN];
+  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[0], l1);
+  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[1], l2);
+  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[2], l3);
+  constexpr int N3 = NN * NN * NN;
+#pragma unroll
+  for (int var = 0; var < 5; ++var) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+      float sk = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NN; ++j) {
+        float sj = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) sj += (float)U[var * N3 + (k * NN + j) * NN + i] * l1[i];
+        sk += sj * l2[j];
+      }
+      s += sk * l3[k];
+    }
+    out[var] = s;
+  }
+}
+
+// drag acceleration f_D (u - v)/tau_p (Sec. 2.2.1); fD returned for the source
+template <typename T>
+__device__ __forceinline__ void drag_accel(int drag, T rho, const T* u, const T* v, T d, T mu, T rho_p, T* a, T& fD) {
+  T w0 = u[0] - v[0], w1 = u[1] - v[1], w2 = u[2] - v[2];
+  fD = T(1);
+  if (drag == 1) {
+    T Re = rho * sqrt(w0 * w0 + w1 * w1 + w2 * w2) * d / mu;
+    fD = (Re < T(800)) ? T(1) + T(0.15) * pow(Re, T(0.687)) : T(0.44) * Re / T(24);
+  }
+  if (drag == 2) {
+    fD = T(0);
+    a[0] = a[1] = a[2] = T(0);
+    return;
+  }
+  T itau = T(18) * mu / (rho_p * d * d);
+  a[0] = fD * w0 * itau;
+  a[1] = fD * w1 * itau;
+  a[2] = fD * w2 * itau;
+}
+
+// ---------------------------------------------------------------------------
+// face intersection (Sec. 3.2.4)
+// ---------------------------------------------------------------------------
+__device__ inline bool bbox_hit(const FaceRec& F, const double* xs, const double* xe) {
+  double pad = 1e-9 * F.diam;
+  double r0[3] = {xs[0] - F.org[0], xs[1] - F.org[1], xs[2] - F.org[2]};
+  double r1[3] = {xe[0] - F.org[0], xe[1] - F.org[1], xe[2] - F.org[2]};
+  const double* ax[3] = {F.nrm, F.e1, F.e2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double p0 = dot3(r0, ax[a]), p1 = dot3(r1, ax[a]);
+    if (fmax(p0, p1) < F.lo[a] - pad || fmin(p0, p1) > F.hi[a] + pad) return false;
+  }
+  return true;
+}
+
+__device__ inline void ray_planes(const double* t, double* n1, double* n2) {
+  int k = 0;
+  if (fabs(t[1]) < fabs(t[k])) k = 1;
+  if (fabs(t[2]) < fabs(t[k])) k = 2;
+  double ek[3] = {0, 0, 0};
+  ek[k] = 1.0;
+  cross3(t, ek, n1);
+  double il = 1.0 / sqrt(dot3(n1, n1));
+  n1[0] *= il; n1[1] *= il; n1[2] *= il;
+  cross3(n1, t, n2);
+}
+
+__device__ inline int planar_hit(const FaceRec& F, const double* x0, const double* t, double* al, double* uv) {
+  double nrm[3];
+  cross3(F.B, F.C, nrm);
+  double tn = dot3(t, nrm);
+  if (tn == 0.0) return 0;
+  double r[3] = {F.D[0] - x0[0], F.D[1] - x0[1], F.D[2] - x0[2]};
+  double a = dot3(r, nrm) / tn;
+  double h[3] = {x0[0] + a * t[0] - F.D[0], x0[1] + a * t[1] - F.D[1], x0[2] + a * t[2] - F.D[2]};
+  double bb = dot3(F.B, F.B), bc = dot3(F.B, F.C), cc = dot3(F.C, F.C);
+  double rb = dot3(h, F.B), rc = dot3(h, F.C);
+  double det = bb * cc - bc * bc;
+  al[0] = a;
+  uv[0] = (rb * cc - rc * bc) / det;
+  uv[1] = (bb * rc - bc * rb) / det;
+  return 1;
+}
+
+__device__ inline int bilinear_hit(const FaceRec& F, const double* x0, const double* t, double* al, double* uv) {
+  double n1[3], n2[3];
+  ray_planes(t, n1, n2);
+  double Dr[3] = {F.D[0] - x0[0], F.D[1] - x0[1], F.D[2] - x0[2]};
+  double a1 = dot3(F.A, n1), b1 = dot3(F.B, n1), c1 = dot3(F.C, n1), d1 = dot3(Dr, n1);
+  double a2 = dot3(F.A, n2), b2 = dot3(F.B, n2), c2 = dot3(F.C, n2), d2 = dot3(Dr, n2);
+  double qa = a1 * c2 - a2 * c1;
+  double qb = a1 * d2 + b1 * c2 - a2 * d1 - b2 * c1;
+  double qc = b1 * d2 - b2 * d1;
+  double scale = fmax(fabs(qa), fmax(fabs(qb), fabs(qc)));
+  if (scale == 0.0) return 0;
+  double vs[2];
+  int nv = 0;
+  if (fabs(qa) <= 1e-14 * scale) {
+    if (qb != 0.0) vs[nv++] = -qc / qb;
+  } else {
+    double disc = qb * qb - 4.0 * qa * qc;
+    if (disc < 0.0) return 0;
+    double sq = sqrt(disc);
+    double q = -0.5 * (qb + (qb >= 0.0 ? sq : -sq));
+    vs[nv++] = q / qa;
+    if (q != 0.0) vs[nv++] = qc / q;
+  }
+  int nr = 0;
+  for (int i = 0; i < nv; ++i) {
+    double v = vs[i];
+    double den1 = a1 * v + b1, den2 = a2 * v + b2, u;
+    if (fabs(den1) >= fabs(den2)) {
+      if (den1 == 0.0) continue;
+      u = -(c1 * v + d1) / den1;
+    } else {
+      u = -(c2 * v + d2) / den2;
+    }
+    double p[3];
+    for (int q = 0; q < 3; ++q) p[q] = F.A[q] * u * v + F.B[q] * u + F.C[q] * v + F.D[q] - x0[q];
+    al[nr] = dot3(p, t);
+    uv[2 * nr] = u;
+    uv[2 * nr + 1] = v;
+    nr++;
+  }
+  return nr;
+}
+
+// Bernstein basis of degree D at t in [0,1] and its t-derivative
+template <int D>
+__device__ __forceinline__ void bern(double t, double* B, double* dB) {
+  double tp[D + 1], sp[D + 1];
+  tp[0] = 1.0; sp[0] = 1.0;
+  double s = 1.0 - t;
+#pragma unroll
+  for (int m = 1; m <= D; ++m) { tp[m] = tp[m - 1] * t; sp[m] = sp[m - 1] * s; }
+  double c = 1.0;
+#pragma unroll
+  for (int m = 0; m <= D; ++m) {
+    B[m] = c * tp[m] * sp[D - m];
+    c = c * (D - m) / (m + 1);
+  }
+  if (dB) {
+    // d/dt B_m^D = D (B_{m-1}^{D-1} - B_m^{D-1})
+    double cb = 1.0, lower[D + 1];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      lower[m] = cb * tp[m] * sp[D - 1 - m];
+      cb = cb * (D - 1 - m) / (m + 1);
+    }
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+      double lo = (m >= 1) ? lower[m - 1] : 0.0;
+      double hi = (m <= D - 1) ? lower[m] : 0.0;
+      dB[m] = D * (lo - hi);
+    }
+  }
+}
+
+template <int NG>
+__device__ inline void bezier_eval(const double* __restrict__ cp, double u, double v, double* p, double* pu,
+                                   double* pv) {
+  constexpr int D = NG - 1;
+  double Bu[NG], Bv[NG], dBu[NG], dBv[NG];
+  bern<D>(0.5 * (u + 1.0), Bu, dBu);
+  bern<D>(0.5 * (v + 1.0), Bv, dBv);
+  for (int q = 0; q < 3; ++q) { p[q] = 0.0; if (pu) { pu[q] = 0.0; pv[q] = 0.0; } }
+  for (int k = 0; k < NG; ++k)
+    for (int mm = 0; mm < NG; ++mm) {
+      const double* P = cp + (k * NG + mm) * 3;
+      double w = Bu[mm] * Bv[k];
+      for (int q = 0; q < 3; ++q) {
+        p[q] += P[q] * w;
+        if (pu) {
+          pu[q] += P[q] * 0.5 * dBu[mm] * Bv[k];
+          pv[q] += P[q] * 0.5 * Bu[mm] * dBv[k];
+        }
+      }
+    }
+}
+
+// restrict a stride-s list of NG Bezier coefficients to [a, b]
+template <int NG>
+__device__ inline void restrict1(double* c, int s, double a, double b) {
+  double tmp[NG], left[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) tmp[i] = c[i * s];
+  left[0] = tmp[0];
+#pragma unroll
+  for (int r = 1; r < NG; ++r) {
+#pragma unroll
+    for (int i = 0; i < NG - r; ++i) tmp[i] = (1.0 - b) * tmp[i] + b * tmp[i + 1];
+    left[r] = tmp[0];
+  }
+  if (b <= 0.0) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) c[i * s] = left[0];
+    return;
+  }
+  double t = a / b;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) tmp[i] = left[i];
+  c[(NG - 1) * s] = tmp[NG - 1];
+#pragma unroll
+  for (int r = 1; r < NG; ++r) {
+#pragma unroll
+    for (int i = 0; i < NG - r; ++i) tmp[i] = (1.0 - t) * tmp[i] + t * tmp[i + 1];
+    c[(NG - 1 - r) * s] = tmp[NG - 1 - r];
+  }
+}
+
+// q[m][k][2] with m along u, k along v; restrict direction dir to [a, b]
+template <int NG>
+__device__ inline void patch_restrict(double* q, int dir, double a, double b) {
+  for (int k = 0; k < NG; ++k)
+    for (int co = 0; co < 2; ++co) {
+      if (dir == 0) restrict1<NG>(q + k * 2 + co, NG * 2, a, b);   // along m
+      else restrict1<NG>(q + k * NG * 2 + co, 2, a, b);            // along k
+    }
+}
+
+template <int NG>
+__device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) {
+  constexpr int N = NG - 1;
+#define QQ(m, k, c) q[((m) * NG + (k)) * 2 + (c)]
+  double L0, L1;
+  if (dir == 0) {
+    L0 = (QQ(0, N, 0) - QQ(0, 0, 0)) + (QQ(N, N, 0) - QQ(N, 0, 0));
+    L1 = (QQ(0, N, 1) - QQ(0, 0, 1)) + (QQ(N, N, 1) - QQ(N, 0, 1));
+  } else {
+    L0 = (QQ(N, 0, 0) - QQ(0, 0, 0)) + (QQ(N, N, 0) - QQ(0, N, 0));
+    L1 = (QQ(N, 0, 1) - QQ(0, 0, 1)) + (QQ(N, N, 1) - QQ(0, N, 1));
+  }
+  double ll = sqrt(L0 * L0 + L1 * L1);
+  if (ll == 0.0) {
+    double K0, K1;
+    if (dir == 0) {
+      K0 = (QQ(N, 0, 0) - QQ(0, 0, 0)) + (QQ(N, N, 0) - QQ(0, N, 0));
+      K1 = (QQ(N, 0, 1) - QQ(0, 0, 1)) + (QQ(N, N, 1) - QQ(0, N, 1));
+    } else {
+      K0 = (QQ(0, N, 0) - QQ(0, 0, 0)) + (QQ(N, N, 0) - QQ(N, 0, 0));
+      K1 = (QQ(0, N, 1) - QQ(0, 0, 1)) + (QQ(N, N, 1) - QQ(N, 0, 1));
+    }
+    L0 = -K1; L1 = K0;
+    ll = sqrt(L0 * L0 + L1 * L1);
+    if (ll == 0.0) { L0 = 1.0; L1 = 0.0; ll = 1.0; }
+  }
+  double nx = -L1 / ll, ny = L0 / ll;
+  double tt[2 * NG], dd[2 * NG];
+  for (int i = 0; i < NG; ++i) {
+    double mn = 1e300, mx = -1e300;
+    for (int k = 0; k < NG; ++k) {
+      double dist = (dir == 0) ? nx * QQ(i, k, 0) + ny * QQ(i, k, 1) : nx * QQ(k, i, 0) + ny * QQ(k, i, 1);
+      mn = fmin(mn, dist);
+      mx = fmax(mx, dist);
+    }
+    tt[2 * i] = tt[2 * i + 1] = (double)i / N;
+    dd[2 * i] = mn;
+    dd[2 * i + 1] = mx;
+  }
+#undef QQ
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < 2 * NG; ++i) {
+    if (dd[i] == 0.0) { lo = fmin(lo, tt[i]); hi = fmax(hi, tt[i]); }
+    for (int j = i + 1; j < 2 * NG; ++j)
+      if ((dd[i] < 0.0 && dd[j] > 0.0) || (dd[i] > 0.0 && dd[j] < 0.0)) {
+        double t = tt[i] + (tt[j] - tt[i]) * (dd[i] / (dd[i] - dd[j]));
+        lo = fmin(lo, t);
+        hi = fmax(hi, t);
+      }
+  }
+  if (lo > hi) return false;
+  a = fmax(0.0, lo - kClipPad);
+  b = fmin(1.0, hi + kClipPad);
+  return true;
+}
+
+// All intersections of the line x0 + alpha t with a curved Bezier face: the
+// face is projected onto two planes containing the line (Sec. 3.2.4) and the
+// zero of the 2-D patch is isolated by Bezier clipping; converged boxes are
+// polished by 2-D Newton on the projected patch.  The stack holds parameter
+// intervals only; a popped interval is restricted again from the full patch.
+template <int NG>
+__device__ int curved_hit(const double* __restrict__ cp, const double* x0, const double* t, double* al, double* uv,
+                          int max_roots) {
+  constexpr int D = NG - 1;
+  double n1[3], n2[3];
+  ray_planes(t, n1, n2);
+  double q0[NG * NG * 2];
+  for (int k = 0; k < NG; ++k)
+    for (int mm = 0; mm < NG; ++mm) {
+      const double* P = cp + (k * NG + mm) * 3;
+      double r[3] = {P[0] - x0[0], P[1] - x0[1], P[2] - x0[2]};
+      q0[(mm * NG + k) * 2 + 0] = dot3(r, n1);
+      q0[(mm * NG + k) * 2 + 1] = dot3(r, n2);
+    }
+  double stk[kClipStack][4];
+  int sp = 1, nroots = 0, budget = kClipSteps;
+  stk[0][0] = 0.0; stk[0][1] = 1.0; stk[0][2] = 0.0; stk[0][3] = 1.0;
+  double q[NG * NG * 2];
+  while (sp > 0 && budget > 0) {
+    --sp;
+    double u0 = stk[sp][0], u1 = stk[sp][1], v0 = stk[sp][2], v1 = stk[sp][3];
+    for (int i = 0; i < NG * NG * 2; ++i) q[i] = q0[i];
+    if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG>(q, 0, u0, u1);
+    if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG>(q, 1, v0, v1);
+    for (;;) {
+      if (--budget < 0) break;
+      double a, b;
+      if (!clip_dir<NG>(q, 0, a, b)) break;
+      patch_restrict<NG>(q, 0, a, b);
+      double w = u1 - u0;
+      double nu0 = u0 + a * w, nu1 = u0 + b * w;
+      u0 = nu0; u1 = nu1;
+      double ru = b - a;
+      if (!clip_dir<NG>(q, 1, a, b)) break;
+      patch_restrict<NG>(q, 1, a, b);
+      w = v1 - v0;
+      double nv0 = v0 + a * w, nv1 = v0 + b * w;
+      v0 = nv0; v1 = nv1;
+      double rv = b - a;
+      double wu = u1 - u0, wv = v1 - v0;
+      bool conv = (wu <= kClipTol && wv <= kClipTol);
+      bool su = (ru > 0.8 && wu > kClipTol), sv = (rv > 0.8 && wv > kClipTol);
+      if (!conv && (su || sv) && sp + 2 > kClipStack) conv = true;
+      if (conv) {
+        double s = 0.5 * (u0 + u1), tt = 0.5 * (v0 + v1);
+        for (int it = 0; it < 3; ++it) {
+          double Bs[NG], Bt[NG], dBs[NG], dBt[NG];
+          bern<D>(s, Bs, dBs);
+          bern<D>(tt, Bt, dBt);
+          double G0 = 0, G1 = 0, Gs0 = 0, Gs1 = 0, Gt0 = 0, Gt1 = 0;
+          for (int mm = 0; mm < NG; ++mm)
+            for (int k = 0; k < NG; ++k) {
+              double qx = q0[(mm * NG + k) * 2], qy = q0[(mm * NG + k) * 2 + 1];
+              G0 += qx * Bs[mm] * Bt[k]; G1 += qy * Bs[mm] * Bt[k];
+              Gs0 += qx * dBs[mm] * Bt[k]; Gs1 += qy * dBs[mm] * Bt[k];
+              Gt0 += qx * Bs[mm] * dBt[k]; Gt1 += qy * Bs[mm] * dBt[k];
+            }
+          double det = Gs0 * Gt1 - Gs1 * Gt0;
+          if (det == 0.0 || !isfinite(det)) break;
+          s += -(G0 * Gt1 - G1 * Gt0) / det;
+          tt += -(Gs0 * G1 - Gs1 * G0) / det;
+        }
+        double u = 2.0 * s - 1.0, v = 2.0 * tt - 1.0;
+        bool dup = false;
+        for (int r = 0; r < nroots; ++r)
+          if (fabs(uv[2 * r] - u) < 1e-9 && fabs(uv[2 * r + 1] - v) < 1e-9) dup = true;
+        if (!dup && nroots < max_roots) {
+          double p[3];
+          bezier_eval<NG>(cp, u, v, p, nullptr, nullptr);
+          double r3[3] = {p[0] - x0[0], p[1] - x0[1], p[2] - x0[2]};
+          al[nroots] = dot3(r3, t);
+          uv[2 * nroots] = u;
+          uv[2 * nroots + 1] = v;
+          nroots++;
+        }
+        break;
+      }
+      if (su || sv) {
+        int dir = (su && sv) ? (wu >= wv ? 0 : 1) : (su ? 0 : 1);
+        if (dir == 0) {
+          double um = 0.5 * (u0 + u1);
+          stk[sp][0] = um; stk[sp][1] = u1; stk[sp][2] = v0; stk[sp][3] = v1; sp++;
+          stk[sp][0] = u0; stk[sp][1] = um; stk[sp][2] = v0; stk[sp][3] = v1; sp++;
+        } else {
+          double vm = 0.5 * (v0 + v1);
+          stk[sp][0] = u0; stk[sp][1] = u1; stk[sp][2] = vm; stk[sp][3] = v1; sp++;
+          stk[sp][0] = u0; stk[sp][1] = u1; stk[sp][2] = v0; stk[sp][3] = vm; sp++;
+        }
+        break;
+      }
+    }
+  }
+  return nroots;
+}
+
+template <int NG>
+__device__ inline int face_roots(const MeshView& m, int fid, const FaceRec& F, const double* x0, const double* t,
+                                 double* al, double* uv) {
+  if (F.type == FACE_PLANAR) return planar_hit(F, x0, t, al, uv);
+  if (F.type == FACE_BILINEAR) return bilinear_hit(F, x0, t, al, uv);
+  return curved_hit<NG>(m.cp + (size_t)fid * (NG * NG * 3), x0, t, al, uv, kMaxRoots);
+}
+
+// Physical-space tracking of the straight stage segment xs -> xe (Sec. 3.2.3):
+// smallest alpha in (1e-12 h_e, remaining length] with (u, v) in [-1,1]^2,
+// ties to the lowest local face; hand-off, periodic shift, specular reflection
+// (Sec. 2.4) of the remaining displacement, v and the stage registers; open
+// boundaries end the particle.
+template <int NG>
+__device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
+                      int max_cross, int8_t& status, int& hits, int& ncross) {
+  double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
+  int excl = -1, count = 0;
+  for (;;) {
+    double t[3] = {xe[0] - xs[0], xe[1] - xs[1], xe[2] - xs[2]};
+    double L = sqrt(dot3(t, t));
+    if (L == 0.0) break;
+    double iL = 1.0 / L;
+    t[0] *= iL; t[1] *= iL; t[2] *= iL;
+    double eps = 1e-12 * m.hE[e];
+    double best = 1e300, bu = 0.0, bv = 0.0;
+    int bf = -1;
+    for (int f = 0; f < 6; ++f) {
+      if (f == excl) continue;
+      int fid = e * 6 + f;
+      const FaceRec& F = m.faces[fid];
+      if (!bbox_hit(F, xs, xe)) continue;
+      double al[kMaxRoots], uv[2 * kMaxRoots];
+      int nr = face_roots<NG>(m, fid, F, xs, t, al, uv);
+      for (int r = 0; r < nr; ++r) {
+        if (!(al[r] > eps && al[r] <= L)) continue;
+        if (fabs(uv[2 * r]) > 1.0 + kUVEps || fabs(uv[2 * r + 1]) > 1.0 + kUVEps) continue;
+        if (al[r] < best) { best = al[r]; bf = f; bu = uv[2 * r]; bv = uv[2 * r + 1]; }
+      }
+    }
+    if (bf < 0) break;
+    if (count >= max_cross) { status = MAX_CROSS; break; }
+    count++;
+    ncross++;
+    double xh[3] = {xs[0] + best * t[0], xs[1] + best * t[1], xs[2] + best * t[2]};
+    int fid = e * 6 + bf;
+    const FaceRec& F = m.faces[fid];
+    int bc = F.bc;
+    if (bc == BC_INTERNAL || bc == BC_PERIODIC) {
+      int ne = F.nbr_elem, nf = F.nbr_face;
+      if (bc == BC_PERIODIC)
+        for (int q = 0; q < 3; ++q) { xh[q] += F.shift[q]; xe[q] += F.shift[q]; }
+      e = ne;
+      excl = (m.faces[ne * 6 + nf].type == FACE_PLANAR) ? nf : -1;
+      xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
+    } else if (bc == BC_REFLECT) {
+      double nrm[3];
+      if (F.type == FACE_CURVED) {
+        double p[3], pu[3], pv[3];
+        bezier_eval<NG>(m.cp + (size_t)fid * (NG * NG * 3), bu, bv, p, pu, pv);
+        cross3(pu, pv, nrm);
+      } else {
+        double pu[3], pv[3];
+        for (int q = 0; q < 3; ++q) { pu[q] = F.A[q] * bv + F.B[q]; pv[q] = F.A[q] * bu + F.C[q]; }
+        cross3(pu, pv, nrm);
+      }
+      double il = 1.0 / sqrt(dot3(nrm, nrm));
+      nrm[0] *= il; nrm[1] *= il; nrm[2] *= il;
+      double r[3] = {xe[0] - xh[0], xe[1] - xh[1], xe[2] - xh[2]};
+      double dr = dot3(r, nrm), dv = dot3(v, nrm), dkx = dot3(kx, nrm), dkv = dot3(kv, nrm);
+      for (int q = 0; q < 3; ++q) {
+        xe[q] = xh[q] + (r[q] - 2.0 * dr * nrm[q]);
+        v[q] -= 2.0 * dv * nrm[q];
+        kx[q] -= 2.0 * dkx * nrm[q];
+        kv[q] -= 2.0 * dkv * nrm[q];
+      }
+      hits++;
+      excl = (F.type == FACE_PLANAR) ? bf : -1;
+      xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
+    } else {
+      status = OPEN_EXIT;
+      xe[0] = xh[0]; xe[1] = xh[1]; xe[2] = xh[2];
+      break;
+    }
+  }
+}
+
+// wave-level sum then one atomic per wave
+__device__ __forceinline__ void wave_add(unsigned long long* dst, long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(dst, (unsigned long long)v);
+}
+
+}  // namespace fp

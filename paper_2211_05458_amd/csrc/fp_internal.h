@@ -1,0 +1,88 @@
+// Internal structures of the flexipart HIP library (gfx950).  Shared by the
+// host API and the kernels of this library only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fp {
+
+constexpr int kMaxNodes = 8;        // n = N+1 <= 8, ng = Ngeo+1 <= 7
+constexpr int kClipStack = 16;      // Bezier-clipping interval stack
+constexpr int kClipSteps = 64;      // clipping iterations per face test
+constexpr int kMaxRoots = 8;
+constexpr int kMlpMaxBatch = 8192;   // rows per MLP gradient evaluation
+constexpr int kMlpRow = 27 + 6 * 64 + 3;  // activations and deltas kept per row
+constexpr int kMlpWeights = 64 * 27 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3;
+constexpr double kNewtonTol = 1e-10;
+constexpr double kInsideEps = 1e-10;
+constexpr double kUVEps = 1e-12;
+constexpr double kClipTol = 1e-12;
+constexpr double kClipPad = 1e-10;
+
+enum { ACTIVE = 0, OPEN_EXIT = 1, LOST_NEWTON = 2, LOST_TRACK = 3, MAX_CROSS = 4, REJECTED = 5 };
+enum { FACE_PLANAR = 0, FACE_BILINEAR = 1, FACE_CURVED = 2 };
+enum { BC_INTERNAL = 0, BC_OPEN = 1, BC_REFLECT = 2, BC_PERIODIC = 3 };
+enum { ST_NEWTON_IT = 0, ST_NEWTON_CALLS, ST_CROSS, ST_HITS, ST_LOST, ST_FALLBACK, ST_SORTS, ST_N };
+
+// One element face: slab bounding box (Sec. 3.2.4), corner bilinear form,
+// connectivity.  Bezier control points live in a separate array.
+struct FaceRec {
+  double nrm[3], e1[3], e2[3], org[3];
+  double lo[3], hi[3];          // extents along (nrm, e1, e2) relative to org
+  double A[3], B[3], C[3], D[3];// p(u,v) = A uv + B u + C v + D from the corners
+  double shift[3];
+  double diam;
+  int32_t type, nbr_elem, nbr_face, bc;
+};
+
+// Everything a kernel needs to know about the mesh (passed by value).
+struct MeshView {
+  int32_t E, ng, n, n_geo;
+  const double* X;        // [E][ng^3][3]
+  const FaceRec* faces;   // [E*6]
+  const double* cp;       // [E*6][ng*ng][3]
+  const double* hE;       // [E]
+  const double* xnode;    // [E][n^3][3] physical DG node positions
+  const double* vol;      // [E][n^3]
+  const double* elo;      // [E][3] padded element box
+  const double* ehi;
+  double xgeo[kMaxNodes], cgeo[kMaxNodes];  // geometry nodes, 1/prod(x_i - x_j)
+  double xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
+  float xdgf[kMaxNodes], cdgf[kMaxNodes];
+  double blo[3], bdx[3];
+  int32_t bn[3];
+  const int32_t* bstart;  // background-mesh cell -> element CSR
+  const int32_t* blist;
+  const uint8_t* mlp_flag;// [E] learned guess enabled
+  const float* mlp_w;     // weights (device), or null
+};
+
+// Particle state, structure of arrays, capacity cap.
+struct Particles {
+  int64_t cap;
+  double* x;      // [3][cap]
+  double* v;      // [3][cap]
+  double* kx;     // [3][cap]
+  double* kv;     // [3][cap]
+  double* d;      // [cap]
+  double* xi;     // [3][cap]
+  int32_t* elem;
+  int32_t* hits;
+  int32_t* id;    // index in push order
+  int8_t* status;
+};
+
+struct Fluid {
+  const void* U;
+  int32_t f32;    // U stored as float
+  double mu, kappa, rho_p;
+};
+
+struct StepParams {
+  double dt;
+  double A, B;          // low-storage coefficients of this stage
+  double gravity[3];
+  int32_t drag, max_it, max_cross, use_mlp;
+};
+
+}  // namespace fp

@@ -1,0 +1,40 @@
+// Kernel launchers of the flexipart library (host side declarations).
+#pragma once
+#include "fp_internal.h"
+
+namespace fp {
+
+// true if (n, ng) has compiled kernels
+bool supported(int n, int ng);
+
+hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* nbr_elem, const int32_t* nbr_face,
+                             const int8_t* bc, const double* shift, const double* Minv, FaceRec* faces, double* cp,
+                             hipStream_t s);
+hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, int32_t* bad, hipStream_t s);
+hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* hint, int64_t n, hipStream_t s);
+hipError_t launch_stage(const MeshView& m, const Particles& P, const Fluid& fl, const StepParams& sp, int64_t n,
+                        int mixed, unsigned long long* stats, hipStream_t s);
+hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, unsigned long long* stats,
+                           hipStream_t s);
+hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
+                                  int s_f32, int drag, hipStream_t s);
+hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
+                                int s_f32, int drag, double R, const double* period, double* norm_buf,
+                                double* force_buf, const int32_t* elem_start, hipStream_t s);
+hipError_t launch_sort(const Particles& src, const Particles& dst, int64_t n, int E, int32_t* count,
+                       int32_t* start, int32_t* rank, int32_t* block_sums, hipStream_t s);
+hipError_t launch_elem_start(const Particles& P, int64_t n, int E, int32_t* elem_start, hipStream_t s);
+
+// learned guess
+hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem, const double* x, float* feat,
+                               hipStream_t s);
+hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
+                               int32_t* count, hipStream_t s);
+hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,
+                                const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s);
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, int64_t nw, int64_t t, float lr,
+                       hipStream_t s);
+hipError_t launch_curved_flags(const MeshView& m, double thresh, uint8_t* flag, int32_t* count, hipStream_t s);
+
+}  // namespace fp

@@ -1,0 +1,262 @@
+// Learned Newton initial guess: features, training pairs from Newton, a
+// 27-64-64-64-3 tanh MLP (forward, backward, Adam) in FP32, and the flags of
+// strongly curved elements on which the guess is used.
+#include "fp_device.h"
+#include "fp_launch.h"
+
+namespace fp {
+
+constexpr int H = 64, NI = 27, NO = 3;
+constexpr int NW = H * NI + H + 2 * (H * H + H) + NO * H + NO;
+constexpr int ROW = NI + 3 * H + 3 * H + NO;   // per-row activations and deltas
+
+template <int NG>
+__global__ void k_mlp_features(MeshView m, int64_t n, const int32_t* __restrict__ elem, const double* __restrict__ x,
+                               float* feat) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double xx[3] = {x[r * 3], x[r * 3 + 1], x[r * 3 + 2]};
+  float f[27];
+  mlp_features<NG>(m, elem[r], xx, f);
+  for (int i = 0; i < 27; ++i) feat[r * 27 + i] = f[i];
+}
+
+template <int NN, int NG>
+__global__ void k_newton_pairs(MeshView m, Particles P, int64_t n, float* feat, float* xo, int32_t* count) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n || P.status[p] != ACTIVE) return;
+  const int64_t cap = P.cap;
+  int e = P.elem[p];
+  double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
+  double xi[3];
+  int it = 0, calls = 0, fb = 0;
+  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb) || !inside_ref(xi)) return;
+  int q = atomicAdd(count, 1);
+  float f[27];
+  mlp_features<NG>(m, e, x, f);
+  for (int i = 0; i < 27; ++i) feat[(int64_t)q * 27 + i] = f[i];
+  for (int k = 0; k < 3; ++k) xo[(int64_t)q * 3 + k] = (float)xi[k];
+}
+
+// max deviation of the geometry nodes from the trilinear map of the corners
+template <int NG>
+__global__ void k_curved_flags(MeshView m, double thresh, uint8_t* flag, int32_t* count) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.E) return;
+  const double* P = m.X + (size_t)e * NG * NG * NG * 3;
+  constexpr int G = NG - 1;
+  double cor[8][3];
+  for (int c = 0; c < 8; ++c) {
+    const double* Q = P + ((((c >> 2) & 1) * G * NG + ((c >> 1) & 1) * G) * NG + (c & 1) * G) * 3;
+    for (int r = 0; r < 3; ++r) cor[c][r] = Q[r];
+  }
+  double dev = 0.0;
+  for (int k = 0; k < NG; ++k)
+    for (int j = 0; j < NG; ++j)
+      for (int i = 0; i < NG; ++i) {
+        double s = (double)i / G, t = (double)j / G, u = (double)k / G;
+        double tri[3] = {0, 0, 0};
+        for (int c = 0; c < 8; ++c) {
+          double w = ((c & 1) ? s : 1 - s) * (((c >> 1) & 1) ? t : 1 - t) * (((c >> 2) & 1) ? u : 1 - u);
+          for (int r = 0; r < 3; ++r) tri[r] += w * cor[c][r];
+        }
+        const double* Q = P + ((k * NG + j) * NG + i) * 3;
+        double dx = Q[0] - tri[0], dy = Q[1] - tri[1], dz = Q[2] - tri[2];
+        dev = fmax(dev, sqrt(dx * dx + dy * dy + dz * dz));
+      }
+  uint8_t fl = dev > thresh * m.hE[e];
+  flag[e] = fl;
+  if (fl) atomicAdd(count, 1);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w, int64_t n,
+                                                     const float* __restrict__ in, float* out) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  float x[27], o[3];
+  for (int i = 0; i < 27; ++i) x[i] = in[r * 27 + i];
+  mlp_forward_row(w, x, o);
+  for (int k = 0; k < 3; ++k) out[r * 3 + k] = o[k];
+}
+
+// per-row forward and backward; activations and deltas to buf[row][ROW]
+__global__ __launch_bounds__(128) void k_mlp_rows(const float* __restrict__ w, int64_t n, const float* __restrict__ in,
+                                                  const float* __restrict__ target, const int32_t* __restrict__ rows,
+                                                  float* buf, float* loss) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float lsum = 0.0f;
+  if (r < n) {
+    int64_t src = rows ? rows[r] : r;
+    const float* W1 = w;
+    const float* b1 = W1 + H * NI;
+    const float* W2 = b1 + H;
+    const float* b2 = W2 + H * H;
+    const float* W3 = b2 + H;
+    const float* b3 = W3 + H * H;
+    const float* W4 = b3 + H;
+    const float* b4 = W4 + NO * H;
+    float* B = buf + r * ROW;
+    float* x = B;
+    float* h1 = x + NI;
+    float* h2 = h1 + H;
+    float* h3 = h2 + H;
+    float* d1 = h3 + H;
+    float* d2 = d1 + H;
+    float* d3 = d2 + H;
+    float* dy = d3 + H;
+    float xr[NI];
+    for (int i = 0; i < NI; ++i) { xr[i] = in[src * NI + i]; x[i] = xr[i]; }
+    float a[H], b[H];
+    for (int o = 0; o < H; ++o) {
+      float s = b1[o];
+      for (int i = 0; i < NI; ++i) s += W1[o * NI + i] * xr[i];
+      a[o] = tanhf(s);
+      h1[o] = a[o];
+    }
+    for (int o = 0; o < H; ++o) {
+      float s = b2[o];
+      for (int i = 0; i < H; ++i) s += W2[o * H + i] * a[i];
+      b[o] = tanhf(s);
+      h2[o] = b[o];
+    }
+    for (int o = 0; o < H; ++o) {
+      float s = b3[o];
+      for (int i = 0; i < H; ++i) s += W3[o * H + i] * b[i];
+      a[o] = tanhf(s);
+      h3[o] = a[o];
+    }
+    const float scale = 1.0f / (float)(n * NO);
+    float g[NO];
+    for (int o = 0; o < NO; ++o) {
+      float s = b4[o];
+      for (int i = 0; i < H; ++i) s += W4[o * H + i] * a[i];
+      float diff = s - target[src * NO + o];
+      lsum += diff * diff * scale;
+      g[o] = 2.0f * diff * scale;
+      dy[o] = g[o];
+    }
+    // deltas (pre-activation gradients)
+    for (int i = 0; i < H; ++i) {
+      float s = 0.0f;
+      for (int o = 0; o < NO; ++o) s += W4[o * H + i] * g[o];
+      b[i] = s * (1.0f - a[i] * a[i]);
+      d3[i] = b[i];
+    }
+    for (int i = 0; i < H; ++i) {
+      float s = 0.0f;
+      for (int o = 0; o < H; ++o) s += W3[o * H + i] * b[o];
+      float hv = h2[i];
+      a[i] = s * (1.0f - hv * hv);
+      d2[i] = a[i];
+    }
+    for (int i = 0; i < H; ++i) {
+      float s = 0.0f;
+      for (int o = 0; o < H; ++o) s += W2[o * H + i] * a[o];
+      float hv = h1[i];
+      d1[i] = s * (1.0f - hv * hv);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, lsum);
+}
+
+// weight gradients: block (o, layer), threads over inputs i, loop over rows
+__global__ __launch_bounds__(64) void k_mlp_wgrad(int64_t n, const float* __restrict__ buf, float* grad) {
+  int o = blockIdx.x, layer = blockIdx.y, i = threadIdx.x;
+  int nin = layer == 0 ? NI : H;
+  int nout = layer == 3 ? NO : H;
+  if (o >= nout) return;
+  int in_off = layer == 0 ? 0 : (layer == 1 ? NI : (layer == 2 ? NI + H : NI + 2 * H));
+  int d_off = layer == 0 ? NI + 3 * H : (layer == 1 ? NI + 4 * H : (layer == 2 ? NI + 5 * H : NI + 6 * H));
+  size_t wofs = layer == 0 ? 0 : (layer == 1 ? H * NI + H : (layer == 2 ? H * NI + H + H * H + H : H * NI + H + 2 * (H * H + H)));
+  float g = 0.0f, gb = 0.0f;
+  for (int64_t r = 0; r < n; ++r) {
+    const float* B = buf + r * ROW;
+    float dlt = B[d_off + o];
+    if (i < nin) g += dlt * B[in_off + i];
+    gb += dlt;
+  }
+  if (i < nin) grad[wofs + (size_t)o * nin + i] = g;
+  if (i == 0) grad[wofs + (size_t)nout * nin + o] = gb;
+}
+
+__global__ void k_zero_f32(float* a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0f;
+}
+
+__global__ void k_adam(float* w, float* m, float* v, const float* __restrict__ g, int64_t nw, float lr, float c1,
+                       float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw) return;
+  float gi = g[i];
+  float mi = 0.9f * m[i] + 0.1f * gi;
+  float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem, const double* x, float* feat,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 g((unsigned)((n + 255) / 256));
+  switch (m.ng) {
+    case 2: k_mlp_features<2><<<g, 256, 0, s>>>(m, n, elem, x, feat); break;
+    case 3: k_mlp_features<3><<<g, 256, 0, s>>>(m, n, elem, x, feat); break;
+    case 5: k_mlp_features<5><<<g, 256, 0, s>>>(m, n, elem, x, feat); break;
+    case 7: k_mlp_features<7><<<g, 256, 0, s>>>(m, n, elem, x, feat); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define FP_FOR_EACH_SHAPE(X) \
+  X(2, 2) X(3, 2) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(3, 5) X(4, 5) X(6, 5) X(8, 5) X(4, 7) X(6, 7)
+
+hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
+                               int32_t* count, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 g((unsigned)((n + 255) / 256));
+#define FP_L(A, B) \
+  if (m.n == A && m.ng == B) { k_newton_pairs<A, B><<<g, 256, 0, s>>>(m, P, n, feat, xi, count); return hipGetLastError(); }
+  FP_FOR_EACH_SHAPE(FP_L)
+#undef FP_L
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_curved_flags(const MeshView& m, double thresh, uint8_t* flag, int32_t* count, hipStream_t s) {
+  dim3 g((unsigned)((m.E + 255) / 256));
+  switch (m.ng) {
+    case 2: k_curved_flags<2><<<g, 256, 0, s>>>(m, thresh, flag, count); break;
+    case 3: k_curved_flags<3><<<g, 256, 0, s>>>(m, thresh, flag, count); break;
+    case 5: k_curved_flags<5><<<g, 256, 0, s>>>(m, thresh, flag, count); break;
+    case 7: k_curved_flags<7><<<g, 256, 0, s>>>(m, thresh, flag, count); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_mlp_forward<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(w, n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,
+                                const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s) {
+  if (n <= 0 || n > kMlpMaxBatch) return hipErrorInvalidValue;
+  k_zero_f32<<<1, 64, 0, s>>>(loss, 1);
+  k_mlp_rows<<<dim3((unsigned)((n + 127) / 128)), 128, 0, s>>>(w, n, in, target, rows, rowbuf, loss);
+  k_mlp_wgrad<<<dim3(H, 4), 64, 0, s>>>(n, rowbuf, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, int64_t nw, int64_t t, float lr, hipStream_t s) {
+  float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+  k_adam<<<dim3((unsigned)((nw + 255) / 256)), 256, 0, s>>>(w, m, v, g, nw, lr, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace fp

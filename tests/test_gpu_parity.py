@@ -1,0 +1,233 @@
+"""GPU (HIP library, through the C ABI) against the FP64 oracle, element by element.
+
+Bar (FP64 path): element ownership, wall-hit counts and statuses bit-exact;
+positions and velocities within 1e-10 relative to the domain size / speed
+scale.  Cases span several waves and a ragged tail; the full-size case runs
+every particle of the 32^3 curved workload in the benchmark's launch
+configuration and compares a deterministic sample with the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2211_05458_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_05458_amd.lib import FlexiPart
+    return FlexiPart
+
+
+def run_gpu(w, n_steps, rk, drag, x=None, v=None, d=None, hint="w", precision=0, sort_every=1, U=None,
+            max_particles=None):
+    FlexiPart = _gpu()
+    x = w.x if x is None else x
+    v = w.v if v is None else v
+    d = w.d if d is None else d
+    h = w.elem_hint if isinstance(hint, str) else hint
+    g = FlexiPart(w.mesh, w.N, max_particles or max(len(x), 1))
+    g.set_fluid_state(w.U if U is None else U)
+    st, nrej = g.push(x, v, d, h)
+    if n_steps:
+        g.step(w.dt, n_steps, rk=rk, drag=drag, precision=precision, sort_every=sort_every)
+    return g, g.read()
+
+
+def run_oracle(w, n_steps, rk, drag, x=None, v=None, d=None, hint="w"):
+    o = O.Oracle(w.mesh, w.N, w.U)
+    x = w.x if x is None else x
+    v = w.v if v is None else v
+    d = w.d if d is None else d
+    h = w.elem_hint if isinstance(hint, str) else hint
+    o.push(x, v, d, h)
+    if n_steps:
+        o.step(w.dt, n_steps, rk=rk, drag=drag)
+    return o, o.read()
+
+
+def assert_parity(ro, rg, L=1.0, vscale=1.0, tol=1e-10):
+    np.testing.assert_array_equal(rg["status"], ro["status"])
+    np.testing.assert_array_equal(rg["elem"], ro["elem"])
+    np.testing.assert_array_equal(rg["hits"], ro["hits"])
+    act = ro["status"] == 0
+    assert np.abs(rg["x"][act] - ro["x"][act]).max(initial=0) <= tol * L
+    assert np.abs(rg["v"][act] - ro["v"][act]).max(initial=0) <= tol * vscale
+    assert np.abs(rg["xi"][act] - ro["xi"][act]).max(initial=0) <= 1e-8
+
+
+def test_config1_parity_lserk4_stokes():
+    w = W.config1(n_particles=3000)
+    _, ro = run_oracle(w, 20, rk=0, drag=0)
+    _, rg = run_gpu(w, 20, rk=0, drag=0)
+    assert (ro["status"] == 0).all()
+    assert_parity(ro, rg, vscale=5.0)
+
+
+def test_curved_box_parity_with_walls():
+    """Curved Ng=4 mesh, N=5 field, Schiller-Naumann, 3-stage RK; velocities
+    amplified so that particles cross many curved faces and hit the walls."""
+    w = W.curved_box(cells=6, N=5, n_particles=2500, n_steps=1, seed=21)
+    v = w.v * 20.0
+    w.dt = 2e-3
+    _, ro = run_oracle(w, 25, rk=1, drag=1, v=v)
+    g, rg = run_gpu(w, 25, rk=1, drag=1, v=v)
+    assert ro["hits"].sum() > 50
+    assert_parity(ro, rg, vscale=40.0)
+    st = g.stats()
+    assert st["crossings"] > 1000 and st["lost"] == 0
+
+
+def test_billiard_closed_form_on_gpu():
+    """No drag: positions are the folded straight lines, wall hits the number of folds."""
+    def node_map(I1, I2, I3, M):
+        out = np.empty(np.broadcast_shapes(I1.shape, I2.shape, I3.shape) + (3,))
+        out[..., 0] = I1 / M[0]; out[..., 1] = I2 / M[1]; out[..., 2] = I3 / M[2]
+        return out
+    X, ne, nf, bc, sh, _ = W.structured_mesh((4, 4, 4), 1, node_map, (False, False, False))
+    mesh = W.Mesh(1, X, ne, nf, bc, sh, h=0.25, cells=(4, 4, 4))
+    rng = np.random.default_rng(8)
+    n = 1000
+    x0 = rng.uniform(0.02, 0.98, (n, 3))
+    v0 = rng.uniform(-3, 3, (n, 3))
+    w = W.Workload("box", mesh, 1, W.uniform_state(64, 1, np.zeros(3)), x0, v0, np.full(n, 1e-4),
+                   np.full(n, -1, np.int32), dt=0.01, n_steps=50, rk=1, drag=2)
+    _, rg = run_gpu(w, 50, rk=1, drag=2, hint=None)
+    X_ = x0 + v0 * 0.5
+    m = np.floor(X_)
+    r = X_ - m
+    xf = np.where(m % 2 == 0, r, 1 - r)
+    assert (rg["status"] == 0).all()
+    np.testing.assert_allclose(rg["x"], xf, atol=1e-12)
+    np.testing.assert_array_equal(rg["hits"], np.abs(m).astype(int).sum(axis=1))
+    np.testing.assert_allclose(np.linalg.norm(rg["v"], axis=1), np.linalg.norm(v0, axis=1), rtol=1e-14)
+
+
+def test_push_without_hint_uses_background_mesh():
+    w = W.curved_box(cells=5, N=3, n_particles=700, n_steps=1, seed=22)
+    _, ro = run_oracle(w, 0, 1, 1, hint=None)
+    _, rg = run_gpu(w, 0, 1, 1, hint=None)
+    np.testing.assert_array_equal(rg["elem"], ro["elem"])
+    np.testing.assert_array_equal(rg["status"], ro["status"])
+    np.testing.assert_allclose(rg["xi"], ro["xi"], atol=1e-12)
+    # generated points lie inside their logical cells, which the mesh reproduces
+    assert (ro["elem"] == w.elem_hint).mean() > 0.99
+
+
+def test_sorting_does_not_change_results():
+    w = W.curved_box(cells=5, N=3, n_particles=1500, n_steps=1, seed=23)
+    v = w.v * 10.0
+    _, r0 = run_gpu(w, 10, rk=1, drag=1, v=v, sort_every=0)
+    _, r1 = run_gpu(w, 10, rk=1, drag=1, v=v, sort_every=1)
+    for k in ("x", "v", "xi", "elem", "hits", "status"):
+        np.testing.assert_array_equal(r0[k], r1[k])
+
+
+def test_edge_cases_empty_ragged_rejected_nan():
+    FlexiPart = _gpu()
+    w = W.config1(n_particles=257)
+    g = FlexiPart(w.mesh, w.N, 300)
+    g.set_fluid_state(w.U)
+    st, nrej = g.push(w.x[:0], w.v[:0], w.d[:0])
+    assert nrej == 0
+    g.step(1e-3, 2, rk=0, drag=0)
+    assert g.read()["x"].shape == (0, 3)
+    x = w.x.copy()
+    v = w.v.copy()
+    x[5] = [1.5, 0.5, 0.5]          # outside the unit cube
+    v[7] = np.nan                   # invalid state: must end as a lost particle, not a fault
+    st, nrej = g.push(x, v, w.d, None)
+    assert nrej == 1 and st[5] == 5
+    g.step(1e-3, 3, rk=0, drag=0)
+    r = g.read()
+    assert r["status"][5] == 5 and r["status"][7] in (2, 3)
+    ok = np.ones(257, bool); ok[[5, 7]] = False
+    assert (r["status"][ok] == 0).all()
+    o = O.Oracle(w.mesh, w.N, w.U)
+    o.push(x, v, w.d)
+    o.step(1e-3, 3, rk=0, drag=0)
+    ro = o.read()
+    np.testing.assert_array_equal(r["status"], ro["status"])
+    np.testing.assert_allclose(r["x"][ok], ro["x"][ok], atol=1e-10)
+
+
+def test_deposit_nearest_parity_and_conservation():
+    import torch
+    w = W.curved_box(cells=4, N=3, n_particles=900, n_steps=1, seed=24)
+    v = w.v + 0.3
+    o, _ = run_oracle(w, 0, 1, 1, v=v)
+    g, _ = run_gpu(w, 0, 1, 1, v=v)
+    So = o.deposit(kind=0)
+    Sg = g.deposit(kind=0).cpu().numpy()
+    np.testing.assert_allclose(Sg, So, rtol=1e-10, atol=1e-12 * np.abs(So).max())
+    # FP32 accumulation: conservation to FP32 rounding
+    Sf = g.deposit(kind=0, dtype=torch.float32).cpu().numpy()
+    V = np.array([[o.volume(e, q) for q in range(64)] for e in range(w.mesh.n_elem)])
+    tot = np.einsum("ecq,eq->c", So, V)
+    totf = np.einsum("ecq,eq->c", Sf.astype(np.float64), V)
+    assert np.abs(totf - tot).max() <= 1e-5 * np.abs(tot).max()
+
+
+def test_deposit_shape_parity_and_conservation():
+    w = W.curved_box(cells=6, N=3, n_particles=600, n_steps=1, seed=25)
+    v = w.v + 0.3
+    o, _ = run_oracle(w, 0, 1, 1, v=v)
+    g, _ = run_gpu(w, 0, 1, 1, v=v)
+    R = 1.5 / 6
+    per = np.array([1.0, 0.0, 1.0])
+    So = o.deposit(kind=1, radius=R, period=per)
+    Sg = g.deposit(kind=1, radius=R, period=per).cpu().numpy()
+    np.testing.assert_allclose(Sg, So, rtol=1e-9, atol=1e-11 * np.abs(So).max())
+
+
+def test_mixed_precision_error_is_bounded():
+    w = W.curved_box(cells=6, N=5, n_particles=2000, n_steps=1, seed=26)
+    import torch
+    _, r64 = run_gpu(w, 20, rk=1, drag=1)
+    _, r32 = run_gpu(w, 20, rk=1, drag=1, precision=1, U=torch.from_numpy(w.U.astype(np.float32)))
+    err = np.abs(r32["x"] - r64["x"]).max()
+    assert err < 1e-6, err
+    assert (r32["elem"] != r64["elem"]).mean() < 1e-3
+
+
+def test_full_size_curved_sampled_parity():
+    """32^3 curved mesh, N=5, 1e6 particles, sorted every step (the benchmark
+    configuration); every 1000th particle is re-run by the oracle."""
+    w = W.config2()
+    n_steps = 3
+    _, rg = run_gpu(w, n_steps, rk=1, drag=1)
+    idx = np.arange(0, w.n_particles, 1000)
+    o = O.Oracle(w.mesh, w.N, w.U)
+    o.push(w.x[idx], w.v[idx], w.d[idx], w.elem_hint[idx])
+    o.step(w.dt, n_steps, rk=1, drag=1)
+    ro = o.read()
+    sub = {k: rg[k][idx] for k in rg}
+    assert_parity(ro, sub, vscale=2.0)
+    assert (rg["status"] == 0).all()
+
+
+def test_mlp_gradients_match_oracle():
+    import torch
+    FlexiPart = _gpu()
+    w = W.config1(n_particles=10, cells=2)
+    g = FlexiPart(w.mesh, w.N, 16)
+    rng = np.random.default_rng(30)
+    nw = FlexiPart.mlp_n_weights()
+    wt = rng.normal(scale=0.15, size=nw)
+    inp = rng.normal(size=(777, 27))
+    tgt = rng.uniform(-1, 1, size=(777, 3))
+    lo, go = O.mlp_loss_grad(wt, inp, tgt)
+    W32 = torch.tensor(wt, dtype=torch.float32, device="cuda")
+    lg, gg = g.mlp_loss_grad(W32, torch.tensor(inp, dtype=torch.float32, device="cuda"),
+                             torch.tensor(tgt, dtype=torch.float32, device="cuda"))
+    gg = gg.cpu().numpy().astype(np.float64)
+    assert abs(lg.item() - lo) <= 1e-5 * lo
+    assert np.abs(gg - go).max() <= 1e-4 * np.abs(go).max()
+    out = g.mlp_forward(W32, torch.tensor(inp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(out, O.mlp_forward(wt, inp), atol=1e-5)
