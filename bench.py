@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the per-particle Lagrangian step on one MI355X.
+
+Workload: curved sine-mapped periodic box with curved reflective walls,
+32^3 hexahedra of geometry degree 4, DG degree 5 random-Fourier fluid state,
+1e6 particles, Schiller-Naumann drag, 3-stage low-storage RK, dt = 1e-3, FP64.
+One timed step = one fp_step(dt, 1): counting sort by element, then three fused
+RK-stage launches (guess, Newton, interpolation, drag, update, tracking with
+face intersection, hand-off and wall reflection, inside verification).
+
+Prints one JSON line.  Also measured: the mixed-precision form (FP32 fluid
+state, FP32 interpolation/drag/RK) with its position error against the FP64
+form, the dominant kernel against its roofline, and the FP64 CPU oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+KERNEL_SOURCES = ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/kernels.hip",
+                  "paper_2211_05458_amd/csrc/fp_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_fp64_config2_traffic.md")
+
+
+def stage_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """Per-launch HBM bytes of the stage kernel from the committed counter summary,
+    only if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("source_hash:"):
+            vals["hash"] = line.split(":", 1)[1].strip()
+        if line.startswith("hbm_bytes_per_launch:"):
+            vals["bytes"] = float(line.split(":", 1)[1].strip())
+    if vals.get("hash") != stage_source_hash() or "bytes" not in vals:
+        return None
+    return vals["bytes"]
+
+
+def flops_per_particle_stage(n, ng, newton_it):
+    """Algorithmic flops of one particle-stage (measurement)."""
+    f_newton = 6 * (2 * ng ** 3 + 3 * ng ** 2 + 4 * ng) + 160
+    f_interp = 10 * (n ** 3 + n ** 2 + n) + 9 * n ** 2
+    f_guess = 8 * ng ** 3
+    f_rest = 300
+    return newton_it * f_newton + f_interp + f_guess + f_rest
+
+
+def bytes_per_particle_stage(n, ng, ppe):
+    """Algorithmic HBM bytes of one particle-stage, FP64 state: particle SoA read
+    (x, v, kx, kv, d, elem, status) and write (x, v, kx, kv, elem), plus the
+    element's fluid state, geometry and face records amortised over its particles."""
+    soa = (12 * 8 + 8 + 4 + 1) + (12 * 8 + 4)
+    elem = 5 * n ** 3 * 8 + 3 * ng ** 3 * 8 + 336
+    return soa + elem / ppe
+
+
+def run_gpu(w, U, precision, steps, warmup):
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd.lib import FlexiPart
+    g = FlexiPart(w.mesh, w.N, w.n_particles)
+    g.set_fluid_state(U)
+    st, nrej = g.push(w.x, w.v, w.d, w.elem_hint)
+    n_active = int((st == 0).sum())
+    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1)
+    for _ in range(warmup):
+        g.step(w.dt, 1, **opts)
+    torch.cuda.synchronize()
+    g.reset_stats()
+    g.timing()
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        g.step(w.dt, 1, **opts)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    timing = g.timing()
+    g.set_timing(False)
+    stats = g.stats()
+    r = g.read()
+    return dict(ms=ms, wall=wall, timing=timing, stats=stats, read=r, n_active=n_active,
+                active_end=int((r["status"] == 0).sum()))
+
+
+def copy_calibration(gib=2, reps=5):
+    """Device-to-device copy of a known byte count (counter calibration)."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-every", type=int, default=50, help="oracle sample: every k-th particle")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
+                    help="copy: a plain device copy of known size, the calibration for HBM counters")
+    args = ap.parse_args()
+    if args.mode == "copy":
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+
+    print("[bench] generating workload", file=sys.stderr, flush=True)
+    w = W.config2(n_particles=args.particles)
+    n, ng = w.N + 1, w.mesh.n_geo + 1
+    U64 = torch.from_numpy(w.U).cuda()
+    print("[bench] FP64 run", file=sys.stderr, flush=True)
+    r64 = run_gpu(w, U64, 0, args.steps, args.warmup)
+    K = args.steps
+    value = r64["n_active"] * K / (r64["ms"] * 1e-3)
+    stages = 3
+    n_launch, stage_ms = r64["timing"]["stage"]
+    sort_launch, sort_ms = r64["timing"]["sort"]
+    avg_stage_ms = stage_ms / max(n_launch, 1)
+    ps = r64["n_active"] * stages * K                       # particle-stages timed
+    it_per_ps = r64["stats"]["newton_iters"] / ps
+    fl_ps = flops_per_particle_stage(n, ng, it_per_ps)
+    ppe = r64["n_active"] / w.mesh.n_elem
+    by_ps = bytes_per_particle_stage(n, ng, ppe)
+    per_launch_flops = fl_ps * r64["n_active"]
+    per_launch_bytes = by_ps * r64["n_active"]
+    achieved_tf = per_launch_flops / (avg_stage_ms * 1e-3) / 1e12
+    achieved_gbs = per_launch_bytes / (avg_stage_ms * 1e-3) / 1e9
+    traffic = read_traffic()
+
+    extras = {}
+    if not args.no_mixed:
+        print("[bench] mixed-precision run", file=sys.stderr, flush=True)
+        U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+        r32 = run_gpu(w, U32, 1, args.steps, args.warmup)
+        x64, x32 = r64["read"]["x"], r32["read"]["x"]
+        both = (r64["read"]["status"] == 0) & (r32["read"]["status"] == 0)
+        dx = np.linalg.norm(x32[both] - x64[both], axis=1)
+        extras["mixed_fp32"] = {
+            "value": r32["n_active"] * K / (r32["ms"] * 1e-3),
+            "ms_per_step": r32["ms"] / K,
+            "stage_ms": r32["timing"]["stage"][1] / max(r32["timing"]["stage"][0], 1),
+            "pos_err_max_m": float(dx.max()), "pos_err_rms_m": float(np.sqrt((dx ** 2).mean())),
+            "pos_err_max_h": float(dx.max() / w.mesh.h),
+            "elem_mismatch_frac": float((r32["read"]["elem"] != r64["read"]["elem"]).mean()),
+            "hits_mismatch_frac": float((r32["read"]["hits"] != r64["read"]["hits"]).mean()),
+            "after_steps": args.warmup + K,
+            "learned_guess": "no element of this mesh deviates from its trilinear corner map by "
+                             "more than 0.05 h, so the learned guess is never used here",
+        }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        idx = np.arange(0, w.n_particles, args.cpu_every)
+        o = O.Oracle(w.mesh, w.N, w.U)
+        o.push(w.x[idx], w.v[idx], w.d[idx], w.elem_hint[idx])
+        t0 = time.perf_counter()
+        o.step(w.dt, args.cpu_steps, rk=w.rk, drag=w.drag)
+        el = time.perf_counter() - t0
+        cpu = {"value": len(idx) * args.cpu_steps / el, "unit": "particle-steps/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": "every %dth particle (%d of %d) for %d steps of the same workload, FP64, "
+                         "%.1f s wall" % (args.cpu_every, len(idx), w.n_particles, args.cpu_steps, el)}
+
+    out = {
+        "metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "curved sine box 32^3 Ngeo=4, DG N=5 random-Fourier state, %d particles, "
+                               "Schiller-Naumann, 3-stage LSERK, dt=1e-3, FP64, one-way" % w.n_particles,
+                   "elements": w.mesh.n_elem, "particles": w.n_particles, "N": w.N, "n_geo": w.mesh.n_geo},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "k_stage<6,5,double,false>", "avg_launch_ms": avg_stage_ms,
+                     "flops_per_particle_stage": fl_ps, "newton_it_per_particle_stage": it_per_ps,
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "algorithmic_GBs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS},
+        "sort_ms": sort_ms / max(sort_launch, 1),
+        "stats": r64["stats"],
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,16 @@ int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* el
 int fp_get_stats(fp_ctx* ctx, int64_t* out7);
 int fp_reset_stats(fp_ctx* ctx);
 
+/* ---- kernel timing (tracing) ---------------------------------------------
+ * When enabled, HIP events on the context stream bracket every launch of the
+ * step and source kernels.  fp_get_timing synchronises and writes, for each
+ * class (0 sort, 1 RK stage, 2 final reference coordinates, 3 nearest-DOF
+ * source, 4 shape-kernel source), out[2*k] = launches and out[2*k+1] = total
+ * milliseconds since the last call; the counters are then cleared. */
+#define FP_TIMING_CLASSES 5
+int fp_set_timing(fp_ctx* ctx, int32_t enable);
+int fp_get_timing(fp_ctx* ctx, double* out /* [2*FP_TIMING_CLASSES] */);
+
 /* ---- learned Newton initial guess (27-64-64-64-3 tanh MLP, FP32) --------- */
 /* Weight layout: W1[64][27] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]. */
 int64_t fp_mlp_n_weights(void);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libflexipart.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "kernels.hip", "sort.hip", "deposit.hip", "mlp.hip"]
+SOURCES = ["api.hip", "kernels.hip", "stage.hip", "sort.hip", "deposit.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -38,6 +38,10 @@ struct fp_ctx {
   double* dep_buf = nullptr;   // per-particle force (4) + normalisation (1)
   float* mlp_rows = nullptr;   // per-row activations for MLP gradients
   float* mlp_grad = nullptr;   // gradient + loss scratch
+  int32_t *tcount = nullptr, *tstart = nullptr, *qcnt = nullptr, *strag = nullptr, *trk_p = nullptr;
+  void* tasks = nullptr;
+  double* trk_x = nullptr;
+  bool tasks_valid = false;
   // fluid
   Fluid fl{};
   bool fluid_ok = false;
@@ -50,6 +54,12 @@ struct fp_ctx {
   // learned guess
   const float* mlp_w = nullptr;
   int64_t n_flagged = 0;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -162,11 +172,38 @@ std::vector<double> bernstein_vandermonde_inverse(int ng, const double* s) {
   return M;
 }
 
+// record an event pair around a launch when timing is enabled
+struct Timed {
+  fp_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t take() {
+    if (c->ev_used == c->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+  }
+  Timed(fp_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (!c->timing) return;
+    a = take();
+    b = take();
+    if (a) hipEventRecord(a, c->stream);
+  }
+  ~Timed() {
+    if (!c->timing || !a || !b) return;
+    hipEventRecord(b, c->stream);
+    c->recs.push_back({cls, a, b});
+  }
+};
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
-      sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, part[2], total;
+      sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
+      strag, trk_p, trk_x, part[2], total;
   size_t part_bytes;
 };
 
@@ -199,6 +236,14 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.dep = take((size_t)std::max<int64_t>(cap, 1) * 5 * 8);
   L.mlp_rows = take((size_t)kMlpMaxBatch * kMlpRow * 4);
   L.mlp_grad = take((size_t)(kMlpWeights + 64) * 4);
+  size_t pc1 = (size_t)std::max<int64_t>(cap, 1);
+  L.tcount = take((E + 1) * 4);
+  L.tstart = take((E + 1) * 4);
+  L.tasks = take((E + pc1 / 64 + 2) * task_bytes());
+  L.qcnt = take(64);
+  L.strag = take(pc1 * 4);
+  L.trk_p = take(pc1 * 4);
+  L.trk_x = take(pc1 * 3 * 8);
   size_t pc = (size_t)std::max<int64_t>(cap, 1);
   L.part_bytes = align256(pc * 15 * 8) + align256(pc * 8) + 3 * align256(pc * 4) + align256(pc);
   L.part[0] = take(L.part_bytes);
@@ -224,6 +269,26 @@ Particles carve(char* base, int64_t cap) {
 
 }  // namespace
 
+namespace {
+// counting sort of the current particle buffer into the other one, then the
+// element tasks of the fast stage kernel
+int sort_particles(fp_ctx* c) {
+  hipStream_t s = c->stream;
+  if (c->np == 0) {   // nothing to bucket: no histogram is computed, so no tasks either
+    c->tasks_valid = false;
+    return FP_OK;
+  }
+  HIPCHK(c, launch_sort(c->P[c->cur], c->P[1 - c->cur], c->np, c->E, c->sort_count, c->sort_start, c->sort_rank,
+                        c->sort_sums, s));
+  c->cur = 1 - c->cur;
+  c->sorts++;
+  HIPCHK(c, launch_tasks(c->sort_count, c->sort_start, c->E, c->tcount, c->tstart, c->sort_sums, c->tasks,
+                         c->qcnt + 4, (int64_t)c->E + c->cap / 64 + 2, s));
+  c->tasks_valid = true;
+  return FP_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int fp_create(fp_ctx** out, void* hip_stream) {
@@ -234,7 +299,11 @@ int fp_create(fp_ctx** out, void* hip_stream) {
   return FP_OK;
 }
 
-void fp_destroy(fp_ctx* c) { delete c; }
+void fp_destroy(fp_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  delete c;
+}
 
 const char* fp_last_error(fp_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
@@ -406,6 +475,14 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   c->dep_buf = (double*)(b + L.dep);
   c->mlp_rows = (float*)(b + L.mlp_rows);
   c->mlp_grad = (float*)(b + L.mlp_grad);
+  c->tcount = (int32_t*)(b + L.tcount);
+  c->tstart = (int32_t*)(b + L.tstart);
+  c->tasks = (void*)(b + L.tasks);
+  c->qcnt = (int32_t*)(b + L.qcnt);
+  c->strag = (int32_t*)(b + L.strag);
+  c->trk_p = (int32_t*)(b + L.trk_p);
+  c->trk_x = (double*)(b + L.trk_x);
+  c->tasks_valid = false;
   c->P[0] = carve(b + L.part[0], c->cap);
   c->P[1] = carve(b + L.part[1], c->cap);
   c->cur = 0;
@@ -475,6 +552,7 @@ int fp_push_particles(fp_ctx* c, int64_t n, const double* x, const double* v, co
   c->np = n;
   c->d_min = dmin;
   c->xi_dirty = false;
+  c->tasks_valid = false;
   c->steps_done = 0;
   return nrej;
 }
@@ -507,15 +585,30 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   hipStream_t s = c->stream;
   for (int st = 0; st < n_steps; ++st) {
     if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
-      HIPCHK(c, launch_sort(c->P[c->cur], c->P[1 - c->cur], c->np, c->E, c->sort_count, c->sort_start,
-                            c->sort_rank, c->sort_sums, s));
-      c->cur = 1 - c->cur;
-      c->sorts++;
+      Timed tm(c, 0);
+      int rc = sort_particles(c);
+      if (rc) return rc;
     }
     for (int i = 0; i < S; ++i) {
       sp.A = A[i];
       sp.B = B[i];
-      HIPCHK(c, launch_stage(c->mv, c->P[c->cur], c->fl, sp, c->np, o->precision, c->stats, s));
+      StageLaunch Lc{};
+      Lc.m = c->mv;
+      Lc.P = c->P[c->cur];
+      Lc.fl = c->fl;
+      Lc.sp = sp;
+      Lc.n = c->np;
+      Lc.mixed = o->precision;
+      Lc.mlp = sp.use_mlp;
+      Lc.tasks = c->tasks_valid ? c->tasks : nullptr;
+      Lc.ntask = c->qcnt + 4;
+      Lc.counters = c->qcnt;
+      Lc.strag = c->strag;
+      Lc.trk_p = c->trk_p;
+      Lc.trk_x = c->trk_x;
+      Lc.stats = c->stats;
+      Timed tm(c, 1);
+      HIPCHK(c, launch_stage(Lc, s));
     }
     c->steps_done++;
   }
@@ -535,6 +628,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   if (!c || !S || kind < 0 || kind > 1) return FP_EINVAL;
   if (!c->ws || !c->fluid_ok) return fail(c, FP_ESTATE, "fp_deposit_source: workspace or fluid state missing");
   if (kind == 0) {
+    Timed tm(c, 3);
     HIPCHK(c, launch_deposit_nearest(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, c->stream));
     return FP_OK;
   }
@@ -545,13 +639,15 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   for (int k = 0; k < 3; ++k)
     if (per[k] > 0.0 && per[k] <= 2.0 * (radius + c->max_extent))
       return fail(c, FP_EINVAL, "fp_deposit_source: period too short for the kernel radius");
+  if (c->np == 0) return FP_OK;
   // gather needs the particles bucketed by their current element
-  HIPCHK(c, launch_sort(c->P[c->cur], c->P[1 - c->cur], c->np, c->E, c->sort_count, c->sort_start, c->sort_rank,
-                        c->sort_sums, c->stream));
-  c->cur = 1 - c->cur;
-  c->sorts++;
-  HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, radius, per,
-                                 c->dep_buf, c->dep_buf, c->sort_start, c->stream));
+  int rc = sort_particles(c);
+  if (rc) return rc;
+  {
+    Timed tm(c, 4);
+    HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, radius, per,
+                                   c->dep_buf, c->dep_buf, c->sort_start, c->stream));
+  }
   return FP_OK;
 }
 
@@ -565,6 +661,7 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
   if (n == 0) return FP_OK;
   Particles& P = c->P[c->cur];
   if (c->xi_dirty) {
+    Timed tm(c, 2);
     HIPCHK(c, launch_finalize(c->mv, P, n, c->stats, s));
     c->xi_dirty = false;
   }
@@ -612,6 +709,27 @@ int fp_reset_stats(fp_ctx* c) {
   if (!c->ws) return fail(c, FP_ESTATE, "fp_reset_stats: no workspace");
   HIPCHK(c, hipMemsetAsync(c->stats, 0, 16 * 8, c->stream));
   c->sorts = 0;
+  return FP_OK;
+}
+
+int fp_set_timing(fp_ctx* c, int32_t enable) {
+  if (!c) return FP_EINVAL;
+  c->timing = enable != 0;
+  return FP_OK;
+}
+
+int fp_get_timing(fp_ctx* c, double* out) {
+  if (!c || !out) return FP_EINVAL;
+  for (int k = 0; k < 2 * FP_TIMING_CLASSES; ++k) out[k] = 0.0;
+  for (auto& r : c->recs) {
+    HIPCHK(c, hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+    out[2 * r.cls] += 1.0;
+    out[2 * r.cls + 1] += ms;
+  }
+  c->recs.clear();
+  c->ev_used = 0;
   return FP_OK;
 }
 

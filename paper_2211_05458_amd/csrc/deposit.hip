@@ -173,8 +173,7 @@ __global__ __launch_bounds__(256) void k_dep_gather(MeshView m, Particles P, con
   }
 }
 
-#define FP_FOR_EACH_SHAPE(X) \
-  X(2, 2) X(3, 2) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(3, 5) X(4, 5) X(6, 5) X(8, 5) X(4, 7) X(6, 7)
+#include "fp_shapes.h"
 
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
                                 int s_f32, int drag, double R, const double* period, double* norm_buf,

@@ -61,27 +61,54 @@ __device__ __forceinline__ void lagrange_d(const double* nodes, const double* cd
 // ---------------------------------------------------------------------------
 // chi_e(xi) and J = d chi / d xi by sum factorisation over i, then j, then k
 // ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void lagrange1_d(const double* nodes, const double* cden, double x, int i, double& l,
+                                            double& dl) {
+  double p = 1.0, dp = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+    if (j != i) {
+      double dx = x - nodes[j];
+      dp = dp * dx + p;
+      p *= dx;
+    }
+  l = cden[i] * p;
+  dl = cden[i] * dp;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ T lagrange1(const T* nodes, const T* cden, T x, int i) {
+  T p = cden[i];
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+    if (j != i) p *= (x - nodes[j]);
+  return p;
+}
+
 template <int NG>
 __device__ __forceinline__ void map_jac(const MeshView& m, const double* __restrict__ X, const double* xi,
                                         double* x, double J[3][3]) {
-  double l1[NG], d1[NG], l2[NG], d2[NG], l3[NG], d3[NG];
+  double l1[NG], d1[NG], l2[NG], d2[NG];
   lagrange_d<NG>(m.xgeo, m.cgeo, xi[0], l1, d1);
   lagrange_d<NG>(m.xgeo, m.cgeo, xi[1], l2, d2);
-  lagrange_d<NG>(m.xgeo, m.cgeo, xi[2], l3, d3);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     x[q] = 0.0;
     J[q][0] = J[q][1] = J[q][2] = 0.0;
   }
-#pragma unroll
+  // one xi3-slab of NG*NG nodes per iteration; l_k(xi3) computed in the slab
+#pragma unroll 1
   for (int k = 0; k < NG; ++k) {
+    double l3, d3;
+    lagrange1_d<NG>(m.xgeo, m.cgeo, xi[2], k, l3, d3);
+    const double* Xk = X + k * NG * NG * 3;
     double a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, c[3] = {0, 0, 0};
 #pragma unroll
     for (int j = 0; j < NG; ++j) {
       double s0[3] = {0, 0, 0}, s1[3] = {0, 0, 0};
 #pragma unroll
       for (int i = 0; i < NG; ++i) {
-        const double* P = X + ((k * NG + j) * NG + i) * 3;
+        const double* P = Xk + (j * NG + i) * 3;
         double p0 = P[0], p1 = P[1], p2 = P[2];
         s0[0] += p0 * l1[i]; s0[1] += p1 * l1[i]; s0[2] += p2 * l1[i];
         s1[0] += p0 * d1[i]; s1[1] += p1 * d1[i]; s1[2] += p2 * d1[i];
@@ -95,10 +122,10 @@ __device__ __forceinline__ void map_jac(const MeshView& m, const double* __restr
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      x[q] += a[q] * l3[k];
-      J[q][0] += b[q] * l3[k];
-      J[q][1] += c[q] * l3[k];
-      J[q][2] += a[q] * d3[k];
+      x[q] += a[q] * l3;
+      J[q][0] += b[q] * l3;
+      J[q][1] += c[q] * l3;
+      J[q][2] += a[q] * d3;
     }
   }
 }
@@ -106,8 +133,8 @@ __device__ __forceinline__ void map_jac(const MeshView& m, const double* __restr
 // Newton for chi(xi) = x (Sec. 3.2.1): Cramer's rule, stop after an update with
 // max-norm <= 1e-10, divergence when |xi| > 2 after the third iteration.
 template <int NG>
-__device__ bool newton(const MeshView& m, int e, const double* x, double* z, int max_it, int& iters) {
-  const double* X = m.X + (size_t)e * (NG * NG * NG * 3);
+__device__ bool newton_e(const MeshView& m, const double* __restrict__ X, const double* x, double* z, int max_it,
+                         int& iters) {
   for (int it = 1; it <= max_it; ++it) {
     double F[3], J[3][3];
     map_jac<NG>(m, X, z, F, J);
@@ -132,42 +159,53 @@ __device__ bool newton(const MeshView& m, int e, const double* x, double* z, int
   return false;
 }
 
+template <int NG>
+__device__ __forceinline__ bool newton(const MeshView& m, int e, const double* x, double* z, int max_it, int& iters) {
+  return newton_e<NG>(m, m.X + (size_t)e * (NG * NG * NG * 3), x, z, max_it, iters);
+}
+
+// nearest of n3 nodes P[q][3] (lowest index on ties)
+template <int N3>
+__device__ __forceinline__ int nearest_node(const double* __restrict__ P, const double* x) {
+  int best = 0;
+  double bd = 1e300;
+#pragma unroll 5
+  for (int q = 0; q < N3; ++q) {
+    double dx = P[q * 3] - x[0], dy = P[q * 3 + 1] - x[1], dz = P[q * 3 + 2] - x[2];
+    double dd = dx * dx + dy * dy + dz * dz;
+    if (dd < bd) { bd = dd; best = q; }
+  }
+  return best;
+}
+
 // Paper's initial guess (Sec. 3.2.1): nearest DG node (straight elements) or
-// nearest geometry node (curved), lowest index on ties.
+// nearest geometry node (curved), lowest index on ties.  Xe / XNe are the
+// element's geometry nodes and physical DG node positions.
 template <int NN, int NG>
-__device__ void guess_paper(const MeshView& m, int e, const double* x, double* g) {
+__device__ __forceinline__ void guess_paper_e(const MeshView& m, const double* __restrict__ Xe,
+                                              const double* __restrict__ XNe, const double* x, double* g) {
   if (NG == 2) {
-    const double* P = m.xnode + (size_t)e * (NN * NN * NN * 3);
-    int best = 0;
-    double bd = 1e300;
-    for (int q = 0; q < NN * NN * NN; ++q) {
-      double dx = P[q * 3] - x[0], dy = P[q * 3 + 1] - x[1], dz = P[q * 3 + 2] - x[2];
-      double dd = dx * dx + dy * dy + dz * dz;
-      if (dd < bd) { bd = dd; best = q; }
-    }
+    int best = nearest_node<NN * NN * NN>(XNe, x);
     g[0] = m.xdg[best % NN];
     g[1] = m.xdg[(best / NN) % NN];
     g[2] = m.xdg[best / (NN * NN)];
   } else {
-    const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
-    int best = 0;
-    double bd = 1e300;
-    for (int q = 0; q < NG * NG * NG; ++q) {
-      double dx = P[q * 3] - x[0], dy = P[q * 3 + 1] - x[1], dz = P[q * 3 + 2] - x[2];
-      double dd = dx * dx + dy * dy + dz * dz;
-      if (dd < bd) { bd = dd; best = q; }
-    }
+    int best = nearest_node<NG * NG * NG>(Xe, x);
     g[0] = m.xgeo[best % NG];
     g[1] = m.xgeo[(best / NG) % NG];
     g[2] = m.xgeo[best / (NG * NG)];
   }
 }
 
+template <int NN, int NG>
+__device__ __forceinline__ void guess_paper(const MeshView& m, int e, const double* x, double* g) {
+  guess_paper_e<NN, NG>(m, m.X + (size_t)e * (NG * NG * NG * 3), m.xnode + (size_t)e * (NN * NN * NN * 3), x, g);
+}
+
 // Third approach of Sec. 3.2.1: projection onto the directions from the node
 // mean to the node means of opposite faces.
 template <int NG>
-__device__ void guess_faces(const MeshView& m, int e, const double* x, double* g) {
-  const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
+__device__ void guess_faces_e(const double* __restrict__ P, const double* x, double* g) {
   double c[3] = {0, 0, 0};
   double f[6][3] = {{0}};
   for (int k = 0; k < NG; ++k)
@@ -196,6 +234,11 @@ __device__ void guess_faces(const MeshView& m, int e, const double* x, double* g
     double val = 0.5 * (dot3(d, sp) / dot3(sp, sp) - dot3(d, sm) / dot3(sm, sm));
     g[a] = fmin(1.0, fmax(-1.0, val));
   }
+}
+
+template <int NG>
+__device__ __forceinline__ void guess_faces(const MeshView& m, int e, const double* x, double* g) {
+  guess_faces_e<NG>(m.X + (size_t)e * (NG * NG * NG * 3), x, g);
 }
 
 __device__ __forceinline__ bool inside_ref(const double* xi) {
@@ -280,28 +323,36 @@ __device__ inline void mlp_forward_row(const float* __restrict__ w, const float*
 
 // Reference coordinates of x in element e: learned guess (flagged elements),
 // then the paper's guess, then the face-barycentre guess.
-template <int NN, int NG>
-__device__ bool locate_xi(const MeshView& m, int e, const double* x, double* xi, int max_it, bool use_mlp,
-                          int& it_sum, int& calls, int& fallbacks) {
+template <int NN, int NG, bool MLP = false>
+__device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__ Xe, const double* __restrict__ XNe,
+                            const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks) {
   double g[3];
-  if (use_mlp && m.mlp_w && m.mlp_flag[e]) {
+  if (MLP && m.mlp_flag[e]) {
     float feat[27], o[3];
     mlp_features<NG>(m, e, x, feat);
     mlp_forward_row(m.mlp_w, feat, o);
     g[0] = o[0]; g[1] = o[1]; g[2] = o[2];
     calls++;
-    if (newton<NG>(m, e, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
     fallbacks++;
   }
-  guess_paper<NN, NG>(m, e, x, g);
+  guess_paper_e<NN, NG>(m, Xe, XNe, x, g);
   calls++;
-  if (newton<NG>(m, e, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+  if (newton_e<NG>(m, Xe, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
   fallbacks++;
-  guess_faces<NG>(m, e, x, g);
+  guess_faces_e<NG>(Xe, x, g);
   calls++;
-  bool ok = newton<NG>(m, e, x, g, max_it, it_sum);
+  bool ok = newton_e<NG>(m, Xe, x, g, max_it, it_sum);
   xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2];
   return ok;
+}
+
+template <int NN, int NG>
+__device__ __forceinline__ bool locate_xi(const MeshView& m, int e, const double* x, double* xi, int max_it,
+                                          bool use_mlp, int& it_sum, int& calls, int& fallbacks) {
+  (void)use_mlp;
+  return locate_xi_e<NN, NG, false>(m, e, m.X + (size_t)e * (NG * NG * NG * 3),
+                                    m.xnode + (size_t)e * (NN * NN * NN * 3), x, xi, max_it, it_sum, calls, fallbacks);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,55 +360,60 @@ __device__ bool locate_xi(const MeshView& m, int e, const double* x, double* xi,
 // ---------------------------------------------------------------------------
 template <int NN, typename UT>
 __device__ __forceinline__ void interp(const MeshView& m, const UT* __restrict__ U, const double* xi, double* out) {
-  double l1[NN], l2[NN], l3[NN];
+  double l1[NN], l2[NN];
   lagrange<NN, double>(m.xdg, m.cdg, xi[0], l1);
   lagrange<NN, double>(m.xdg, m.cdg, xi[1], l2);
-  lagrange<NN, double>(m.xdg, m.cdg, xi[2], l3);
   constexpr int N3 = NN * NN * NN;
+  double acc[5] = {0, 0, 0, 0, 0};
+  // one xi3-slab per iteration: the NN*NN nodes of every variable
+#pragma unroll 1
+  for (int k = 0; k < NN; ++k) {
+    double l3 = lagrange1<NN, double>(m.xdg, m.cdg, xi[2], k);
 #pragma unroll
-  for (int var = 0; var < 5; ++var) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < NN; ++k) {
+    for (int var = 0; var < 5; ++var) {
+      const UT* Uk = U + var * N3 + k * NN * NN;
       double sk = 0.0;
 #pragma unroll
       for (int j = 0; j < NN; ++j) {
         double sj = 0.0;
 #pragma unroll
-        for (int i = 0; i < NN; ++i) sj += (double)U[var * N3 + (k * NN + j) * NN + i] * l1[i];
+        for (int i = 0; i < NN; ++i) sj += (double)Uk[j * NN + i] * l1[i];
         sk += sj * l2[j];
       }
-      s += sk * l3[k];
+      acc[var] += sk * l3;
     }
-    out[var] = s;
   }
+#pragma unroll
+  for (int var = 0; var < 5; ++var) out[var] = acc[var];
 }
 
 // FP32 interpolation (mixed precision): FP32 basis and accumulation.
 template <int NN, typename UT>
 __device__ __forceinline__ void interp_f32(const MeshView& m, const UT* __restrict__ U, const double* xi, float* out) {
-  float l1[NN], l2[NN], l3[NN];
+  float l1[NN], l2[NN];
   lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[0], l1);
   lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[1], l2);
-  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[2], l3);
   constexpr int N3 = NN * NN * NN;
+  float acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int k = 0; k < NN; ++k) {
+    float l3 = lagrange1<NN, float>(m.xdgf, m.cdgf, (float)xi[2], k);
 #pragma unroll
-  for (int var = 0; var < 5; ++var) {
-    float s = 0.0f;
-#pragma unroll
-    for (int k = 0; k < NN; ++k) {
+    for (int var = 0; var < 5; ++var) {
+      const UT* Uk = U + var * N3 + k * NN * NN;
       float sk = 0.0f;
 #pragma unroll
       for (int j = 0; j < NN; ++j) {
         float sj = 0.0f;
 #pragma unroll
-        for (int i = 0; i < NN; ++i) sj += (float)U[var * N3 + (k * NN + j) * NN + i] * l1[i];
+        for (int i = 0; i < NN; ++i) sj += (float)Uk[j * NN + i] * l1[i];
         sk += sj * l2[j];
       }
-      s += sk * l3[k];
+      acc[var] += sk * l3;
     }
-    out[var] = s;
   }
+#pragma unroll
+  for (int var = 0; var < 5; ++var) out[var] = acc[var];
 }
 
 // drag acceleration f_D (u - v)/tau_p (Sec. 2.2.1); fD returned for the source
@@ -802,6 +858,19 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       break;
     }
   }
+}
+
+// wave-aggregated queue append: returns the slot of each predicated lane (-1
+// otherwise); must be reached by every lane of the wave
+__device__ __forceinline__ int wave_push(int32_t* counter, bool pred) {
+  unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return -1;
+  int lane = threadIdx.x & 63;
+  int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  return pred ? base + (int)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
 }
 
 // wave-level sum then one atomic per wave

@@ -12,8 +12,26 @@ hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* 
                              hipStream_t s);
 hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, int32_t* bad, hipStream_t s);
 hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* hint, int64_t n, hipStream_t s);
-hipError_t launch_stage(const MeshView& m, const Particles& P, const Fluid& fl, const StepParams& sp, int64_t n,
-                        int mixed, unsigned long long* stats, hipStream_t s);
+struct StageLaunch {
+  MeshView m;
+  Particles P;
+  Fluid fl;
+  StepParams sp;
+  int64_t n;
+  int mixed, mlp;
+  const void* tasks;        // element tasks from the last sort, or null
+  const int32_t* ntask;
+  int32_t* counters;        // queue counters [2]
+  int32_t* strag;           // [cap]
+  int32_t* trk_p;           // [cap]
+  double* trk_x;            // [3][cap]
+  unsigned long long* stats;
+};
+hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
+hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int32_t* tcount, int32_t* tstart,
+                        int32_t* sums, void* tasks, int32_t* ntask, int64_t max_tasks, hipStream_t s);
+size_t task_bytes();
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s);
 hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, unsigned long long* stats,
                            hipStream_t s);
 hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,

@@ -186,92 +186,6 @@ __global__ __launch_bounds__(256) void k_locate(MeshView m, Particles P, const i
   }
 }
 
-// ---------------------------------------------------------------------------
-// one low-storage RK stage for every active particle (Sec. 3.2):
-// locate xi (guess + Newton + inside check), interpolate, drag, update, track
-// ---------------------------------------------------------------------------
-template <int NN, int NG, typename UT, bool MIXED>
-__global__ __launch_bounds__(256) void k_stage(MeshView m, Particles P, Fluid fl, StepParams sp, int64_t n,
-                                               unsigned long long* stats) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int it_sum = 0, calls = 0, fb = 0, ncross = 0, nhits = 0, nlost = 0;
-  constexpr int N3 = NN * NN * NN;
-  if (p < n && P.status[p] == ACTIVE) {
-    const int64_t cap = P.cap;
-    int e = P.elem[p];
-    double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
-    double xi[3];
-    if (!locate_xi<NN, NG>(m, e, x, xi, sp.max_it, sp.use_mlp != 0, it_sum, calls, fb)) {
-      P.status[p] = LOST_NEWTON;
-      nlost++;
-    } else if (!inside_ref(xi)) {
-      P.status[p] = LOST_TRACK;
-      nlost++;
-    } else {
-      double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
-      double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
-      double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
-      double d = P.d[p];
-      const UT* U = (const UT*)fl.U + (size_t)e * 5 * N3;
-      double xe[3];
-      if (!MIXED) {
-        double Uc[5];
-        interp<NN, UT>(m, U, xi, Uc);
-        double rho = Uc[0], ir = 1.0 / rho;
-        double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
-        double a[3], fD;
-        drag_accel<double>(sp.drag, rho, u, v, d, fl.mu, fl.rho_p, a, fD);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          a[k] += sp.gravity[k];
-          kx[k] = sp.A * kx[k] + sp.dt * v[k];
-          kv[k] = sp.A * kv[k] + sp.dt * a[k];
-          xe[k] = x[k] + sp.B * kx[k];
-          v[k] = v[k] + sp.B * kv[k];
-        }
-      } else {
-        float Uc[5];
-        interp_f32<NN, UT>(m, U, xi, Uc);
-        float ir = 1.0f / Uc[0];
-        float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
-        float vf[3] = {(float)v[0], (float)v[1], (float)v[2]};
-        float a[3], fD;
-        drag_accel<float>(sp.drag, Uc[0], u, vf, (float)d, (float)fl.mu, (float)fl.rho_p, a, fD);
-        const float A = (float)sp.A, B = (float)sp.B, dt = (float)sp.dt;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          a[k] += (float)sp.gravity[k];
-          float kxf = A * (float)kx[k] + dt * vf[k];
-          float kvf = A * (float)kv[k] + dt * a[k];
-          kx[k] = kxf;
-          kv[k] = kvf;
-          xe[k] = x[k] + (double)(B * kxf);
-          v[k] = (double)(vf[k] + B * kvf);
-        }
-      }
-      int8_t st = ACTIVE;
-      int h = 0;
-      track<NG>(m, e, x, xe, v, kx, kv, sp.max_cross, st, h, ncross);
-      nhits += h;
-      for (int k = 0; k < 3; ++k) {
-        P.x[k * cap + p] = xe[k];
-        P.v[k * cap + p] = v[k];
-        P.kx[k * cap + p] = kx[k];
-        P.kv[k * cap + p] = kv[k];
-      }
-      P.elem[p] = e;
-      if (h) P.hits[p] += h;
-      if (st != ACTIVE) P.status[p] = st;
-    }
-  }
-  wave_add(stats + ST_NEWTON_IT, it_sum);
-  wave_add(stats + ST_NEWTON_CALLS, calls);
-  wave_add(stats + ST_FALLBACK, fb);
-  wave_add(stats + ST_CROSS, ncross);
-  wave_add(stats + ST_HITS, nhits);
-  wave_add(stats + ST_LOST, nlost);
-}
-
 // reference coordinates of the current positions, with the inside check
 template <int NN, int NG>
 __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, unsigned long long* stats) {
@@ -337,8 +251,7 @@ __global__ __launch_bounds__(256) void k_deposit_nearest(MeshView m, Particles P
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-#define FP_FOR_EACH_SHAPE(X) \
-  X(2, 2) X(3, 2) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(3, 5) X(4, 5) X(6, 5) X(8, 5) X(4, 7) X(6, 7)
+#include "fp_shapes.h"
 
 bool supported(int n, int ng) {
 #define FP_SUP(A, B) if (n == A && ng == B) return true;
@@ -378,23 +291,6 @@ hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* h
   if (n == 0) return hipSuccess;
 #define FP_L(A, B) \
   if (m.n == A && m.ng == B) { k_locate<A, B><<<grid_for(n), 256, 0, s>>>(m, P, hint, n); return hipGetLastError(); }
-  FP_FOR_EACH_SHAPE(FP_L)
-#undef FP_L
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_stage(const MeshView& m, const Particles& P, const Fluid& fl, const StepParams& sp, int64_t n,
-                        int mixed, unsigned long long* stats, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  dim3 g = grid_for(n);
-#define FP_L(A, B)                                                                                  \
-  if (m.n == A && m.ng == B) {                                                                      \
-    if (!mixed && !fl.f32) k_stage<A, B, double, false><<<g, 256, 0, s>>>(m, P, fl, sp, n, stats); \
-    else if (!mixed && fl.f32) k_stage<A, B, float, false><<<g, 256, 0, s>>>(m, P, fl, sp, n, stats); \
-    else if (fl.f32) k_stage<A, B, float, true><<<g, 256, 0, s>>>(m, P, fl, sp, n, stats);         \
-    else k_stage<A, B, double, true><<<g, 256, 0, s>>>(m, P, fl, sp, n, stats);                    \
-    return hipGetLastError();                                                                       \
-  }
   FP_FOR_EACH_SHAPE(FP_L)
 #undef FP_L
   return hipErrorInvalidValue;

@@ -212,8 +212,7 @@ hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem
   return hipGetLastError();
 }
 
-#define FP_FOR_EACH_SHAPE(X) \
-  X(2, 2) X(3, 2) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(3, 5) X(4, 5) X(6, 5) X(8, 5) X(4, 7) X(6, 7)
+#include "fp_shapes.h"
 
 hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
                                int32_t* count, hipStream_t s) {

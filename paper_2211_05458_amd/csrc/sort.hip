@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Particles S, Particles D, 
   D.status[q] = st;
 }
 
-static hipError_t scan(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s) {
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s) {
   int64_t nt = (n + 1023) / 1024;
   k_scan_tiles<<<dim3((unsigned)nt), 256, 0, s>>>(in, out, n, sums);
   k_scan_sums<<<1, 256, 0, s>>>(sums, nt);
@@ -117,7 +117,7 @@ hipError_t launch_sort(const Particles& src, const Particles& dst, int64_t n, in
   int64_t nb = E + 1;
   k_fill_i32<<<dim3((unsigned)((nb + 255) / 256)), 256, 0, s>>>(count, nb, 0);
   k_sort_hist<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(src.status, src.elem, n, E, count, rank);
-  hipError_t err = scan(count, start, nb, block_sums, s);
+  hipError_t err = scan_i32(count, start, nb, block_sums, s);
   if (err != hipSuccess) return err;
   k_sort_scatter<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(src, dst, n, E, start, rank);
   return hipGetLastError();

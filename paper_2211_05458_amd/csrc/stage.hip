@@ -1,0 +1,331 @@
+// One low-storage RK stage (Sec. 3.2), split by the data each part touches:
+//
+//  k_stage_elem  one wavefront per (element, <= 64 particles) task built after
+//                the counting sort.  The element's geometry nodes, fluid state
+//                and face boxes are wave-uniform, so they stream through the
+//                scalar cache as SGPR operands of the FMAs.  Per particle:
+//                guess, Newton, inside check, interpolation, drag, stage
+//                update, and the bounding-box test of the element's faces
+//                (Sec. 3.2.4).  Particles whose segment touches a face box go
+//                to the tracking queue; particles that left the task element
+//                in an earlier stage go to the straggler queue.
+//  k_stage_lane  the same stage for the straggler queue (or for all particles
+//                when no sort has been done), with per-lane element data.
+//  k_track       physical-space tracking (Sec. 3.2.3/3.2.4) of the queued
+//                segments: face intersection, hand-off, periodic shift, wall
+//                reflection.
+#include "fp_device.h"
+#include "fp_launch.h"
+
+namespace fp {
+
+// interpolation, drag and the low-storage update for one particle
+template <int NN, typename UT, bool MIXED>
+__device__ __forceinline__ void stage_update(const MeshView& m, const UT* __restrict__ Ue, const double* xi,
+                                             const double* x, double* v, double* kx, double* kv, double d,
+                                             const Fluid& fl, const StepParams& sp, double* xe) {
+  if (!MIXED) {
+    double Uc[5];
+    interp<NN, UT>(m, Ue, xi, Uc);
+    double rho = Uc[0], ir = 1.0 / rho;
+    double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+    double a[3], fD;
+    drag_accel<double>(sp.drag, rho, u, v, d, fl.mu, fl.rho_p, a, fD);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] += sp.gravity[k];
+      kx[k] = sp.A * kx[k] + sp.dt * v[k];
+      kv[k] = sp.A * kv[k] + sp.dt * a[k];
+      xe[k] = x[k] + sp.B * kx[k];
+      v[k] = v[k] + sp.B * kv[k];
+    }
+  } else {
+    float Uc[5];
+    interp_f32<NN, UT>(m, Ue, xi, Uc);
+    float ir = 1.0f / Uc[0];
+    float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+    float vf[3] = {(float)v[0], (float)v[1], (float)v[2]};
+    float a[3], fD;
+    drag_accel<float>(sp.drag, Uc[0], u, vf, (float)d, (float)fl.mu, (float)fl.rho_p, a, fD);
+    const float A = (float)sp.A, B = (float)sp.B, dt = (float)sp.dt;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] += (float)sp.gravity[k];
+      float kxf = A * (float)kx[k] + dt * vf[k];
+      float kvf = A * (float)kv[k] + dt * a[k];
+      kx[k] = kxf;
+      kv[k] = kvf;
+      xe[k] = x[k] + (double)(B * kxf);
+      v[k] = (double)(vf[k] + B * kvf);
+    }
+  }
+}
+
+struct Task { int32_t e, p0, cnt, pad; };
+
+struct Queues {
+  int32_t* counters;  // [0] stragglers, [1] tracking
+  int32_t* strag;     // [cap]
+  int32_t* trk_p;     // [cap]
+  double* trk_x;      // [3][cap] segment start
+};
+
+template <int NN, int NG, typename UT, bool MIXED, bool MLP>
+__global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __restrict__ X,
+                                                    const double* __restrict__ XN, const UT* __restrict__ U,
+                                                    const FaceRec* __restrict__ faces, const Task* __restrict__ tasks,
+                                                    const int32_t* __restrict__ ntask, Particles P, Fluid fl,
+                                                    StepParams sp, Queues q, unsigned long long* stats) {
+  constexpr int NG3 = NG * NG * NG, NN3 = NN * NN * NN;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  const int nt = __builtin_amdgcn_readfirstlane(*ntask);
+  int it_sum = 0, calls = 0, fb = 0, nlost = 0;
+  bool strag = false, trk = false;
+  int64_t p = 0;
+  double xs0 = 0, xs1 = 0, xs2 = 0;
+  const int64_t cap = P.cap;
+  if (wid < nt) {
+    const Task t = tasks[wid];
+    const int e = __builtin_amdgcn_readfirstlane(t.e);
+    const int p0 = __builtin_amdgcn_readfirstlane(t.p0);
+    const int cnt = __builtin_amdgcn_readfirstlane(t.cnt);
+    p = (int64_t)p0 + lane;
+    bool act = lane < cnt && P.status[p] == ACTIVE;
+    if (act && P.elem[p] != e) {
+      strag = true;
+      act = false;
+    }
+    if (act) {
+      const double* Xe = X + (size_t)e * NG3 * 3;
+      const double* XNe = XN + (size_t)e * NN3 * 3;
+      double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
+      double xi[3];
+      if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb)) {
+        P.status[p] = LOST_NEWTON;
+        nlost++;
+      } else if (!inside_ref(xi)) {
+        P.status[p] = LOST_TRACK;
+        nlost++;
+      } else {
+        double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
+        double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
+        double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
+        double xe[3];
+        stage_update<NN, UT, MIXED>(m, U + (size_t)e * 5 * NN3, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
+        const FaceRec* Fe = faces + (size_t)e * 6;
+        bool any = false;
+#pragma unroll 1
+        for (int f = 0; f < 6; ++f) any = any || bbox_hit(Fe[f], x, xe);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          P.x[k * cap + p] = xe[k];
+          P.v[k * cap + p] = v[k];
+          P.kx[k * cap + p] = kx[k];
+          P.kv[k * cap + p] = kv[k];
+        }
+        if (any) {
+          trk = true;
+          xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
+        }
+      }
+    }
+  }
+  int s1 = wave_push(q.counters + 0, strag);
+  if (strag) q.strag[s1] = (int32_t)p;
+  int s2 = wave_push(q.counters + 1, trk);
+  if (trk) {
+    q.trk_p[s2] = (int32_t)p;
+    q.trk_x[s2] = xs0;
+    q.trk_x[cap + s2] = xs1;
+    q.trk_x[2 * cap + s2] = xs2;
+  }
+  wave_add(stats + ST_NEWTON_IT, it_sum);
+  wave_add(stats + ST_NEWTON_CALLS, calls);
+  wave_add(stats + ST_FALLBACK, fb);
+  wave_add(stats + ST_LOST, nlost);
+}
+
+// per-lane stage for the straggler queue (list != null) or all n particles;
+// every updated particle goes to the tracking queue
+template <int NN, int NG, typename UT, bool MIXED, bool MLP>
+__global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* __restrict__ list, int64_t n_all,
+                                                    Particles P, Fluid fl, StepParams sp, Queues q,
+                                                    unsigned long long* stats) {
+  constexpr int NG3 = NG * NG * NG, NN3 = NN * NN * NN;
+  const int64_t count = list ? (int64_t)q.counters[0] : n_all;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t cap = P.cap;
+  int it_sum = 0, calls = 0, fb = 0, nlost = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < count; i += stride) {
+    bool trk = false;
+    int64_t p = 0;
+    double xs0 = 0, xs1 = 0, xs2 = 0;
+    if (i < count) {
+      p = list ? (int64_t)list[i] : i;
+      if (P.status[p] == ACTIVE) {
+        const int e = P.elem[p];
+        double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
+        double xi[3];
+        if (!locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi, sp.max_it,
+                                      it_sum, calls, fb)) {
+          P.status[p] = LOST_NEWTON;
+          nlost++;
+        } else if (!inside_ref(xi)) {
+          P.status[p] = LOST_TRACK;
+          nlost++;
+        } else {
+          double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
+          double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
+          double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
+          double xe[3];
+          stage_update<NN, UT, MIXED>(m, (const UT*)fl.U + (size_t)e * 5 * NN3, xi, x, v, kx, kv, P.d[p], fl, sp,
+                                      xe);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            P.x[k * cap + p] = xe[k];
+            P.v[k * cap + p] = v[k];
+            P.kx[k * cap + p] = kx[k];
+            P.kv[k * cap + p] = kv[k];
+          }
+          trk = true;
+          xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
+        }
+      }
+    }
+    int s = wave_push(q.counters + 1, trk);
+    if (trk) {
+      q.trk_p[s] = (int32_t)p;
+      q.trk_x[s] = xs0;
+      q.trk_x[cap + s] = xs1;
+      q.trk_x[2 * cap + s] = xs2;
+    }
+  }
+  wave_add(stats + ST_NEWTON_IT, it_sum);
+  wave_add(stats + ST_NEWTON_CALLS, calls);
+  wave_add(stats + ST_FALLBACK, fb);
+  wave_add(stats + ST_LOST, nlost);
+}
+
+template <int NG>
+__global__ __launch_bounds__(256) void k_track(MeshView m, Particles P, Queues q, StepParams sp,
+                                               unsigned long long* stats) {
+  const int64_t count = q.counters[1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t cap = P.cap;
+  int ncross = 0, nhits = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const int64_t p = q.trk_p[i];
+    double xs[3] = {q.trk_x[i], q.trk_x[cap + i], q.trk_x[2 * cap + i]};
+    double xe[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
+    double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
+    double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
+    double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
+    int e = P.elem[p], e0 = e, h = 0, nc = 0;
+    int8_t st = ACTIVE;
+    track<NG>(m, e, xs, xe, v, kx, kv, sp.max_cross, st, h, nc);
+    ncross += nc;
+    nhits += h;
+    if (nc || st != ACTIVE) {
+      for (int k = 0; k < 3; ++k) {
+        P.x[k * cap + p] = xe[k];
+        P.v[k * cap + p] = v[k];
+        P.kx[k * cap + p] = kx[k];
+        P.kv[k * cap + p] = kv[k];
+      }
+      if (e != e0) P.elem[p] = e;
+      if (h) P.hits[p] += h;
+      if (st != ACTIVE) P.status[p] = st;
+    }
+  }
+  wave_add(stats + ST_CROSS, ncross);
+  wave_add(stats + ST_HITS, nhits);
+}
+
+__global__ void k_reset_counters(int32_t* c) {
+  if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
+// tasks of <= 64 particles per element after the counting sort
+__global__ void k_task_count(const int32_t* __restrict__ count, int E, int32_t* tcount) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) tcount[e] = (count[e] + 63) / 64;
+  else if (e == E) tcount[E] = 0;
+}
+
+__global__ void k_task_fill(const int32_t* __restrict__ count, const int32_t* __restrict__ start,
+                            const int32_t* __restrict__ tstart, int E, Task* tasks, int32_t* ntask,
+                            int64_t max_tasks) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  int c = count[e], t0 = tstart[e], s0 = start[e];
+  for (int j = 0; 64 * j < c && (int64_t)t0 + j < max_tasks; ++j) {
+    Task t;
+    t.e = e;
+    t.p0 = s0 + 64 * j;
+    t.cnt = min(64, c - 64 * j);
+    t.pad = 0;
+    tasks[t0 + j] = t;
+  }
+  if (e == E - 1) *ntask = (int32_t)min((int64_t)tstart[E], max_tasks);
+}
+
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s);
+
+hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int32_t* tcount, int32_t* tstart,
+                        int32_t* sums, void* tasks, int32_t* ntask, int64_t max_tasks, hipStream_t s) {
+  dim3 g((unsigned)((E + 1 + 255) / 256));
+  k_task_count<<<g, 256, 0, s>>>(count, E, tcount);
+  hipError_t err = scan_i32(tcount, tstart, E + 1, sums, s);
+  if (err != hipSuccess) return err;
+  k_task_fill<<<g, 256, 0, s>>>(count, start, tstart, E, (Task*)tasks, ntask, max_tasks);
+  return hipGetLastError();
+}
+
+size_t task_bytes() { return sizeof(Task); }
+
+#include "fp_shapes.h"
+
+template <int NN, int NG, typename UT, bool MIXED, bool MLP>
+static void run_stage(const StageLaunch& L, hipStream_t s) {
+  const MeshView& m = L.m;
+  Queues q{L.counters, L.strag, L.trk_p, L.trk_x};
+  k_reset_counters<<<1, 64, 0, s>>>(L.counters);
+  int64_t lane_blocks;
+  if (L.tasks) {
+    int64_t waves = (int64_t)m.E + L.P.cap / 64 + 1;
+    k_stage_elem<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(
+        m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
+    lane_blocks = std::min<int64_t>((L.n + 255) / 256, 256);
+    k_stage_lane<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)std::max<int64_t>(lane_blocks, 1)), 256, 0, s>>>(
+        m, L.strag, L.n, L.P, L.fl, L.sp, q, L.stats);
+  } else {
+    lane_blocks = (L.n + 255) / 256;
+    k_stage_lane<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)std::max<int64_t>(lane_blocks, 1)), 256, 0, s>>>(
+        m, nullptr, L.n, L.P, L.fl, L.sp, q, L.stats);
+  }
+  int64_t trk_blocks = std::max<int64_t>(1, std::min<int64_t>((L.n + 255) / 256, 1024));
+  k_track<NG><<<dim3((unsigned)trk_blocks), 256, 0, s>>>(m, L.P, q, L.sp, L.stats);
+}
+
+hipError_t launch_stage(const StageLaunch& L, hipStream_t s) {
+  if (L.n == 0) return hipSuccess;
+  const MeshView& m = L.m;
+  const bool f32 = L.fl.f32 != 0, mixed = L.mixed != 0, mlp = L.mlp != 0;
+#define FP_L(A, B)                                                                            \
+  if (m.n == A && m.ng == B) {                                                                \
+    if (mixed != f32) return hipErrorInvalidValue;                                            \
+    if (mlp) {                                                                                \
+      if (f32) run_stage<A, B, float, true, true>(L, s);                                      \
+      else run_stage<A, B, double, false, true>(L, s);                                        \
+    } else if (f32) run_stage<A, B, float, true, false>(L, s);                                \
+    else run_stage<A, B, double, false, false>(L, s);                                         \
+    return hipGetLastError();                                                                 \
+  }
+  FP_FOR_EACH_SHAPE(FP_L)
+#undef FP_L
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fp

@@ -23,7 +23,9 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_bind_workspace", "fp_set_fluid_state", "fp_push_particles", "fp_step",
            "fp_deposit_source", "fp_read_particles", "fp_get_stats", "fp_reset_stats",
            "fp_mlp_n_weights", "fp_mlp_features", "fp_newton_pairs", "fp_mlp_forward",
-           "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged"]
+           "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged",
+           "fp_set_timing", "fp_get_timing"]
+TIMING_CLASSES = ("sort", "stage", "finalize", "deposit_nearest", "deposit_shape")
 
 
 class FPError(RuntimeError):
@@ -82,6 +84,8 @@ def load():
     L.fp_mlp_train_epoch.argtypes = [P, P, P, P, C.POINTER(I64), P, P, P, I64, I32, C.c_float, P]
     L.fp_mlp_set_weights.argtypes = [P, P, D]
     L.fp_mlp_num_flagged.argtypes = [P, C.POINTER(I64)]
+    L.fp_set_timing.argtypes = [P, I32]
+    L.fp_get_timing.argtypes = [P, P]
     for name in EXPORTS:       # every documented entry point must resolve
         getattr(L, name)
     _lib = L
@@ -196,6 +200,15 @@ class FlexiPart:
         self._check(self.L.fp_get_stats(self.ctx, _ptr(s)), "fp_get_stats")
         return dict(newton_iters=int(s[0]), newton_calls=int(s[1]), crossings=int(s[2]), wall_hits=int(s[3]),
                     lost=int(s[4]), fallbacks=int(s[5]), sorts=int(s[6]))
+
+    def set_timing(self, enable=True):
+        self._check(self.L.fp_set_timing(self.ctx, int(bool(enable))), "fp_set_timing")
+
+    def timing(self):
+        """{class: (launches, total ms)} since the last call (synchronises)."""
+        out = np.zeros(2 * len(TIMING_CLASSES))
+        self._check(self.L.fp_get_timing(self.ctx, _ptr(out)), "fp_get_timing")
+        return {k: (int(out[2 * i]), float(out[2 * i + 1])) for i, k in enumerate(TIMING_CLASSES)}
 
     def reset_stats(self):
         self._check(self.L.fp_reset_stats(self.ctx), "fp_reset_stats")
