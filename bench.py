@@ -27,9 +27,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
-KERNEL_SOURCES = ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/kernels.hip",
+KERNEL_SOURCES = ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/stage.hip",
                   "paper_2211_05458_amd/csrc/fp_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_fp64_config2_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_elem_fp64_curved32_traffic.md")
 
 
 def stage_source_hash():
@@ -155,7 +155,7 @@ def main():
     K = args.steps
     value = r64["n_active"] * K / (r64["ms"] * 1e-3)
     stages = 3
-    n_launch, stage_ms = r64["timing"]["stage"]
+    n_launch, stage_ms = r64["timing"]["stage_elem"]
     sort_launch, sort_ms = r64["timing"]["sort"]
     avg_stage_ms = stage_ms / max(n_launch, 1)
     ps = r64["n_active"] * stages * K                       # particle-stages timed
@@ -163,8 +163,12 @@ def main():
     fl_ps = flops_per_particle_stage(n, ng, it_per_ps)
     ppe = r64["n_active"] / w.mesh.n_elem
     by_ps = bytes_per_particle_stage(n, ng, ppe)
-    per_launch_flops = fl_ps * r64["n_active"]
-    per_launch_bytes = by_ps * r64["n_active"]
+    # particles handled by the element-wise kernel per launch (the rest left
+    # their sorted element and go through the per-lane kernel)
+    per_launch_particles = (ps - r64["stats"]["stragglers"]) / max(n_launch, 1)
+    per_launch_flops = fl_ps * per_launch_particles
+    per_launch_bytes = by_ps * per_launch_particles
+    kern_ms = {k: (v[1] / v[0] if v[0] else 0.0) for k, v in r64["timing"].items()}
     achieved_tf = per_launch_flops / (avg_stage_ms * 1e-3) / 1e12
     achieved_gbs = per_launch_bytes / (avg_stage_ms * 1e-3) / 1e9
     traffic = read_traffic()
@@ -180,7 +184,7 @@ def main():
         extras["mixed_fp32"] = {
             "value": r32["n_active"] * K / (r32["ms"] * 1e-3),
             "ms_per_step": r32["ms"] / K,
-            "stage_ms": r32["timing"]["stage"][1] / max(r32["timing"]["stage"][0], 1),
+            "kernel_ms": {k: (v[1] / v[0] if v[0] else 0.0) for k, v in r32["timing"].items()},
             "pos_err_max_m": float(dx.max()), "pos_err_rms_m": float(np.sqrt((dx ** 2).mean())),
             "pos_err_max_h": float(dx.max() / w.mesh.h),
             "elem_mismatch_frac": float((r32["read"]["elem"] != r64["read"]["elem"]).mean()),
@@ -223,11 +227,12 @@ def main():
                    "elements": w.mesh.n_elem, "particles": w.n_particles, "N": w.N, "n_geo": w.mesh.n_geo},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "k_stage<6,5,double,false>", "avg_launch_ms": avg_stage_ms,
+                     "kernel": "k_stage_elem<6,5,double,false,false>", "avg_launch_ms": avg_stage_ms,
+                     "particles_per_launch": per_launch_particles,
                      "flops_per_particle_stage": fl_ps, "newton_it_per_particle_stage": it_per_ps,
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "algorithmic_GBs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS},
-        "sort_ms": sort_ms / max(sort_launch, 1),
+        "kernel_ms": kern_ms,
         "stats": r64["stats"],
         "cpu_baseline": cpu,
     }

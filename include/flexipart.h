@@ -139,17 +139,20 @@ int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* el
 
 /* Counters since the last reset: out[0] Newton iterations, out[1] Newton
  * solves, out[2] face crossings, out[3] wall hits, out[4] lost particles,
- * out[5] learned-guess fallbacks, out[6] sorts.  Synchronises. */
-int fp_get_stats(fp_ctx* ctx, int64_t* out7);
+ * out[5] learned-guess fallbacks, out[6] sorts, out[7] particle-stages taken
+ * by the per-lane kernel because they left their sorted element, out[8]
+ * particle-stages queued for face intersection.  Synchronises. */
+int fp_get_stats(fp_ctx* ctx, int64_t* out9);
 int fp_reset_stats(fp_ctx* ctx);
 
 /* ---- kernel timing (tracing) ---------------------------------------------
  * When enabled, HIP events on the context stream bracket every launch of the
  * step and source kernels.  fp_get_timing synchronises and writes, for each
- * class (0 sort, 1 RK stage, 2 final reference coordinates, 3 nearest-DOF
- * source, 4 shape-kernel source), out[2*k] = launches and out[2*k+1] = total
- * milliseconds since the last call; the counters are then cleared. */
-#define FP_TIMING_CLASSES 5
+ * class (0 sort, 1 element-wise stage kernel, 2 final reference coordinates,
+ * 3 nearest-DOF source, 4 shape-kernel source, 5 per-lane stage kernel,
+ * 6 tracking kernel), out[2*k] = launches and out[2*k+1] = total milliseconds
+ * since the last call; the counters are then cleared. */
+#define FP_TIMING_CLASSES 7
 int fp_set_timing(fp_ctx* ctx, int32_t enable);
 int fp_get_timing(fp_ctx* ctx, double* out /* [2*FP_TIMING_CLASSES] */);
 

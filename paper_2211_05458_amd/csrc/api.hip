@@ -173,22 +173,25 @@ std::vector<double> bernstein_vandermonde_inverse(int ng, const double* s) {
 }
 
 // record an event pair around a launch when timing is enabled
+// event pool for the optional kernel timing
+hipEvent_t take_event(fp_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// record an event pair around the launches in its scope when timing is enabled
 struct Timed {
   fp_ctx* c;
   int cls;
   hipEvent_t a = nullptr, b = nullptr;
-  hipEvent_t take() {
-    if (c->ev_used == c->ev_pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      c->ev_pool.push_back(e);
-    }
-    return c->ev_pool[c->ev_used++];
-  }
   Timed(fp_ctx* c_, int cls_) : c(c_), cls(cls_) {
     if (!c->timing) return;
-    a = take();
-    b = take();
+    a = take_event(c);
+    b = take_event(c);
     if (a) hipEventRecord(a, c->stream);
   }
   ~Timed() {
@@ -227,7 +230,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.bstart = take(c->bstart.size() * 4);
   L.blist = take(std::max<size_t>(1, c->blist.size()) * 4);
   L.mlp_flag = take(E);
-  L.stats = take(16 * 8);
+  L.stats = take(16 * kStatSlots * 8);
   L.sort_count = take((E + 1) * 4);
   L.sort_start = take((E + 1) * 4);
   L.sort_rank = take((size_t)std::max<int64_t>(cap, 1) * 4);
@@ -438,7 +441,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   HIPCHK(c, hipMemcpyAsync(b + L.bstart, c->bstart.data(), c->bstart.size() * 4, hipMemcpyHostToDevice, s));
   if (!c->blist.empty())
     HIPCHK(c, hipMemcpyAsync(b + L.blist, c->blist.data(), c->blist.size() * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemsetAsync(b + L.stats, 0, 16 * 8, s));
+  HIPCHK(c, hipMemsetAsync(b + L.stats, 0, 16 * kStatSlots * 8, s));
   HIPCHK(c, hipMemsetAsync(b + L.mlp_flag, 0, E, s));
   MeshView& m = c->mv;
   m = MeshView{};
@@ -607,8 +610,14 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
       Lc.trk_p = c->trk_p;
       Lc.trk_x = c->trk_x;
       Lc.stats = c->stats;
-      Timed tm(c, 1);
+      if (c->timing)
+        for (int k = 0; k < 6; ++k) Lc.ev[k] = take_event(c);
       HIPCHK(c, launch_stage(Lc, s));
+      if (c->timing) {
+        if (Lc.tasks && Lc.ev[0] && Lc.ev[1]) c->recs.push_back({1, Lc.ev[0], Lc.ev[1]});
+        if (Lc.ev[2] && Lc.ev[3]) c->recs.push_back({5, Lc.ev[2], Lc.ev[3]});
+        if (Lc.ev[4] && Lc.ev[5]) c->recs.push_back({6, Lc.ev[4], Lc.ev[5]});
+      }
     }
     c->steps_done++;
   }
@@ -696,18 +705,23 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
 int fp_get_stats(fp_ctx* c, int64_t* out) {
   if (!c || !out) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_get_stats: no workspace");
-  unsigned long long h[ST_N];
-  HIPCHK(c, hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  std::vector<unsigned long long> slots((size_t)ST_N * kStatSlots);
+  HIPCHK(c, hipMemcpyAsync(slots.data(), c->stats, slots.size() * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  unsigned long long h[ST_N] = {0};
+  for (int k = 0; k < ST_N; ++k)
+    for (int j = 0; j < kStatSlots; ++j) h[k] += slots[(size_t)k * kStatSlots + j];
   for (int i = 0; i < 6; ++i) out[i] = (int64_t)h[i];
   out[6] = c->sorts;
+  out[7] = (int64_t)h[ST_STRAG];
+  out[8] = (int64_t)h[ST_TRACKQ];
   return FP_OK;
 }
 
 int fp_reset_stats(fp_ctx* c) {
   if (!c) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_reset_stats: no workspace");
-  HIPCHK(c, hipMemsetAsync(c->stats, 0, 16 * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->stats, 0, 16 * kStatSlots * 8, c->stream));
   c->sorts = 0;
   return FP_OK;
 }

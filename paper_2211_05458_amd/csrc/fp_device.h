@@ -563,7 +563,9 @@ __device__ inline void bezier_eval(const double* __restrict__ cp, double u, doub
   bern<D>(0.5 * (u + 1.0), Bu, dBu);
   bern<D>(0.5 * (v + 1.0), Bv, dBv);
   for (int q = 0; q < 3; ++q) { p[q] = 0.0; if (pu) { pu[q] = 0.0; pv[q] = 0.0; } }
+#pragma unroll 1
   for (int k = 0; k < NG; ++k)
+#pragma unroll 1
     for (int mm = 0; mm < NG; ++mm) {
       const double* P = cp + (k * NG + mm) * 3;
       double w = Bu[mm] * Bv[k];
@@ -607,16 +609,54 @@ __device__ inline void restrict1(double* c, int s, double a, double b) {
   }
 }
 
-// q[m][k][2] with m along u, k along v; restrict direction dir to [a, b]
-template <int NG>
+// q[m][k][C] with m along u, k along v; restrict direction dir to [a, b]
+template <int NG, int C>
 __device__ inline void patch_restrict(double* q, int dir, double a, double b) {
+#pragma unroll
   for (int k = 0; k < NG; ++k)
-    for (int co = 0; co < 2; ++co) {
-      if (dir == 0) restrict1<NG>(q + k * 2 + co, NG * 2, a, b);   // along m
-      else restrict1<NG>(q + k * NG * 2 + co, 2, a, b);            // along k
+#pragma unroll
+    for (int co = 0; co < C; ++co) {
+      if (dir == 0) restrict1<NG>(q + k * C + co, NG * C, a, b);   // along m
+      else restrict1<NG>(q + k * NG * C + co, C, a, b);            // along k
     }
 }
 
+// t-extent of H intersected with {y >= c} (ge) or {y <= c}, where H is the
+// convex hull of the columns t_i = i/(NP-1), y in [lo_i, hi_i].  Only the
+// column maxima (ge) or minima bound that intersection; its extent is spanned
+// by the columns inside the half-plane and by the crossings of y = c on the
+// segments between a column inside and a column outside (every such crossing
+// lies in H, and the hull edge that leaves the half-plane is one of them).
+template <int NP>
+__device__ __forceinline__ bool half_extent(const double* lo, const double* hi, double c, bool ge, double& a,
+                                            double& b) {
+  const double* y = ge ? hi : lo;
+  const double step = 1.0 / (NP - 1);
+  double tmin = 1e300, tmax = -1e300;
+  bool in[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    in[i] = ge ? (y[i] >= c) : (y[i] <= c);
+    if (in[i]) { tmin = fmin(tmin, i * step); tmax = fmax(tmax, i * step); }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = i + 1; j < NP; ++j)
+      if (in[i] != in[j]) {
+        double t = (i + (j - i) * ((c - y[i]) / (y[j] - y[i]))) * step;
+        tmin = fmin(tmin, t);
+        tmax = fmax(tmax, t);
+      }
+  a = tmin;
+  b = tmax;
+  return tmin <= tmax;
+}
+
+// Clip direction dir (0: u, 1: v) of the projected patch q[m][k][2] (signed
+// distances to the two planes that contain the ray): Bezier clipping against
+// the line through the origin that runs along the other parameter direction.
+// The convex-hull property of the Bernstein form keeps every root.
 template <int NG>
 __device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) {
   constexpr int N = NG - 1;
@@ -644,54 +684,59 @@ __device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) 
     if (ll == 0.0) { L0 = 1.0; L1 = 0.0; ll = 1.0; }
   }
   double nx = -L1 / ll, ny = L0 / ll;
-  double tt[2 * NG], dd[2 * NG];
+  double dlo[NG], dhi[NG];
+#pragma unroll
   for (int i = 0; i < NG; ++i) {
     double mn = 1e300, mx = -1e300;
+#pragma unroll
     for (int k = 0; k < NG; ++k) {
       double dist = (dir == 0) ? nx * QQ(i, k, 0) + ny * QQ(i, k, 1) : nx * QQ(k, i, 0) + ny * QQ(k, i, 1);
       mn = fmin(mn, dist);
       mx = fmax(mx, dist);
     }
-    tt[2 * i] = tt[2 * i + 1] = (double)i / N;
-    dd[2 * i] = mn;
-    dd[2 * i + 1] = mx;
+    dlo[i] = mn;
+    dhi[i] = mx;
   }
 #undef QQ
-  double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < 2 * NG; ++i) {
-    if (dd[i] == 0.0) { lo = fmin(lo, tt[i]); hi = fmax(hi, tt[i]); }
-    for (int j = i + 1; j < 2 * NG; ++j)
-      if ((dd[i] < 0.0 && dd[j] > 0.0) || (dd[i] > 0.0 && dd[j] < 0.0)) {
-        double t = tt[i] + (tt[j] - tt[i]) * (dd[i] / (dd[i] - dd[j]));
-        lo = fmin(lo, t);
-        hi = fmax(hi, t);
-      }
-  }
+  double a1, b1, a2, b2;
+  if (!half_extent<NG>(dlo, dhi, 0.0, true, a1, b1)) return false;
+  if (!half_extent<NG>(dlo, dhi, 0.0, false, a2, b2)) return false;
+  double lo = fmax(a1, a2), hi = fmin(b1, b2);
   if (lo > hi) return false;
   a = fmax(0.0, lo - kClipPad);
   b = fmin(1.0, hi + kClipPad);
   return true;
 }
 
-// All intersections of the line x0 + alpha t with a curved Bezier face: the
-// face is projected onto two planes containing the line (Sec. 3.2.4) and the
-// zero of the 2-D patch is isolated by Bezier clipping; converged boxes are
-// polished by 2-D Newton on the projected patch.  The stack holds parameter
-// intervals only; a popped interval is restricted again from the full patch.
+// Intersections of the line x0 + alpha t (|t| = 1) with a curved Bezier face,
+// keeping those with displacement in [amin, amax]: the face is projected onto
+// two planes containing the line (Sec. 3.2.4) and the zero of the 2-D patch is
+// isolated by Bezier clipping, alternating u and v and splitting where a clip
+// removes less than 20 %.  Faces whose control points all lie outside the
+// displacement band are rejected at once (convex hull).  Boxes narrower than
+// 1e-7 are finished by 2-D Newton on the projected patch (quadratic from there).
 template <int NG>
-__device__ int curved_hit(const double* __restrict__ cp, const double* x0, const double* t, double* al, double* uv,
-                          int max_roots) {
+__device__ int curved_hit(const double* __restrict__ cp, const double* x0, const double* t, double amin, double amax,
+                          double* al, double* uv, int max_roots) {
   constexpr int D = NG - 1;
+  constexpr double kBoxTol = 1e-7;
   double n1[3], n2[3];
   ray_planes(t, n1, n2);
   double q0[NG * NG * 2];
+  double fa = 1e300, fb = -1e300;
+#pragma unroll
   for (int k = 0; k < NG; ++k)
+#pragma unroll
     for (int mm = 0; mm < NG; ++mm) {
       const double* P = cp + (k * NG + mm) * 3;
       double r[3] = {P[0] - x0[0], P[1] - x0[1], P[2] - x0[2]};
       q0[(mm * NG + k) * 2 + 0] = dot3(r, n1);
       q0[(mm * NG + k) * 2 + 1] = dot3(r, n2);
+      double ar = dot3(r, t);
+      fa = fmin(fa, ar);
+      fb = fmax(fb, ar);
     }
+  if (fb < amin || fa > amax) return 0;
   double stk[kClipStack][4];
   int sp = 1, nroots = 0, budget = kClipSteps;
   stk[0][0] = 0.0; stk[0][1] = 1.0; stk[0][2] = 0.0; stk[0][3] = 1.0;
@@ -699,36 +744,40 @@ __device__ int curved_hit(const double* __restrict__ cp, const double* x0, const
   while (sp > 0 && budget > 0) {
     --sp;
     double u0 = stk[sp][0], u1 = stk[sp][1], v0 = stk[sp][2], v1 = stk[sp][3];
+#pragma unroll
     for (int i = 0; i < NG * NG * 2; ++i) q[i] = q0[i];
-    if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG>(q, 0, u0, u1);
-    if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG>(q, 1, v0, v1);
+    if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG, 2>(q, 0, u0, u1);
+    if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG, 2>(q, 1, v0, v1);
     for (;;) {
       if (--budget < 0) break;
       double a, b;
       if (!clip_dir<NG>(q, 0, a, b)) break;
-      patch_restrict<NG>(q, 0, a, b);
+      patch_restrict<NG, 2>(q, 0, a, b);
       double w = u1 - u0;
       double nu0 = u0 + a * w, nu1 = u0 + b * w;
       u0 = nu0; u1 = nu1;
       double ru = b - a;
       if (!clip_dir<NG>(q, 1, a, b)) break;
-      patch_restrict<NG>(q, 1, a, b);
+      patch_restrict<NG, 2>(q, 1, a, b);
       w = v1 - v0;
       double nv0 = v0 + a * w, nv1 = v0 + b * w;
       v0 = nv0; v1 = nv1;
       double rv = b - a;
       double wu = u1 - u0, wv = v1 - v0;
-      bool conv = (wu <= kClipTol && wv <= kClipTol);
-      bool su = (ru > 0.8 && wu > kClipTol), sv = (rv > 0.8 && wv > kClipTol);
+      bool conv = (wu <= kBoxTol && wv <= kBoxTol);
+      bool su = (ru > 0.8 && wu > kBoxTol), sv = (rv > 0.8 && wv > kBoxTol);
       if (!conv && (su || sv) && sp + 2 > kClipStack) conv = true;
       if (conv) {
         double s = 0.5 * (u0 + u1), tt = 0.5 * (v0 + v1);
+#pragma unroll 1
         for (int it = 0; it < 3; ++it) {
           double Bs[NG], Bt[NG], dBs[NG], dBt[NG];
           bern<D>(s, Bs, dBs);
           bern<D>(tt, Bt, dBt);
           double G0 = 0, G1 = 0, Gs0 = 0, Gs1 = 0, Gt0 = 0, Gt1 = 0;
+#pragma unroll
           for (int mm = 0; mm < NG; ++mm)
+#pragma unroll
             for (int k = 0; k < NG; ++k) {
               double qx = q0[(mm * NG + k) * 2], qy = q0[(mm * NG + k) * 2 + 1];
               G0 += qx * Bs[mm] * Bt[k]; G1 += qy * Bs[mm] * Bt[k];
@@ -775,10 +824,10 @@ __device__ int curved_hit(const double* __restrict__ cp, const double* x0, const
 
 template <int NG>
 __device__ inline int face_roots(const MeshView& m, int fid, const FaceRec& F, const double* x0, const double* t,
-                                 double* al, double* uv) {
+                                 double amin, double amax, double* al, double* uv) {
   if (F.type == FACE_PLANAR) return planar_hit(F, x0, t, al, uv);
   if (F.type == FACE_BILINEAR) return bilinear_hit(F, x0, t, al, uv);
-  return curved_hit<NG>(m.cp + (size_t)fid * (NG * NG * 3), x0, t, al, uv, kMaxRoots);
+  return curved_hit<NG>(m.cp + (size_t)fid * (NG * NG * 3), x0, t, amin, amax, al, uv, kMaxRoots);
 }
 
 // Physical-space tracking of the straight stage segment xs -> xe (Sec. 3.2.3):
@@ -806,7 +855,9 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       const FaceRec& F = m.faces[fid];
       if (!bbox_hit(F, xs, xe)) continue;
       double al[kMaxRoots], uv[2 * kMaxRoots];
-      int nr = face_roots<NG>(m, fid, F, xs, t, al, uv);
+      // only roots with displacement in (eps, L] matter: clip to a padded band
+      double pad = 1e-9 * F.diam;
+      int nr = face_roots<NG>(m, fid, F, xs, t, eps - pad, L + pad, al, uv);
       for (int r = 0; r < nr; ++r) {
         if (!(al[r] > eps && al[r] <= L)) continue;
         if (fabs(uv[2 * r]) > 1.0 + kUVEps || fabs(uv[2 * r + 1]) > 1.0 + kUVEps) continue;
@@ -873,11 +924,32 @@ __device__ __forceinline__ int wave_push(int32_t* counter, bool pred) {
   return pred ? base + (int)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
 }
 
-// wave-level sum then one atomic per wave
+// wave-level sum then one atomic per wave into counter slot blockIdx % 64
+// (stats + counter * kStatSlots is the base of a counter's slots)
 __device__ __forceinline__ void wave_add(unsigned long long* dst, long long v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(dst, (unsigned long long)v);
+  if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(dst + (blockIdx.x & (kStatSlots - 1)), (unsigned long long)v);
+}
+
+// workgroup-aggregated queue append (blockDim.x == 256): one atomic per
+// workgroup; returns each predicated thread's slot (-1 otherwise).  Must be
+// reached by every thread of the workgroup.
+__device__ __forceinline__ int block_push(int32_t* counter, bool pred, int* sh /* [5] shared */) {
+  unsigned long long mask = __ballot(pred);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[wid] = (int)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = sh[0] + sh[1] + sh[2] + sh[3];
+    sh[4] = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  int base = sh[4];
+  for (int w = 0; w < wid; ++w) base += sh[w];
+  int r = pred ? base + (int)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
+  __syncthreads();
+  return r;
 }
 
 }  // namespace fp

@@ -26,6 +26,7 @@ struct StageLaunch {
   int32_t* trk_p;           // [cap]
   double* trk_x;            // [3][cap]
   unsigned long long* stats;
+  hipEvent_t ev[6];         // optional (start, end) pairs around the elem, lane and track kernels
 };
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
 hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int32_t* tcount, int32_t* tstart,

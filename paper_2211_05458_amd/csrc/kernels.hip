@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64
     else if (!inside_ref(xi)) { P.status[p] = LOST_TRACK; nlost++; }
     for (int k = 0; k < 3; ++k) P.xi[k * cap + p] = xi[k];
   }
-  wave_add(stats + ST_LOST, nlost);
+  wave_add(stats + ST_LOST * kStatSlots, nlost);
 }
 
 // ---------------------------------------------------------------------------

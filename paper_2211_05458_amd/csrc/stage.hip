@@ -131,19 +131,22 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
       }
     }
   }
-  int s1 = wave_push(q.counters + 0, strag);
+  __shared__ int sh[5];
+  int s1 = block_push(q.counters + 0, strag, sh);
   if (strag) q.strag[s1] = (int32_t)p;
-  int s2 = wave_push(q.counters + 1, trk);
+  wave_add(stats + ST_STRAG * kStatSlots, strag ? 1 : 0);
+  wave_add(stats + ST_TRACKQ * kStatSlots, trk ? 1 : 0);
+  int s2 = block_push(q.counters + 1, trk, sh);
   if (trk) {
     q.trk_p[s2] = (int32_t)p;
     q.trk_x[s2] = xs0;
     q.trk_x[cap + s2] = xs1;
     q.trk_x[2 * cap + s2] = xs2;
   }
-  wave_add(stats + ST_NEWTON_IT, it_sum);
-  wave_add(stats + ST_NEWTON_CALLS, calls);
-  wave_add(stats + ST_FALLBACK, fb);
-  wave_add(stats + ST_LOST, nlost);
+  wave_add(stats + ST_NEWTON_IT * kStatSlots, it_sum);
+  wave_add(stats + ST_NEWTON_CALLS * kStatSlots, calls);
+  wave_add(stats + ST_FALLBACK * kStatSlots, fb);
+  wave_add(stats + ST_LOST * kStatSlots, nlost);
 }
 
 // per-lane stage for the straggler queue (list != null) or all n particles;
@@ -202,10 +205,10 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
       q.trk_x[2 * cap + s] = xs2;
     }
   }
-  wave_add(stats + ST_NEWTON_IT, it_sum);
-  wave_add(stats + ST_NEWTON_CALLS, calls);
-  wave_add(stats + ST_FALLBACK, fb);
-  wave_add(stats + ST_LOST, nlost);
+  wave_add(stats + ST_NEWTON_IT * kStatSlots, it_sum);
+  wave_add(stats + ST_NEWTON_CALLS * kStatSlots, calls);
+  wave_add(stats + ST_FALLBACK * kStatSlots, fb);
+  wave_add(stats + ST_LOST * kStatSlots, nlost);
 }
 
 template <int NG>
@@ -239,8 +242,8 @@ __global__ __launch_bounds__(256) void k_track(MeshView m, Particles P, Queues q
       if (st != ACTIVE) P.status[p] = st;
     }
   }
-  wave_add(stats + ST_CROSS, ncross);
-  wave_add(stats + ST_HITS, nhits);
+  wave_add(stats + ST_CROSS * kStatSlots, ncross);
+  wave_add(stats + ST_HITS * kStatSlots, nhits);
 }
 
 __global__ void k_reset_counters(int32_t* c) {
@@ -293,20 +296,29 @@ static void run_stage(const StageLaunch& L, hipStream_t s) {
   Queues q{L.counters, L.strag, L.trk_p, L.trk_x};
   k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   int64_t lane_blocks;
+  auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
   if (L.tasks) {
     int64_t waves = (int64_t)m.E + L.P.cap / 64 + 1;
+    rec(0);
     k_stage_elem<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(
         m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
+    rec(1);
     lane_blocks = std::min<int64_t>((L.n + 255) / 256, 256);
+    rec(2);
     k_stage_lane<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)std::max<int64_t>(lane_blocks, 1)), 256, 0, s>>>(
         m, L.strag, L.n, L.P, L.fl, L.sp, q, L.stats);
+    rec(3);
   } else {
     lane_blocks = (L.n + 255) / 256;
+    rec(2);
     k_stage_lane<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)std::max<int64_t>(lane_blocks, 1)), 256, 0, s>>>(
         m, nullptr, L.n, L.P, L.fl, L.sp, q, L.stats);
+    rec(3);
   }
   int64_t trk_blocks = std::max<int64_t>(1, std::min<int64_t>((L.n + 255) / 256, 1024));
+  rec(4);
   k_track<NG><<<dim3((unsigned)trk_blocks), 256, 0, s>>>(m, L.P, q, L.sp, L.stats);
+  rec(5);
 }
 
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s) {

@@ -25,7 +25,7 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_mlp_n_weights", "fp_mlp_features", "fp_newton_pairs", "fp_mlp_forward",
            "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged",
            "fp_set_timing", "fp_get_timing"]
-TIMING_CLASSES = ("sort", "stage", "finalize", "deposit_nearest", "deposit_shape")
+TIMING_CLASSES = ("sort", "stage_elem", "finalize", "deposit_nearest", "deposit_shape", "stage_lane", "track")
 
 
 class FPError(RuntimeError):
@@ -196,10 +196,11 @@ class FlexiPart:
         return out
 
     def stats(self):
-        s = np.zeros(7, np.int64)
+        s = np.zeros(9, np.int64)
         self._check(self.L.fp_get_stats(self.ctx, _ptr(s)), "fp_get_stats")
         return dict(newton_iters=int(s[0]), newton_calls=int(s[1]), crossings=int(s[2]), wall_hits=int(s[3]),
-                    lost=int(s[4]), fallbacks=int(s[5]), sorts=int(s[6]))
+                    lost=int(s[4]), fallbacks=int(s[5]), sorts=int(s[6]), stragglers=int(s[7]),
+                    track_queue=int(s[8]))
 
     def set_timing(self, enable=True):
         self._check(self.L.fp_set_timing(self.ctx, int(bool(enable))), "fp_set_timing")
