@@ -156,16 +156,22 @@ int fp_reset_stats(fp_ctx* ctx);
 int fp_set_timing(fp_ctx* ctx, int32_t enable);
 int fp_get_timing(fp_ctx* ctx, double* out /* [2*FP_TIMING_CLASSES] */);
 
-/* ---- learned Newton initial guess (27-64-64-64-3 tanh MLP, FP32) --------- */
-/* Weight layout: W1[64][27] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]. */
+/* ---- learned Newton initial guess (84-64-64-64-3 tanh MLP, FP32) --------- */
+/* Extension of the initial-guess approaches of Sec. 3.2.1 (not in the paper).
+ * Weight layout: W1[64][84] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]. */
 int64_t fp_mlp_n_weights(void);
-/* Features of n (element, point) pairs: 24 corner offsets and the point
- * offset from the corner mean, scaled by the mean corner-edge length
- * (device in/out: elem[n] i32, x[n][3] f64 -> feat[n][27] f32). */
+/* Features of n (element, point) pairs: the 8 corners relative to their mean
+ * (24), the deviation of the element map from the trilinear corner map at the
+ * 19 non-corner points of the {-1,0,1}^3 lattice (57), and the point (3); all
+ * divided by the mean corner-edge length (device in/out: elem[n] i32,
+ * x[n][3] f64 -> feat[n][84] f32). */
 int fp_mlp_features(fp_ctx* ctx, int64_t n, const int32_t* elem_dev, const double* x_dev, float* feat_dev);
 /* Training pairs from the current particles: features and the converged
- * Newton xi (device outputs feat[n][27], xi[n][3]); n = active particle count. */
-int fp_newton_pairs(fp_ctx* ctx, int64_t* n, float* feat_dev, float* xi_dev, int64_t capacity);
+ * Newton xi (device outputs feat[n][84], xi[n][3]; ids[n], may be NULL,
+ * receives each row's particle index in push order).  Rows are in no
+ * particular order; *n = number of particles whose Newton solve converged
+ * inside their element.  capacity (rows) must be >= the particle count. */
+int fp_newton_pairs(fp_ctx* ctx, int64_t* n, float* feat_dev, float* xi_dev, int32_t* ids_dev, int64_t capacity);
 /* Forward pass (device): out[n][3]. */
 int fp_mlp_forward(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in_dev, float* out_dev);
 /* Mean squared error loss and its gradient over n rows (device; grad[nw]). */

@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "oracle.c")
 
 ACTIVE, OPEN_EXIT, LOST_NEWTON, LOST_TRACK, MAX_CROSS, REJECTED = range(6)
 FACE_PLANAR, FACE_BILINEAR, FACE_CURVED = range(3)
-MLP_NIN, MLP_H, MLP_NOUT = 27, 64, 3
+MLP_NIN, MLP_H, MLP_NOUT = 84, 64, 3
 
 
 def build(force=True):

@@ -1461,16 +1461,19 @@ int or_deposit(or_ctx* c, double* S, int kind, double R, const double* period, i
 }
 
 /* ======================================================================== */
-/* learned initial guess: 27 -> 64 -> 64 -> 64 -> 3 tanh MLP                  */
+/* learned initial guess: 84 -> 64 -> 64 -> 64 -> 3 tanh MLP                  */
 /* ======================================================================== */
-/* weight layout: W1[64][27] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3] */
+/* weight layout: W1[64][84] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3] */
 int64_t or_mlp_n_weights(void) {
   return (int64_t)OR_MLP_H * OR_MLP_NIN + OR_MLP_H + 2 * (OR_MLP_H * OR_MLP_H + OR_MLP_H) +
          OR_MLP_NOUT * OR_MLP_H + OR_MLP_NOUT;
 }
 
-/* Inputs: the 8 element corners and the point, relative to the corner mean
- * and scaled by the mean corner-edge length. */
+/* Inputs (84): the 8 element corners relative to the corner mean (24); the
+ * deviation of the element map from the trilinear map of its corners at the 19
+ * other points of the {-1,0,1}^3 lattice (57), which carries the curvature; the
+ * point relative to the corner mean (3).  All lengths are divided by the mean
+ * corner-edge length. */
 void or_mlp_features(const or_ctx* c, int e, const double* x, double* feat) {
   int ng = c->ng, G = c->n_geo;
   const double* P = c->X + (size_t)e * ng * ng * ng * 3;
@@ -1493,7 +1496,26 @@ void or_mlp_features(const or_ctx* c, int e, const double* x, double* feat) {
   double h = hs / 12.0;
   for (int a = 0; a < 8; ++a)
     for (int r = 0; r < 3; ++r) feat[a * 3 + r] = (cor[a][r] - ctr[r]) / h;
-  for (int r = 0; r < 3; ++r) feat[24 + r] = (x[r] - ctr[r]) / h;
+  int f = 24;
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) {
+        if (i != 1 && j != 1 && k != 1) continue;     /* corners */
+        double xi[3] = {(double)(i - 1), (double)(j - 1), (double)(k - 1)};
+        double pm[3];
+        or_map(c, e, xi, pm, NULL);
+        double tri[3] = {0, 0, 0};
+        for (int kk = 0; kk < 2; ++kk)
+          for (int jj = 0; jj < 2; ++jj)
+            for (int ii = 0; ii < 2; ++ii) {
+              double wgt = 0.125 * (1.0 + (ii ? 1 : -1) * xi[0]) * (1.0 + (jj ? 1 : -1) * xi[1]) *
+                           (1.0 + (kk ? 1 : -1) * xi[2]);
+              for (int r = 0; r < 3; ++r) tri[r] += wgt * cor[(kk * 2 + jj) * 2 + ii][r];
+            }
+        for (int r = 0; r < 3; ++r) feat[f + r] = (pm[r] - tri[r]) / h;
+        f += 3;
+      }
+  for (int r = 0; r < 3; ++r) feat[81 + r] = (x[r] - ctr[r]) / h;
 }
 
 static double* mlp_forward1(const double* w, const double* in, double* out) {

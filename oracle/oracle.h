@@ -82,11 +82,11 @@ int  or_deposit(or_ctx*, double* S /*[E][4][(N+1)^3]*/, int kind, double radius,
                 const double* period, int drag);
 
 /* learned initial guess --------------------------------------------------- */
-#define OR_MLP_NIN 27
+#define OR_MLP_NIN 84
 #define OR_MLP_H 64
 #define OR_MLP_NOUT 3
 int64_t or_mlp_n_weights(void);
-void or_mlp_features(const or_ctx*, int e, const double* x, double* feat /*27*/);
+void or_mlp_features(const or_ctx*, int e, const double* x, double* feat /*84*/);
 void or_mlp_forward(const double* w, int64_t n, const double* in, double* out);
 double or_mlp_loss_grad(const double* w, int64_t n, const double* in, const double* target,
                         double* grad);

@@ -748,7 +748,7 @@ int fp_get_timing(fp_ctx* c, double* out) {
 }
 
 // ---- learned guess --------------------------------------------------------
-int64_t fp_mlp_n_weights(void) { return 64 * 27 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3; }
+int64_t fp_mlp_n_weights(void) { return kMlpWeights; }
 
 int fp_mlp_features(fp_ctx* c, int64_t n, const int32_t* elem, const double* x, float* feat) {
   if (!c || n < 0 || (n > 0 && (!elem || !x || !feat))) return FP_EINVAL;
@@ -757,12 +757,12 @@ int fp_mlp_features(fp_ctx* c, int64_t n, const int32_t* elem, const double* x, 
   return FP_OK;
 }
 
-int fp_newton_pairs(fp_ctx* c, int64_t* n_out, float* feat, float* xi, int64_t capacity) {
+int fp_newton_pairs(fp_ctx* c, int64_t* n_out, float* feat, float* xi, int32_t* ids, int64_t capacity) {
   if (!c || !n_out || !feat || !xi) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_newton_pairs: no workspace");
   if (capacity < c->np) return fail(c, FP_EINVAL, "fp_newton_pairs: capacity below particle count");
   HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 4, c->stream));
-  HIPCHK(c, launch_newton_pairs(c->mv, c->P[c->cur], c->np, feat, xi, c->scratch_i32, c->stream));
+  HIPCHK(c, launch_newton_pairs(c->mv, c->P[c->cur], c->np, feat, xi, ids, c->scratch_i32, c->stream));
   int32_t cnt = 0;
   HIPCHK(c, hipMemcpyAsync(&cnt, c->scratch_i32, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

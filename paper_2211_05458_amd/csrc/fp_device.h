@@ -248,6 +248,10 @@ __device__ __forceinline__ bool inside_ref(const double* xi) {
 // ---------------------------------------------------------------------------
 // learned guess: features and forward pass (FP32)
 // ---------------------------------------------------------------------------
+// Learned-guess inputs (84): corners relative to their mean (24), deviation of
+// the element map from the trilinear map of the corners at the 19 non-corner
+// points of the {-1,0,1}^3 lattice (57; zero for straight elements), and the
+// point (3); lengths divided by the mean corner-edge length.
 template <int NG>
 __device__ void mlp_features(const MeshView& m, int e, const double* x, float* feat) {
   const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
@@ -274,15 +278,35 @@ __device__ void mlp_features(const MeshView& m, int e, const double* x, float* f
 #pragma unroll
   for (int a = 0; a < 8; ++a)
     for (int r = 0; r < 3; ++r) feat[a * 3 + r] = (float)((cor[a][r] - ctr[r]) * ih);
-  for (int r = 0; r < 3; ++r) feat[24 + r] = (float)((x[r] - ctr[r]) * ih);
+  int f = 24;
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) {
+        if (i != 1 && j != 1 && k != 1) continue;
+        if (G % 2 != 0) {
+          feat[f] = feat[f + 1] = feat[f + 2] = 0.0f;   // degree-1 geometry is trilinear
+        } else {
+          const double* Q = P + (((k * G / 2) * NG + j * G / 2) * NG + i * G / 2) * 3;
+          double s0 = i - 1.0, s1 = j - 1.0, s2 = k - 1.0;
+          for (int r = 0; r < 3; ++r) {
+            double tri = 0.0;
+            for (int c = 0; c < 8; ++c)
+              tri += 0.125 * (1.0 + ((c & 1) ? 1 : -1) * s0) * (1.0 + (((c >> 1) & 1) ? 1 : -1) * s1) *
+                     (1.0 + ((c >> 2) ? 1 : -1) * s2) * cor[c][r];
+            feat[f + r] = (float)((Q[r] - tri) * ih);
+          }
+        }
+        f += 3;
+      }
+  for (int r = 0; r < 3; ++r) feat[81 + r] = (float)((x[r] - ctr[r]) * ih);
 }
 
 __device__ __forceinline__ float fast_tanh(float s) { return tanhf(s); }
 
-// 27-64-64-64-3 forward for one row; weights read through the scalar path
+// 84-64-64-64-3 forward for one row; weights read through the scalar path
 // (uniform addresses).
 __device__ inline void mlp_forward_row(const float* __restrict__ w, const float* in, float* out) {
-  constexpr int H = 64, NI = 27;
+  constexpr int H = 64, NI = kMlpIn;
   const float* W1 = w;
   const float* b1 = W1 + H * NI;
   const float* W2 = b1 + H;
@@ -328,7 +352,7 @@ __device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__
                             const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks) {
   double g[3];
   if (MLP && m.mlp_flag[e]) {
-    float feat[27], o[3];
+    float feat[kMlpIn], o[3];
     mlp_features<NG>(m, e, x, feat);
     mlp_forward_row(m.mlp_w, feat, o);
     g[0] = o[0]; g[1] = o[1]; g[2] = o[2];

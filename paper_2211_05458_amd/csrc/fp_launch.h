@@ -48,7 +48,7 @@ hipError_t launch_elem_start(const Particles& P, int64_t n, int E, int32_t* elem
 hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem, const double* x, float* feat,
                                hipStream_t s);
 hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
-                               int32_t* count, hipStream_t s);
+                               int32_t* ids, int32_t* count, hipStream_t s);
 hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s);
 hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,
                                 const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s);

@@ -1,14 +1,14 @@
 // Learned Newton initial guess: features, training pairs from Newton, a
-// 27-64-64-64-3 tanh MLP (forward, backward, Adam) in FP32, and the flags of
+// 84-64-64-64-3 tanh MLP (forward, backward, Adam) in FP32, and the flags of
 // strongly curved elements on which the guess is used.
 #include "fp_device.h"
 #include "fp_launch.h"
 
 namespace fp {
 
-constexpr int H = 64, NI = 27, NO = 3;
+constexpr int H = 64, NI = kMlpIn, NO = 3;
 constexpr int NW = H * NI + H + 2 * (H * H + H) + NO * H + NO;
-constexpr int ROW = NI + 3 * H + 3 * H + NO;   // per-row activations and deltas
+constexpr int ROW = kMlpRow;   // per-row activations and deltas
 
 template <int NG>
 __global__ void k_mlp_features(MeshView m, int64_t n, const int32_t* __restrict__ elem, const double* __restrict__ x,
@@ -16,13 +16,14 @@ __global__ void k_mlp_features(MeshView m, int64_t n, const int32_t* __restrict_
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   double xx[3] = {x[r * 3], x[r * 3 + 1], x[r * 3 + 2]};
-  float f[27];
+  float f[NI];
   mlp_features<NG>(m, elem[r], xx, f);
-  for (int i = 0; i < 27; ++i) feat[r * 27 + i] = f[i];
+  for (int i = 0; i < NI; ++i) feat[r * NI + i] = f[i];
 }
 
 template <int NN, int NG>
-__global__ void k_newton_pairs(MeshView m, Particles P, int64_t n, float* feat, float* xo, int32_t* count) {
+__global__ void k_newton_pairs(MeshView m, Particles P, int64_t n, float* feat, float* xo, int32_t* ids,
+                               int32_t* count) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n || P.status[p] != ACTIVE) return;
   const int64_t cap = P.cap;
@@ -32,10 +33,11 @@ __global__ void k_newton_pairs(MeshView m, Particles P, int64_t n, float* feat, 
   int it = 0, calls = 0, fb = 0;
   if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb) || !inside_ref(xi)) return;
   int q = atomicAdd(count, 1);
-  float f[27];
+  float f[NI];
   mlp_features<NG>(m, e, x, f);
-  for (int i = 0; i < 27; ++i) feat[(int64_t)q * 27 + i] = f[i];
+  for (int i = 0; i < NI; ++i) feat[(int64_t)q * NI + i] = f[i];
   for (int k = 0; k < 3; ++k) xo[(int64_t)q * 3 + k] = (float)xi[k];
+  if (ids) ids[q] = P.id[p];
 }
 
 // max deviation of the geometry nodes from the trilinear map of the corners
@@ -73,8 +75,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w
                                                      const float* __restrict__ in, float* out) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  float x[27], o[3];
-  for (int i = 0; i < 27; ++i) x[i] = in[r * 27 + i];
+  float x[NI], o[3];
+  for (int i = 0; i < NI; ++i) x[i] = in[r * NI + i];
   mlp_forward_row(w, x, o);
   for (int k = 0; k < 3; ++k) out[r * 3 + k] = o[k];
 }
@@ -161,24 +163,29 @@ __global__ __launch_bounds__(128) void k_mlp_rows(const float* __restrict__ w, i
   if ((threadIdx.x & 63) == 0) atomicAdd(loss, lsum);
 }
 
-// weight gradients: block (o, layer), threads over inputs i, loop over rows
-__global__ __launch_bounds__(64) void k_mlp_wgrad(int64_t n, const float* __restrict__ buf, float* grad) {
-  int o = blockIdx.x, layer = blockIdx.y, i = threadIdx.x;
+// weight gradients: block (o, layer), threads stride over the layer's inputs,
+// each summing over the rows
+__global__ __launch_bounds__(128) void k_mlp_wgrad(int64_t n, const float* __restrict__ buf, float* grad) {
+  int o = blockIdx.x, layer = blockIdx.y;
   int nin = layer == 0 ? NI : H;
   int nout = layer == 3 ? NO : H;
   if (o >= nout) return;
   int in_off = layer == 0 ? 0 : (layer == 1 ? NI : (layer == 2 ? NI + H : NI + 2 * H));
   int d_off = layer == 0 ? NI + 3 * H : (layer == 1 ? NI + 4 * H : (layer == 2 ? NI + 5 * H : NI + 6 * H));
   size_t wofs = layer == 0 ? 0 : (layer == 1 ? H * NI + H : (layer == 2 ? H * NI + H + H * H + H : H * NI + H + 2 * (H * H + H)));
-  float g = 0.0f, gb = 0.0f;
-  for (int64_t r = 0; r < n; ++r) {
-    const float* B = buf + r * ROW;
-    float dlt = B[d_off + o];
-    if (i < nin) g += dlt * B[in_off + i];
-    gb += dlt;
+  for (int i = threadIdx.x; i < nin; i += blockDim.x) {
+    float g = 0.0f;
+    for (int64_t r = 0; r < n; ++r) {
+      const float* B = buf + r * ROW;
+      g += B[d_off + o] * B[in_off + i];
+    }
+    grad[wofs + (size_t)o * nin + i] = g;
   }
-  if (i < nin) grad[wofs + (size_t)o * nin + i] = g;
-  if (i == 0) grad[wofs + (size_t)nout * nin + o] = gb;
+  if (threadIdx.x == 0) {
+    float gb = 0.0f;
+    for (int64_t r = 0; r < n; ++r) gb += buf[r * ROW + d_off + o];
+    grad[wofs + (size_t)nout * nin + o] = gb;
+  }
 }
 
 __global__ void k_zero_f32(float* a, int64_t n) {
@@ -215,11 +222,11 @@ hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem
 #include "fp_shapes.h"
 
 hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
-                               int32_t* count, hipStream_t s) {
+                               int32_t* ids, int32_t* count, hipStream_t s) {
   if (n == 0) return hipSuccess;
   dim3 g((unsigned)((n + 255) / 256));
 #define FP_L(A, B) \
-  if (m.n == A && m.ng == B) { k_newton_pairs<A, B><<<g, 256, 0, s>>>(m, P, n, feat, xi, count); return hipGetLastError(); }
+  if (m.n == A && m.ng == B) { k_newton_pairs<A, B><<<g, 256, 0, s>>>(m, P, n, feat, xi, ids, count); return hipGetLastError(); }
   FP_FOR_EACH_SHAPE(FP_L)
 #undef FP_L
   return hipErrorInvalidValue;
@@ -248,7 +255,7 @@ hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, cons
   if (n <= 0 || n > kMlpMaxBatch) return hipErrorInvalidValue;
   k_zero_f32<<<1, 64, 0, s>>>(loss, 1);
   k_mlp_rows<<<dim3((unsigned)((n + 127) / 128)), 128, 0, s>>>(w, n, in, target, rows, rowbuf, loss);
-  k_mlp_wgrad<<<dim3(H, 4), 64, 0, s>>>(n, rowbuf, grad);
+  k_mlp_wgrad<<<dim3(H, 4), 128, 0, s>>>(n, rowbuf, grad);
   return hipGetLastError();
 }
 

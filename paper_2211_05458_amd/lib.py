@@ -78,7 +78,7 @@ def load():
     L.fp_mlp_n_weights.argtypes = []
     L.fp_mlp_n_weights.restype = I64
     L.fp_mlp_features.argtypes = [P, I64, P, P, P]
-    L.fp_newton_pairs.argtypes = [P, C.POINTER(I64), P, P, I64]
+    L.fp_newton_pairs.argtypes = [P, C.POINTER(I64), P, P, P, I64]
     L.fp_mlp_forward.argtypes = [P, P, I64, P, P]
     L.fp_mlp_loss_grad.argtypes = [P, P, I64, P, P, P, P]
     L.fp_mlp_train_epoch.argtypes = [P, P, P, P, C.POINTER(I64), P, P, P, I64, I32, C.c_float, P]
@@ -90,6 +90,22 @@ def load():
         getattr(L, name)
     _lib = L
     return L
+
+
+MLP_IN = 84
+MLP_SHAPES = [(64, MLP_IN), (64,), (64, 64), (64,), (64, 64), (64,), (3, 64), (3,)]
+
+
+def xavier_init(rng):
+    """Xavier-uniform weights and zero biases of the 84-64-64-64-3 network, flat (FP64)."""
+    parts = []
+    for shp in MLP_SHAPES:
+        if len(shp) == 2:
+            a = np.sqrt(6.0 / (shp[0] + shp[1]))
+            parts.append(rng.uniform(-a, a, size=shp).ravel())
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts)
 
 
 def _ptr(a):
@@ -223,18 +239,21 @@ class FlexiPart:
         t = self.torch
         elem = t.as_tensor(np.ascontiguousarray(elem, np.int32), device=self.device)
         x = t.as_tensor(np.ascontiguousarray(x, np.float64), device=self.device)
-        feat = t.empty((elem.shape[0], 27), dtype=t.float32, device=self.device)
+        feat = t.empty((elem.shape[0], MLP_IN), dtype=t.float32, device=self.device)
         self._check(self.L.fp_mlp_features(self.ctx, elem.shape[0], _ptr(elem), _ptr(x), _ptr(feat)),
                     "fp_mlp_features")
         return feat
 
-    def newton_pairs(self):
+    def newton_pairs(self, with_ids=False):
         t = self.torch
-        feat = t.empty((max(self.np, 1), 27), dtype=t.float32, device=self.device)
+        feat = t.empty((max(self.np, 1), MLP_IN), dtype=t.float32, device=self.device)
         xi = t.empty((max(self.np, 1), 3), dtype=t.float32, device=self.device)
+        ids = t.empty(max(self.np, 1), dtype=t.int32, device=self.device)
         n = C.c_int64(0)
-        self._check(self.L.fp_newton_pairs(self.ctx, C.byref(n), _ptr(feat), _ptr(xi), feat.shape[0]),
+        self._check(self.L.fp_newton_pairs(self.ctx, C.byref(n), _ptr(feat), _ptr(xi), _ptr(ids), feat.shape[0]),
                     "fp_newton_pairs")
+        if with_ids:
+            return feat[:n.value], xi[:n.value], ids[:n.value]
         return feat[:n.value], xi[:n.value]
 
     def mlp_forward(self, w, inp):
@@ -259,6 +278,25 @@ class FlexiPart:
                                               _ptr(target), _ptr(order), n, int(batch), float(lr), _ptr(losses)),
                     "fp_mlp_train_epoch")
         return tt.value, losses[:n // batch]
+
+    def mlp_train(self, feat, target, epochs=20, batch=4096, lr=1e-3, seed=4, w0=None):
+        """Minibatch Adam on the GPU kernels; returns (weights, mean loss per epoch).
+
+        The initial weights (Xavier-uniform, zero biases) and the per-epoch row
+        order are drawn on the host from `seed` and passed in."""
+        t = self.torch
+        rng = np.random.default_rng(seed)
+        w = t.tensor(xavier_init(rng) if w0 is None else np.asarray(w0), dtype=t.float32, device=self.device)
+        m = t.zeros_like(w)
+        v = t.zeros_like(w)
+        step = 0
+        hist = []
+        n = feat.shape[0]
+        for _ in range(epochs):
+            order = t.tensor(rng.permutation(n).astype(np.int32), device=self.device)
+            step, losses = self.mlp_train_epoch(w, m, v, step, feat, target, order, batch, lr)
+            hist.append(float(losses.mean().item()) if losses.numel() else float("nan"))
+        return w, hist
 
     def mlp_set_weights(self, w, thresh=0.05):
         self.mlp_w = w

@@ -220,7 +220,7 @@ def test_mlp_gradients_match_oracle():
     rng = np.random.default_rng(30)
     nw = FlexiPart.mlp_n_weights()
     wt = rng.normal(scale=0.15, size=nw)
-    inp = rng.normal(size=(777, 27))
+    inp = rng.normal(size=(777, 84))
     tgt = rng.uniform(-1, 1, size=(777, 3))
     lo, go = O.mlp_loss_grad(wt, inp, tgt)
     W32 = torch.tensor(wt, dtype=torch.float32, device="cuda")

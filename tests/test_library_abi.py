@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_export_list_matches_header():
     from paper_2211_05458_amd import lib
     assert sorted(lib.EXPORTS) == _declared()
-    assert lib.load().fp_mlp_n_weights() == 64 * 27 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3
+    assert lib.load().fp_mlp_n_weights() == 64 * 84 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

@@ -667,15 +667,15 @@ def test_deposit_conservation_and_single_node():
 def test_mlp_gradient_central_differences():
     rng = np.random.default_rng(14)
     nw = O.mlp_n_weights()
-    assert nw == 64 * 27 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3
+    assert nw == 64 * 84 + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3
     w = rng.normal(scale=0.2, size=nw)
-    inp = rng.normal(size=(16, 27))
+    inp = rng.normal(size=(16, 84))
     tgt = rng.uniform(-1, 1, size=(16, 3))
     loss, g = O.mlp_loss_grad(w, inp, tgt)
     out = O.mlp_forward(w, inp)
     assert abs(loss - np.mean((out - tgt) ** 2)) < 1e-14
     idx = rng.choice(nw, 60, replace=False)
-    idx = np.concatenate([idx, [0, 64 * 27, nw - 1, nw - 4]])
+    idx = np.concatenate([idx, [0, 64 * 84, nw - 1, nw - 4]])
     h = 1e-6
     for i in idx:
         wp = w.copy(); wp[i] += h
@@ -692,3 +692,28 @@ def test_adam_matches_definition():
     O.adam(w, m, v, g1, 1, 1e-2)
     # first Adam step moves every weight by lr * sign(g) (bias-corrected m/sqrt(v) = g/|g|)
     np.testing.assert_allclose(w, w0 - 1e-2 * g1 / (np.abs(g1) + 1e-8), rtol=1e-12)
+
+
+def test_mlp_features_carry_corners_curvature_and_point():
+    """Corners, the deviation from the trilinear corner map (exact for a
+    polynomial map) and the point, scaled by the mean corner-edge length."""
+    mesh = W.single_element(4, _poly_map)
+    o = O.Oracle(mesh, 2, _dummy_state(1, 2))
+    x = np.array([1.1, -0.2, 0.3])
+    f = o.mlp_features(0, x)
+    c = np.array([[i, j, k] for k in (-1, 1) for j in (-1, 1) for i in (-1, 1)], dtype=float)
+    cor = _poly_map(c)
+    ctr = cor.mean(axis=0)
+    edges = [np.linalg.norm(cor[a] - cor[a ^ (1 << b)]) for a in range(8) for b in range(3) if a ^ (1 << b) > a]
+    h = np.mean(edges)
+    np.testing.assert_allclose(f[:24], ((cor - ctr) / h).ravel(), atol=1e-14)
+    np.testing.assert_allclose(f[81:], (x - ctr) / h, atol=1e-14)
+    pts = [np.array([i - 1.0, j - 1.0, k - 1.0]) for k in range(3) for j in range(3) for i in range(3)
+           if 1 in (i, j, k)]
+    for r, xi in enumerate(pts):
+        w8 = np.array([0.125 * (1 + ci[0] * xi[0]) * (1 + ci[1] * xi[1]) * (1 + ci[2] * xi[2]) for ci in c])
+        dev = _poly_map(xi[None])[0] - w8 @ cor
+        np.testing.assert_allclose(f[24 + 3 * r: 27 + 3 * r], dev / h, atol=1e-13)
+    # an affine element has no curvature features
+    o2 = O.Oracle(W.single_element(4, lambda xi: xi @ np.diag([0.5, 0.4, 0.6]).T), 2, _dummy_state(1, 2))
+    assert np.abs(o2.mlp_features(0, x)[24:81]).max() < 1e-14
