@@ -74,7 +74,9 @@ def bytes_per_particle_stage(n, ng, ppe):
     return soa + elem / ppe
 
 
-def run_gpu(w, U, precision, steps, warmup):
+def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False):
+    """Push w's particles, run `warmup` untimed then `steps` timed fp_step(dt, 1)
+    calls (each followed by deposit(g) if given); returns timings and the state."""
     import numpy as np
     import torch
     from paper_2211_05458_amd.lib import FlexiPart
@@ -82,9 +84,12 @@ def run_gpu(w, U, precision, steps, warmup):
     g.set_fluid_state(U)
     st, nrej = g.push(w.x, w.v, w.d, w.elem_hint)
     n_active = int((st == 0).sum())
-    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1)
+    n_flagged = g.mlp_set_weights(weights) if weights is not None else 0
+    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1, guess=guess)
     for _ in range(warmup):
         g.step(w.dt, 1, **opts)
+        if deposit:
+            deposit(g)
     torch.cuda.synchronize()
     g.reset_stats()
     g.timing()
@@ -96,6 +101,8 @@ def run_gpu(w, U, precision, steps, warmup):
     ev0.record()
     for _ in range(steps):
         g.step(w.dt, 1, **opts)
+        if deposit:
+            deposit(g)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -104,8 +111,146 @@ def run_gpu(w, U, precision, steps, warmup):
     g.set_timing(False)
     stats = g.stats()
     r = g.read()
-    return dict(ms=ms, wall=wall, timing=timing, stats=stats, read=r, n_active=n_active,
-                active_end=int((r["status"] == 0).sum()))
+    out = dict(ms=ms, wall=wall, timing=timing, stats=stats, read=r, n_active=n_active, n_flagged=n_flagged,
+               active_end=int((r["status"] == 0).sum()),
+               kernel_ms={k: (v[1] / v[0] if v[0] else 0.0) for k, v in timing.items()})
+    if keep:
+        out["ctx"] = g
+    else:
+        g.close()
+    return out
+
+
+def pos_error(ref, other, h):
+    """Position difference of two runs from the same initial state."""
+    import numpy as np
+    both = (ref["read"]["status"] == 0) & (other["read"]["status"] == 0)
+    dx = np.linalg.norm(other["read"]["x"][both] - ref["read"]["x"][both], axis=1)
+    return {"pos_err_max_m": float(dx.max()), "pos_err_rms_m": float(np.sqrt((dx ** 2).mean())),
+            "pos_err_max_h": float(dx.max() / h),
+            "elem_mismatch_frac": float((other["read"]["elem"] != ref["read"]["elem"]).mean()),
+            "hits_mismatch_frac": float((other["read"]["hits"] != ref["read"]["hits"]).mean())}
+
+
+def summary(r, K):
+    return {"value": r["n_active"] * K / (r["ms"] * 1e-3), "ms_per_step": r["ms"] / K,
+            "kernel_ms": r["kernel_ms"],
+            "newton_it_per_solve": r["stats"]["newton_iters"] / max(r["stats"]["newton_calls"], 1),
+            "fallbacks": r["stats"]["fallbacks"], "lost": r["stats"]["lost"]}
+
+
+def bench_annulus(args):
+    """Annular-sector passage 48x24x48, Ngeo=6, N=5: plain FP64 against the
+    mixed form with the learned Newton guess trained on the GPU."""
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+    from paper_2211_05458_amd.lib import FlexiPart
+    n = args.particles or 10_000_000
+    K, Wm = args.steps or 10, args.warmup
+    print("[bench] generating annulus workload", file=sys.stderr, flush=True)
+    w = W.config4(n_particles=n)
+    U64 = torch.from_numpy(w.U).cuda()
+    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+    print("[bench] training pairs and training", file=sys.stderr, flush=True)
+    n_train = min(n, 1_000_000)
+    t0 = time.perf_counter()
+    g = FlexiPart(w.mesh, w.N, n_train)
+    g.set_fluid_state(U64)
+    g.push(w.x[:n_train], w.v[:n_train], w.d[:n_train], w.elem_hint[:n_train])
+    feat, xi = g.newton_pairs()
+    wts, hist = g.mlp_train(feat, xi, epochs=args.epochs, batch=1024, lr=2e-3, seed=4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    pred = g.mlp_forward(wts, feat)
+    guess_err = float((pred - xi).abs().max(dim=1).values.median().item())
+    g.close()
+    runs = {}
+    for name, U, prec, guess in [("fp64", U64, 0, 0), ("fp64_learned", U64, 0, 1), ("mixed", U32, 1, 0),
+                                 ("mixed_learned", U32, 1, 1)]:
+        print("[bench] run", name, file=sys.stderr, flush=True)
+        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None)
+    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
+           "value": summary(runs["mixed_learned"], K)["value"], "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": K, "warmup": Wm, "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "annular passage 48x24x48 Ngeo=6, DG N=5, %d particles, Schiller-Naumann, "
+                                  "3-stage LSERK, dt=1e-3" % n, "elements": w.mesh.n_elem},
+           "training": {"pairs": int(feat.shape[0]), "epochs": args.epochs, "batch": 1024, "seconds": train_s,
+                        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+                        "median_guess_error": guess_err, "flagged_elements": runs["fp64_learned"]["n_flagged"]}}
+    for k, r in runs.items():
+        out[k] = summary(r, K)
+        if k != "fp64":
+            out[k].update(pos_error(runs["fp64"], r, w.mesh.h))
+    out["speedup_mixed_learned_vs_fp64"] = out["mixed_learned"]["value"] / out["fp64"]["value"]
+    print(json.dumps(out))
+
+
+def bench_precision(args):
+    """64^3 curved box, Ngeo=4, N=7, FP32 fluid state: FP64 against mixed."""
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+    n = args.particles or 10_000_000
+    K, Wm = args.steps or 10, args.warmup
+    print("[bench] generating 64^3 N=7 workload", file=sys.stderr, flush=True)
+    w = W.config3(n_particles=n)
+    U64 = torch.from_numpy(w.U).cuda()
+    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+    del w.U
+    r64 = run_gpu(w, U64, 0, K, Wm)
+    del U64
+    r32 = run_gpu(w, U32, 1, K, Wm)
+    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
+           "value": summary(r32, K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+           "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "curved sine box 64^3 Ngeo=4, DG N=7 (fluid state FP32), %d particles, "
+                                  "Schiller-Naumann, 3-stage LSERK, dt=1e-3" % n, "elements": w.mesh.n_elem},
+           "fp64": summary(r64, K), "mixed": summary(r32, K)}
+    out["mixed"].update(pos_error(r64, r32, w.mesh.h))
+    out["mixed"]["after_steps"] = K + Wm
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    print(json.dumps(out))
+
+
+def bench_twoway(args):
+    """96^3 curved box, Ngeo=4, N=5, 2e7 particles, mixed form, shape-kernel
+    source (R = 1.5 h) deposited after every step."""
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+    n = args.particles or 20_000_000
+    K, Wm = args.steps or 5, min(args.warmup, 2)
+    print("[bench] generating 96^3 workload", file=sys.stderr, flush=True)
+    w = W.config5(n_particles=n)
+    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+    del w.U
+    R = 1.5 * w.mesh.h
+    per = np.array([1.0, 0.0, 1.0])
+    S = {}
+
+    def dep(g):
+        if "S" not in S:
+            S["S"] = torch.zeros((g.E, 4, g.n3), dtype=torch.float32, device="cuda")
+        S["S"].zero_()
+        g.deposit(S["S"], kind=1, radius=R, period=per)
+
+    r = run_gpu(w, U32, 1, K, Wm, deposit=dep, keep=True)
+    g = r["ctx"]
+    V = g.node_volumes()
+    tot_shape = torch.einsum("ecq,eq->c", S["S"].double(), V)
+    Sn = g.deposit(None, kind=0, dtype=torch.float64)
+    tot_near = torch.einsum("ecq,eq->c", Sn, V)
+    cons = float(((tot_shape - tot_near).abs().max() / tot_near.abs().max()).item())
+    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
+           "value": summary(r, K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+           "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "curved sine box 96^3 Ngeo=4, DG N=5, %d particles, mixed form, shape-kernel "
+                                  "two-way source R=1.5h every step" % n, "elements": w.mesh.n_elem},
+           "run": summary(r, K),
+           "conservation_rel_err_fp32": cons,
+           "deposited_momentum": [float(v) for v in tot_near[:3].tolist()]}
+    print(json.dumps(out))
 
 
 def copy_calibration(gib=2, reps=5):
@@ -124,9 +269,12 @@ def copy_calibration(gib=2, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--particles", type=int, default=None)
+    ap.add_argument("--workload", choices=["curved32", "annulus", "precision", "twoway"], default="curved32",
+                    help="curved32: the benchmark line; the others measure the remaining workloads")
+    ap.add_argument("--epochs", type=int, default=20, help="learned-guess training epochs (annulus)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-every", type=int, default=50, help="oracle sample: every k-th particle")
@@ -141,6 +289,13 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    from paper_2211_05458_amd import workloads as W
+    W.VERBOSE = True
+    if args.workload != "curved32":
+        {"annulus": bench_annulus, "precision": bench_precision, "twoway": bench_twoway}[args.workload](args)
+        return
+    args.steps = args.steps or 100
+    args.particles = args.particles or 1_000_000
 
     import numpy as np
     import torch
@@ -168,7 +323,7 @@ def main():
     per_launch_particles = (ps - r64["stats"]["stragglers"]) / max(n_launch, 1)
     per_launch_flops = fl_ps * per_launch_particles
     per_launch_bytes = by_ps * per_launch_particles
-    kern_ms = {k: (v[1] / v[0] if v[0] else 0.0) for k, v in r64["timing"].items()}
+    kern_ms = r64["kernel_ms"]
     achieved_tf = per_launch_flops / (avg_stage_ms * 1e-3) / 1e12
     achieved_gbs = per_launch_bytes / (avg_stage_ms * 1e-3) / 1e9
     traffic = read_traffic()
@@ -178,21 +333,13 @@ def main():
         print("[bench] mixed-precision run", file=sys.stderr, flush=True)
         U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
         r32 = run_gpu(w, U32, 1, args.steps, args.warmup)
-        x64, x32 = r64["read"]["x"], r32["read"]["x"]
-        both = (r64["read"]["status"] == 0) & (r32["read"]["status"] == 0)
-        dx = np.linalg.norm(x32[both] - x64[both], axis=1)
-        extras["mixed_fp32"] = {
-            "value": r32["n_active"] * K / (r32["ms"] * 1e-3),
-            "ms_per_step": r32["ms"] / K,
-            "kernel_ms": {k: (v[1] / v[0] if v[0] else 0.0) for k, v in r32["timing"].items()},
-            "pos_err_max_m": float(dx.max()), "pos_err_rms_m": float(np.sqrt((dx ** 2).mean())),
-            "pos_err_max_h": float(dx.max() / w.mesh.h),
-            "elem_mismatch_frac": float((r32["read"]["elem"] != r64["read"]["elem"]).mean()),
-            "hits_mismatch_frac": float((r32["read"]["hits"] != r64["read"]["hits"]).mean()),
+        extras["mixed_fp32"] = summary(r32, K)
+        extras["mixed_fp32"].update(pos_error(r64, r32, w.mesh.h))
+        extras["mixed_fp32"].update({
             "after_steps": args.warmup + K,
             "learned_guess": "no element of this mesh deviates from its trilinear corner map by "
                              "more than 0.05 h, so the learned guess is never used here",
-        }
+        })
 
     cpu = None
     if not args.no_cpu_baseline:

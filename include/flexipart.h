@@ -132,6 +132,11 @@ int fp_step(fp_ctx* ctx, double dt, int32_t n_steps, const fp_step_opts* opts);
 int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, double radius,
                       const double* period, int32_t drag);
 
+/* Copy the quadrature volumes V_ijk = w_i w_j w_k J(xi_ijk) of all DG nodes
+ * (device output V[n_elem][(n_dg+1)^3], f64) -- the measure in which the
+ * deposited source is conservative: sum_k S_k V_k = -sum_p F_p.  Async. */
+int fp_node_volumes(fp_ctx* ctx, double* V_dev);
+
 /* Copy the particle state to host buffers (any may be NULL) in the order of
  * fp_push_particles.  xi is the reference position in elem.  Synchronises. */
 int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* elem, double* xi,

@@ -660,6 +660,14 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   return FP_OK;
 }
 
+int fp_node_volumes(fp_ctx* c, double* V) {
+  if (!c || !V) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_node_volumes: no workspace");
+  size_t bytes = (size_t)c->E * c->n * c->n * c->n * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(V, c->mv.vol, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return FP_OK;
+}
+
 int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* elem, double* xi,
                       int32_t* hits, int8_t* status) {
   if (!c) return FP_EINVAL;

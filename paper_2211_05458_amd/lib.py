@@ -24,7 +24,7 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_deposit_source", "fp_read_particles", "fp_get_stats", "fp_reset_stats",
            "fp_mlp_n_weights", "fp_mlp_features", "fp_newton_pairs", "fp_mlp_forward",
            "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged",
-           "fp_set_timing", "fp_get_timing"]
+           "fp_set_timing", "fp_get_timing", "fp_node_volumes"]
 TIMING_CLASSES = ("sort", "stage_elem", "finalize", "deposit_nearest", "deposit_shape", "stage_lane", "track")
 
 
@@ -85,6 +85,7 @@ def load():
     L.fp_mlp_set_weights.argtypes = [P, P, D]
     L.fp_mlp_num_flagged.argtypes = [P, C.POINTER(I64)]
     L.fp_set_timing.argtypes = [P, I32]
+    L.fp_node_volumes.argtypes = [P, P]
     L.fp_get_timing.argtypes = [P, P]
     for name in EXPORTS:       # every documented entry point must resolve
         getattr(L, name)
@@ -200,6 +201,11 @@ class FlexiPart:
         self._check(self.L.fp_deposit_source(self.ctx, _ptr(S), dt, int(kind), float(radius), _ptr(per), int(drag)),
                     "fp_deposit_source")
         return S
+
+    def node_volumes(self):
+        V = self.torch.empty((self.E, self.n3), dtype=self.torch.float64, device=self.device)
+        self._check(self.L.fp_node_volumes(self.ctx, _ptr(V)), "fp_node_volumes")
+        return V
 
     def read(self):
         n = self.np

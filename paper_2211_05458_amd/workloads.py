@@ -39,6 +39,14 @@ RHO_P = 2500.0
 
 BC_INTERNAL, BC_OPEN, BC_REFLECT, BC_PERIODIC = 0, 1, 2, 3
 
+VERBOSE = False   # report generation progress on stderr (large workloads)
+
+
+def _progress(what, done, total):
+    if VERBOSE:
+        import sys
+        print("[workloads] %s %d/%d" % (what, done, total), file=sys.stderr, flush=True)
+
 
 @dataclasses.dataclass
 class Mesh:
@@ -223,7 +231,10 @@ def _dg_state(cells, N, logical_to_phys, field):
     cnt = np.array([n1, n2, n3], dtype=np.float64)
     U = np.empty((E, 5, n ** 3))
     chunk = max(1, 2_000_000 // (n ** 3))
+    report = max(chunk, (E // 10) // chunk * chunk)
     for s in range(0, E, chunk):
+        if s % report == 0:
+            _progress("fluid state", s, E)
         cs = c[s:s + chunk]
         sl = (cs[:, None, :] + 0.5 * (loc[None, :, :] + 1.0)) / cnt   # logical coords
         xp = logical_to_phys(sl)
