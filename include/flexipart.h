@@ -120,7 +120,11 @@ int fp_set_fluid_state(fp_ctx* ctx, const void* U_dev, fp_dtype dtype, const fp_
 int fp_push_particles(fp_ctx* ctx, int64_t n, const double* x, const double* v, const double* d,
                       const int32_t* elem_hint, int32_t* status_out);
 
-/* Advance all active particles by n_steps steps of size dt.  Asynchronous. */
+/* Advance all active particles by n_steps steps of size dt.  Each stage
+ * locates the particle in its element by Newton (Sec. 3.2.1); one that lies
+ * outside it (a crossing missed by the face intersection, at grazing incidence)
+ * is followed across the face its reference coordinate left through, up to
+ * three internal or periodic faces, before it is counted lost.  Asynchronous. */
 int fp_step(fp_ctx* ctx, double dt, int32_t n_steps, const fp_step_opts* opts);
 
 /* Add the two-way coupling source of the current particle state to S (device)
@@ -128,7 +132,10 @@ int fp_step(fp_ctx* ctx, double dt, int32_t n_steps, const fp_step_opts* opts);
  * kind 0: nearest DOF, S = -F/V_ijk (Sec. 2.3).  kind 1: polynomial shape
  * kernel (1-(r/R)^2)^2 of radius `radius` over all DG nodes, normalised so that
  * sum_k S_k V_k = -F; period[3] (host, may be NULL) are the domain periods for
- * the minimum-image distance (0: not periodic).  Asynchronous. */
+ * the minimum-image distance (0: not periodic).  Each positive period must
+ * exceed 2 * radius (FP_EINVAL otherwise), so that at most one image of a node
+ * lies within reach of a particle.  Particles with no node within reach deposit
+ * nothing.  Sorts the particles by element.  Asynchronous. */
 int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, double radius,
                       const double* period, int32_t drag);
 
@@ -142,12 +149,14 @@ int fp_node_volumes(fp_ctx* ctx, double* V_dev);
 int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* elem, double* xi,
                       int32_t* wall_hits, int8_t* status);
 
-/* Counters since the last reset: out[0] Newton iterations, out[1] Newton
- * solves, out[2] face crossings, out[3] wall hits, out[4] lost particles,
- * out[5] learned-guess fallbacks, out[6] sorts, out[7] particle-stages taken
- * by the per-lane kernel because they left their sorted element, out[8]
- * particle-stages queued for face intersection.  Synchronises. */
-int fp_get_stats(fp_ctx* ctx, int64_t* out9);
+/* Counters since the last reset (host out[10]): out[0] Newton iterations,
+ * out[1] Newton solves, out[2] face crossings, out[3] wall hits, out[4] lost
+ * particles, out[5] learned-guess fallbacks, out[6] sorts, out[7]
+ * particle-stages taken by the per-lane kernel (they left their sorted element
+ * or lie outside it), out[8] particle-stages queued for face intersection,
+ * out[9] particles recovered in a neighbour element after a crossing the face
+ * intersection missed (see fp_step).  Synchronises. */
+int fp_get_stats(fp_ctx* ctx, int64_t* out10);
 int fp_reset_stats(fp_ctx* ctx);
 
 /* ---- kernel timing (tracing) ---------------------------------------------

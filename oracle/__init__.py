@@ -309,10 +309,10 @@ class Oracle:
         return out
 
     def stats(self):
-        s = np.zeros(6, np.int64)
+        s = np.zeros(7, np.int64)
         lib().or_stats(self.ctx, _p(s))
         return dict(newton_iters=int(s[0]), newton_calls=int(s[1]), crossings=int(s[2]),
-                    wall_hits=int(s[3]), lost=int(s[4]), fallbacks=int(s[5]))
+                    wall_hits=int(s[3]), lost=int(s[4]), fallbacks=int(s[5]), recovered=int(s[6]))
 
     def reset_stats(self):
         lib().or_reset_stats(self.ctx)

@@ -35,6 +35,8 @@
 #define NEWTON_TOL 1e-10  /* stop once an applied update has max-norm <= tol */
 #define INSIDE_EPS 1e-10  /* xi in [-1-eps, 1+eps]^3 counts as inside */
 #define UV_EPS 1e-12      /* face parameter tolerance */
+#define ENTRY_REL 1e-9    /* entry-face root threshold, relative to the face diameter */
+#define RECOVER_HOPS 3    /* neighbour hops for a located particle outside its element */
 #define CLIP_TOL 1e-12    /* Bezier clipping interval width (parameter space [0,1]) */
 #define CLIP_PAD 1e-10    /* relative padding of each clipped interval */
 #define CLIP_STACK 16
@@ -72,7 +74,7 @@ struct or_ctx {
   int32_t *elem, *hits;
   int8_t *status;
   /* stats */
-  int64_t st_newton_it, st_newton_calls, st_cross, st_hits, st_lost, st_fallback;
+  int64_t st_newton_it, st_newton_calls, st_cross, st_hits, st_lost, st_fallback, st_recover;
   /* learned guess */
   double *mlp_w;
   uint8_t *mlp_flag;
@@ -699,9 +701,27 @@ static int bilinear_intersect(const double* A, const double* B, const double* C,
 
 /* ---- Bezier clipping (Sec. 3.2.4; Nishita et al. 1990) --------------------- */
 typedef struct {
-  double q[MAXG][MAXG][2];   /* [m along u][n along v] projected control points */
+  /* [m along u][n along v]: signed distances of the control points to the two
+   * planes that contain the line (0, 1) and their displacement along it (2) */
+  double q[MAXG][MAXG][3];
   double u0, u1, v0, v1;     /* parameter interval in [0,1] */
 } clip_patch;
+
+/* Reading (the paper leaves the clipping loop to the literature): a
+ * sub-patch whose control points all have displacement outside [amin, amax]
+ * holds no root in that band (convex hull) and is dropped.  At grazing
+ * incidence the zero set of the two plane distances is a long thin band in
+ * (u, v) of which only the part within the stage segment matters; without
+ * this test the clipping budget can run out before the root is isolated. */
+static int patch_outside_band(const clip_patch* P, int ng, double amin, double amax) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int m = 0; m < ng; ++m)
+    for (int n = 0; n < ng; ++n) {
+      if (P->q[m][n][2] < lo) lo = P->q[m][n][2];
+      if (P->q[m][n][2] > hi) hi = P->q[m][n][2];
+    }
+  return hi < amin || lo > amax;
+}
 
 /* interval of t where the convex hull of (t_m, dmin_m), (t_m, dmax_m) meets 0 */
 static int hull_zero(int ng, const double* dmin, const double* dmax, double* ta, double* tb) {
@@ -756,7 +776,7 @@ static void restrict_1d(double* c, int n, double a, double b) {
 static void patch_restrict(clip_patch* P, int ng, int dir, double a, double b) {
   double col[MAXG];
   for (int k = 0; k < ng; ++k)
-    for (int co = 0; co < 2; ++co) {
+    for (int co = 0; co < 3; ++co) {
       for (int i = 0; i < ng; ++i) col[i] = (dir == 0) ? P->q[i][k][co] : P->q[k][i][co];
       restrict_1d(col, ng, a, b);
       for (int i = 0; i < ng; ++i) {
@@ -857,8 +877,9 @@ static void bezier_eval(int ng, const double* cp, double u, double v, double* p,
 }
 
 /* all intersections of the line x0 + alpha t (|t| = 1) with a Bezier face */
-int or_bezier_intersect(int ng, const double* cp, const double* x0, const double* t,
-                        double* alpha, double* uv, int max_roots) {
+/* roots with displacement in [amin, amax] (all roots: +-INFINITY) */
+static int bezier_band(int ng, const double* cp, const double* x0, const double* t, double amin,
+                       double amax, double* alpha, double* uv, int max_roots) {
   double n1[3], n2[3];
   ray_planes(t, n1, n2);
   static __thread clip_patch stack[CLIP_STACK];
@@ -869,15 +890,18 @@ int or_bezier_intersect(int ng, const double* cp, const double* x0, const double
       double r[3] = {P[0] - x0[0], P[1] - x0[1], P[2] - x0[2]};
       q0[m][k][0] = dot3(r, n1);
       q0[m][k][1] = dot3(r, n2);
+      stack[0].q[m][k][0] = q0[m][k][0];
+      stack[0].q[m][k][1] = q0[m][k][1];
+      stack[0].q[m][k][2] = dot3(r, t);
     }
   int sp = 0, nroots = 0, budget = CLIP_STEPS;
-  memcpy(stack[0].q, q0, sizeof(q0));
   stack[0].u0 = 0.0; stack[0].u1 = 1.0; stack[0].v0 = 0.0; stack[0].v1 = 1.0;
   sp = 1;
   while (sp > 0 && budget > 0) {
     clip_patch P = stack[--sp];
     for (;;) {
       if (--budget < 0) break;
+      if (patch_outside_band(&P, ng, amin, amax)) break;
       double a, b, ru, rv;
       if (!clip_dir(&P, ng, 0, &a, &b)) break;
       patch_restrict(&P, ng, 0, a, b);
@@ -919,6 +943,11 @@ int or_bezier_intersect(int ng, const double* cp, const double* x0, const double
     }
   }
   return nroots;
+}
+
+int or_bezier_intersect(int ng, const double* cp, const double* x0, const double* t,
+                        double* alpha, double* uv, int max_roots) {
+  return bezier_band(ng, cp, x0, t, -INFINITY, INFINITY, alpha, uv, max_roots);
 }
 
 /* all roots of the face equation along the line (any alpha) */
@@ -1185,7 +1214,8 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
                   int max_cross, int64_t* ncross, int64_t* nhits) {
   int e = c->elem[p];
   double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
-  int excl = -1;
+  int excl = -1;   /* planar face just entered through: no further root possible */
+  int entry = -1;  /* non-planar face just entered through (see below) */
   int count = 0;
   for (;;) {
     double t[3] = {xe[0] - xs[0], xe[1] - xs[1], xe[2] - xs[2]};
@@ -1199,10 +1229,26 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
       if (f == excl) continue;
       int fid = e * 6 + f;
       if (!bbox_hit(c, fid, xs, xe)) continue;
+      /* Reading (the paper accepts 0 < alpha <= remaining length and says
+       * nothing about the entry point): a non-planar face the particle has
+       * just entered through (hand-off or reflection) returns the entry point
+       * itself as a root at alpha ~ 0, whose rounding error grows like
+       * 1 / sin(incidence) at grazing incidence and can exceed eps.  On that
+       * face only roots beyond ENTRY_REL * face diameter count; a genuine
+       * second crossing closer than that requires near-tangency, and its
+       * excursion outside the element stays far below INSIDE_EPS. */
+      double amin = (f == entry) ? fmax(eps, ENTRY_REL * c->fdiam[fid]) : eps;
       double al[8], uv[16];
-      int nr = or_face_intersect(c, e, f, xs, t, al, uv, 8);
+      int nr;
+      if (c->ftype[fid] == OR_FACE_CURVED) {
+        /* only roots in (amin, L] matter: clip to that band, padded */
+        double pad = 1e-9 * c->fdiam[fid];
+        nr = bezier_band(c->ng, c->cp + (size_t)fid * c->ng * c->ng * 3, xs, t, amin - pad, L + pad, al, uv, 8);
+      } else {
+        nr = or_face_intersect(c, e, f, xs, t, al, uv, 8);
+      }
       for (int r = 0; r < nr; ++r) {
-        if (!(al[r] > eps && al[r] <= L)) continue;
+        if (!(al[r] > amin && al[r] <= L)) continue;
         if (fabs(uv[2 * r]) > 1.0 + UV_EPS || fabs(uv[2 * r + 1]) > 1.0 + UV_EPS) continue;
         if (al[r] < best) { best = al[r]; bf = f; bu = uv[2 * r]; bv = uv[2 * r + 1]; }
       }
@@ -1220,6 +1266,7 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
         for (int q = 0; q < 3; ++q) { xh[q] += c->shift[fid * 3 + q]; xe[q] += c->shift[fid * 3 + q]; }
       e = ne;
       excl = (c->ftype[ne * 6 + nf] == OR_FACE_PLANAR) ? nf : -1;
+      entry = (c->ftype[ne * 6 + nf] == OR_FACE_PLANAR) ? -1 : nf;
       for (int q = 0; q < 3; ++q) xs[q] = xh[q];
     } else if (bc == 2) {
       double nrm[3];
@@ -1235,6 +1282,7 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
       c->hits[p]++;
       (*nhits)++;
       excl = (c->ftype[fid] == OR_FACE_PLANAR) ? bf : -1;
+      entry = (c->ftype[fid] == OR_FACE_PLANAR) ? -1 : bf;
       for (int q = 0; q < 3; ++q) xs[q] = xh[q];
     } else {
       c->status[p] = OR_OPEN_EXIT;
@@ -1243,6 +1291,34 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
     }
   }
   c->elem[p] = e;
+}
+
+/* Reading (the paper verifies a located particle by xi in [-1,1]^3 and does
+ * not say what follows a failed check): a particle that the location step
+ * finds outside its element crossed a face that the intersection search
+ * missed (the clipping budget can run out at grazing incidence).  Internal
+ * faces do not change the path, so the particle is followed across the face
+ * through which its reference coordinate left (largest |xi_d|, lowest axis on
+ * ties), with the periodic shift where the face is periodic, and located
+ * again, at most RECOVER_HOPS times.  A wall or open face ends the search: the
+ * particle is lost.  Returns 1 with e, x, xi updated when inside. */
+static int recover_elem(or_ctx* c, int* e, double* x, double* xi, int max_it, int64_t* it_sum,
+                        int64_t* calls, int64_t* nfb) {
+  for (int hop = 0; hop < RECOVER_HOPS; ++hop) {
+    int d = 0;
+    double ex = fabs(xi[0]);
+    if (fabs(xi[1]) > ex) { d = 1; ex = fabs(xi[1]); }
+    if (fabs(xi[2]) > ex) { d = 2; ex = fabs(xi[2]); }
+    int fid = *e * 6 + 2 * d + (xi[d] > 0.0 ? 1 : 0);
+    int bc = c->bc[fid];
+    if (bc != 0 && bc != 3) return 0;
+    if (bc == 3)
+      for (int q = 0; q < 3; ++q) x[q] += c->shift[fid * 3 + q];
+    *e = c->nbr_elem[fid];
+    if (!newton_chain(c, *e, x, xi, max_it, 0, it_sum, calls, nfb)) return 0;
+    if (inside_ref(xi)) return 1;
+  }
+  return 0;
 }
 
 void or_default_opts(or_step_opts* o) {
@@ -1259,10 +1335,10 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
   int S;
   double A[5], B[5], cc[5];
   or_rk_coeffs(o->rk, &S, A, B, cc);
-  int64_t it_sum = 0, calls = 0, ncross = 0, nhits = 0, nlost = 0, nfb = 0;
+  int64_t it_sum = 0, calls = 0, ncross = 0, nhits = 0, nlost = 0, nfb = 0, nrec = 0;
   for (int step = 0; step < n_steps; ++step)
     for (int s = 0; s < S; ++s) {
-#pragma omp parallel for schedule(static) reduction(+ : it_sum, calls, ncross, nhits, nlost, nfb)
+#pragma omp parallel for schedule(static) reduction(+ : it_sum, calls, ncross, nhits, nlost, nfb, nrec)
       for (int64_t p = 0; p < c->np; ++p) {
         if (c->status[p] != OR_ACTIVE) continue;
         int e = c->elem[p];
@@ -1274,7 +1350,13 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
         if (!newton_chain(c, e, x, xi, o->max_newton_it, o->use_mlp, &it_sum, &calls, &nfb)) {
           c->status[p] = OR_LOST_NEWTON; nlost++; continue;
         }
-        if (!inside_ref(xi)) { c->status[p] = OR_LOST_TRACK; nlost++; continue; }
+        if (!inside_ref(xi)) {
+          if (!recover_elem(c, &e, x, xi, o->max_newton_it, &it_sum, &calls, &nfb)) {
+            c->status[p] = OR_LOST_TRACK; nlost++; continue;
+          }
+          c->elem[p] = e;
+          nrec++;
+        }
         for (int k = 0; k < 3; ++k) c->xi[p * 3 + k] = xi[k];
         double Uc[5], prim[5], a[3];
         or_interp(c, e, xi, Uc);
@@ -1293,19 +1375,27 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
       }
     }
   /* reference coordinates of the final positions (and the inside verification) */
-#pragma omp parallel for schedule(static) reduction(+ : nlost)
+#pragma omp parallel for schedule(static) reduction(+ : nlost, nrec)
   for (int64_t p = 0; p < c->np; ++p) {
     if (c->status[p] != OR_ACTIVE) continue;
     double xi[3];
     int64_t a0 = 0, a1 = 0, a2 = 0;
-    if (!newton_chain(c, c->elem[p], c->x + p * 3, xi, o->max_newton_it, 0, &a0, &a1, &a2)) {
+    int e = c->elem[p];
+    if (!newton_chain(c, e, c->x + p * 3, xi, o->max_newton_it, 0, &a0, &a1, &a2)) {
       c->status[p] = OR_LOST_NEWTON; nlost++; continue;
     }
-    if (!inside_ref(xi)) { c->status[p] = OR_LOST_TRACK; nlost++; }
+    if (!inside_ref(xi)) {
+      if (recover_elem(c, &e, c->x + p * 3, xi, o->max_newton_it, &a0, &a1, &a2)) {
+        c->elem[p] = e;
+        nrec++;
+      } else {
+        c->status[p] = OR_LOST_TRACK; nlost++;
+      }
+    }
     for (int k = 0; k < 3; ++k) c->xi[p * 3 + k] = xi[k];
   }
   c->st_newton_it += it_sum; c->st_newton_calls += calls; c->st_cross += ncross;
-  c->st_hits += nhits; c->st_lost += nlost; c->st_fallback += nfb;
+  c->st_hits += nhits; c->st_lost += nlost; c->st_fallback += nfb; c->st_recover += nrec;
   return 0;
 }
 
@@ -1321,10 +1411,11 @@ void or_read(or_ctx* c, double* x, double* v, int32_t* elem, double* xi, int32_t
 
 void or_stats(const or_ctx* c, int64_t* out) {
   out[0] = c->st_newton_it; out[1] = c->st_newton_calls; out[2] = c->st_cross;
-  out[3] = c->st_hits; out[4] = c->st_lost; out[5] = c->st_fallback;
+  out[3] = c->st_hits; out[4] = c->st_lost; out[5] = c->st_fallback; out[6] = c->st_recover;
 }
 void or_reset_stats(or_ctx* c) {
   c->st_newton_it = c->st_newton_calls = c->st_cross = c->st_hits = c->st_lost = c->st_fallback = 0;
+  c->st_recover = 0;
 }
 
 /* ======================================================================== */

@@ -74,7 +74,7 @@ void or_default_opts(or_step_opts*);
 int  or_step(or_ctx*, double dt, int n_steps, const or_step_opts*);
 void or_read(or_ctx*, double* x, double* v, int32_t* elem, double* xi, int32_t* hits,
              int8_t* status);
-void or_stats(const or_ctx*, int64_t* out /*6: newton_iters, newton_calls, crossings, wall_hits, lost, fallbacks*/);
+void or_stats(const or_ctx*, int64_t* out /*7: newton_iters, newton_calls, crossings, wall_hits, lost, fallbacks, recovered*/);
 void or_reset_stats(or_ctx*);
 
 /* two-way coupling source ------------------------------------------------- */

@@ -23,6 +23,7 @@ struct fp_ctx {
   double blo[3], bdx[3];
   int bn[3];
   double max_extent = 0.0;   // largest element box edge
+  double node_pad = 0.0;     // largest distance of a DG node outside its padded element box
   double xgeo[kMaxNodes], cgeo[kMaxNodes], xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
   // workspace
   char* ws = nullptr;
@@ -35,7 +36,8 @@ struct fp_ctx {
   int32_t *sort_count = nullptr, *sort_start = nullptr, *sort_rank = nullptr, *sort_sums = nullptr;
   int32_t* scratch_i32 = nullptr;
   uint8_t* mlp_flag = nullptr;
-  double* dep_buf = nullptr;   // per-particle force (4) + normalisation (1)
+  double* dep_buf = nullptr;   // per-particle force (4 doubles), then a validity flag (int32)
+  unsigned long long* dep_pad = nullptr;   // largest distance of a particle outside its element box
   float* mlp_rows = nullptr;   // per-row activations for MLP gradients
   float* mlp_grad = nullptr;   // gradient + loss scratch
   int32_t *tcount = nullptr, *tstart = nullptr, *qcnt = nullptr, *strag = nullptr, *trk_p = nullptr;
@@ -204,7 +206,7 @@ struct Timed {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
+  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, part[2], total;
   size_t part_bytes;
@@ -223,6 +225,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.vol = take(E * n3 * 8);
   L.elo = take(E * 3 * 8);
   L.ehi = take(E * 3 * 8);
+  L.nbox = take(E * 6 * 8);
   L.nbr_elem = take(E * 6 * 4);
   L.nbr_face = take(E * 6 * 4);
   L.bc = take(E * 6);
@@ -454,6 +457,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   m.vol = (const double*)(b + L.vol);
   m.elo = (const double*)(b + L.elo);
   m.ehi = (const double*)(b + L.ehi);
+  m.nbox = (const double*)(b + L.nbox);
   for (int i = 0; i < kMaxNodes; ++i) {
     m.xgeo[i] = i < c->ng ? c->xgeo[i] : 0.0;
     m.cgeo[i] = i < c->ng ? c->cgeo[i] : 0.0;
@@ -493,11 +497,16 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   HIPCHK(c, launch_face_setup(m, m.X, (const int32_t*)(b + L.nbr_elem), (const int32_t*)(b + L.nbr_face),
                               (const int8_t*)(b + L.bc), (const double*)(b + L.shift), c->Minv.data(),
                               (FaceRec*)(b + L.faces), (double*)(b + L.cp), s));
-  HIPCHK(c, launch_nodes(m, (double*)(b + L.xnode), (double*)(b + L.vol), (double*)(b + L.hE), c->scratch_i32, s));
+  HIPCHK(c, launch_nodes(m, (double*)(b + L.xnode), (double*)(b + L.vol), (double*)(b + L.hE), (double*)(b + L.nbox),
+                         c->scratch_i32, (unsigned long long*)(b + L.scratch + 8), s));
   int32_t bad = 0;
+  unsigned long long pad_bits = 0;
   HIPCHK(c, hipMemcpyAsync(&bad, c->scratch_i32, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&pad_bits, b + L.scratch + 8, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (bad) return fail(c, FP_EMESH, "fp_bind_workspace: non-positive Jacobian at " + std::to_string(bad) + " nodes");
+  std::memcpy(&c->node_pad, &pad_bits, 8);
+  c->dep_pad = (unsigned long long*)(b + L.scratch + 16);
   c->np = 0;
   return FP_OK;
 }
@@ -646,8 +655,8 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   if (period)
     for (int k = 0; k < 3; ++k) per[k] = period[k];
   for (int k = 0; k < 3; ++k)
-    if (per[k] > 0.0 && per[k] <= 2.0 * (radius + c->max_extent))
-      return fail(c, FP_EINVAL, "fp_deposit_source: period too short for the kernel radius");
+    if (per[k] > 0.0 && per[k] <= 2.0 * radius)
+      return fail(c, FP_EINVAL, "fp_deposit_source: a period must exceed twice the kernel radius");
   if (c->np == 0) return FP_OK;
   // gather needs the particles bucketed by their current element
   int rc = sort_particles(c);
@@ -655,7 +664,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   {
     Timed tm(c, 4);
     HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, radius, per,
-                                   c->dep_buf, c->dep_buf, c->sort_start, c->stream));
+                                   c->node_pad, c->dep_buf, c->sort_start, c->dep_pad, c->stream));
   }
   return FP_OK;
 }
@@ -723,6 +732,7 @@ int fp_get_stats(fp_ctx* c, int64_t* out) {
   out[6] = c->sorts;
   out[7] = (int64_t)h[ST_STRAG];
   out[8] = (int64_t)h[ST_TRACKQ];
+  out[9] = (int64_t)h[ST_RECOVER];
   return FP_OK;
 }
 

@@ -3,70 +3,177 @@
 // sum_k S_k V_k = -F (the projection keeps the conservation property of the
 // nearest-DOF operator of Sec. 2.3 while spreading the source).
 //
-// Two kernels, no atomics:
-//  1. per particle: drag force F and the normalisation sum_j K(r_j) V_j,
-//     stored as G = F / norm;
-//  2. per target element (one workgroup): every node gathers K(r) G over the
-//     particles of the candidate source elements (particles sorted by element).
+// Three kernels, no atomics on the source itself:
+//  1. per particle: drag force F and a validity flag;
+//  2. per source element (one workgroup): the normalisation sum_j K(r_j) V_j
+//     of each of its particles.  Lanes hold the DG nodes of one candidate
+//     target element; the test "particle within R of the target's node box"
+//     is uniform over the wave, so far pairs cost one branch.  F is replaced
+//     in place by G = -F / norm;
+//  3. per target element (one workgroup, one thread per DG node): candidate
+//     source particles are staged through LDS in chunks, culled against the
+//     target's node box, and every node accumulates K(r) G.
+// Candidate elements come from the background mesh and are streamed through
+// LDS in windows, so no element count is limited by LDS capacity.
+// Workgroups are mapped to elements XCD by XCD (contiguous element ranges per
+// XCD), so neighbouring elements share an L2.
 #include "fp_device.h"
 #include "fp_launch.h"
 
 namespace fp {
 
+namespace {
+
+constexpr int kDepThreads = 256;
+constexpr int kDepWaves = kDepThreads / 64;
+constexpr int kDepCand = 256;   // candidate elements per LDS window
+constexpr int kDepChunk = 16;   // particles per normalisation pass
+constexpr int kXcd = 8;
+
 struct DepGeo {
   double R, R2, iR2;
+  double node_pad;     // largest distance of a DG node outside its element box
   double period[3];
 };
 
-// element candidates of the box [lo, hi] through the background mesh; each
-// element is visited once (in the first background cell of the overlap)
-template <typename F>
-__device__ inline void for_each_candidate(const MeshView& m, const double* lo, const double* hi, F&& fn) {
-  int c0[3], c1[3];
-  for (int k = 0; k < 3; ++k) {
-    c0[k] = (int)floor((lo[k] - m.blo[k]) / m.bdx[k]);
-    c1[k] = (int)floor((hi[k] - m.blo[k]) / m.bdx[k]);
-    c0[k] = max(c0[k], 0);
-    c1[k] = min(c1[k], m.bn[k] - 1);
-    if (c0[k] > c1[k]) return;
-  }
-  for (int z = c0[2]; z <= c1[2]; ++z)
-    for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x) {
-        int64_t cell = ((int64_t)z * m.bn[1] + y) * m.bn[0] + x;
-        for (int q = m.bstart[cell]; q < m.bstart[cell + 1]; ++q) {
-          int e = m.blist[q];
-          int own[3] = {x, y, z};
-          bool first = true;
-          for (int k = 0; k < 3; ++k) {
-            int ec = (int)floor((m.elo[e * 3 + k] - m.blo[k]) / m.bdx[k]);
-            ec = max(ec, 0);
-            if (own[k] != max(c0[k], ec)) first = false;
-          }
-          if (!first) continue;
-          // box distance test
-          bool near = true;
-          for (int k = 0; k < 3; ++k)
-            if (m.elo[e * 3 + k] > hi[k] || m.ehi[e * 3 + k] < lo[k]) near = false;
-          if (near) fn(e);
-        }
-      }
+struct CandLds {
+  int32_t e[kDepCand];
+  int8_t img[kDepCand];        // ((iz+1)*3 + (iy+1))*3 + (ix+1)
+  int32_t wsum[kDepWaves];
+};
+
+__device__ __forceinline__ int xcd_element(int b, int E) {
+  int per = (E + kXcd - 1) / kXcd;
+  return (b % kXcd) * per + b / kXcd;
 }
 
-__device__ __forceinline__ void min_image(double* r, const double* period) {
+__device__ __forceinline__ void image_shift(int code, const double* period, double* s) {
+  s[0] = (code % 3 - 1) * period[0];
+  s[1] = ((code / 3) % 3 - 1) * period[1];
+  s[2] = (code / 9 - 1) * period[2];
+}
+
+// squared distance from x to the box [lo, hi]
+__device__ __forceinline__ double box_dist2(const double* x, const double* lo, const double* hi) {
+  double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (period[k] > 0.0) r[k] -= period[k] * rint(r[k] / period[k]);
+  for (int k = 0; k < 3; ++k) {
+    double d = fmax(fmax(lo[k] - x[k], x[k] - hi[k]), 0.0);
+    s += d * d;
+  }
+  return s;
 }
 
+__device__ __forceinline__ int lane_rank(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// exclusive prefix sum over the workgroup; every thread must call it
+__device__ inline int block_excl_scan(int v, int32_t* wsum, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kDepWaves; ++k) {
+    int t = wsum[k];
+    base += (k < w) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
+
+// Every element whose (padded) box overlaps [lo - pad, hi + pad], or a periodic
+// image of that box shifted by +img * period, is passed exactly once (in the
+// first background cell of the overlap) to body(count), in windows of at most
+// kDepCand entries held in L.e / L.img.  Order is deterministic.  All threads
+// of the workgroup must call it with the same arguments.
+template <class Body>
+__device__ __forceinline__ void stream_candidates(const MeshView& m, const double* period, const double* lo,
+                                                  const double* hi, double pad, CandLds& L, Body&& body) {
+  for (int code = 0; code < 27; ++code) {
+    const int im[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
+    bool skip = false;
+    double qlo[3], qhi[3];
+    int c0[3], c1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (im[k] != 0 && !(period[k] > 0.0)) skip = true;
+      qlo[k] = lo[k] + im[k] * period[k] - pad;
+      qhi[k] = hi[k] + im[k] * period[k] + pad;
+      c0[k] = max((int)floor((qlo[k] - m.blo[k]) / m.bdx[k]), 0);
+      c1[k] = min((int)floor((qhi[k] - m.blo[k]) / m.bdx[k]), m.bn[k] - 1);
+      if (c0[k] > c1[k]) skip = true;
+    }
+    if (skip) continue;
+    const int nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1, nz = c1[2] - c0[2] + 1;
+    const int ncell = nx * ny * nz;
+    for (int cb = 0; cb < ncell; cb += kDepThreads) {
+      const int ci = cb + threadIdx.x;
+      int own[3] = {0, 0, 0}, beg = 0, end = 0;
+      if (ci < ncell) {
+        own[0] = c0[0] + ci % nx;
+        own[1] = c0[1] + (ci / nx) % ny;
+        own[2] = c0[2] + ci / (nx * ny);
+        int64_t cell = ((int64_t)own[2] * m.bn[1] + own[1]) * m.bn[0] + own[0];
+        beg = m.bstart[cell];
+        end = m.bstart[cell + 1];
+      }
+      auto accept = [&](int e) {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          double el = m.elo[e * 3 + k];
+          int ec = max((int)floor((el - m.blo[k]) / m.bdx[k]), 0);
+          if (own[k] != max(c0[k], ec)) ok = false;
+          if (el > qhi[k] || m.ehi[e * 3 + k] < qlo[k]) ok = false;
+        }
+        return ok;
+      };
+      int cnt = 0;
+      for (int q = beg; q < end; ++q) cnt += accept(m.blist[q]) ? 1 : 0;
+      int tot = 0;
+      const int off = block_excl_scan(cnt, L.wsum, tot);
+      for (int w0 = 0; w0 < tot; w0 += kDepCand) {
+        if (cnt > 0 && off < w0 + kDepCand && off + cnt > w0) {
+          int r = off;
+          for (int q = beg; q < end; ++q) {
+            int e = m.blist[q];
+            if (!accept(e)) continue;
+            if (r >= w0 && r < w0 + kDepCand) {
+              L.e[r - w0] = e;
+              L.img[r - w0] = (int8_t)code;
+            }
+            ++r;
+          }
+        }
+        __syncthreads();
+        body(min(tot - w0, kDepCand));
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// 1. force and validity ------------------------------------------------------
 template <int NN, int NG, typename UT>
-__global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Fluid fl, int64_t n, int drag, DepGeo g,
-                                                   double* G) {
+__global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Fluid fl, int64_t n, int drag, double* F,
+                                                   int32_t* ok, unsigned long long* povh) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) *povh = 0ull;
   if (p >= n) return;
   constexpr int N3 = NN * NN * NN;
-  double* Gp = G + p * 4;
-  Gp[0] = Gp[1] = Gp[2] = Gp[3] = 0.0;
+  double* Fp = F + p * 4;
+  Fp[0] = Fp[1] = Fp[2] = Fp[3] = 0.0;
+  ok[p] = 0;
   if (P.status[p] != ACTIVE) return;
   const int64_t cap = P.cap;
   int e = P.elem[p];
@@ -82,90 +189,218 @@ __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Flui
   double d = P.d[p], a[3], fD;
   drag_accel<double>(drag, Uc[0], u, v, d, fl.mu, fl.rho_p, a, fD);
   double c = 3.0 * M_PI * fl.mu * d * fD;
-  double F[4] = {c * (u[0] - v[0]), c * (u[1] - v[1]), c * (u[2] - v[2]), 0.0};
-  F[3] = F[0] * v[0] + F[1] * v[1] + F[2] * v[2];
-  // normalisation over all nodes within R (periodic images by shifted boxes)
-  double norm = 0.0;
-  int nimg[3];
-  for (int k = 0; k < 3; ++k) nimg[k] = g.period[k] > 0.0 ? 3 : 1;
-  for (int iz = 0; iz < nimg[2]; ++iz)
-    for (int iy = 0; iy < nimg[1]; ++iy)
-      for (int ix = 0; ix < nimg[0]; ++ix) {
-        int img[3] = {ix == 2 ? -1 : ix, iy == 2 ? -1 : iy, iz == 2 ? -1 : iz};
-        double lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-          double cc = x[k] + img[k] * g.period[k];
-          lo[k] = cc - g.R;
-          hi[k] = cc + g.R;
-        }
-        for_each_candidate(m, lo, hi, [&](int es) {
-          const double* xn = m.xnode + (size_t)es * N3 * 3;
-          const double* vol = m.vol + (size_t)es * N3;
-          for (int q = 0; q < N3; ++q) {
-            double r[3] = {xn[q * 3] - x[0], xn[q * 3 + 1] - x[1], xn[q * 3 + 2] - x[2]};
-            min_image(r, g.period);
-            double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            if (r2 < g.R2) {
-              double s = 1.0 - r2 * g.iR2;
-              norm += s * s * vol[q];
-            }
-          }
-        });
+  Fp[0] = c * (u[0] - v[0]);
+  Fp[1] = c * (u[1] - v[1]);
+  Fp[2] = c * (u[2] - v[2]);
+  Fp[3] = Fp[0] * v[0] + Fp[1] * v[1] + Fp[2] * v[2];
+  ok[p] = 1;
+}
+
+// 2. normalisation per source element ---------------------------------------
+// Each lane keeps its partial sums in its own LDS column (s_acc[wave][i][lane]),
+// so the particle loop stays dynamic and no per-pair reduction is needed.
+template <int NN>
+__global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles P, const int32_t* __restrict__ elem_start,
+                                                          DepGeo g, double* F, const int32_t* __restrict__ ok,
+                                                          unsigned long long* povh) {
+  const int es = xcd_element(blockIdx.x, m.E);
+  if (es >= m.E) return;
+  const int p0 = elem_start[es], p1 = elem_start[es + 1];
+  if (p0 == p1) return;
+  constexpr int N3 = NN * NN * NN;
+  constexpr int NPL = (N3 + 63) / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t cap = P.cap;
+  __shared__ CandLds L;
+  __shared__ double s_x[kDepChunk][3];
+  __shared__ double s_acc[kDepWaves][kDepChunk][64];
+  __shared__ double s_q[6];
+  __shared__ int s_any;
+  for (int c0 = p0; c0 < p1; c0 += kDepChunk) {
+    const int cnt = min(kDepChunk, p1 - c0);
+    if (threadIdx.x < kDepChunk) {
+      const int i = threadIdx.x;
+      double x[3] = {1e300, 1e300, 1e300};
+      if (i < cnt && ok[c0 + i]) {
+        const int64_t p = c0 + i;
+        x[0] = P.x[p]; x[1] = P.x[cap + p]; x[2] = P.x[2 * cap + p];
+        double ov = 0.0;
+        for (int k = 0; k < 3; ++k)
+          ov = fmax(ov, fmax(m.elo[es * 3 + k] - x[k], x[k] - m.ehi[es * 3 + k]));
+        if (ov > 0.0) atomicMax(povh, (unsigned long long)__double_as_longlong(ov));
       }
-  if (norm > 0.0) {
-    double in = 1.0 / norm;
-    for (int k = 0; k < 4; ++k) Gp[k] = -F[k] * in;
+      for (int k = 0; k < 3; ++k) s_x[i][k] = x[k];
+    }
+    for (int i = 0; i < kDepChunk; ++i) s_acc[wave][i][lane] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      int any = 0;
+      for (int i = 0; i < cnt; ++i)
+        if (s_x[i][0] < 1e299) {
+          any = 1;
+          for (int k = 0; k < 3; ++k) { lo[k] = fmin(lo[k], s_x[i][k]); hi[k] = fmax(hi[k], s_x[i][k]); }
+        }
+      for (int k = 0; k < 3; ++k) { s_q[k] = lo[k]; s_q[3 + k] = hi[k]; }
+      s_any = any;
+    }
+    __syncthreads();
+    if (!s_any) continue;   // uniform
+    double qlo[3] = {s_q[0], s_q[1], s_q[2]}, qhi[3] = {s_q[3], s_q[4], s_q[5]};
+    stream_candidates(m, g.period, qlo, qhi, g.R + g.node_pad, L, [&](int nc) {
+      for (int t = wave; t < nc; t += kDepWaves) {
+        const int e = L.e[t];
+        double sh[3];
+        image_shift(L.img[t], g.period, sh);
+        const double* nb = m.nbox + (size_t)e * 6;
+        const double blo[3] = {nb[0] - sh[0], nb[1] - sh[1], nb[2] - sh[2]};
+        const double bhi[3] = {nb[3] - sh[0], nb[4] - sh[1], nb[5] - sh[2]};
+        double xn[NPL][3], vn[NPL];
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          const int q = lane + 64 * j;
+          if (q < N3) {
+            const double* src = m.xnode + ((size_t)e * N3 + q) * 3;
+            xn[j][0] = src[0] - sh[0]; xn[j][1] = src[1] - sh[1]; xn[j][2] = src[2] - sh[2];
+            vn[j] = m.vol[(size_t)e * N3 + q];
+          } else {
+            xn[j][0] = xn[j][1] = xn[j][2] = 1e300;
+            vn[j] = 0.0;
+          }
+        }
+        for (int i = 0; i < cnt; ++i) {
+          const double px[3] = {s_x[i][0], s_x[i][1], s_x[i][2]};
+          if (!(box_dist2(px, blo, bhi) < g.R2)) continue;
+          double a = 0.0;
+#pragma unroll
+          for (int j = 0; j < NPL; ++j) {
+            const double r0 = xn[j][0] - px[0], r1 = xn[j][1] - px[1], r2 = xn[j][2] - px[2];
+            const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+            const double s = 1.0 - rr * g.iR2;
+            a += (rr < g.R2) ? s * s * vn[j] : 0.0;
+          }
+          s_acc[wave][i][lane] += a;
+        }
+      }
+    });
+    // sum over waves and lanes: 16 threads per particle, fixed order
+    {
+      constexpr int TPP = kDepThreads / kDepChunk;   // threads per particle
+      const int i = threadIdx.x / TPP, sub = threadIdx.x % TPP;
+      double v = 0.0;
+      for (int w = 0; w < kDepWaves; ++w)
+        for (int l = sub; l < 64; l += TPP) v += s_acc[w][i][l];
+#pragma unroll
+      for (int off = TPP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (sub == 0 && i < cnt) {
+        const int64_t p = c0 + i;
+        double* Fp = F + p * 4;
+        const bool use = ok[p] && v > 0.0;
+        const double in = use ? -1.0 / v : 0.0;
+        for (int k = 0; k < 4; ++k) Fp[k] = use ? Fp[k] * in : 0.0;
+      }
+    }
+    __syncthreads();
   }
 }
 
+// 3. gather per target element ----------------------------------------------
 template <int NN, typename ST>
-__global__ __launch_bounds__(256) void k_dep_gather(MeshView m, Particles P, const int32_t* __restrict__ elem_start,
-                                                    DepGeo g, const double* __restrict__ G, ST* S) {
-  int t = blockIdx.x;
+__global__ __launch_bounds__(kDepThreads) void k_dep_gather(MeshView m, Particles P,
+                                                            const int32_t* __restrict__ elem_start, DepGeo g,
+                                                            const double* __restrict__ G,
+                                                            const unsigned long long* __restrict__ povh, ST* S) {
+  const int t = xcd_element(blockIdx.x, m.E);
+  if (t >= m.E) return;
   constexpr int N3 = NN * NN * NN;
-  constexpr int PER = (N3 + 255) / 256;
+  constexpr int PER = (N3 + kDepThreads - 1) / kDepThreads;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t cap = P.cap;
+  __shared__ CandLds L;
+  __shared__ int32_t s_pre[kDepCand + 1];
+  __shared__ double s_px[kDepThreads][3];
+  __shared__ double s_pg[kDepThreads][4];
+  __shared__ int32_t s_wcnt[kDepWaves];
   double xn[PER][3], acc[PER][4];
+#pragma unroll
   for (int s = 0; s < PER; ++s) {
-    int q = threadIdx.x + s * 256;
+    const int q = threadIdx.x + s * kDepThreads;
+#pragma unroll
     for (int k = 0; k < 4; ++k) acc[s][k] = 0.0;
+#pragma unroll
     for (int k = 0; k < 3; ++k) xn[s][k] = (q < N3) ? m.xnode[((size_t)t * N3 + q) * 3 + k] : 1e300;
   }
-  const int64_t cap = P.cap;
-  int nimg[3];
-  for (int k = 0; k < 3; ++k) nimg[k] = g.period[k] > 0.0 ? 3 : 1;
-  for (int iz = 0; iz < nimg[2]; ++iz)
-    for (int iy = 0; iy < nimg[1]; ++iy)
-      for (int ix = 0; ix < nimg[0]; ++ix) {
-        int img[3] = {ix == 2 ? -1 : ix, iy == 2 ? -1 : iy, iz == 2 ? -1 : iz};
-        double lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = m.elo[t * 3 + k] + img[k] * g.period[k] - g.R;
-          hi[k] = m.ehi[t * 3 + k] + img[k] * g.period[k] + g.R;
+  const double* nb = m.nbox + (size_t)t * 6;
+  const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
+  const double part_pad = __longlong_as_double((long long)*povh);
+  stream_candidates(m, g.period, blo, bhi, g.R + part_pad, L, [&](int nc) {
+    const int cntc = (threadIdx.x < nc) ? elem_start[L.e[threadIdx.x] + 1] - elem_start[L.e[threadIdx.x]] : 0;
+    int T = 0;
+    const int off = block_excl_scan(cntc, L.wsum, T);
+    if (threadIdx.x < nc) s_pre[threadIdx.x] = off;
+    __syncthreads();
+    for (int jb = 0; jb < T; jb += kDepThreads) {
+      const int j = jb + threadIdx.x;
+      bool keep = false;
+      double px[3] = {0, 0, 0}, pg[4] = {0, 0, 0, 0};
+      if (j < T) {
+        int lo = 0, hi = nc - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= j) lo = mid;
+          else hi = mid - 1;
         }
-        for_each_candidate(m, lo, hi, [&](int es) {
-          for (int p = elem_start[es]; p < elem_start[es + 1]; ++p) {
-            double xp[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
-            double G0 = G[(int64_t)p * 4], G1 = G[(int64_t)p * 4 + 1], G2 = G[(int64_t)p * 4 + 2],
-                   G3 = G[(int64_t)p * 4 + 3];
-            for (int s = 0; s < PER; ++s) {
-              double r[3] = {xn[s][0] - xp[0], xn[s][1] - xp[1], xn[s][2] - xp[2]};
-              min_image(r, g.period);
-              double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-              if (r2 < g.R2) {
-                double w = 1.0 - r2 * g.iR2;
-                w *= w;
-                acc[s][0] += w * G0;
-                acc[s][1] += w * G1;
-                acc[s][2] += w * G2;
-                acc[s][3] += w * G3;
-              }
-            }
-          }
-        });
+        const int e = L.e[lo];
+        const int64_t p = elem_start[e] + (j - s_pre[lo]);
+        double sh[3];
+        image_shift(L.img[lo], g.period, sh);
+        px[0] = P.x[p] - sh[0];
+        px[1] = P.x[cap + p] - sh[1];
+        px[2] = P.x[2 * cap + p] - sh[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pg[k] = G[p * 4 + k];
+        keep = (pg[0] != 0.0 || pg[1] != 0.0 || pg[2] != 0.0 || pg[3] != 0.0) && box_dist2(px, blo, bhi) < g.R2;
       }
+      const unsigned long long bal = __ballot(keep);
+      if (lane == 0) s_wcnt[wave] = (int)__popcll(bal);
+      __syncthreads();
+      int base = 0, nk = 0;
+#pragma unroll
+      for (int w = 0; w < kDepWaves; ++w) {
+        base += (w < wave) ? s_wcnt[w] : 0;
+        nk += s_wcnt[w];
+      }
+      if (keep) {
+        const int slot = base + lane_rank(bal);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_px[slot][k] = px[k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_pg[slot][k] = pg[k];
+      }
+      __syncthreads();
+      for (int k = 0; k < nk; ++k) {
+        const double x0 = s_px[k][0], x1 = s_px[k][1], x2 = s_px[k][2];
+        const double g0 = s_pg[k][0], g1 = s_pg[k][1], g2 = s_pg[k][2], g3 = s_pg[k][3];
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+          const double r0 = xn[s][0] - x0, r1 = xn[s][1] - x1, r2 = xn[s][2] - x2;
+          const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+          double w = 1.0 - rr * g.iR2;
+          w = (rr < g.R2) ? w * w : 0.0;
+          acc[s][0] += w * g0;
+          acc[s][1] += w * g1;
+          acc[s][2] += w * g2;
+          acc[s][3] += w * g3;
+        }
+      }
+      __syncthreads();
+    }
+  });
+#pragma unroll
   for (int s = 0; s < PER; ++s) {
-    int q = threadIdx.x + s * 256;
+    const int q = threadIdx.x + s * kDepThreads;
     if (q < N3)
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         ST* dst = S + ((size_t)t * 4 + k) * N3 + q;
         *dst = (ST)((double)*dst + acc[s][k]);
@@ -173,27 +408,31 @@ __global__ __launch_bounds__(256) void k_dep_gather(MeshView m, Particles P, con
   }
 }
 
+}  // namespace
+
 #include "fp_shapes.h"
 
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
-                                int s_f32, int drag, double R, const double* period, double* norm_buf,
-                                double* force_buf, const int32_t* elem_start, hipStream_t s) {
-  (void)norm_buf;
+                                int s_f32, int drag, double R, const double* period, double node_pad, double* dep,
+                                const int32_t* elem_start, unsigned long long* povh, hipStream_t s) {
   DepGeo g;
   g.R = R;
   g.R2 = R * R;
   g.iR2 = 1.0 / (R * R);
+  g.node_pad = node_pad;
   for (int k = 0; k < 3; ++k) g.period[k] = period[k];
+  double* F = dep;
+  int32_t* ok = (int32_t*)(dep + 4 * P.cap);
   dim3 gp((unsigned)((std::max<int64_t>(n, 1) + 255) / 256));
-#define FP_L(A, B)                                                                                     \
-  if (m.n == A && m.ng == B) {                                                                         \
-    if (n > 0) {                                                                                       \
-      if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, drag, g, force_buf);      \
-      else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, drag, g, force_buf);            \
-    }                                                                                                  \
-    if (s_f32) k_dep_gather<A, float><<<m.E, 256, 0, s>>>(m, P, elem_start, g, force_buf, (float*)S);  \
-    else k_dep_gather<A, double><<<m.E, 256, 0, s>>>(m, P, elem_start, g, force_buf, (double*)S);     \
-    return hipGetLastError();                                                                          \
+  dim3 ge((unsigned)(((m.E + kXcd - 1) / kXcd) * kXcd));
+#define FP_L(A, B)                                                                                           \
+  if (m.n == A && m.ng == B) {                                                                               \
+    if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, drag, F, ok, povh);                 \
+    else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, drag, F, ok, povh);                       \
+    k_dep_norm<A><<<ge, kDepThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                              \
+    if (s_f32) k_dep_gather<A, float><<<ge, kDepThreads, 0, s>>>(m, P, elem_start, g, F, povh, (float*)S);   \
+    else k_dep_gather<A, double><<<ge, kDepThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);      \
+    return hipGetLastError();                                                                                \
   }
   FP_FOR_EACH_SHAPE(FP_L)
 #undef FP_L

@@ -379,6 +379,32 @@ __device__ __forceinline__ bool locate_xi(const MeshView& m, int e, const double
                                     m.xnode + (size_t)e * (NN * NN * NN * 3), x, xi, max_it, it_sum, calls, fallbacks);
 }
 
+// A located particle lies outside its element (a crossing that the clipping
+// budget missed at grazing incidence): follow the reference coordinate with
+// the largest excess to the neighbour across that face (lowest axis on ties),
+// applying the periodic shift, and locate again, at most kRecoverHops times.
+// Walls and open faces end the search (a missed reflection cannot be undone).
+// On success e, x and xi describe the particle in its element.
+template <int NN, int NG>
+__device__ inline bool recover_elem(const MeshView& m, int& e, double* x, double* xi, int max_it, int& it_sum,
+                                    int& calls, int& fallbacks) {
+#pragma unroll 1
+  for (int hop = 0; hop < kRecoverHops; ++hop) {
+    int d = 0;
+    double ex = fabs(xi[0]);
+    if (fabs(xi[1]) > ex) { d = 1; ex = fabs(xi[1]); }
+    if (fabs(xi[2]) > ex) { d = 2; ex = fabs(xi[2]); }
+    const FaceRec& F = m.faces[e * 6 + 2 * d + (xi[d] > 0.0 ? 1 : 0)];
+    if (F.bc != BC_INTERNAL && F.bc != BC_PERIODIC) return false;
+    if (F.bc == BC_PERIODIC)
+      for (int k = 0; k < 3; ++k) x[k] += F.shift[k];
+    e = F.nbr_elem;
+    if (!locate_xi<NN, NG>(m, e, x, xi, max_it, false, it_sum, calls, fallbacks)) return false;
+    if (inside_ref(xi)) return true;
+  }
+  return false;
+}
+
 // ---------------------------------------------------------------------------
 // interpolation of the five conservative variables (eq. part_interpolation)
 // ---------------------------------------------------------------------------
@@ -463,6 +489,96 @@ __device__ __forceinline__ void drag_accel(int drag, T rho, const T* u, const T*
 // ---------------------------------------------------------------------------
 // face intersection (Sec. 3.2.4)
 // ---------------------------------------------------------------------------
+// Bezier control points of local face f of an element (Lagrange geometry
+// nodes Xe -> Bernstein form, P = M^-1 F M^-T with Mi = M^-1 row-major), its
+// oriented bounding box, corner bilinear coefficients and type (Sec. 3.2.4).
+// Neighbour, boundary and shift fields are left to the caller.
+template <int NG>
+__device__ inline void face_setup(const double* __restrict__ Xe, int f, const double* __restrict__ Mi, double* cp,
+                                  FaceRec& F) {
+  constexpr int D = NG - 1;
+  int d = f / 2, a = (d == 0) ? 1 : 0, b = (d == 2) ? 1 : 2;
+  int fix = (f & 1) ? D : 0;
+  double T[NG * NG][3];
+  for (int n = 0; n < NG; ++n)
+    for (int mm = 0; mm < NG; ++mm) {
+      double s[3] = {0, 0, 0};
+      for (int r = 0; r < NG; ++r) {
+        int idx[3];
+        idx[d] = fix; idx[a] = r; idx[b] = n;
+        const double* P = Xe + ((idx[2] * NG + idx[1]) * NG + idx[0]) * 3;
+        double w = Mi[mm * NG + r];
+        s[0] += w * P[0]; s[1] += w * P[1]; s[2] += w * P[2];
+      }
+      T[n * NG + mm][0] = s[0]; T[n * NG + mm][1] = s[1]; T[n * NG + mm][2] = s[2];
+    }
+  for (int n = 0; n < NG; ++n)
+    for (int mm = 0; mm < NG; ++mm) {
+      double s[3] = {0, 0, 0};
+      for (int r = 0; r < NG; ++r) {
+        double w = Mi[n * NG + r];
+        s[0] += w * T[r * NG + mm][0]; s[1] += w * T[r * NG + mm][1]; s[2] += w * T[r * NG + mm][2];
+      }
+      cp[(n * NG + mm) * 3 + 0] = s[0]; cp[(n * NG + mm) * 3 + 1] = s[1]; cp[(n * NG + mm) * 3 + 2] = s[2];
+    }
+  const double* C00 = cp;
+  const double* CN0 = cp + D * 3;
+  const double* C0N = cp + D * NG * 3;
+  const double* CNN = cp + (D * NG + D) * 3;
+  double diam = 0.0;
+  for (int i = 0; i < NG * NG; ++i)
+    for (int j = i + 1; j < NG * NG; ++j) {
+      double r[3] = {cp[i * 3] - cp[j * 3], cp[i * 3 + 1] - cp[j * 3 + 1], cp[i * 3 + 2] - cp[j * 3 + 2]};
+      diam = fmax(diam, sqrt(dot3(r, r)));
+    }
+  double g1[3], g2[3], eu[3];
+  for (int q = 0; q < 3; ++q) {
+    g1[q] = CNN[q] - C00[q];
+    g2[q] = C0N[q] - CN0[q];
+    eu[q] = (CN0[q] - C00[q]) + (CNN[q] - C0N[q]);
+  }
+  cross3(g1, g2, F.nrm);
+  double il = 1.0 / sqrt(dot3(F.nrm, F.nrm));
+  for (int q = 0; q < 3; ++q) F.nrm[q] *= il;
+  double pr = dot3(eu, F.nrm);
+  for (int q = 0; q < 3; ++q) eu[q] -= pr * F.nrm[q];
+  il = 1.0 / sqrt(dot3(eu, eu));
+  for (int q = 0; q < 3; ++q) F.e1[q] = eu[q] * il;
+  cross3(F.nrm, F.e1, F.e2);
+  for (int q = 0; q < 3; ++q) {
+    F.org[q] = C00[q];
+    F.lo[q] = 1e300;
+    F.hi[q] = -1e300;
+  }
+  for (int i = 0; i < NG * NG; ++i) {
+    double r[3] = {cp[i * 3] - F.org[0], cp[i * 3 + 1] - F.org[1], cp[i * 3 + 2] - F.org[2]};
+    double p0 = dot3(r, F.nrm), p1 = dot3(r, F.e1), p2 = dot3(r, F.e2);
+    F.lo[0] = fmin(F.lo[0], p0); F.hi[0] = fmax(F.hi[0], p0);
+    F.lo[1] = fmin(F.lo[1], p1); F.hi[1] = fmax(F.hi[1], p1);
+    F.lo[2] = fmin(F.lo[2], p2); F.hi[2] = fmax(F.hi[2], p2);
+  }
+  F.diam = diam;
+  for (int q = 0; q < 3; ++q) {
+    F.A[q] = 0.25 * (C00[q] - CN0[q] - C0N[q] + CNN[q]);
+    F.B[q] = 0.25 * (-C00[q] + CN0[q] - C0N[q] + CNN[q]);
+    F.C[q] = 0.25 * (-C00[q] - CN0[q] + C0N[q] + CNN[q]);
+    F.D[q] = 0.25 * (C00[q] + CN0[q] + C0N[q] + CNN[q]);
+  }
+  double tol = 1e-12 * diam;
+  bool planar = (F.hi[0] - F.lo[0]) <= tol;
+  bool bilin = true;
+  for (int n = 0; n < NG && bilin; ++n)
+    for (int mm = 0; mm < NG && bilin; ++mm) {
+      double s = (double)mm / D, t = (double)n / D;
+      for (int q = 0; q < 3; ++q) {
+        double p = (1 - s) * (1 - t) * C00[q] + s * (1 - t) * CN0[q] + (1 - s) * t * C0N[q] + s * t * CNN[q];
+        if (fabs(p - cp[(n * NG + mm) * 3 + q]) > tol) { bilin = false; break; }
+      }
+    }
+  double tw = sqrt(dot3(F.A, F.A));
+  F.type = (planar && bilin && tw <= tol) ? FACE_PLANAR : (bilin ? FACE_BILINEAR : FACE_CURVED);
+}
+
 __device__ inline bool bbox_hit(const FaceRec& F, const double* xs, const double* xe) {
   double pad = 1e-9 * F.diam;
   double r0[3] = {xs[0] - F.org[0], xs[1] - F.org[1], xs[2] - F.org[2]};
@@ -677,14 +793,15 @@ __device__ __forceinline__ bool half_extent(const double* lo, const double* hi, 
   return tmin <= tmax;
 }
 
-// Clip direction dir (0: u, 1: v) of the projected patch q[m][k][2] (signed
-// distances to the two planes that contain the ray): Bezier clipping against
-// the line through the origin that runs along the other parameter direction.
-// The convex-hull property of the Bernstein form keeps every root.
+// Clip direction dir (0: u, 1: v) of the projected patch q[m][k][3] (signed
+// distances to the two planes that contain the ray in components 0 and 1):
+// Bezier clipping against the line through the origin that runs along the
+// other parameter direction.  The convex-hull property of the Bernstein form
+// keeps every root.
 template <int NG>
 __device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) {
   constexpr int N = NG - 1;
-#define QQ(m, k, c) q[((m) * NG + (k)) * 2 + (c)]
+#define QQ(m, k, c) q[((m) * NG + (k)) * 3 + (c)]
   double L0, L1;
   if (dir == 0) {
     L0 = (QQ(0, N, 0) - QQ(0, 0, 0)) + (QQ(N, N, 0) - QQ(N, 0, 0));
@@ -732,57 +849,73 @@ __device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) 
   return true;
 }
 
-// Intersections of the line x0 + alpha t (|t| = 1) with a curved Bezier face,
-// keeping those with displacement in [amin, amax]: the face is projected onto
-// two planes containing the line (Sec. 3.2.4) and the zero of the 2-D patch is
-// isolated by Bezier clipping, alternating u and v and splitting where a clip
-// removes less than 20 %.  Faces whose control points all lie outside the
-// displacement band are rejected at once (convex hull).  Boxes narrower than
-// 1e-7 are finished by 2-D Newton on the projected patch (quadratic from there).
+// projected control points of the whole face: distances to the planes n1, n2
+// (components 0, 1) and displacement along t (component 2), [m along u][k along v]
 template <int NG>
-__device__ int curved_hit(const double* __restrict__ cp, const double* x0, const double* t, double amin, double amax,
-                          double* al, double* uv, int max_roots) {
-  constexpr int D = NG - 1;
-  constexpr double kBoxTol = 1e-7;
-  double n1[3], n2[3];
-  ray_planes(t, n1, n2);
-  double q0[NG * NG * 2];
-  double fa = 1e300, fb = -1e300;
+__device__ __forceinline__ void project_face(const double* __restrict__ cp, const double* x0, const double* t,
+                                             const double* n1, const double* n2, double* q) {
 #pragma unroll
   for (int k = 0; k < NG; ++k)
 #pragma unroll
     for (int mm = 0; mm < NG; ++mm) {
       const double* P = cp + (k * NG + mm) * 3;
       double r[3] = {P[0] - x0[0], P[1] - x0[1], P[2] - x0[2]};
-      q0[(mm * NG + k) * 2 + 0] = dot3(r, n1);
-      q0[(mm * NG + k) * 2 + 1] = dot3(r, n2);
-      double ar = dot3(r, t);
-      fa = fmin(fa, ar);
-      fb = fmax(fb, ar);
+      q[(mm * NG + k) * 3 + 0] = dot3(r, n1);
+      q[(mm * NG + k) * 3 + 1] = dot3(r, n2);
+      q[(mm * NG + k) * 3 + 2] = dot3(r, t);
     }
-  if (fb < amin || fa > amax) return 0;
+}
+
+// the displacement of every point of the (sub-)patch lies outside [amin, amax]
+template <int NG>
+__device__ __forceinline__ bool outside_band(const double* q, double amin, double amax) {
+  double lo = 1e300, hi = -1e300;
+#pragma unroll
+  for (int i = 0; i < NG * NG; ++i) {
+    lo = fmin(lo, q[i * 3 + 2]);
+    hi = fmax(hi, q[i * 3 + 2]);
+  }
+  return hi < amin || lo > amax;
+}
+
+// Intersections of the line x0 + alpha t (|t| = 1) with a curved Bezier face,
+// keeping those with displacement in [amin, amax]: the face is projected onto
+// two planes containing the line (Sec. 3.2.4) and the zero of the 2-D patch is
+// isolated by Bezier clipping, alternating u and v and splitting where a clip
+// removes less than 20 %.  A (sub-)patch whose displacement range misses
+// [amin, amax] is dropped (convex hull), which keeps the search on the stage
+// segment at grazing incidence.  Boxes narrower than 1e-7 are finished by 2-D
+// Newton on the plane distances (quadratic from there).  Sub-patches are
+// rebuilt from the face control points when popped, so only one projected
+// patch is live.
+template <int NG>
+__device__ int curved_hit(const double* __restrict__ cp, const double* x0, const double* t, double amin, double amax,
+                          double* al, double* uv, int max_roots) {
+  constexpr double kBoxTol = 1e-7;
+  double n1[3], n2[3];
+  ray_planes(t, n1, n2);
   double stk[kClipStack][4];
   int sp = 1, nroots = 0, budget = kClipSteps;
   stk[0][0] = 0.0; stk[0][1] = 1.0; stk[0][2] = 0.0; stk[0][3] = 1.0;
-  double q[NG * NG * 2];
+  double q[NG * NG * 3];
   while (sp > 0 && budget > 0) {
     --sp;
     double u0 = stk[sp][0], u1 = stk[sp][1], v0 = stk[sp][2], v1 = stk[sp][3];
-#pragma unroll
-    for (int i = 0; i < NG * NG * 2; ++i) q[i] = q0[i];
-    if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG, 2>(q, 0, u0, u1);
-    if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG, 2>(q, 1, v0, v1);
+    project_face<NG>(cp, x0, t, n1, n2, q);
+    if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG, 3>(q, 0, u0, u1);
+    if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG, 3>(q, 1, v0, v1);
     for (;;) {
       if (--budget < 0) break;
+      if (outside_band<NG>(q, amin, amax)) break;
       double a, b;
       if (!clip_dir<NG>(q, 0, a, b)) break;
-      patch_restrict<NG, 2>(q, 0, a, b);
+      patch_restrict<NG, 3>(q, 0, a, b);
       double w = u1 - u0;
       double nu0 = u0 + a * w, nu1 = u0 + b * w;
       u0 = nu0; u1 = nu1;
       double ru = b - a;
       if (!clip_dir<NG>(q, 1, a, b)) break;
-      patch_restrict<NG, 2>(q, 1, a, b);
+      patch_restrict<NG, 3>(q, 1, a, b);
       w = v1 - v0;
       double nv0 = v0 + a * w, nv1 = v0 + b * w;
       v0 = nv0; v1 = nv1;
@@ -792,33 +925,23 @@ __device__ int curved_hit(const double* __restrict__ cp, const double* x0, const
       bool su = (ru > 0.8 && wu > kBoxTol), sv = (rv > 0.8 && wv > kBoxTol);
       if (!conv && (su || sv) && sp + 2 > kClipStack) conv = true;
       if (conv) {
-        double s = 0.5 * (u0 + u1), tt = 0.5 * (v0 + v1);
+        double u = (u0 + u1) - 1.0, v = (v0 + v1) - 1.0;   // box centre in [-1, 1]
+        double p[3], pu[3], pv[3];
 #pragma unroll 1
         for (int it = 0; it < 3; ++it) {
-          double Bs[NG], Bt[NG], dBs[NG], dBt[NG];
-          bern<D>(s, Bs, dBs);
-          bern<D>(tt, Bt, dBt);
-          double G0 = 0, G1 = 0, Gs0 = 0, Gs1 = 0, Gt0 = 0, Gt1 = 0;
-#pragma unroll
-          for (int mm = 0; mm < NG; ++mm)
-#pragma unroll
-            for (int k = 0; k < NG; ++k) {
-              double qx = q0[(mm * NG + k) * 2], qy = q0[(mm * NG + k) * 2 + 1];
-              G0 += qx * Bs[mm] * Bt[k]; G1 += qy * Bs[mm] * Bt[k];
-              Gs0 += qx * dBs[mm] * Bt[k]; Gs1 += qy * dBs[mm] * Bt[k];
-              Gt0 += qx * Bs[mm] * dBt[k]; Gt1 += qy * Bs[mm] * dBt[k];
-            }
-          double det = Gs0 * Gt1 - Gs1 * Gt0;
+          bezier_eval<NG>(cp, u, v, p, pu, pv);
+          double r[3] = {p[0] - x0[0], p[1] - x0[1], p[2] - x0[2]};
+          double G0 = dot3(r, n1), G1 = dot3(r, n2);
+          double Gu0 = dot3(pu, n1), Gu1 = dot3(pu, n2), Gv0 = dot3(pv, n1), Gv1 = dot3(pv, n2);
+          double det = Gu0 * Gv1 - Gu1 * Gv0;
           if (det == 0.0 || !isfinite(det)) break;
-          s += -(G0 * Gt1 - G1 * Gt0) / det;
-          tt += -(Gs0 * G1 - Gs1 * G0) / det;
+          u += -(G0 * Gv1 - G1 * Gv0) / det;
+          v += -(Gu0 * G1 - Gu1 * G0) / det;
         }
-        double u = 2.0 * s - 1.0, v = 2.0 * tt - 1.0;
         bool dup = false;
         for (int r = 0; r < nroots; ++r)
           if (fabs(uv[2 * r] - u) < 1e-9 && fabs(uv[2 * r + 1] - v) < 1e-9) dup = true;
         if (!dup && nroots < max_roots) {
-          double p[3];
           bezier_eval<NG>(cp, u, v, p, nullptr, nullptr);
           double r3[3] = {p[0] - x0[0], p[1] - x0[1], p[2] - x0[2]};
           al[nroots] = dot3(r3, t);
@@ -863,7 +986,11 @@ template <int NG>
 __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
                       int max_cross, int8_t& status, int& hits, int& ncross) {
   double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
-  int excl = -1, count = 0;
+  // excl: planar face just entered through (no further root possible);
+  // entry: non-planar face just entered through, whose root at the entry point
+  // (alpha ~ 0, error growing like 1/sin(incidence)) is ignored below
+  // kEntryRel * face diameter
+  int excl = -1, entry = -1, count = 0;
   for (;;) {
     double t[3] = {xe[0] - xs[0], xe[1] - xs[1], xe[2] - xs[2]};
     double L = sqrt(dot3(t, t));
@@ -879,11 +1006,12 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       const FaceRec& F = m.faces[fid];
       if (!bbox_hit(F, xs, xe)) continue;
       double al[kMaxRoots], uv[2 * kMaxRoots];
-      // only roots with displacement in (eps, L] matter: clip to a padded band
+      // only roots with displacement in (amin, L] matter: clip to a padded band
+      double amin = (f == entry) ? fmax(eps, kEntryRel * F.diam) : eps;
       double pad = 1e-9 * F.diam;
-      int nr = face_roots<NG>(m, fid, F, xs, t, eps - pad, L + pad, al, uv);
+      int nr = face_roots<NG>(m, fid, F, xs, t, amin - pad, L + pad, al, uv);
       for (int r = 0; r < nr; ++r) {
-        if (!(al[r] > eps && al[r] <= L)) continue;
+        if (!(al[r] > amin && al[r] <= L)) continue;
         if (fabs(uv[2 * r]) > 1.0 + kUVEps || fabs(uv[2 * r + 1]) > 1.0 + kUVEps) continue;
         if (al[r] < best) { best = al[r]; bf = f; bu = uv[2 * r]; bv = uv[2 * r + 1]; }
       }
@@ -901,7 +1029,9 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       if (bc == BC_PERIODIC)
         for (int q = 0; q < 3; ++q) { xh[q] += F.shift[q]; xe[q] += F.shift[q]; }
       e = ne;
-      excl = (m.faces[ne * 6 + nf].type == FACE_PLANAR) ? nf : -1;
+      const bool planar = m.faces[ne * 6 + nf].type == FACE_PLANAR;
+      excl = planar ? nf : -1;
+      entry = planar ? -1 : nf;
       xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
     } else if (bc == BC_REFLECT) {
       double nrm[3];
@@ -926,6 +1056,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       }
       hits++;
       excl = (F.type == FACE_PLANAR) ? bf : -1;
+      entry = (F.type == FACE_PLANAR) ? -1 : bf;
       xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
     } else {
       status = OPEN_EXIT;

@@ -19,11 +19,13 @@ constexpr double kInsideEps = 1e-10;
 constexpr double kUVEps = 1e-12;
 constexpr double kClipTol = 1e-12;
 constexpr double kClipPad = 1e-10;
+constexpr double kEntryRel = 1e-9;   // entry-face root threshold, relative to the face diameter
+constexpr int kRecoverHops = 3;      // neighbour hops when a located particle lies outside its element
 
 enum { ACTIVE = 0, OPEN_EXIT = 1, LOST_NEWTON = 2, LOST_TRACK = 3, MAX_CROSS = 4, REJECTED = 5 };
 enum { FACE_PLANAR = 0, FACE_BILINEAR = 1, FACE_CURVED = 2 };
 enum { BC_INTERNAL = 0, BC_OPEN = 1, BC_REFLECT = 2, BC_PERIODIC = 3 };
-enum { ST_NEWTON_IT = 0, ST_NEWTON_CALLS, ST_CROSS, ST_HITS, ST_LOST, ST_FALLBACK, ST_STRAG, ST_TRACKQ, ST_N };
+enum { ST_NEWTON_IT = 0, ST_NEWTON_CALLS, ST_CROSS, ST_HITS, ST_LOST, ST_FALLBACK, ST_STRAG, ST_TRACKQ, ST_RECOVER, ST_N };
 constexpr int kStatSlots = 64;   // each counter is spread over slots (blockIdx % 64) to avoid atomic contention
 
 // One element face: slab bounding box (Sec. 3.2.4), corner bilinear form,
@@ -48,6 +50,7 @@ struct MeshView {
   const double* vol;      // [E][n^3]
   const double* elo;      // [E][3] padded element box
   const double* ehi;
+  const double* nbox;     // [E][6] box of the DG nodes (lo xyz, hi xyz)
   double xgeo[kMaxNodes], cgeo[kMaxNodes];  // geometry nodes, 1/prod(x_i - x_j)
   double xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
   float xdgf[kMaxNodes], cdgf[kMaxNodes];

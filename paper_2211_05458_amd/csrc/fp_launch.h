@@ -10,7 +10,8 @@ bool supported(int n, int ng);
 hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* nbr_elem, const int32_t* nbr_face,
                              const int8_t* bc, const double* shift, const double* Minv, FaceRec* faces, double* cp,
                              hipStream_t s);
-hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, int32_t* bad, hipStream_t s);
+hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, int32_t* bad,
+                        unsigned long long* node_pad, hipStream_t s);
 hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* hint, int64_t n, hipStream_t s);
 struct StageLaunch {
   MeshView m;
@@ -38,8 +39,8 @@ hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, uns
 hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
                                   int s_f32, int drag, hipStream_t s);
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
-                                int s_f32, int drag, double R, const double* period, double* norm_buf,
-                                double* force_buf, const int32_t* elem_start, hipStream_t s);
+                                int s_f32, int drag, double R, const double* period, double node_pad, double* dep,
+                                const int32_t* elem_start, unsigned long long* povh, hipStream_t s);
 hipError_t launch_sort(const Particles& src, const Particles& dst, int64_t n, int E, int32_t* count,
                        int32_t* start, int32_t* rank, int32_t* block_sums, hipStream_t s);
 hipError_t launch_elem_start(const Particles& P, int64_t n, int E, int32_t* elem_start, hipStream_t s);

@@ -19,91 +19,8 @@ __global__ void k_face_setup(int E, const double* __restrict__ X, const int32_t*
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= E * 6) return;
   int e = gid / 6, f = gid % 6;
-  constexpr int D = NG - 1;
-  int d = f / 2, a = (d == 0) ? 1 : 0, b = (d == 2) ? 1 : 2;
-  int fix = (f & 1) ? D : 0;
-  const double* Xe = X + (size_t)e * NG * NG * NG * 3;
-  double T[NG * NG][3];
-  // Lagrange nodes -> Bernstein control points: P = M^-1 F M^-T
-  for (int n = 0; n < NG; ++n)
-    for (int mm = 0; mm < NG; ++mm) {
-      double s[3] = {0, 0, 0};
-      for (int r = 0; r < NG; ++r) {
-        int idx[3];
-        idx[d] = fix; idx[a] = r; idx[b] = n;
-        const double* P = Xe + ((idx[2] * NG + idx[1]) * NG + idx[0]) * 3;
-        double w = Mi.v[mm * NG + r];
-        s[0] += w * P[0]; s[1] += w * P[1]; s[2] += w * P[2];
-      }
-      T[n * NG + mm][0] = s[0]; T[n * NG + mm][1] = s[1]; T[n * NG + mm][2] = s[2];
-    }
-  double* cp = cpo + (size_t)gid * NG * NG * 3;
-  for (int n = 0; n < NG; ++n)
-    for (int mm = 0; mm < NG; ++mm) {
-      double s[3] = {0, 0, 0};
-      for (int r = 0; r < NG; ++r) {
-        double w = Mi.v[n * NG + r];
-        s[0] += w * T[r * NG + mm][0]; s[1] += w * T[r * NG + mm][1]; s[2] += w * T[r * NG + mm][2];
-      }
-      cp[(n * NG + mm) * 3 + 0] = s[0]; cp[(n * NG + mm) * 3 + 1] = s[1]; cp[(n * NG + mm) * 3 + 2] = s[2];
-    }
   FaceRec F;
-  const double* C00 = cp;
-  const double* CN0 = cp + D * 3;
-  const double* C0N = cp + D * NG * 3;
-  const double* CNN = cp + (D * NG + D) * 3;
-  double diam = 0.0;
-  for (int i = 0; i < NG * NG; ++i)
-    for (int j = i + 1; j < NG * NG; ++j) {
-      double r[3] = {cp[i * 3] - cp[j * 3], cp[i * 3 + 1] - cp[j * 3 + 1], cp[i * 3 + 2] - cp[j * 3 + 2]};
-      diam = fmax(diam, sqrt(dot3(r, r)));
-    }
-  double g1[3], g2[3], eu[3];
-  for (int q = 0; q < 3; ++q) {
-    g1[q] = CNN[q] - C00[q];
-    g2[q] = C0N[q] - CN0[q];
-    eu[q] = (CN0[q] - C00[q]) + (CNN[q] - C0N[q]);
-  }
-  cross3(g1, g2, F.nrm);
-  double il = 1.0 / sqrt(dot3(F.nrm, F.nrm));
-  for (int q = 0; q < 3; ++q) F.nrm[q] *= il;
-  double pr = dot3(eu, F.nrm);
-  for (int q = 0; q < 3; ++q) eu[q] -= pr * F.nrm[q];
-  il = 1.0 / sqrt(dot3(eu, eu));
-  for (int q = 0; q < 3; ++q) F.e1[q] = eu[q] * il;
-  cross3(F.nrm, F.e1, F.e2);
-  for (int q = 0; q < 3; ++q) {
-    F.org[q] = C00[q];
-    F.lo[q] = 1e300;
-    F.hi[q] = -1e300;
-  }
-  for (int i = 0; i < NG * NG; ++i) {
-    double r[3] = {cp[i * 3] - F.org[0], cp[i * 3 + 1] - F.org[1], cp[i * 3 + 2] - F.org[2]};
-    double p0 = dot3(r, F.nrm), p1 = dot3(r, F.e1), p2 = dot3(r, F.e2);
-    F.lo[0] = fmin(F.lo[0], p0); F.hi[0] = fmax(F.hi[0], p0);
-    F.lo[1] = fmin(F.lo[1], p1); F.hi[1] = fmax(F.hi[1], p1);
-    F.lo[2] = fmin(F.lo[2], p2); F.hi[2] = fmax(F.hi[2], p2);
-  }
-  F.diam = diam;
-  for (int q = 0; q < 3; ++q) {
-    F.A[q] = 0.25 * (C00[q] - CN0[q] - C0N[q] + CNN[q]);
-    F.B[q] = 0.25 * (-C00[q] + CN0[q] - C0N[q] + CNN[q]);
-    F.C[q] = 0.25 * (-C00[q] - CN0[q] + C0N[q] + CNN[q]);
-    F.D[q] = 0.25 * (C00[q] + CN0[q] + C0N[q] + CNN[q]);
-  }
-  double tol = 1e-12 * diam;
-  bool planar = (F.hi[0] - F.lo[0]) <= tol;
-  bool bilin = true;
-  for (int n = 0; n < NG && bilin; ++n)
-    for (int mm = 0; mm < NG && bilin; ++mm) {
-      double s = (double)mm / D, t = (double)n / D;
-      for (int q = 0; q < 3; ++q) {
-        double p = (1 - s) * (1 - t) * C00[q] + s * (1 - t) * CN0[q] + (1 - s) * t * C0N[q] + s * t * CNN[q];
-        if (fabs(p - cp[(n * NG + mm) * 3 + q]) > tol) { bilin = false; break; }
-      }
-    }
-  double tw = sqrt(dot3(F.A, F.A));
-  F.type = (planar && bilin && tw <= tol) ? FACE_PLANAR : (bilin ? FACE_BILINEAR : FACE_CURVED);
+  face_setup<NG>(X + (size_t)e * NG * NG * NG * 3, f, Mi.v, cpo + (size_t)gid * NG * NG * 3, F);
   F.nbr_elem = nbr_elem[gid];
   F.nbr_face = nbr_face[gid];
   F.bc = bc[gid];
@@ -139,6 +56,36 @@ __global__ void k_nodes(MeshView m, double* xnode, double* vol, double* hE, int3
         hm = fmax(hm, sqrt(dot3(r, r)));
       }
     hE[e] = hm;
+  }
+}
+
+// box of each element's DG nodes (one wave per element) and the largest
+// distance by which a node lies outside the padded element box
+template <int NN>
+__global__ __launch_bounds__(64) void k_node_box(MeshView m, const double* xnode, double* nbox,
+                                                 unsigned long long* node_pad) {
+  constexpr int N3 = NN * NN * NN;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int q = lane; q < N3; q += 64)
+    for (int k = 0; k < 3; ++k) {
+      double x = xnode[((size_t)e * N3 + q) * 3 + k];
+      lo[k] = fmin(lo[k], x);
+      hi[k] = fmax(hi[k], x);
+    }
+  for (int k = 0; k < 3; ++k)
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
+      hi[k] = fmax(hi[k], __shfl_xor(hi[k], off, 64));
+    }
+  if (lane == 0) {
+    double ov = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      nbox[(size_t)e * 6 + k] = lo[k];
+      nbox[(size_t)e * 6 + 3 + k] = hi[k];
+      ov = fmax(ov, fmax(m.elo[e * 3 + k] - lo[k], hi[k] - m.ehi[e * 3 + k]));
+    }
+    if (ov > 0.0) atomicMax(node_pad, (unsigned long long)__double_as_longlong(ov));
   }
 }
 
@@ -190,18 +137,26 @@ __global__ __launch_bounds__(256) void k_locate(MeshView m, Particles P, const i
 template <int NN, int NG>
 __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, unsigned long long* stats) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int nlost = 0;
+  int nlost = 0, nrec = 0;
   if (p < n && P.status[p] == ACTIVE) {
     const int64_t cap = P.cap;
     double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
     double xi[3];
-    int it = 0, calls = 0, fb = 0;
-    bool ok = locate_xi<NN, NG>(m, P.elem[p], x, xi, 50, false, it, calls, fb);
+    int it = 0, calls = 0, fb = 0, e = P.elem[p];
+    bool ok = locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb);
+    bool inside = ok && inside_ref(xi);
+    if (ok && !inside && recover_elem<NN, NG>(m, e, x, xi, 50, it, calls, fb)) {
+      inside = true;
+      nrec++;
+      P.elem[p] = e;
+      for (int k = 0; k < 3; ++k) P.x[k * cap + p] = x[k];
+    }
     if (!ok) { P.status[p] = LOST_NEWTON; nlost++; }
-    else if (!inside_ref(xi)) { P.status[p] = LOST_TRACK; nlost++; }
+    else if (!inside) { P.status[p] = LOST_TRACK; nlost++; }
     for (int k = 0; k < 3; ++k) P.xi[k * cap + p] = xi[k];
   }
   wave_add(stats + ST_LOST * kStatSlots, nlost);
+  wave_add(stats + ST_RECOVER * kStatSlots, nrec);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,10 +233,15 @@ hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, int32_t* bad, hipStream_t s) {
+hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, int32_t* bad,
+                        unsigned long long* node_pad, hipStream_t s) {
   int64_t tot = (int64_t)m.E * m.n * m.n * m.n;
-#define FP_L(A, B) \
-  if (m.n == A && m.ng == B) { k_nodes<A, B><<<grid_for(tot), 256, 0, s>>>(m, xnode, vol, hE, bad); return hipGetLastError(); }
+#define FP_L(A, B)                                                                           \
+  if (m.n == A && m.ng == B) {                                                               \
+    k_nodes<A, B><<<grid_for(tot), 256, 0, s>>>(m, xnode, vol, hE, bad);                     \
+    k_node_box<A><<<m.E, 64, 0, s>>>(m, xnode, nbox, node_pad);                              \
+    return hipGetLastError();                                                                \
+  }
   FP_FOR_EACH_SHAPE(FP_L)
 #undef FP_L
   return hipErrorInvalidValue;

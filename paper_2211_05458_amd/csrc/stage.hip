@@ -105,8 +105,7 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
         P.status[p] = LOST_NEWTON;
         nlost++;
       } else if (!inside_ref(xi)) {
-        P.status[p] = LOST_TRACK;
-        nlost++;
+        strag = true;   // outside its element: the per-lane kernel recovers it
       } else {
         double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
         double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t cap = P.cap;
-  int it_sum = 0, calls = 0, fb = 0, nlost = 0;
+  int it_sum = 0, calls = 0, fb = 0, nlost = 0, nrec = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < count; i += stride) {
     bool trk = false;
     int64_t p = 0;
@@ -168,14 +167,23 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
     if (i < count) {
       p = list ? (int64_t)list[i] : i;
       if (P.status[p] == ACTIVE) {
-        const int e = P.elem[p];
+        int e = P.elem[p];
         double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
         double xi[3];
-        if (!locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi, sp.max_it,
-                                      it_sum, calls, fb)) {
+        bool ok = locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi,
+                                           sp.max_it, it_sum, calls, fb);
+        bool inside = ok && inside_ref(xi);
+        if (ok && !inside) {
+          inside = recover_elem<NN, NG>(m, e, x, xi, sp.max_it, it_sum, calls, fb);
+          if (inside) {
+            nrec++;
+            P.elem[p] = e;
+          }
+        }
+        if (!ok) {
           P.status[p] = LOST_NEWTON;
           nlost++;
-        } else if (!inside_ref(xi)) {
+        } else if (!inside) {
           P.status[p] = LOST_TRACK;
           nlost++;
         } else {
@@ -208,6 +216,7 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
   wave_add(stats + ST_NEWTON_IT * kStatSlots, it_sum);
   wave_add(stats + ST_NEWTON_CALLS * kStatSlots, calls);
   wave_add(stats + ST_FALLBACK * kStatSlots, fb);
+  wave_add(stats + ST_RECOVER * kStatSlots, nrec);
   wave_add(stats + ST_LOST * kStatSlots, nlost);
 }
 

@@ -231,3 +231,35 @@ def test_mlp_gradients_match_oracle():
     assert np.abs(gg - go).max() <= 1e-4 * np.abs(go).max()
     out = g.mlp_forward(W32, torch.tensor(inp, dtype=torch.float32, device="cuda")).cpu().numpy()
     np.testing.assert_allclose(out, O.mlp_forward(wt, inp), atol=1e-5)
+
+
+def test_grazing_crossings_parity():
+    """Drag-free paths crossing curved faces at incidence 1e-7..1e-1: entry-face
+    roots after a hand-off and crossings the clipping misses (recovered in the
+    neighbour) end identically in both codes."""
+    from grazing_paths import grazing_paths
+    w = W.curved_box(cells=4, N=3, n_particles=1, n_steps=1, seed=13)
+    o = O.Oracle(w.mesh, w.N, w.U)
+    rng = np.random.default_rng(15)
+    L, dt = 0.05, 1e-3
+    x0, d, h = grazing_paths(o, w.mesh, 3000, rng, L)
+    v = d * (L / dt)
+    dd = np.full(len(x0), 1e-5)
+    _, ro = run_oracle(w, 1, rk=1, drag=2, x=x0, v=v, d=dd, hint=h)
+    g, rg = run_gpu(w, 1, rk=1, drag=2, x=x0, v=v, d=dd, hint=h)
+    assert_parity(ro, rg, vscale=50.0, tol=1e-12)
+    assert (ro["status"][ro["status"] != O.REJECTED] == O.ACTIVE).all()
+    assert g.stats()["lost"] == 0
+
+
+def test_grazing_handoff_on_curved_32cube():
+    """A particle of the 32^3 curved workload whose path grazes a curved face:
+    after the hand-off the entry face of the new element returns the entry
+    point itself as a root just above the displacement threshold; both codes
+    must keep it in the new element over the whole run."""
+    w = W.config2()
+    b = np.array([981813])
+    _, ro = run_oracle(w, 30, rk=1, drag=1, x=w.x[b], v=w.v[b], d=w.d[b], hint=w.elem_hint[b])
+    _, rg = run_gpu(w, 30, rk=1, drag=1, x=w.x[b], v=w.v[b], d=w.d[b], hint=w.elem_hint[b])
+    assert ro["status"][0] == O.ACTIVE
+    assert_parity(ro, rg, vscale=2.0)

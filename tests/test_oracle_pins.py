@@ -717,3 +717,32 @@ def test_mlp_features_carry_corners_curvature_and_point():
     # an affine element has no curvature features
     o2 = O.Oracle(W.single_element(4, lambda xi: xi @ np.diag([0.5, 0.4, 0.6]).T), 2, _dummy_state(1, 2))
     assert np.abs(o2.mlp_features(0, x)[24:81]).max() < 1e-14
+
+
+def test_grazing_face_crossings_stay_tracked():
+    """Straight (drag-free) paths crossing curved internal faces at incidence
+    angles 1e-7..1e-1: every particle ends in the element that contains its
+    final position (an independent Newton check) and at the straight-line
+    position (modulo the periodic directions).  Exercises the entry-face
+    threshold after a hand-off and the neighbour recovery of crossings that
+    the clipping misses."""
+    from grazing_paths import grazing_paths
+    w = W.curved_box(cells=4, N=3, n_particles=1, n_steps=1, seed=13)
+    o = O.Oracle(w.mesh, w.N, w.U)
+    rng = np.random.default_rng(14)
+    L, dt = 0.05, 1e-3
+    x0, d, h = grazing_paths(o, w.mesh, 1500, rng, L)
+    st, nbad = o.push(x0, d * (L / dt), np.full(len(x0), 1e-5), h)
+    ok = st == O.ACTIVE
+    o.step(dt, 1, rk=1, drag=2)
+    r = o.read()
+    assert np.all(r["status"][ok] == O.ACTIVE)
+    s = o.stats()
+    assert s["lost"] == 0 and s["recovered"] > 0 and s["crossings"] > 1000
+    for p in np.nonzero(ok)[0]:
+        conv, xi, _ = o.newton(r["elem"][p], r["x"][p], o.guess(r["elem"][p], r["x"][p]))
+        assert conv and np.abs(xi).max() <= 1 + 1e-10
+    free = ok & (r["hits"] == 0)
+    dx = r["x"][free] - (x0[free] + d[free] * L)
+    dx[:, [0, 2]] -= np.round(dx[:, [0, 2]])            # periods 1 in x and z
+    assert np.abs(dx).max() < 1e-12
