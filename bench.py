@@ -277,7 +277,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="learned-guess training epochs (annulus)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-every", type=int, default=50, help="oracle sample: every k-th particle")
+    ap.add_argument("--cpu-every", type=int, default=25, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: a plain device copy of known size, the calibration for HBM counters")

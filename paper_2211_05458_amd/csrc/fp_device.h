@@ -982,86 +982,202 @@ __device__ inline int face_roots(const MeshView& m, int fid, const FaceRec& F, c
 // ties to the lowest local face; hand-off, periodic shift, specular reflection
 // (Sec. 2.4) of the remaining displacement, v and the stage registers; open
 // boundaries end the particle.
+//
+// Written as a per-lane state machine: one loop iteration advances a lane by
+// one step of its own work (next candidate face, pop of a clipping box, one
+// Bezier-clipping iteration, end of a leg), so the lanes of a wavefront that
+// test different faces, need different iteration counts or cross different
+// numbers of faces all share the clipping iteration that dominates the cost,
+// instead of the wavefront running every face to the slowest lane.
 template <int NG>
 __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
                       int max_cross, int8_t& status, int& hits, int& ncross) {
+  constexpr double kBoxTol = 1e-7;
+  enum { NEW_LEG, NEXT_FACE, POP, CLIP, LEG_END, DONE };
   double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
   // excl: planar face just entered through (no further root possible);
   // entry: non-planar face just entered through, whose root at the entry point
   // (alpha ~ 0, error growing like 1/sin(incidence)) is ignored below
   // kEntryRel * face diameter
   int excl = -1, entry = -1, count = 0;
-  for (;;) {
-    double t[3] = {xe[0] - xs[0], xe[1] - xs[1], xe[2] - xs[2]};
-    double L = sqrt(dot3(t, t));
-    if (L == 0.0) break;
-    double iL = 1.0 / L;
-    t[0] *= iL; t[1] *= iL; t[2] *= iL;
-    double eps = 1e-12 * m.hE[e];
-    double best = 1e300, bu = 0.0, bv = 0.0;
-    int bf = -1;
-    for (int f = 0; f < 6; ++f) {
-      if (f == excl) continue;
-      int fid = e * 6 + f;
-      const FaceRec& F = m.faces[fid];
-      if (!bbox_hit(F, xs, xe)) continue;
-      double al[kMaxRoots], uv[2 * kMaxRoots];
-      // only roots with displacement in (amin, L] matter: clip to a padded band
-      double amin = (f == entry) ? fmax(eps, kEntryRel * F.diam) : eps;
-      double pad = 1e-9 * F.diam;
-      int nr = face_roots<NG>(m, fid, F, xs, t, amin - pad, L + pad, al, uv);
-      for (int r = 0; r < nr; ++r) {
-        if (!(al[r] > amin && al[r] <= L)) continue;
-        if (fabs(uv[2 * r]) > 1.0 + kUVEps || fabs(uv[2 * r + 1]) > 1.0 + kUVEps) continue;
-        if (al[r] < best) { best = al[r]; bf = f; bu = uv[2 * r]; bv = uv[2 * r + 1]; }
+  double t[3] = {0, 0, 0}, n1[3] = {0, 0, 0}, n2[3] = {0, 0, 0}, L = 0.0, eps = 0.0;
+  double best = 1e300, bu = 0.0, bv = 0.0, amin = 0.0, bmin = 0.0, bmax = 0.0;
+  int bf = -1, f = 0;
+  const double* cpf = m.cp;
+  double stk[kClipStack][4];
+  int sp = 0, budget = 0;
+  double u0 = 0.0, u1 = 1.0, v0 = 0.0, v1 = 1.0;
+  double q[NG * NG * 3];
+  auto consider = [&](double a, double uu, double vv) {
+    if (!(a > amin && a <= L)) return;
+    if (fabs(uu) > 1.0 + kUVEps || fabs(vv) > 1.0 + kUVEps) return;
+    if (a < best) { best = a; bf = f; bu = uu; bv = vv; }
+  };
+  int mode = NEW_LEG;
+#pragma unroll 1
+  while (mode != DONE) {
+    if (mode == NEW_LEG) {
+      t[0] = xe[0] - xs[0]; t[1] = xe[1] - xs[1]; t[2] = xe[2] - xs[2];
+      L = sqrt(dot3(t, t));
+      if (L == 0.0) {
+        mode = DONE;
+      } else {
+        double iL = 1.0 / L;
+        t[0] *= iL; t[1] *= iL; t[2] *= iL;
+        ray_planes(t, n1, n2);
+        eps = 1e-12 * m.hE[e];
+        best = 1e300;
+        bf = -1;
+        f = 0;
+        mode = NEXT_FACE;
       }
     }
-    if (bf < 0) break;
-    if (count >= max_cross) { status = MAX_CROSS; break; }
-    count++;
-    ncross++;
-    double xh[3] = {xs[0] + best * t[0], xs[1] + best * t[1], xs[2] + best * t[2]};
-    int fid = e * 6 + bf;
-    const FaceRec& F = m.faces[fid];
-    int bc = F.bc;
-    if (bc == BC_INTERNAL || bc == BC_PERIODIC) {
-      int ne = F.nbr_elem, nf = F.nbr_face;
-      if (bc == BC_PERIODIC)
-        for (int q = 0; q < 3; ++q) { xh[q] += F.shift[q]; xe[q] += F.shift[q]; }
-      e = ne;
-      const bool planar = m.faces[ne * 6 + nf].type == FACE_PLANAR;
-      excl = planar ? nf : -1;
-      entry = planar ? -1 : nf;
-      xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
-    } else if (bc == BC_REFLECT) {
-      double nrm[3];
-      if (F.type == FACE_CURVED) {
-        double p[3], pu[3], pv[3];
-        bezier_eval<NG>(m.cp + (size_t)fid * (NG * NG * 3), bu, bv, p, pu, pv);
-        cross3(pu, pv, nrm);
+    if (mode == NEXT_FACE) {
+      while (f < 6 && (f == excl || !bbox_hit(m.faces[e * 6 + f], xs, xe))) f++;
+      if (f == 6) {
+        mode = LEG_END;
       } else {
-        double pu[3], pv[3];
-        for (int q = 0; q < 3; ++q) { pu[q] = F.A[q] * bv + F.B[q]; pv[q] = F.A[q] * bu + F.C[q]; }
-        cross3(pu, pv, nrm);
+        const FaceRec& F = m.faces[e * 6 + f];
+        amin = (f == entry) ? fmax(eps, kEntryRel * F.diam) : eps;
+        if (F.type != FACE_CURVED) {
+          double al[2], uv[4];
+          int nr = (F.type == FACE_PLANAR) ? planar_hit(F, xs, t, al, uv) : bilinear_hit(F, xs, t, al, uv);
+          for (int r = 0; r < nr; ++r) consider(al[r], uv[2 * r], uv[2 * r + 1]);
+          f++;
+        } else {
+          // only roots with displacement in (amin, L] matter: clip to a padded band
+          const double pad = 1e-9 * F.diam;
+          bmin = amin - pad;
+          bmax = L + pad;
+          cpf = m.cp + (size_t)(e * 6 + f) * (NG * NG * 3);
+          stk[0][0] = 0.0; stk[0][1] = 1.0; stk[0][2] = 0.0; stk[0][3] = 1.0;
+          sp = 1;
+          budget = kClipSteps;
+          mode = POP;
+        }
       }
-      double il = 1.0 / sqrt(dot3(nrm, nrm));
-      nrm[0] *= il; nrm[1] *= il; nrm[2] *= il;
-      double r[3] = {xe[0] - xh[0], xe[1] - xh[1], xe[2] - xh[2]};
-      double dr = dot3(r, nrm), dv = dot3(v, nrm), dkx = dot3(kx, nrm), dkv = dot3(kv, nrm);
-      for (int q = 0; q < 3; ++q) {
-        xe[q] = xh[q] + (r[q] - 2.0 * dr * nrm[q]);
-        v[q] -= 2.0 * dv * nrm[q];
-        kx[q] -= 2.0 * dkx * nrm[q];
-        kv[q] -= 2.0 * dkv * nrm[q];
+    }
+    if (mode == POP) {
+      if (sp == 0 || budget <= 0) {
+        f++;
+        mode = NEXT_FACE;
+      } else {
+        --sp;
+        u0 = stk[sp][0]; u1 = stk[sp][1]; v0 = stk[sp][2]; v1 = stk[sp][3];
+        project_face<NG>(cpf, xs, t, n1, n2, q);
+        if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG, 3>(q, 0, u0, u1);
+        if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG, 3>(q, 1, v0, v1);
+        mode = CLIP;
       }
-      hits++;
-      excl = (F.type == FACE_PLANAR) ? bf : -1;
-      entry = (F.type == FACE_PLANAR) ? -1 : bf;
-      xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
-    } else {
-      status = OPEN_EXIT;
-      xe[0] = xh[0]; xe[1] = xh[1]; xe[2] = xh[2];
-      break;
+    } else if (mode == CLIP) {
+      // one Bezier-clipping iteration (Sec. 3.2.4) on the live box
+      double a, b;
+      mode = POP;
+      if (--budget >= 0 && !outside_band<NG>(q, bmin, bmax) && clip_dir<NG>(q, 0, a, b)) {
+        patch_restrict<NG, 3>(q, 0, a, b);
+        double w = u1 - u0;
+        double nu0 = u0 + a * w, nu1 = u0 + b * w;
+        u0 = nu0; u1 = nu1;
+        const double ru = b - a;
+        if (clip_dir<NG>(q, 1, a, b)) {
+          patch_restrict<NG, 3>(q, 1, a, b);
+          w = v1 - v0;
+          double nv0 = v0 + a * w, nv1 = v0 + b * w;
+          v0 = nv0; v1 = nv1;
+          const double rv = b - a;
+          const double wu = u1 - u0, wv = v1 - v0;
+          bool conv = (wu <= kBoxTol && wv <= kBoxTol);
+          const bool su = (ru > 0.8 && wu > kBoxTol), sv = (rv > 0.8 && wv > kBoxTol);
+          if (!conv && (su || sv) && sp + 2 > kClipStack) conv = true;
+          if (conv) {
+            // 2-D Newton on the plane distances from the box centre
+            double u = (u0 + u1) - 1.0, vv = (v0 + v1) - 1.0;
+            double pp[3], pu[3], pv[3];
+#pragma unroll 1
+            for (int it = 0; it < 3; ++it) {
+              bezier_eval<NG>(cpf, u, vv, pp, pu, pv);
+              double r[3] = {pp[0] - xs[0], pp[1] - xs[1], pp[2] - xs[2]};
+              double G0 = dot3(r, n1), G1 = dot3(r, n2);
+              double Gu0 = dot3(pu, n1), Gu1 = dot3(pu, n2), Gv0 = dot3(pv, n1), Gv1 = dot3(pv, n2);
+              double det = Gu0 * Gv1 - Gu1 * Gv0;
+              if (det == 0.0 || !isfinite(det)) break;
+              u += -(G0 * Gv1 - G1 * Gv0) / det;
+              vv += -(Gu0 * G1 - Gu1 * G0) / det;
+            }
+            bezier_eval<NG>(cpf, u, vv, pp, nullptr, nullptr);
+            double r3[3] = {pp[0] - xs[0], pp[1] - xs[1], pp[2] - xs[2]};
+            consider(dot3(r3, t), u, vv);
+          } else if (su || sv) {
+            const int dir = (su && sv) ? (wu >= wv ? 0 : 1) : (su ? 0 : 1);
+            if (dir == 0) {
+              const double um = 0.5 * (u0 + u1);
+              stk[sp][0] = um; stk[sp][1] = u1; stk[sp][2] = v0; stk[sp][3] = v1; sp++;
+              stk[sp][0] = u0; stk[sp][1] = um; stk[sp][2] = v0; stk[sp][3] = v1; sp++;
+            } else {
+              const double vm = 0.5 * (v0 + v1);
+              stk[sp][0] = u0; stk[sp][1] = u1; stk[sp][2] = vm; stk[sp][3] = v1; sp++;
+              stk[sp][0] = u0; stk[sp][1] = u1; stk[sp][2] = v0; stk[sp][3] = vm; sp++;
+            }
+          } else {
+            mode = CLIP;   // the box shrank: clip it again
+          }
+        }
+      }
+    }
+    if (mode == LEG_END) {
+      if (bf < 0) {
+        mode = DONE;
+      } else if (count >= max_cross) {
+        status = MAX_CROSS;
+        mode = DONE;
+      } else {
+        count++;
+        ncross++;
+        double xh[3] = {xs[0] + best * t[0], xs[1] + best * t[1], xs[2] + best * t[2]};
+        const int fid = e * 6 + bf;
+        const FaceRec& F = m.faces[fid];
+        const int bc = F.bc;
+        mode = NEW_LEG;
+        if (bc == BC_INTERNAL || bc == BC_PERIODIC) {
+          const int ne = F.nbr_elem, nf = F.nbr_face;
+          if (bc == BC_PERIODIC)
+            for (int k = 0; k < 3; ++k) { xh[k] += F.shift[k]; xe[k] += F.shift[k]; }
+          e = ne;
+          const bool planar = m.faces[ne * 6 + nf].type == FACE_PLANAR;
+          excl = planar ? nf : -1;
+          entry = planar ? -1 : nf;
+          xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
+        } else if (bc == BC_REFLECT) {
+          double nrm[3];
+          if (F.type == FACE_CURVED) {
+            double pp[3], pu[3], pv[3];
+            bezier_eval<NG>(m.cp + (size_t)fid * (NG * NG * 3), bu, bv, pp, pu, pv);
+            cross3(pu, pv, nrm);
+          } else {
+            double pu[3], pv[3];
+            for (int k = 0; k < 3; ++k) { pu[k] = F.A[k] * bv + F.B[k]; pv[k] = F.A[k] * bu + F.C[k]; }
+            cross3(pu, pv, nrm);
+          }
+          const double il = 1.0 / sqrt(dot3(nrm, nrm));
+          nrm[0] *= il; nrm[1] *= il; nrm[2] *= il;
+          const double r[3] = {xe[0] - xh[0], xe[1] - xh[1], xe[2] - xh[2]};
+          const double dr = dot3(r, nrm), dv = dot3(v, nrm), dkx = dot3(kx, nrm), dkv = dot3(kv, nrm);
+          for (int k = 0; k < 3; ++k) {
+            xe[k] = xh[k] + (r[k] - 2.0 * dr * nrm[k]);
+            v[k] -= 2.0 * dv * nrm[k];
+            kx[k] -= 2.0 * dkx * nrm[k];
+            kv[k] -= 2.0 * dkv * nrm[k];
+          }
+          hits++;
+          excl = (F.type == FACE_PLANAR) ? bf : -1;
+          entry = (F.type == FACE_PLANAR) ? -1 : bf;
+          xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
+        } else {
+          status = OPEN_EXIT;
+          xe[0] = xh[0]; xe[1] = xh[1]; xe[2] = xh[2];
+          mode = DONE;
+        }
+      }
     }
   }
 }
