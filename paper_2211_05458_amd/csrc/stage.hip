@@ -77,7 +77,14 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
                                                     const int32_t* __restrict__ ntask, Particles P, Fluid fl,
                                                     StepParams sp, Queues q, unsigned long long* stats) {
   constexpr int NG3 = NG * NG * NG, NN3 = NN * NN * NN;
-  const int lane = threadIdx.x & 63;
+  // the task element's geometry nodes and fluid state, staged once per
+  // wavefront with coalesced vector loads and read as LDS broadcasts by every
+  // Newton iteration and the interpolation; U stays in global memory when both
+  // would not fit three wavefronts per SIMD
+  constexpr bool kStageU = NG3 * 3 * 8 + 5 * NN3 * (int)sizeof(UT) <= 12 * 1024;
+  __shared__ double sX[4][NG3 * 3];
+  __shared__ UT sU[4][kStageU ? 5 * NN3 : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nt = __builtin_amdgcn_readfirstlane(*ntask);
   int it_sum = 0, calls = 0, fb = 0, nlost = 0;
@@ -85,8 +92,19 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
   int64_t p = 0;
   double xs0 = 0, xs1 = 0, xs2 = 0;
   const int64_t cap = P.cap;
+  Task t{0, 0, 0, 0};
   if (wid < nt) {
-    const Task t = tasks[wid];
+    t = tasks[wid];
+    const int e = __builtin_amdgcn_readfirstlane(t.e);
+    const double* Xg = X + (size_t)e * NG3 * 3;
+    for (int i = lane; i < NG3 * 3; i += 64) sX[w][i] = Xg[i];
+    if (kStageU) {
+      const UT* Ug = U + (size_t)e * 5 * NN3;
+      for (int i = lane; i < 5 * NN3; i += 64) sU[w][i] = Ug[i];
+    }
+  }
+  __syncthreads();
+  if (wid < nt) {
     const int e = __builtin_amdgcn_readfirstlane(t.e);
     const int p0 = __builtin_amdgcn_readfirstlane(t.p0);
     const int cnt = __builtin_amdgcn_readfirstlane(t.cnt);
@@ -97,8 +115,9 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
       act = false;
     }
     if (act) {
-      const double* Xe = X + (size_t)e * NG3 * 3;
+      const double* Xe = sX[w];
       const double* XNe = XN + (size_t)e * NN3 * 3;
+      const UT* Ue = kStageU ? sU[w] : U + (size_t)e * 5 * NN3;
       double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
       double xi[3];
       if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb)) {
@@ -111,7 +130,7 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
         double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
         double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
         double xe[3];
-        stage_update<NN, UT, MIXED>(m, U + (size_t)e * 5 * NN3, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
+        stage_update<NN, UT, MIXED>(m, Ue, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
         const FaceRec* Fe = faces + (size_t)e * 6;
         bool any = false;
 #pragma unroll 1
