@@ -74,7 +74,7 @@ def bytes_per_particle_stage(n, ng, ppe):
     return soa + elem / ppe
 
 
-def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False):
+def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False, tracking=0):
     """Push w's particles, run `warmup` untimed then `steps` timed fp_step(dt, 1)
     calls (each followed by deposit(g) if given); returns timings and the state."""
     import numpy as np
@@ -85,7 +85,7 @@ def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None,
     st, nrej = g.push(w.x, w.v, w.d, w.elem_hint)
     n_active = int((st == 0).sum())
     n_flagged = g.mlp_set_weights(weights) if weights is not None else 0
-    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1, guess=guess)
+    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1, guess=guess, tracking=tracking)
     for _ in range(warmup):
         g.step(w.dt, 1, **opts)
         if deposit:
@@ -277,6 +277,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="learned-guess training epochs (annulus)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-refspace", action="store_true", help="skip the reference-space localisation run")
     ap.add_argument("--cpu-every", type=int, default=25, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
@@ -340,6 +341,17 @@ def main():
             "learned_guess": "no element of this mesh deviates from its trilinear corner map by "
                              "more than 0.05 h, so the learned guess is never used here",
         })
+
+    if not args.no_refspace:
+        # the paper's reference-space localisation: segments that cannot reach a
+        # wall or periodic face are localised by Newton instead of traced
+        print("[bench] reference-space localisation run", file=sys.stderr, flush=True)
+        rr = run_gpu(w, U64, 0, args.steps, args.warmup, tracking=1)
+        extras["fp64_refspace"] = summary(rr, K)
+        extras["fp64_refspace"].update(pos_error(r64, rr, w.mesh.h))
+        extras["fp64_refspace"].update({"crossings_traced": rr["stats"]["crossings"],
+                                        "localised": rr["stats"]["recovered"],
+                                        "track_queue": rr["stats"]["track_queue"]})
 
     cpu = None
     if not args.no_cpu_baseline:

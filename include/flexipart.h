@@ -85,7 +85,10 @@ typedef struct {
   int32_t sort_every;    /* counting-sort particles by element every k steps (0: never) */
   int32_t max_newton_it; /* Newton iteration cap (50) */
   int32_t max_crossings; /* face crossings per stage before FP_MAX_CROSS (64) */
-  int32_t pad_;
+  int32_t tracking;      /* 0: physical-space tracking of every segment (Sec. 3.2.3);
+                            1: reference-space localisation: a segment that cannot reach a
+                            face that is not internal (wall, open, periodic) is not traced,
+                            the next location step finds its element */
   double gravity[3];     /* added body acceleration */
 } fp_step_opts;
 

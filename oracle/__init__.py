@@ -77,6 +77,8 @@ def _declare(L):
     L.or_dg_node_pos.argtypes = [P, I, I, P]
     L.or_locate.restype = I
     L.or_locate.argtypes = [P, P, I, P]
+    L.or_boundary_distance.restype = C.c_double
+    L.or_boundary_distance.argtypes = [P, I]
     L.or_push.restype = I
     L.or_push.argtypes = [P, I64, P, P, P, P, P]
     L.or_default_opts.argtypes = [P]
@@ -101,7 +103,7 @@ def _declare(L):
 
 class StepOpts(C.Structure):
     _fields_ = [("rk", C.c_int32), ("drag", C.c_int32), ("max_newton_it", C.c_int32),
-                ("max_crossings", C.c_int32), ("use_mlp", C.c_int32), ("pad_", C.c_int32),
+                ("max_crossings", C.c_int32), ("use_mlp", C.c_int32), ("tracking", C.c_int32),
                 ("gravity", C.c_double * 3), ("drag_mask", C.c_double * 3)]
 
 
@@ -275,6 +277,9 @@ class Oracle:
         lib().or_dg_node_pos(self.ctx, int(e), int(node), _p(x))
         return x
 
+    def boundary_distance(self, e):
+        return lib().or_boundary_distance(self.ctx, int(e))
+
     def locate(self, x, hint=-1):
         xi = np.zeros(3)
         e = lib().or_locate(self.ctx, _p(_f64(x)), int(hint), _p(xi))
@@ -291,10 +296,11 @@ class Oracle:
         return st, nbad
 
     def step(self, dt, n_steps=1, rk=0, drag=1, max_newton_it=50, max_crossings=64,
-             gravity=(0, 0, 0), drag_mask=(1, 1, 1), use_mlp=False):
+             gravity=(0, 0, 0), drag_mask=(1, 1, 1), use_mlp=False, tracking=0):
         o = StepOpts()
         o.rk = rk; o.drag = drag; o.max_newton_it = max_newton_it; o.max_crossings = max_crossings
         o.use_mlp = int(bool(use_mlp))
+        o.tracking = int(tracking)
         for k in range(3):
             o.gravity[k] = gravity[k]
             o.drag_mask[k] = drag_mask[k]

@@ -36,6 +36,9 @@
 #define INSIDE_EPS 1e-10  /* xi in [-1-eps, 1+eps]^3 counts as inside */
 #define UV_EPS 1e-12      /* face parameter tolerance */
 #define ENTRY_REL 1e-9    /* entry-face root threshold, relative to the face diameter */
+/* sign that turns dp/du x dp/dv of local face f into its outward normal (face
+ * parameters are the two other reference axes in increasing order) */
+static const double FACE_SIGN[6] = {-1.0, 1.0, 1.0, -1.0, -1.0, 1.0};
 #define RECOVER_HOPS 3    /* neighbour hops for a located particle outside its element */
 #define CLIP_TOL 1e-12    /* Bezier clipping interval width (parameter space [0,1]) */
 #define CLIP_PAD 1e-10    /* relative padding of each clipped interval */
@@ -65,6 +68,7 @@ struct or_ctx {
   int bn[3];
   int *bstart, *blist;
   double *elo, *ehi;      /* padded element AABB [E][3] */
+  double *dsafe;          /* [E] lower bound of the distance to a boundary face */
   /* fluid */
   const double *U;
   double mu, kappa, rho_p;
@@ -797,7 +801,40 @@ static void patch_restrict(clip_patch* P, int ng, int dir, double a, double b) {
 
 /* clip direction dir (0: u, 1: v) against the line through the origin that
  * runs along the other parameter direction */
-static int clip_dir(const clip_patch* P, int ng, int dir, double* a, double* b) {
+/* t-extent of the part of the convex hull of (t_m, lo_m), (t_m, hi_m) with
+ * y >= c (ge) or y <= c: its vertices are hull points on that side and the
+ * crossings of y = c by hull edges; every segment between two points on
+ * opposite sides crosses inside the hull, so all such pairs are taken */
+static int hull_side(int ng, const double* lo, const double* hi, double c, int ge, double* ta, double* tb) {
+  double tt[2 * MAXG], yy[2 * MAXG];
+  int np = 0;
+  for (int m = 0; m < ng; ++m) {
+    double t = (double)m / (ng - 1);
+    tt[np] = t; yy[np++] = lo[m];
+    tt[np] = t; yy[np++] = hi[m];
+  }
+  double a = INFINITY, b = -INFINITY;
+  for (int i = 0; i < np; ++i) {
+    int in_i = ge ? yy[i] >= c : yy[i] <= c;
+    if (in_i) { if (tt[i] < a) a = tt[i]; if (tt[i] > b) b = tt[i]; }
+    for (int j = i + 1; j < np; ++j) {
+      int in_j = ge ? yy[j] >= c : yy[j] <= c;
+      if (in_i == in_j || yy[i] == yy[j]) continue;
+      double t = tt[i] + (tt[j] - tt[i]) * ((c - yy[i]) / (yy[j] - yy[i]));
+      if (t < a) a = t;
+      if (t > b) b = t;
+    }
+  }
+  if (a > b) return 0;
+  *ta = a; *tb = b;
+  return 1;
+}
+
+/* Reading (the paper leaves the clipping loop to the literature): besides the
+ * two plane distances, each direction is also clipped to the part of the
+ * patch whose displacement lies in [amin, amax] (same convex-hull argument),
+ * so the search starts on the stage segment's strip of the face. */
+static int clip_dir(const clip_patch* P, int ng, int dir, double amin, double amax, double* a, double* b) {
   int N = ng - 1;
   double L[2];
   if (dir == 0)
@@ -828,6 +865,22 @@ static int clip_dir(const clip_patch* P, int ng, int dir, double* a, double* b) 
     }
   }
   if (!hull_zero(ng, dmin, dmax, a, b)) return 0;
+  for (int i = 0; i < ng; ++i) {
+    dmin[i] = INFINITY; dmax[i] = -INFINITY;
+    for (int k = 0; k < ng; ++k) {
+      double al = (dir == 0) ? P->q[i][k][2] : P->q[k][i][2];
+      if (al < dmin[i]) dmin[i] = al;
+      if (al > dmax[i]) dmax[i] = al;
+    }
+  }
+  double a1, b1, a2, b2;
+  if (!hull_side(ng, dmin, dmax, amin, 1, &a1, &b1)) return 0;
+  if (!hull_side(ng, dmin, dmax, amax, 0, &a2, &b2)) return 0;
+  if (a1 > *a) *a = a1;
+  if (a2 > *a) *a = a2;
+  if (b1 < *b) *b = b1;
+  if (b2 < *b) *b = b2;
+  if (*a > *b) return 0;
   *a -= CLIP_PAD; *b += CLIP_PAD;
   if (*a < 0.0) *a = 0.0;
   if (*b > 1.0) *b = 1.0;
@@ -903,10 +956,10 @@ static int bezier_band(int ng, const double* cp, const double* x0, const double*
       if (--budget < 0) break;
       if (patch_outside_band(&P, ng, amin, amax)) break;
       double a, b, ru, rv;
-      if (!clip_dir(&P, ng, 0, &a, &b)) break;
+      if (!clip_dir(&P, ng, 0, amin, amax, &a, &b)) break;
       patch_restrict(&P, ng, 0, a, b);
       ru = b - a;
-      if (!clip_dir(&P, ng, 1, &a, &b)) break;
+      if (!clip_dir(&P, ng, 1, amin, amax, &a, &b)) break;
       patch_restrict(&P, ng, 1, a, b);
       rv = b - a;
       double wu = P.u1 - P.u0, wv = P.v1 - P.v0;
@@ -1047,6 +1100,97 @@ static void build_bgm(or_ctx* c) {
   }
 }
 
+/* Reading (the paper traces particles near boundaries in physical space and
+ * localises the others in reference space, but gives no distance rule): a
+ * lower bound of the distance from element e to any face that is not
+ * internal (wall, open, periodic): the distance between e's padded node box
+ * and the face's control-point box (which contains the face, convex hull),
+ * over the boundary faces within h_e, less 0.1 h_e; capped at 0.9 h_e. */
+static double box_gap(const double* alo, const double* ahi, const double* blo, const double* bhi) {
+  double s = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double d = 0.0;
+    if (blo[k] > ahi[k]) d = blo[k] - ahi[k];
+    else if (alo[k] > bhi[k]) d = alo[k] - bhi[k];
+    s += d * d;
+  }
+  return sqrt(s);
+}
+
+static void build_boundary_distance(or_ctx* c) {
+  int E = c->E, ng = c->ng;
+  size_t ncell = (size_t)c->bn[0] * c->bn[1] * c->bn[2];
+  /* boundary-face boxes bucketed in the background-mesh cells */
+  int nbf = 0;
+  for (int i = 0; i < E * 6; ++i) nbf += c->bc[i] != 0;
+  double* fb = (double*)malloc(sizeof(double) * 6 * (nbf + 1));
+  int* fstart = (int*)calloc(ncell + 1, sizeof(int));
+  int nf = 0;
+  for (int i = 0; i < E * 6; ++i) {
+    if (c->bc[i] == 0) continue;
+    double* b = fb + 6 * nf++;
+    for (int k = 0; k < 3; ++k) { b[k] = INFINITY; b[3 + k] = -INFINITY; }
+    const double* P = c->cp + (size_t)i * ng * ng * 3;
+    for (int q = 0; q < ng * ng; ++q)
+      for (int k = 0; k < 3; ++k) {
+        if (P[q * 3 + k] < b[k]) b[k] = P[q * 3 + k];
+        if (P[q * 3 + k] > b[3 + k]) b[3 + k] = P[q * 3 + k];
+      }
+  }
+  int* flist = NULL;
+  for (int pass = 0; pass < 2; ++pass) {
+    int* fill = NULL;
+    if (pass == 1) {
+      for (size_t q = 0; q < ncell; ++q) fstart[q + 1] += fstart[q];
+      flist = (int*)malloc(sizeof(int) * (fstart[ncell] + 1));
+      fill = (int*)calloc(ncell, sizeof(int));
+    }
+    for (int j = 0; j < nf; ++j) {
+      int lo[3], hi[3];
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = (int)floor((fb[6 * j + k] - c->blo[k]) / c->bdx[k]);
+        hi[k] = (int)floor((fb[6 * j + 3 + k] - c->blo[k]) / c->bdx[k]);
+        if (lo[k] < 0) lo[k] = 0;
+        if (hi[k] >= c->bn[k]) hi[k] = c->bn[k] - 1;
+      }
+      for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+          for (int x = lo[0]; x <= hi[0]; ++x) {
+            size_t id = ((size_t)z * c->bn[1] + y) * c->bn[0] + x;
+            if (pass == 0) fstart[id + 1]++;
+            else flist[fstart[id] + fill[id]++] = j;
+          }
+    }
+    free(fill);
+  }
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < E; ++e) {
+    double h = c->hE[e], best = h;
+    const double* alo = c->elo + e * 3;
+    const double* ahi = c->ehi + e * 3;
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = (int)floor((alo[k] - h - c->blo[k]) / c->bdx[k]);
+      hi[k] = (int)floor((ahi[k] + h - c->blo[k]) / c->bdx[k]);
+      if (lo[k] < 0) lo[k] = 0;
+      if (hi[k] >= c->bn[k]) hi[k] = c->bn[k] - 1;
+    }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x) {
+          size_t id = ((size_t)z * c->bn[1] + y) * c->bn[0] + x;
+          for (int q = fstart[id]; q < fstart[id + 1]; ++q) {
+            const double* b = fb + 6 * flist[q];
+            double g = box_gap(alo, ahi, b, b + 3);
+            if (g < best) best = g;
+          }
+        }
+    best -= 0.1 * h;
+    c->dsafe[e] = best > 0.0 ? best : 0.0;
+  }
+  free(fb); free(fstart); free(flist);
+}
+
 or_ctx* or_create(int n_elem, int n_geo, const double* X, const int32_t* nbr_elem,
                   const int32_t* nbr_face, const int8_t* bc, const double* shift, int N,
                   int dg_nodes) {
@@ -1119,6 +1263,8 @@ or_ctx* or_create(int n_elem, int n_geo, const double* X, const int32_t* nbr_ele
   c->elo = (double*)malloc(sizeof(double) * E * 3);
   c->ehi = (double*)malloc(sizeof(double) * E * 3);
   build_bgm(c);
+  c->dsafe = (double*)malloc(sizeof(double) * E);
+  build_boundary_distance(c);
   c->mu = 1.8e-5; c->kappa = 1.4; c->rho_p = 2500.0;
   return c;
 }
@@ -1128,7 +1274,7 @@ void or_destroy(or_ctx* c) {
   free(c->X); free(c->nbr_elem); free(c->nbr_face); free(c->bc); free(c->shift);
   free(c->xnode); free(c->vol); free(c->hE); free(c->cp); free(c->ftype); free(c->fframe);
   free(c->forig); free(c->flo); free(c->fhi); free(c->fdiam); free(c->bstart); free(c->blist);
-  free(c->elo); free(c->ehi);
+  free(c->elo); free(c->ehi); free(c->dsafe);
   free(c->x); free(c->v); free(c->kx); free(c->kv); free(c->d); free(c->xi); free(c->elem);
   free(c->hits); free(c->status); free(c->mlp_w); free(c->mlp_flag);
   free(c);
@@ -1250,6 +1396,15 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
       for (int r = 0; r < nr; ++r) {
         if (!(al[r] > amin && al[r] <= L)) continue;
         if (fabs(uv[2 * r]) > 1.0 + UV_EPS || fabs(uv[2 * r + 1]) > 1.0 + UV_EPS) continue;
+        /* Reading (the paper counts every root in (0, remaining length]): only a
+         * root where the path leaves the element is a crossing.  A root where
+         * it enters (the other half of a tangential touch of a curved face, or
+         * the entry point) is not; without this a touch whose leaving root the
+         * clipping does not separate hands the particle over at the entering
+         * one.  Outward normal: FACE_SIGN[f] * (dp/du x dp/dv) for J > 0. */
+        double nrm[3];
+        face_normal(c, fid, uv[2 * r], uv[2 * r + 1], nrm);
+        if (!(FACE_SIGN[f] * dot3(nrm, t) > 0.0)) continue;
         if (al[r] < best) { best = al[r]; bf = f; bu = uv[2 * r]; bv = uv[2 * r + 1]; }
       }
     }
@@ -1295,31 +1450,46 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
 
 /* Reading (the paper verifies a located particle by xi in [-1,1]^3 and does
  * not say what follows a failed check): a particle that the location step
- * finds outside its element crossed a face that the intersection search
- * missed (the clipping budget can run out at grazing incidence).  Internal
- * faces do not change the path, so the particle is followed across the face
- * through which its reference coordinate left (largest |xi_d|, lowest axis on
- * ties), with the periodic shift where the face is periodic, and located
- * again, at most RECOVER_HOPS times.  A wall or open face ends the search: the
- * particle is lost.  Returns 1 with e, x, xi updated when inside. */
+ * finds outside its element crossed a face that was not traced (reference-
+ * space localisation) or that the intersection search missed (the clipping
+ * budget can run out at grazing incidence).  Internal faces do not change the
+ * path, so the particle is followed across the face through which its
+ * reference coordinate left (largest |xi_d|, lowest axis on ties), with the
+ * periodic shift where the face is periodic, and located again, at most
+ * RECOVER_HOPS times; then, as in the paper's localisation, the
+ * background-mesh candidates of the point are tried.  A wall or open face
+ * ends the hops.  Returns 1 with e, x, xi updated when inside. */
 static int recover_elem(or_ctx* c, int* e, double* x, double* xi, int max_it, int64_t* it_sum,
                         int64_t* calls, int64_t* nfb) {
+  int eh = *e;
+  double xh[3] = {x[0], x[1], x[2]};
   for (int hop = 0; hop < RECOVER_HOPS; ++hop) {
     int d = 0;
     double ex = fabs(xi[0]);
     if (fabs(xi[1]) > ex) { d = 1; ex = fabs(xi[1]); }
     if (fabs(xi[2]) > ex) { d = 2; ex = fabs(xi[2]); }
-    int fid = *e * 6 + 2 * d + (xi[d] > 0.0 ? 1 : 0);
+    int fid = eh * 6 + 2 * d + (xi[d] > 0.0 ? 1 : 0);
     int bc = c->bc[fid];
-    if (bc != 0 && bc != 3) return 0;
+    if (bc != 0 && bc != 3) break;
     if (bc == 3)
-      for (int q = 0; q < 3; ++q) x[q] += c->shift[fid * 3 + q];
-    *e = c->nbr_elem[fid];
-    if (!newton_chain(c, *e, x, xi, max_it, 0, it_sum, calls, nfb)) return 0;
-    if (inside_ref(xi)) return 1;
+      for (int q = 0; q < 3; ++q) xh[q] += c->shift[fid * 3 + q];
+    eh = c->nbr_elem[fid];
+    if (!newton_chain(c, eh, xh, xi, max_it, 0, it_sum, calls, nfb)) break;
+    if (inside_ref(xi)) {
+      *e = eh;
+      for (int q = 0; q < 3; ++q) x[q] = xh[q];
+      return 1;
+    }
   }
-  return 0;
+  /* the paper's localisation: the background-mesh candidates of the point,
+   * in element order, the first that contains it */
+  int f = or_locate(c, x, -1, xi);
+  if (f < 0) return 0;
+  *e = f;
+  return 1;
 }
+
+double or_boundary_distance(const or_ctx* c, int e) { return c->dsafe[e]; }
 
 void or_default_opts(or_step_opts* o) {
   memset(o, 0, sizeof(*o));
@@ -1370,7 +1540,13 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
           xe[k] = x[k] + B[s] * kx[k];
           v[k] = v[k] + B[s] * kv[k];
         }
-        track(c, p, x, xe, v, kx, kv, o->max_crossings, &ncross, &nhits);
+        /* reference-space localisation (Sec. 3.2.3): a segment that cannot
+         * reach a boundary face is not traced; the next location step finds
+         * the element (recover_elem) */
+        double L = sqrt((xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
+                        (xe[2] - x[2]) * (xe[2] - x[2]));
+        if (!(o->tracking == 1 && L < c->dsafe[e]))
+          track(c, p, x, xe, v, kx, kv, o->max_crossings, &ncross, &nhits);
         for (int k = 0; k < 3; ++k) x[k] = xe[k];
       }
     }

@@ -59,14 +59,17 @@ int  or_bezier_intersect(int ng, const double* cp, const double* x0, const doubl
 double or_volume(const or_ctx*, int e, int node);
 void or_dg_node_pos(const or_ctx*, int e, int node, double* x);
 int  or_locate(or_ctx*, const double* x, int hint, double* xi);
+double or_boundary_distance(const or_ctx*, int e);
 
 /* particles / step ---------------------------------------------------------- */
 int  or_push(or_ctx*, int64_t n, const double* x, const double* v, const double* d,
              const int32_t* elem_hint, int32_t* status_out);
 /* opts: rk (0 = 5-stage 4th order, 1 = 3-stage 3rd order), drag (0 Stokes, 1 SN, 2 none),
- * max_newton_it, max_crossings, gravity[3], drag_mask[3] (1 keeps drag in that axis) */
+ * max_newton_it, max_crossings, use_mlp, tracking (0 physical space; 1 reference-space
+ * localisation: segments that cannot reach a boundary face are not traced),
+ * gravity[3], drag_mask[3] (1 keeps drag in that axis) */
 typedef struct {
-  int32_t rk, drag, max_newton_it, max_crossings, use_mlp, pad_;
+  int32_t rk, drag, max_newton_it, max_crossings, use_mlp, tracking;
   double gravity[3];
   double drag_mask[3];
 } or_step_opts;

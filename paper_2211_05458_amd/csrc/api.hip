@@ -16,7 +16,7 @@ struct fp_ctx {
   // mesh (host staging)
   bool mesh_ok = false;
   int E = 0, n_geo = 0, ng = 0, N = 0, n = 0, dg_nodes = 0;
-  std::vector<double> X, shift, elo, ehi;
+  std::vector<double> X, shift, elo, ehi, dsafe;
   std::vector<int32_t> nbr_elem, nbr_face, bstart, blist;
   std::vector<int8_t> bc;
   std::vector<double> Minv;
@@ -206,7 +206,7 @@ struct Timed {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
+  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, part[2], total;
   size_t part_bytes;
@@ -226,6 +226,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.elo = take(E * 3 * 8);
   L.ehi = take(E * 3 * 8);
   L.nbox = take(E * 6 * 8);
+  L.dsafe = take(E * 8);
   L.nbr_elem = take(E * 6 * 4);
   L.nbr_face = take(E * 6 * 4);
   L.bc = take(E * 6);
@@ -278,6 +279,111 @@ Particles carve(char* base, int64_t cap) {
 namespace {
 // counting sort of the current particle buffer into the other one, then the
 // element tasks of the fast stage kernel
+// Lower bound of the distance from each element to any face that is not
+// internal (wall, open, periodic), for the reference-space localisation: the
+// gap between the element's padded node box and the face's Bernstein
+// control-point box (which contains the face), over the faces within h_e of
+// the element, less 0.1 h_e, in [0, 0.9 h_e].  Host, at mesh set-up.
+void boundary_distance(fp_ctx* c) {
+  const int E = c->E, ng = c->ng, D = ng - 1;
+  const size_t ng3 = (size_t)ng * ng * ng;
+  const size_t ncell = (size_t)c->bn[0] * c->bn[1] * c->bn[2];
+  std::vector<double> fbox;   // [6] per boundary face
+  for (int e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      if (c->bc[e * 6 + f] == 0) continue;
+      // Lagrange nodes of the face -> Bernstein control points, P = M^-1 F M^-T
+      int d = f / 2, a = (d == 0) ? 1 : 0, b = (d == 2) ? 1 : 2, fix = (f & 1) ? D : 0;
+      const double* Xe = c->X.data() + (size_t)e * ng3 * 3;
+      std::vector<double> T((size_t)ng * ng * 3), P((size_t)ng * ng * 3);
+      for (int n = 0; n < ng; ++n)
+        for (int mm = 0; mm < ng; ++mm)
+          for (int q = 0; q < 3; ++q) {
+            double acc = 0.0;
+            for (int r = 0; r < ng; ++r) {
+              int idx[3];
+              idx[d] = fix; idx[a] = r; idx[b] = n;
+              acc += c->Minv[mm * ng + r] * Xe[((idx[2] * ng + idx[1]) * ng + idx[0]) * 3 + q];
+            }
+            T[(n * ng + mm) * 3 + q] = acc;
+          }
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int n = 0; n < ng; ++n)
+        for (int mm = 0; mm < ng; ++mm)
+          for (int q = 0; q < 3; ++q) {
+            double acc = 0.0;
+            for (int r = 0; r < ng; ++r) acc += c->Minv[n * ng + r] * T[(r * ng + mm) * 3 + q];
+            lo[q] = std::min(lo[q], acc);
+            hi[q] = std::max(hi[q], acc);
+          }
+      for (int q = 0; q < 3; ++q) fbox.push_back(lo[q]);
+      for (int q = 0; q < 3; ++q) fbox.push_back(hi[q]);
+    }
+  const int nbf = (int)(fbox.size() / 6);
+  auto cell_range = [&](const double* lo, const double* hi, double pad, int* c0, int* c1) {
+    for (int k = 0; k < 3; ++k) {
+      c0[k] = std::max(0, (int)std::floor((lo[k] - pad - c->blo[k]) / c->bdx[k]));
+      c1[k] = std::min(c->bn[k] - 1, (int)std::floor((hi[k] + pad - c->blo[k]) / c->bdx[k]));
+    }
+  };
+  std::vector<int> fstart(ncell + 1, 0), flist;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int> fill;
+    if (pass == 1) {
+      for (size_t q = 0; q < ncell; ++q) fstart[q + 1] += fstart[q];
+      flist.assign(std::max(1, fstart[ncell]), 0);
+      fill.assign(ncell, 0);
+    }
+    for (int j = 0; j < nbf; ++j) {
+      int c0[3], c1[3];
+      cell_range(&fbox[6 * j], &fbox[6 * j + 3], 0.0, c0, c1);
+      for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+          for (int x = c0[0]; x <= c1[0]; ++x) {
+            size_t id = ((size_t)z * c->bn[1] + y) * c->bn[0] + x;
+            if (pass == 0) fstart[id + 1]++;
+            else flist[fstart[id] + fill[id]++] = j;
+          }
+    }
+  }
+  c->dsafe.assign(E, 0.0);
+  for (int e = 0; e < E; ++e) {
+    // element length scale: longest corner-to-corner edge
+    const double* Pn = c->X.data() + (size_t)e * ng3 * 3;
+    double h = 0.0;
+    for (int v = 0; v < 8; ++v)
+      for (int bit = 0; bit < 3; ++bit) {
+        int w = v ^ (1 << bit);
+        if (w < v) continue;
+        int iv = ((((v >> 2) & 1) * D) * ng + ((v >> 1) & 1) * D) * ng + (v & 1) * D;
+        int iw = ((((w >> 2) & 1) * D) * ng + ((w >> 1) & 1) * D) * ng + (w & 1) * D;
+        double r2 = 0.0;
+        for (int q = 0; q < 3; ++q) r2 += (Pn[iv * 3 + q] - Pn[iw * 3 + q]) * (Pn[iv * 3 + q] - Pn[iw * 3 + q]);
+        h = std::max(h, std::sqrt(r2));
+      }
+    const double* lo = &c->elo[e * 3];
+    const double* hi = &c->ehi[e * 3];
+    double best = h;
+    int c0[3], c1[3];
+    cell_range(lo, hi, h, c0, c1);
+    for (int z = c0[2]; z <= c1[2]; ++z)
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x) {
+          size_t id = ((size_t)z * c->bn[1] + y) * c->bn[0] + x;
+          for (int q = fstart[id]; q < fstart[id + 1]; ++q) {
+            const double* fb = &fbox[6 * flist[q]];
+            double g2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+              double gap = std::max(0.0, std::max(fb[k] - hi[k], lo[k] - fb[3 + k]));
+              g2 += gap * gap;
+            }
+            best = std::min(best, std::sqrt(g2));
+          }
+        }
+    c->dsafe[e] = std::max(0.0, best - 0.1 * h);
+  }
+}
+
 int sort_particles(fp_ctx* c) {
   hipStream_t s = c->stream;
   if (c->np == 0) {   // nothing to bucket: no histogram is computed, so no tasks either
@@ -400,6 +506,7 @@ int fp_init_mesh(fp_ctx* c, const fp_mesh_desc* d) {
             else c->blist[c->bstart[cell] + fill[cell]++] = e;
           }
   }
+  boundary_distance(c);
   c->mesh_ok = true;
   c->ws = nullptr;
   c->np = 0;
@@ -436,6 +543,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   size_t E = c->E, ng3 = (size_t)c->ng * c->ng * c->ng;
   HIPCHK(c, hipMemcpyAsync(b + L.X, c->X.data(), E * ng3 * 3 * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.elo, c->elo.data(), E * 3 * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(b + L.dsafe, c->dsafe.data(), E * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.ehi, c->ehi.data(), E * 3 * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.nbr_elem, c->nbr_elem.data(), E * 6 * 4, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.nbr_face, c->nbr_face.data(), E * 6 * 4, hipMemcpyHostToDevice, s));
@@ -458,6 +566,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   m.elo = (const double*)(b + L.elo);
   m.ehi = (const double*)(b + L.ehi);
   m.nbox = (const double*)(b + L.nbox);
+  m.dsafe = (const double*)(b + L.dsafe);
   for (int i = 0; i < kMaxNodes; ++i) {
     m.xgeo[i] = i < c->ng ? c->xgeo[i] : 0.0;
     m.cgeo[i] = i < c->ng ? c->cgeo[i] : 0.0;
@@ -572,7 +681,8 @@ int fp_push_particles(fp_ctx* c, int64_t n, const double* x, const double* v, co
 int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   if (!c || !o || n_steps < 0 || !(dt > 0.0)) return FP_EINVAL;
   if (!c->ws || !c->fluid_ok) return fail(c, FP_ESTATE, "fp_step: workspace or fluid state missing");
-  if (o->rk < 0 || o->rk > 1 || o->drag < 0 || o->drag > 2 || o->precision < 0 || o->precision > 1)
+  if (o->rk < 0 || o->rk > 1 || o->drag < 0 || o->drag > 2 || o->precision < 0 || o->precision > 1 ||
+      o->tracking < 0 || o->tracking > 1)
     return fail(c, FP_EINVAL, "fp_step: bad options");
   if (o->precision == 0 && c->fl.f32)
     ;  // FP64 arithmetic on an FP32 state is allowed (values widened on load)
@@ -594,6 +704,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   sp.max_it = o->max_newton_it > 0 ? o->max_newton_it : 50;
   sp.max_cross = o->max_crossings > 0 ? o->max_crossings : 64;
   sp.use_mlp = (o->guess == 1 && c->mlp_w) ? 1 : 0;
+  sp.refspace = o->tracking;
   hipStream_t s = c->stream;
   for (int st = 0; st < n_steps; ++st) {
     if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {

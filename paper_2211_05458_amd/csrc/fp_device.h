@@ -379,30 +379,68 @@ __device__ __forceinline__ bool locate_xi(const MeshView& m, int e, const double
                                     m.xnode + (size_t)e * (NN * NN * NN * 3), x, xi, max_it, it_sum, calls, fallbacks);
 }
 
-// A located particle lies outside its element (a crossing that the clipping
-// budget missed at grazing incidence): follow the reference coordinate with
-// the largest excess to the neighbour across that face (lowest axis on ties),
-// applying the periodic shift, and locate again, at most kRecoverHops times.
-// Walls and open faces end the search (a missed reflection cannot be undone).
-// On success e, x and xi describe the particle in its element.
+// A located particle lies outside its element: a crossing that was not traced
+// (reference-space localisation) or that the clipping budget missed at
+// grazing incidence.  Follow the reference coordinate with the largest excess
+// to the neighbour across that face (lowest axis on ties), applying the
+// periodic shift, and locate again, at most kRecoverHops times; then try the
+// background-mesh candidates of the point (the paper's localisation).  Walls
+// and open faces end the hops.  On success e, x and xi describe the particle
+// in its element.
+template <int NN, int NG>
+__device__ inline int bgm_locate(const MeshView& m, const double* x, double* xi, int& it_sum, int& calls,
+                                 int& fallbacks);
+
 template <int NN, int NG>
 __device__ inline bool recover_elem(const MeshView& m, int& e, double* x, double* xi, int max_it, int& it_sum,
                                     int& calls, int& fallbacks) {
+  int eh = e;
+  double xh[3] = {x[0], x[1], x[2]};
 #pragma unroll 1
   for (int hop = 0; hop < kRecoverHops; ++hop) {
     int d = 0;
     double ex = fabs(xi[0]);
     if (fabs(xi[1]) > ex) { d = 1; ex = fabs(xi[1]); }
     if (fabs(xi[2]) > ex) { d = 2; ex = fabs(xi[2]); }
-    const FaceRec& F = m.faces[e * 6 + 2 * d + (xi[d] > 0.0 ? 1 : 0)];
-    if (F.bc != BC_INTERNAL && F.bc != BC_PERIODIC) return false;
+    const FaceRec& F = m.faces[eh * 6 + 2 * d + (xi[d] > 0.0 ? 1 : 0)];
+    if (F.bc != BC_INTERNAL && F.bc != BC_PERIODIC) break;
     if (F.bc == BC_PERIODIC)
-      for (int k = 0; k < 3; ++k) x[k] += F.shift[k];
-    e = F.nbr_elem;
-    if (!locate_xi<NN, NG>(m, e, x, xi, max_it, false, it_sum, calls, fallbacks)) return false;
-    if (inside_ref(xi)) return true;
+      for (int k = 0; k < 3; ++k) xh[k] += F.shift[k];
+    eh = F.nbr_elem;
+    if (!locate_xi<NN, NG>(m, eh, xh, xi, max_it, false, it_sum, calls, fallbacks)) break;
+    if (inside_ref(xi)) {
+      e = eh;
+      x[0] = xh[0]; x[1] = xh[1]; x[2] = xh[2];
+      return true;
+    }
   }
-  return false;
+  // the paper's localisation: the background-mesh candidates of the point
+  const int f = bgm_locate<NN, NG>(m, x, xi, it_sum, calls, fallbacks);
+  if (f < 0) return false;
+  e = f;
+  return true;
+}
+
+// first background-mesh candidate of x (element order) whose padded box holds
+// x and whose Newton solution lies inside; -1 if none
+template <int NN, int NG>
+__device__ inline int bgm_locate(const MeshView& m, const double* x, double* xi, int& it_sum, int& calls,
+                                 int& fallbacks) {
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = (int)floor((x[k] - m.blo[k]) / m.bdx[k]);
+    if (!(c[k] >= 0 && c[k] < m.bn[k])) return -1;
+  }
+  const int64_t cell = ((int64_t)c[2] * m.bn[1] + c[1]) * m.bn[0] + c[0];
+#pragma unroll 1
+  for (int q = m.bstart[cell]; q < m.bstart[cell + 1]; ++q) {
+    const int e = m.blist[q];
+    if (x[0] < m.elo[e * 3] || x[0] > m.ehi[e * 3] || x[1] < m.elo[e * 3 + 1] || x[1] > m.ehi[e * 3 + 1] ||
+        x[2] < m.elo[e * 3 + 2] || x[2] > m.ehi[e * 3 + 2])
+      continue;
+    if (locate_xi<NN, NG>(m, e, x, xi, 50, false, it_sum, calls, fallbacks) && inside_ref(xi)) return e;
+  }
+  return -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -799,7 +837,7 @@ __device__ __forceinline__ bool half_extent(const double* lo, const double* hi, 
 // other parameter direction.  The convex-hull property of the Bernstein form
 // keeps every root.
 template <int NG>
-__device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) {
+__device__ inline bool clip_dir(const double* q, int dir, double amin, double amax, double& a, double& b) {
   constexpr int N = NG - 1;
 #define QQ(m, k, c) q[((m) * NG + (k)) * 3 + (c)]
   double L0, L1;
@@ -844,6 +882,25 @@ __device__ inline bool clip_dir(const double* q, int dir, double& a, double& b) 
   if (!half_extent<NG>(dlo, dhi, 0.0, false, a2, b2)) return false;
   double lo = fmax(a1, a2), hi = fmin(b1, b2);
   if (lo > hi) return false;
+  // the displacement band amin <= alpha <= amax (component 2), on the same
+  // convex hull of the rows' ranges
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    double mn = 1e300, mx = -1e300;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      double al = (dir == 0) ? q[(i * NG + k) * 3 + 2] : q[(k * NG + i) * 3 + 2];
+      mn = fmin(mn, al);
+      mx = fmax(mx, al);
+    }
+    dlo[i] = mn;
+    dhi[i] = mx;
+  }
+  if (!half_extent<NG>(dlo, dhi, amin, true, a1, b1)) return false;
+  if (!half_extent<NG>(dlo, dhi, amax, false, a2, b2)) return false;
+  lo = fmax(lo, fmax(a1, a2));
+  hi = fmin(hi, fmin(b1, b2));
+  if (lo > hi) return false;
   a = fmax(0.0, lo - kClipPad);
   b = fmin(1.0, hi + kClipPad);
   return true;
@@ -878,105 +935,6 @@ __device__ __forceinline__ bool outside_band(const double* q, double amin, doubl
   return hi < amin || lo > amax;
 }
 
-// Intersections of the line x0 + alpha t (|t| = 1) with a curved Bezier face,
-// keeping those with displacement in [amin, amax]: the face is projected onto
-// two planes containing the line (Sec. 3.2.4) and the zero of the 2-D patch is
-// isolated by Bezier clipping, alternating u and v and splitting where a clip
-// removes less than 20 %.  A (sub-)patch whose displacement range misses
-// [amin, amax] is dropped (convex hull), which keeps the search on the stage
-// segment at grazing incidence.  Boxes narrower than 1e-7 are finished by 2-D
-// Newton on the plane distances (quadratic from there).  Sub-patches are
-// rebuilt from the face control points when popped, so only one projected
-// patch is live.
-template <int NG>
-__device__ int curved_hit(const double* __restrict__ cp, const double* x0, const double* t, double amin, double amax,
-                          double* al, double* uv, int max_roots) {
-  constexpr double kBoxTol = 1e-7;
-  double n1[3], n2[3];
-  ray_planes(t, n1, n2);
-  double stk[kClipStack][4];
-  int sp = 1, nroots = 0, budget = kClipSteps;
-  stk[0][0] = 0.0; stk[0][1] = 1.0; stk[0][2] = 0.0; stk[0][3] = 1.0;
-  double q[NG * NG * 3];
-  while (sp > 0 && budget > 0) {
-    --sp;
-    double u0 = stk[sp][0], u1 = stk[sp][1], v0 = stk[sp][2], v1 = stk[sp][3];
-    project_face<NG>(cp, x0, t, n1, n2, q);
-    if (u0 != 0.0 || u1 != 1.0) patch_restrict<NG, 3>(q, 0, u0, u1);
-    if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG, 3>(q, 1, v0, v1);
-    for (;;) {
-      if (--budget < 0) break;
-      if (outside_band<NG>(q, amin, amax)) break;
-      double a, b;
-      if (!clip_dir<NG>(q, 0, a, b)) break;
-      patch_restrict<NG, 3>(q, 0, a, b);
-      double w = u1 - u0;
-      double nu0 = u0 + a * w, nu1 = u0 + b * w;
-      u0 = nu0; u1 = nu1;
-      double ru = b - a;
-      if (!clip_dir<NG>(q, 1, a, b)) break;
-      patch_restrict<NG, 3>(q, 1, a, b);
-      w = v1 - v0;
-      double nv0 = v0 + a * w, nv1 = v0 + b * w;
-      v0 = nv0; v1 = nv1;
-      double rv = b - a;
-      double wu = u1 - u0, wv = v1 - v0;
-      bool conv = (wu <= kBoxTol && wv <= kBoxTol);
-      bool su = (ru > 0.8 && wu > kBoxTol), sv = (rv > 0.8 && wv > kBoxTol);
-      if (!conv && (su || sv) && sp + 2 > kClipStack) conv = true;
-      if (conv) {
-        double u = (u0 + u1) - 1.0, v = (v0 + v1) - 1.0;   // box centre in [-1, 1]
-        double p[3], pu[3], pv[3];
-#pragma unroll 1
-        for (int it = 0; it < 3; ++it) {
-          bezier_eval<NG>(cp, u, v, p, pu, pv);
-          double r[3] = {p[0] - x0[0], p[1] - x0[1], p[2] - x0[2]};
-          double G0 = dot3(r, n1), G1 = dot3(r, n2);
-          double Gu0 = dot3(pu, n1), Gu1 = dot3(pu, n2), Gv0 = dot3(pv, n1), Gv1 = dot3(pv, n2);
-          double det = Gu0 * Gv1 - Gu1 * Gv0;
-          if (det == 0.0 || !isfinite(det)) break;
-          u += -(G0 * Gv1 - G1 * Gv0) / det;
-          v += -(Gu0 * G1 - Gu1 * G0) / det;
-        }
-        bool dup = false;
-        for (int r = 0; r < nroots; ++r)
-          if (fabs(uv[2 * r] - u) < 1e-9 && fabs(uv[2 * r + 1] - v) < 1e-9) dup = true;
-        if (!dup && nroots < max_roots) {
-          bezier_eval<NG>(cp, u, v, p, nullptr, nullptr);
-          double r3[3] = {p[0] - x0[0], p[1] - x0[1], p[2] - x0[2]};
-          al[nroots] = dot3(r3, t);
-          uv[2 * nroots] = u;
-          uv[2 * nroots + 1] = v;
-          nroots++;
-        }
-        break;
-      }
-      if (su || sv) {
-        int dir = (su && sv) ? (wu >= wv ? 0 : 1) : (su ? 0 : 1);
-        if (dir == 0) {
-          double um = 0.5 * (u0 + u1);
-          stk[sp][0] = um; stk[sp][1] = u1; stk[sp][2] = v0; stk[sp][3] = v1; sp++;
-          stk[sp][0] = u0; stk[sp][1] = um; stk[sp][2] = v0; stk[sp][3] = v1; sp++;
-        } else {
-          double vm = 0.5 * (v0 + v1);
-          stk[sp][0] = u0; stk[sp][1] = u1; stk[sp][2] = vm; stk[sp][3] = v1; sp++;
-          stk[sp][0] = u0; stk[sp][1] = u1; stk[sp][2] = v0; stk[sp][3] = vm; sp++;
-        }
-        break;
-      }
-    }
-  }
-  return nroots;
-}
-
-template <int NG>
-__device__ inline int face_roots(const MeshView& m, int fid, const FaceRec& F, const double* x0, const double* t,
-                                 double amin, double amax, double* al, double* uv) {
-  if (F.type == FACE_PLANAR) return planar_hit(F, x0, t, al, uv);
-  if (F.type == FACE_BILINEAR) return bilinear_hit(F, x0, t, al, uv);
-  return curved_hit<NG>(m.cp + (size_t)fid * (NG * NG * 3), x0, t, amin, amax, al, uv, kMaxRoots);
-}
-
 // Physical-space tracking of the straight stage segment xs -> xe (Sec. 3.2.3):
 // smallest alpha in (1e-12 h_e, remaining length] with (u, v) in [-1,1]^2,
 // ties to the lowest local face; hand-off, periodic shift, specular reflection
@@ -1008,9 +966,13 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
   int sp = 0, budget = 0;
   double u0 = 0.0, u1 = 1.0, v0 = 0.0, v1 = 1.0;
   double q[NG * NG * 3];
-  auto consider = [&](double a, double uu, double vv) {
+  // a root counts if it lies in (amin, L], on the face, and the path leaves
+  // the element there: tn = t . outward normal > 0 (a root where the path
+  // enters, at a tangential touch or the entry point, is not a crossing)
+  auto consider = [&](double a, double uu, double vv, double tn) {
     if (!(a > amin && a <= L)) return;
     if (fabs(uu) > 1.0 + kUVEps || fabs(vv) > 1.0 + kUVEps) return;
+    if (!(tn > 0.0)) return;
     if (a < best) { best = a; bf = f; bu = uu; bv = vv; }
   };
   int mode = NEW_LEG;
@@ -1042,7 +1004,15 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         if (F.type != FACE_CURVED) {
           double al[2], uv[4];
           int nr = (F.type == FACE_PLANAR) ? planar_hit(F, xs, t, al, uv) : bilinear_hit(F, xs, t, al, uv);
-          for (int r = 0; r < nr; ++r) consider(al[r], uv[2 * r], uv[2 * r + 1]);
+          for (int r = 0; r < nr; ++r) {
+            double pu[3], pv[3], nrm[3];
+            for (int k = 0; k < 3; ++k) {
+              pu[k] = F.A[k] * uv[2 * r + 1] + F.B[k];
+              pv[k] = F.A[k] * uv[2 * r] + F.C[k];
+            }
+            cross3(pu, pv, nrm);
+            consider(al[r], uv[2 * r], uv[2 * r + 1], kFaceSign[f] * dot3(nrm, t));
+          }
           f++;
         } else {
           // only roots with displacement in (amin, L] matter: clip to a padded band
@@ -1073,13 +1043,13 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       // one Bezier-clipping iteration (Sec. 3.2.4) on the live box
       double a, b;
       mode = POP;
-      if (--budget >= 0 && !outside_band<NG>(q, bmin, bmax) && clip_dir<NG>(q, 0, a, b)) {
+      if (--budget >= 0 && !outside_band<NG>(q, bmin, bmax) && clip_dir<NG>(q, 0, bmin, bmax, a, b)) {
         patch_restrict<NG, 3>(q, 0, a, b);
         double w = u1 - u0;
         double nu0 = u0 + a * w, nu1 = u0 + b * w;
         u0 = nu0; u1 = nu1;
         const double ru = b - a;
-        if (clip_dir<NG>(q, 1, a, b)) {
+        if (clip_dir<NG>(q, 1, bmin, bmax, a, b)) {
           patch_restrict<NG, 3>(q, 1, a, b);
           w = v1 - v0;
           double nv0 = v0 + a * w, nv1 = v0 + b * w;
@@ -1104,9 +1074,10 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
               u += -(G0 * Gv1 - G1 * Gv0) / det;
               vv += -(Gu0 * G1 - Gu1 * G0) / det;
             }
-            bezier_eval<NG>(cpf, u, vv, pp, nullptr, nullptr);
-            double r3[3] = {pp[0] - xs[0], pp[1] - xs[1], pp[2] - xs[2]};
-            consider(dot3(r3, t), u, vv);
+            bezier_eval<NG>(cpf, u, vv, pp, pu, pv);
+            double r3[3] = {pp[0] - xs[0], pp[1] - xs[1], pp[2] - xs[2]}, nrm[3];
+            cross3(pu, pv, nrm);
+            consider(dot3(r3, t), u, vv, kFaceSign[f] * dot3(nrm, t));
           } else if (su || sv) {
             const int dir = (su && sv) ? (wu >= wv ? 0 : 1) : (su ? 0 : 1);
             if (dir == 0) {

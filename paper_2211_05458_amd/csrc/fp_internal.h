@@ -20,6 +20,9 @@ constexpr double kUVEps = 1e-12;
 constexpr double kClipTol = 1e-12;
 constexpr double kClipPad = 1e-10;
 constexpr double kEntryRel = 1e-9;   // entry-face root threshold, relative to the face diameter
+// sign that turns dp/du x dp/dv of local face f into its outward normal (face
+// parameters are the two other reference axes in increasing order, J > 0)
+__device__ constexpr double kFaceSign[6] = {-1.0, 1.0, 1.0, -1.0, -1.0, 1.0};
 constexpr int kRecoverHops = 3;      // neighbour hops when a located particle lies outside its element
 
 enum { ACTIVE = 0, OPEN_EXIT = 1, LOST_NEWTON = 2, LOST_TRACK = 3, MAX_CROSS = 4, REJECTED = 5 };
@@ -51,6 +54,7 @@ struct MeshView {
   const double* elo;      // [E][3] padded element box
   const double* ehi;
   const double* nbox;     // [E][6] box of the DG nodes (lo xyz, hi xyz)
+  const double* dsafe;    // [E] lower bound of the distance to a face that is not internal
   double xgeo[kMaxNodes], cgeo[kMaxNodes];  // geometry nodes, 1/prod(x_i - x_j)
   double xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
   float xdgf[kMaxNodes], cdgf[kMaxNodes];
@@ -88,6 +92,7 @@ struct StepParams {
   double A, B;          // low-storage coefficients of this stage
   double gravity[3];
   int32_t drag, max_it, max_cross, use_mlp;
+  int32_t refspace;     // reference-space localisation of segments that cannot reach a boundary face
 };
 
 }  // namespace fp

@@ -133,8 +133,15 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
         stage_update<NN, UT, MIXED>(m, Ue, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
         const FaceRec* Fe = faces + (size_t)e * 6;
         bool any = false;
+        // reference-space localisation: a segment that cannot reach a
+        // boundary face is not traced (the next location step finds it)
+        const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
+                          (xe[2] - x[2]) * (xe[2] - x[2]);
+        const double ds = m.dsafe[e];
+        if (!(sp.refspace && L2 < ds * ds)) {
 #pragma unroll 1
-        for (int f = 0; f < 6; ++f) any = any || bbox_hit(Fe[f], x, xe);
+          for (int f = 0; f < 6; ++f) any = any || bbox_hit(Fe[f], x, xe);
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           P.x[k * cap + p] = xe[k];
@@ -219,7 +226,10 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
             P.kx[k * cap + p] = kx[k];
             P.kv[k * cap + p] = kv[k];
           }
-          trk = true;
+          const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
+                            (xe[2] - x[2]) * (xe[2] - x[2]);
+          const double ds = m.dsafe[e];
+          trk = !(sp.refspace && L2 < ds * ds);
           xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
         }
       }

@@ -45,7 +45,7 @@ class FluidParams(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("rk", C.c_int32), ("drag", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32),
                 ("sort_every", C.c_int32), ("max_newton_it", C.c_int32), ("max_crossings", C.c_int32),
-                ("pad_", C.c_int32), ("gravity", C.c_double * 3)]
+                ("tracking", C.c_int32), ("gravity", C.c_double * 3)]
 
 
 _lib = None
@@ -187,8 +187,8 @@ class FlexiPart:
         return st, rc
 
     def step(self, dt, n_steps=1, rk=1, drag=1, precision=0, guess=0, sort_every=1, max_newton_it=50,
-             max_crossings=64, gravity=(0.0, 0.0, 0.0)):
-        o = StepOpts(rk, drag, precision, guess, sort_every, max_newton_it, max_crossings, 0,
+             max_crossings=64, gravity=(0.0, 0.0, 0.0), tracking=0):
+        o = StepOpts(rk, drag, precision, guess, sort_every, max_newton_it, max_crossings, int(tracking),
                      (C.c_double * 3)(*gravity))
         return self._check(self.L.fp_step(self.ctx, float(dt), int(n_steps), C.byref(o)), "fp_step")
 

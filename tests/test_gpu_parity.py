@@ -263,3 +263,30 @@ def test_grazing_handoff_on_curved_32cube():
     _, rg = run_gpu(w, 30, rk=1, drag=1, x=w.x[b], v=w.v[b], d=w.d[b], hint=w.elem_hint[b])
     assert ro["status"][0] == O.ACTIVE
     assert_parity(ro, rg, vscale=2.0)
+
+
+def test_reference_space_localisation_parity():
+    """Tracking mode 1 (segments that cannot reach a wall or periodic face are
+    localised, not traced): parity with the oracle in the same mode, and the
+    same result as physical tracking on the GPU."""
+    w = W.curved_box(cells=8, N=3, n_particles=6000, n_steps=1, seed=31)
+    v = w.v * 20.0
+    w.dt = 2e-3
+    o = O.Oracle(w.mesh, w.N, w.U)
+    o.push(w.x, v, w.d, w.elem_hint)
+    o.step(w.dt, 12, rk=1, drag=1, tracking=1)
+    ro = o.read()
+    FlexiPart = _gpu()
+    res = []
+    for tracking in (1, 0):
+        g = FlexiPart(w.mesh, w.N, len(w.x))
+        g.set_fluid_state(w.U)
+        g.push(w.x, v, w.d, w.elem_hint)
+        g.step(w.dt, 12, rk=1, drag=1, tracking=tracking)
+        res.append((g.read(), g.stats()))
+    (r1, s1), (r0, s0) = res
+    assert_parity(ro, r1, vscale=40.0)
+    for k in ("status", "elem", "hits"):
+        np.testing.assert_array_equal(r1[k], r0[k])
+    assert np.abs(r1["x"] - r0["x"]).max() <= 1e-12
+    assert s1["recovered"] > 1000 and s1["crossings"] < 0.8 * s0["crossings"] and s1["lost"] == 0

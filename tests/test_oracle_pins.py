@@ -746,3 +746,54 @@ def test_grazing_face_crossings_stay_tracked():
     dx = r["x"][free] - (x0[free] + d[free] * L)
     dx[:, [0, 2]] -= np.round(dx[:, [0, 2]])            # periods 1 in x and z
     assert np.abs(dx).max() < 1e-12
+
+
+def test_reference_space_localisation_equals_physical_tracking():
+    """Internal faces do not change a path, so localising the segments that
+    cannot reach a boundary face (instead of tracing them) must give the same
+    elements, positions, velocities and wall hits, bit for bit."""
+    w = W.curved_box(cells=8, N=3, n_particles=6000, n_steps=1, seed=31)
+    out = []
+    for tracking in (0, 1):
+        o = O.Oracle(w.mesh, w.N, w.U)
+        o.push(w.x, w.v * 20.0, w.d, w.elem_hint)
+        o.step(2e-3, 12, rk=1, drag=1, tracking=tracking)
+        out.append((o.read(), o.stats()))
+    (a, sa), (b, sb) = out
+    for k in ("status", "elem", "hits", "x", "v"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert sa["wall_hits"] > 100 and sb["crossings"] < 0.8 * sa["crossings"] and sb["recovered"] > 1000
+
+
+def test_boundary_distance_is_a_lower_bound():
+    """Brute force: points of each element against dense samples of every wall
+    and periodic face; no point is closer to such a face than the element's
+    bound, and interior elements get a positive bound."""
+    w = W.curved_box(cells=6, N=2, n_particles=1, n_steps=1, seed=32)
+    o = O.Oracle(w.mesh, w.N, w.U)
+    mesh = w.mesh
+    E = mesh.n_elem
+    g = np.linspace(-1, 1, 9)
+    U, V = np.meshgrid(g, g, indexing="ij")
+    pts_face = []
+    for e in range(E):
+        for f in range(6):
+            if mesh.bc[e, f] == 0:
+                continue
+            ax = f // 2
+            free = [a for a in range(3) if a != ax]
+            for u, v in zip(U.ravel(), V.ravel()):
+                xi = np.zeros(3)
+                xi[ax] = 1.0 if f % 2 else -1.0
+                xi[free[0]], xi[free[1]] = u, v
+                pts_face.append(o.map(e, xi)[0])
+    pts_face = np.array(pts_face)
+    rng = np.random.default_rng(33)
+    d = np.array([o.boundary_distance(e) for e in range(E)])
+    assert (d > 0).sum() >= 4 * 4 * 2          # elements two layers from walls and periodic faces
+    for e in range(E):
+        if d[e] == 0.0:
+            continue
+        xs = np.array([o.map(e, rng.uniform(-1, 1, 3))[0] for _ in range(20)])
+        dist = np.sqrt(((xs[:, None, :] - pts_face[None, :, :]) ** 2).sum(-1)).min()
+        assert dist >= d[e]
