@@ -797,3 +797,32 @@ def test_boundary_distance_is_a_lower_bound():
         xs = np.array([o.map(e, rng.uniform(-1, 1, 3))[0] for _ in range(20)])
         dist = np.sqrt(((xs[:, None, :] - pts_face[None, :, :]) ** 2).sum(-1)).min()
         assert dist >= d[e]
+
+
+def test_face_sign_gives_outward_normals():
+    """The exit-direction rule uses n_out = s_f (dp/du x dp/dv) with face
+    parameters the two other reference axes in increasing order and
+    s = (-1, 1, 1, -1, -1, 1).  Checked with finite differences of the element
+    map (not the face code): at face centres and random face points of curved
+    elements, n_out points away from the element's interior."""
+    s = [-1.0, 1.0, 1.0, -1.0, -1.0, 1.0]
+    w = W.curved_box(cells=3, N=2, n_particles=1, n_steps=1, seed=34)
+    o = O.Oracle(w.mesh, w.N, w.U)
+    rng = np.random.default_rng(35)
+    hstep = 1e-6
+    for e in range(w.mesh.n_elem):
+        for f in range(6):
+            ax = f // 2
+            a, b = [k for k in range(3) if k != ax]
+            for uv in [(0.0, 0.0)] + [tuple(rng.uniform(-0.9, 0.9, 2)) for _ in range(2)]:
+                xi = np.zeros(3)
+                xi[ax] = 1.0 if f % 2 else -1.0
+                xi[a], xi[b] = uv
+                def at(d, k):
+                    z = xi.copy(); z[k] += d
+                    return o.map(e, z)[0]
+                pu = (at(hstep, a) - at(-hstep, a)) / (2 * hstep)
+                pv = (at(hstep, b) - at(-hstep, b)) / (2 * hstep)
+                n = s[f] * np.cross(pu, pv)
+                inward = o.map(e, xi * np.where(np.arange(3) == ax, 0.9, 1.0))[0] - o.map(e, xi)[0]
+                assert np.dot(n, inward) < 0
