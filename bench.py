@@ -166,10 +166,10 @@ def bench_annulus(args):
     guess_err = float((pred - xi).abs().max(dim=1).values.median().item())
     g.close()
     runs = {}
-    for name, U, prec, guess in [("fp64", U64, 0, 0), ("fp64_learned", U64, 0, 1), ("mixed", U32, 1, 0),
-                                 ("mixed_learned", U32, 1, 1)]:
+    for name, U, prec, guess, tr in [("fp64", U64, 0, 0, 0), ("fp64_learned", U64, 0, 1, 0), ("mixed", U32, 1, 0, 0),
+                                     ("mixed_learned", U32, 1, 1, 0), ("mixed_learned_refspace", U32, 1, 1, 1)]:
         print("[bench] run", name, file=sys.stderr, flush=True)
-        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None)
+        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None, tracking=tr)
     out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
            "value": summary(runs["mixed_learned"], K)["value"], "unit": "particle-steps/s", "n_gpus": 1,
            "steps": K, "warmup": Wm, "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
@@ -183,6 +183,7 @@ def bench_annulus(args):
         if k != "fp64":
             out[k].update(pos_error(runs["fp64"], r, w.mesh.h))
     out["speedup_mixed_learned_vs_fp64"] = out["mixed_learned"]["value"] / out["fp64"]["value"]
+    out["speedup_mixed_learned_refspace_vs_fp64"] = out["mixed_learned_refspace"]["value"] / out["fp64"]["value"]
     print(json.dumps(out))
 
 
@@ -238,9 +239,9 @@ def bench_twoway(args):
     r = run_gpu(w, U32, 1, K, Wm, deposit=dep, keep=True)
     g = r["ctx"]
     V = g.node_volumes()
-    tot_shape = torch.einsum("ecq,eq->c", S["S"].double(), V)
+    tot_shape = (S["S"].double() * V[:, None, :]).sum(dim=(0, 2))
     Sn = g.deposit(None, kind=0, dtype=torch.float64)
-    tot_near = torch.einsum("ecq,eq->c", Sn, V)
+    tot_near = (Sn * V[:, None, :]).sum(dim=(0, 2))
     cons = float(((tot_shape - tot_near).abs().max() / tot_near.abs().max()).item())
     out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
            "value": summary(r, K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,

@@ -24,10 +24,10 @@ namespace fp {
 
 namespace {
 
-constexpr int kDepThreads = 256;
-constexpr int kDepWaves = kDepThreads / 64;
-constexpr int kDepCand = 256;   // candidate elements per LDS window
-constexpr int kDepChunk = 16;   // particles per normalisation pass
+constexpr int kNormThreads = 128;    // k_dep_norm: two wavefronts per source element
+constexpr int kGatherThreads = 128;  // k_dep_gather: each thread holds several target nodes
+constexpr int kDepCand = 256;        // candidate elements per LDS window
+constexpr int kNormChunk = 32;       // particles per normalisation pass
 constexpr int kXcd = 8;
 
 struct DepGeo {
@@ -36,10 +36,11 @@ struct DepGeo {
   double period[3];
 };
 
+template <int TH>
 struct CandLds {
   int32_t e[kDepCand];
   int8_t img[kDepCand];        // ((iz+1)*3 + (iy+1))*3 + (ix+1)
-  int32_t wsum[kDepWaves];
+  int32_t wsum[TH / 64];
 };
 
 __device__ __forceinline__ int xcd_element(int b, int E) {
@@ -68,7 +69,8 @@ __device__ __forceinline__ int lane_rank(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// exclusive prefix sum over the workgroup; every thread must call it
+// exclusive prefix sum over the workgroup of TH threads; every thread must call it
+template <int TH>
 __device__ inline int block_excl_scan(int v, int32_t* wsum, int& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int x = v;
@@ -81,7 +83,7 @@ __device__ inline int block_excl_scan(int v, int32_t* wsum, int& total) {
   __syncthreads();
   int base = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < kDepWaves; ++k) {
+  for (int k = 0; k < TH / 64; ++k) {
     int t = wsum[k];
     base += (k < w) ? t : 0;
     tot += t;
@@ -96,9 +98,9 @@ __device__ inline int block_excl_scan(int v, int32_t* wsum, int& total) {
 // first background cell of the overlap) to body(count), in windows of at most
 // kDepCand entries held in L.e / L.img.  Order is deterministic.  All threads
 // of the workgroup must call it with the same arguments.
-template <class Body>
+template <int TH, class Body>
 __device__ __forceinline__ void stream_candidates(const MeshView& m, const double* period, const double* lo,
-                                                  const double* hi, double pad, CandLds& L, Body&& body) {
+                                                  const double* hi, double pad, CandLds<TH>& L, Body&& body) {
   for (int code = 0; code < 27; ++code) {
     const int im[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
     bool skip = false;
@@ -116,7 +118,7 @@ __device__ __forceinline__ void stream_candidates(const MeshView& m, const doubl
     if (skip) continue;
     const int nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1, nz = c1[2] - c0[2] + 1;
     const int ncell = nx * ny * nz;
-    for (int cb = 0; cb < ncell; cb += kDepThreads) {
+    for (int cb = 0; cb < ncell; cb += TH) {
       const int ci = cb + threadIdx.x;
       int own[3] = {0, 0, 0}, beg = 0, end = 0;
       if (ci < ncell) {
@@ -141,7 +143,7 @@ __device__ __forceinline__ void stream_candidates(const MeshView& m, const doubl
       int cnt = 0;
       for (int q = beg; q < end; ++q) cnt += accept(m.blist[q]) ? 1 : 0;
       int tot = 0;
-      const int off = block_excl_scan(cnt, L.wsum, tot);
+      const int off = block_excl_scan<TH>(cnt, L.wsum, tot);
       for (int w0 = 0; w0 < tot; w0 += kDepCand) {
         if (cnt > 0 && off < w0 + kDepCand && off + cnt > w0) {
           int r = off;
@@ -198,11 +200,15 @@ __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Flui
 
 // 2. normalisation per source element ---------------------------------------
 // Each lane keeps its partial sums in its own LDS column (s_acc[wave][i][lane]),
-// so the particle loop stays dynamic and no per-pair reduction is needed.
+// so the particle loop stays dynamic and no per-pair reduction is needed; the
+// two wavefronts split the candidate target elements, and the next target's
+// nodes are loaded while the current one is evaluated.
 template <int NN>
-__global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles P, const int32_t* __restrict__ elem_start,
-                                                          DepGeo g, double* F, const int32_t* __restrict__ ok,
-                                                          unsigned long long* povh) {
+__global__ __launch_bounds__(kNormThreads) void k_dep_norm(MeshView m, Particles P,
+                                                           const int32_t* __restrict__ elem_start, DepGeo g,
+                                                           double* F, const int32_t* __restrict__ ok,
+                                                           unsigned long long* povh) {
+  constexpr int TH = kNormThreads, NW = TH / 64, CH = kNormChunk;
   const int es = xcd_element(blockIdx.x, m.E);
   if (es >= m.E) return;
   const int p0 = elem_start[es], p1 = elem_start[es + 1];
@@ -211,14 +217,14 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles 
   constexpr int NPL = (N3 + 63) / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t cap = P.cap;
-  __shared__ CandLds L;
-  __shared__ double s_x[kDepChunk][3];
-  __shared__ double s_acc[kDepWaves][kDepChunk][64];
+  __shared__ CandLds<TH> L;
+  __shared__ double s_x[CH][3];
+  __shared__ double s_acc[NW][CH][64];
   __shared__ double s_q[6];
   __shared__ int s_any;
-  for (int c0 = p0; c0 < p1; c0 += kDepChunk) {
-    const int cnt = min(kDepChunk, p1 - c0);
-    if (threadIdx.x < kDepChunk) {
+  for (int c0 = p0; c0 < p1; c0 += CH) {
+    const int cnt = min(CH, p1 - c0);
+    if (threadIdx.x < CH) {
       const int i = threadIdx.x;
       double x[3] = {1e300, 1e300, 1e300};
       if (i < cnt && ok[c0 + i]) {
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles 
       }
       for (int k = 0; k < 3; ++k) s_x[i][k] = x[k];
     }
-    for (int i = 0; i < kDepChunk; ++i) s_acc[wave][i][lane] = 0.0;
+    for (int i = 0; i < CH; ++i) s_acc[wave][i][lane] = 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
       double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -247,30 +253,38 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles 
     __syncthreads();
     if (!s_any) continue;   // uniform
     double qlo[3] = {s_q[0], s_q[1], s_q[2]}, qhi[3] = {s_q[3], s_q[4], s_q[5]};
-    stream_candidates(m, g.period, qlo, qhi, g.R + g.node_pad, L, [&](int nc) {
-      for (int t = wave; t < nc; t += kDepWaves) {
+    stream_candidates<TH>(m, g.period, qlo, qhi, g.R + g.node_pad, L, [&](int nc) {
+      double xn[NPL][3], vn[NPL], xn2[NPL][3], vn2[NPL];
+      // nodes of candidate T for this lane, shifted into the particles' image
+#define FP_LOAD_NODES(T, XN, VN)                                                                  \
+  {                                                                                               \
+    const int e_ = L.e[T];                                                                        \
+    double sh_[3];                                                                                \
+    image_shift(L.img[T], g.period, sh_);                                                         \
+    _Pragma("unroll") for (int j = 0; j < NPL; ++j) {                                             \
+      const int q = lane + 64 * j;                                                                \
+      if (q < N3) {                                                                               \
+        const double* src = m.xnode + ((size_t)e_ * N3 + q) * 3;                                  \
+        XN[j][0] = src[0] - sh_[0]; XN[j][1] = src[1] - sh_[1]; XN[j][2] = src[2] - sh_[2];       \
+        VN[j] = m.vol[(size_t)e_ * N3 + q];                                                       \
+      } else {                                                                                    \
+        XN[j][0] = XN[j][1] = XN[j][2] = 1e300;                                                   \
+        VN[j] = 0.0;                                                                              \
+      }                                                                                           \
+    }                                                                                             \
+  }
+      if (wave < nc) FP_LOAD_NODES(wave, xn, vn)
+      for (int t = wave; t < nc; t += NW) {
+        if (t + NW < nc) FP_LOAD_NODES(t + NW, xn2, vn2)
         const int e = L.e[t];
         double sh[3];
         image_shift(L.img[t], g.period, sh);
         const double* nb = m.nbox + (size_t)e * 6;
         const double blo[3] = {nb[0] - sh[0], nb[1] - sh[1], nb[2] - sh[2]};
         const double bhi[3] = {nb[3] - sh[0], nb[4] - sh[1], nb[5] - sh[2]};
-        double xn[NPL][3], vn[NPL];
-#pragma unroll
-        for (int j = 0; j < NPL; ++j) {
-          const int q = lane + 64 * j;
-          if (q < N3) {
-            const double* src = m.xnode + ((size_t)e * N3 + q) * 3;
-            xn[j][0] = src[0] - sh[0]; xn[j][1] = src[1] - sh[1]; xn[j][2] = src[2] - sh[2];
-            vn[j] = m.vol[(size_t)e * N3 + q];
-          } else {
-            xn[j][0] = xn[j][1] = xn[j][2] = 1e300;
-            vn[j] = 0.0;
-          }
-        }
         for (int i = 0; i < cnt; ++i) {
           const double px[3] = {s_x[i][0], s_x[i][1], s_x[i][2]};
-          if (!(box_dist2(px, blo, bhi) < g.R2)) continue;
+          if (!(box_dist2(px, blo, bhi) < g.R2)) continue;   // wave-uniform
           double a = 0.0;
 #pragma unroll
           for (int j = 0; j < NPL; ++j) {
@@ -281,14 +295,20 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles 
           }
           s_acc[wave][i][lane] += a;
         }
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          xn[j][0] = xn2[j][0]; xn[j][1] = xn2[j][1]; xn[j][2] = xn2[j][2];
+          vn[j] = vn2[j];
+        }
       }
+#undef FP_LOAD_NODES
     });
-    // sum over waves and lanes: 16 threads per particle, fixed order
+    // sum over waves and lanes: TH / CH threads per particle, fixed order
     {
-      constexpr int TPP = kDepThreads / kDepChunk;   // threads per particle
+      constexpr int TPP = TH / CH;
       const int i = threadIdx.x / TPP, sub = threadIdx.x % TPP;
       double v = 0.0;
-      for (int w = 0; w < kDepWaves; ++w)
+      for (int w = 0; w < NW; ++w)
         for (int l = sub; l < 64; l += TPP) v += s_acc[w][i][l];
 #pragma unroll
       for (int off = TPP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -305,26 +325,29 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_norm(MeshView m, Particles 
 }
 
 // 3. gather per target element ----------------------------------------------
+// Each thread holds PER target nodes, so every staged particle read from LDS
+// serves PER kernel evaluations.
 template <int NN, typename ST>
-__global__ __launch_bounds__(kDepThreads) void k_dep_gather(MeshView m, Particles P,
-                                                            const int32_t* __restrict__ elem_start, DepGeo g,
-                                                            const double* __restrict__ G,
-                                                            const unsigned long long* __restrict__ povh, ST* S) {
+__global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Particles P,
+                                                               const int32_t* __restrict__ elem_start, DepGeo g,
+                                                               const double* __restrict__ G,
+                                                               const unsigned long long* __restrict__ povh, ST* S) {
+  constexpr int TH = kGatherThreads, NW = TH / 64;
   const int t = xcd_element(blockIdx.x, m.E);
   if (t >= m.E) return;
   constexpr int N3 = NN * NN * NN;
-  constexpr int PER = (N3 + kDepThreads - 1) / kDepThreads;
+  constexpr int PER = (N3 + TH - 1) / TH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t cap = P.cap;
-  __shared__ CandLds L;
+  __shared__ CandLds<TH> L;
   __shared__ int32_t s_pre[kDepCand + 1];
-  __shared__ double s_px[kDepThreads][3];
-  __shared__ double s_pg[kDepThreads][4];
-  __shared__ int32_t s_wcnt[kDepWaves];
+  __shared__ double s_px[TH][3];
+  __shared__ double s_pg[TH][4];
+  __shared__ int32_t s_wcnt[NW];
   double xn[PER][3], acc[PER][4];
 #pragma unroll
   for (int s = 0; s < PER; ++s) {
-    const int q = threadIdx.x + s * kDepThreads;
+    const int q = threadIdx.x + s * TH;
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[s][k] = 0.0;
 #pragma unroll
@@ -333,13 +356,19 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_gather(MeshView m, Particle
   const double* nb = m.nbox + (size_t)t * 6;
   const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
   const double part_pad = __longlong_as_double((long long)*povh);
-  stream_candidates(m, g.period, blo, bhi, g.R + part_pad, L, [&](int nc) {
-    const int cntc = (threadIdx.x < nc) ? elem_start[L.e[threadIdx.x] + 1] - elem_start[L.e[threadIdx.x]] : 0;
+  stream_candidates<TH>(m, g.period, blo, bhi, g.R + part_pad, L, [&](int nc) {
+    // prefix over the candidates' particle counts (windows hold <= kDepCand)
     int T = 0;
-    const int off = block_excl_scan(cntc, L.wsum, T);
-    if (threadIdx.x < nc) s_pre[threadIdx.x] = off;
+    for (int cb = 0; cb < nc; cb += TH) {
+      const int c = cb + threadIdx.x;
+      const int cntc = (c < nc) ? elem_start[L.e[c] + 1] - elem_start[L.e[c]] : 0;
+      int tot = 0;
+      const int off = block_excl_scan<TH>(cntc, L.wsum, tot);
+      if (c < nc) s_pre[c] = T + off;
+      T += tot;
+    }
     __syncthreads();
-    for (int jb = 0; jb < T; jb += kDepThreads) {
+    for (int jb = 0; jb < T; jb += TH) {
       const int j = jb + threadIdx.x;
       bool keep = false;
       double px[3] = {0, 0, 0}, pg[4] = {0, 0, 0, 0};
@@ -366,7 +395,7 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_gather(MeshView m, Particle
       __syncthreads();
       int base = 0, nk = 0;
 #pragma unroll
-      for (int w = 0; w < kDepWaves; ++w) {
+      for (int w = 0; w < NW; ++w) {
         base += (w < wave) ? s_wcnt[w] : 0;
         nk += s_wcnt[w];
       }
@@ -378,6 +407,7 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_gather(MeshView m, Particle
         for (int k = 0; k < 4; ++k) s_pg[slot][k] = pg[k];
       }
       __syncthreads();
+#pragma unroll 4
       for (int k = 0; k < nk; ++k) {
         const double x0 = s_px[k][0], x1 = s_px[k][1], x2 = s_px[k][2];
         const double g0 = s_pg[k][0], g1 = s_pg[k][1], g2 = s_pg[k][2], g3 = s_pg[k][3];
@@ -398,7 +428,7 @@ __global__ __launch_bounds__(kDepThreads) void k_dep_gather(MeshView m, Particle
   });
 #pragma unroll
   for (int s = 0; s < PER; ++s) {
-    const int q = threadIdx.x + s * kDepThreads;
+    const int q = threadIdx.x + s * TH;
     if (q < N3)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -429,9 +459,9 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
   if (m.n == A && m.ng == B) {                                                                               \
     if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, drag, F, ok, povh);                 \
     else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, drag, F, ok, povh);                       \
-    k_dep_norm<A><<<ge, kDepThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                              \
-    if (s_f32) k_dep_gather<A, float><<<ge, kDepThreads, 0, s>>>(m, P, elem_start, g, F, povh, (float*)S);   \
-    else k_dep_gather<A, double><<<ge, kDepThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);      \
+    k_dep_norm<A><<<ge, kNormThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                             \
+    if (s_f32) k_dep_gather<A, float><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (float*)S); \
+    else k_dep_gather<A, double><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);    \
     return hipGetLastError();                                                                                \
   }
   FP_FOR_EACH_SHAPE(FP_L)
