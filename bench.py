@@ -56,10 +56,14 @@ def read_traffic():
     return vals["bytes"]
 
 
+# variables the drag law reads (density, momentum); the energy is not needed
+INTERP_VARS = 4
+
+
 def flops_per_particle_stage(n, ng, newton_it):
     """Algorithmic flops of one particle-stage (measurement)."""
     f_newton = 6 * (2 * ng ** 3 + 3 * ng ** 2 + 4 * ng) + 160
-    f_interp = 10 * (n ** 3 + n ** 2 + n) + 9 * n ** 2
+    f_interp = 2 * INTERP_VARS * (n ** 3 + n ** 2 + n) + 9 * n ** 2
     f_guess = 8 * ng ** 3
     f_rest = 300
     return newton_it * f_newton + f_interp + f_guess + f_rest
@@ -68,9 +72,10 @@ def flops_per_particle_stage(n, ng, newton_it):
 def bytes_per_particle_stage(n, ng, ppe):
     """Algorithmic HBM bytes of one particle-stage, FP64 state: particle SoA read
     (x, v, kx, kv, d, elem, status) and write (x, v, kx, kv, elem), plus the
-    element's fluid state, geometry and face records amortised over its particles."""
+    element's fluid state (the variables read), geometry and face records amortised
+    over its particles."""
     soa = (12 * 8 + 8 + 4 + 1) + (12 * 8 + 4)
-    elem = 5 * n ** 3 * 8 + 3 * ng ** 3 * 8 + 336
+    elem = INTERP_VARS * n ** 3 * 8 + 3 * ng ** 3 * 8 + 336
     return soa + elem / ppe
 
 

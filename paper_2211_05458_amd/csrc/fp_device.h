@@ -444,21 +444,25 @@ __device__ inline int bgm_locate(const MeshView& m, const double* x, double* xi,
 }
 
 // ---------------------------------------------------------------------------
-// interpolation of the five conservative variables (eq. part_interpolation)
+// interpolation of the conservative variables (eq. part_interpolation).  The
+// drag law reads density and momentum only (constant viscosity), so the
+// energy, the fifth variable of each element's block, is not interpolated.
 // ---------------------------------------------------------------------------
+constexpr int kInterpVars = 4;
+
 template <int NN, typename UT>
 __device__ __forceinline__ void interp(const MeshView& m, const UT* __restrict__ U, const double* xi, double* out) {
   double l1[NN], l2[NN];
   lagrange<NN, double>(m.xdg, m.cdg, xi[0], l1);
   lagrange<NN, double>(m.xdg, m.cdg, xi[1], l2);
   constexpr int N3 = NN * NN * NN;
-  double acc[5] = {0, 0, 0, 0, 0};
-  // one xi3-slab per iteration: the NN*NN nodes of every variable
+  double acc[kInterpVars] = {};
+  // one xi3-slab per iteration: the NN*NN nodes of every variable read
 #pragma unroll 1
   for (int k = 0; k < NN; ++k) {
     double l3 = lagrange1<NN, double>(m.xdg, m.cdg, xi[2], k);
 #pragma unroll
-    for (int var = 0; var < 5; ++var) {
+    for (int var = 0; var < kInterpVars; ++var) {
       const UT* Uk = U + var * N3 + k * NN * NN;
       double sk = 0.0;
 #pragma unroll
@@ -472,7 +476,7 @@ __device__ __forceinline__ void interp(const MeshView& m, const UT* __restrict__
     }
   }
 #pragma unroll
-  for (int var = 0; var < 5; ++var) out[var] = acc[var];
+  for (int var = 0; var < kInterpVars; ++var) out[var] = acc[var];
 }
 
 // FP32 interpolation (mixed precision): FP32 basis and accumulation.
@@ -482,12 +486,12 @@ __device__ __forceinline__ void interp_f32(const MeshView& m, const UT* __restri
   lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[0], l1);
   lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[1], l2);
   constexpr int N3 = NN * NN * NN;
-  float acc[5] = {0, 0, 0, 0, 0};
+  float acc[kInterpVars] = {};
 #pragma unroll 1
   for (int k = 0; k < NN; ++k) {
     float l3 = lagrange1<NN, float>(m.xdgf, m.cdgf, (float)xi[2], k);
 #pragma unroll
-    for (int var = 0; var < 5; ++var) {
+    for (int var = 0; var < kInterpVars; ++var) {
       const UT* Uk = U + var * N3 + k * NN * NN;
       float sk = 0.0f;
 #pragma unroll
@@ -501,7 +505,7 @@ __device__ __forceinline__ void interp_f32(const MeshView& m, const UT* __restri
     }
   }
 #pragma unroll
-  for (int var = 0; var < 5; ++var) out[var] = acc[var];
+  for (int var = 0; var < kInterpVars; ++var) out[var] = acc[var];
 }
 
 // drag acceleration f_D (u - v)/tau_p (Sec. 2.2.1); fD returned for the source

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_deposit_nearest(MeshView m, Particles P
   double xi[3];
   int it = 0, calls = 0, fb = 0;
   if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb)) return;
-  double Uc[5];
+  double Uc[kInterpVars];
   interp<NN, UT>(m, (const UT*)fl.U + (size_t)e * 5 * N3, xi, Uc);
   double ir = 1.0 / Uc[0];
   double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};

@@ -25,7 +25,7 @@ __device__ __forceinline__ void stage_update(const MeshView& m, const UT* __rest
                                              const double* x, double* v, double* kx, double* kv, double d,
                                              const Fluid& fl, const StepParams& sp, double* xe) {
   if (!MIXED) {
-    double Uc[5];
+    double Uc[kInterpVars];
     interp<NN, UT>(m, Ue, xi, Uc);
     double rho = Uc[0], ir = 1.0 / rho;
     double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
@@ -40,7 +40,7 @@ __device__ __forceinline__ void stage_update(const MeshView& m, const UT* __rest
       v[k] = v[k] + sp.B * kv[k];
     }
   } else {
-    float Uc[5];
+    float Uc[kInterpVars];
     interp_f32<NN, UT>(m, Ue, xi, Uc);
     float ir = 1.0f / Uc[0];
     float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
@@ -70,8 +70,11 @@ struct Queues {
   double* trk_x;      // [3][cap] segment start
 };
 
+// Four wavefronts per SIMD (at most 128 VGPRs): the Newton and interpolation
+// loops wait on LDS reads, and the fourth wavefront hides more of that latency
+// than the few spilled registers cost.
 template <int NN, int NG, typename UT, bool MIXED, bool MLP>
-__global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_stage_elem(MeshView m, const double* __restrict__ X,
                                                     const double* __restrict__ XN, const UT* __restrict__ U,
                                                     const FaceRec* __restrict__ faces, const Task* __restrict__ tasks,
                                                     const int32_t* __restrict__ ntask, Particles P, Fluid fl,
@@ -80,10 +83,10 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
   // the task element's geometry nodes and fluid state, staged once per
   // wavefront with coalesced vector loads and read as LDS broadcasts by every
   // Newton iteration and the interpolation; U stays in global memory when both
-  // would not fit three wavefronts per SIMD
-  constexpr bool kStageU = NG3 * 3 * 8 + 5 * NN3 * (int)sizeof(UT) <= 12 * 1024;
+  // would not fit three to four wavefronts per SIMD
+  constexpr bool kStageU = NG3 * 3 * 8 + kInterpVars * NN3 * (int)sizeof(UT) <= 12 * 1024;
   __shared__ double sX[4][NG3 * 3];
-  __shared__ UT sU[4][kStageU ? 5 * NN3 : 1];
+  __shared__ UT sU[4][kStageU ? kInterpVars * NN3 : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nt = __builtin_amdgcn_readfirstlane(*ntask);
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(256) void k_stage_elem(MeshView m, const double* __
     for (int i = lane; i < NG3 * 3; i += 64) sX[w][i] = Xg[i];
     if (kStageU) {
       const UT* Ug = U + (size_t)e * 5 * NN3;
-      for (int i = lane; i < 5 * NN3; i += 64) sU[w][i] = Ug[i];
+      for (int i = lane; i < kInterpVars * NN3; i += 64) sU[w][i] = Ug[i];
     }
   }
   __syncthreads();
