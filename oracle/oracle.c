@@ -1237,6 +1237,7 @@ or_ctx* or_create(int n_elem, int n_geo, const double* X, const int32_t* nbr_ele
   /* DG node positions and volumes V_ijk = w_i w_j w_k J(xi_ijk) */
   c->xnode = (double*)malloc(sizeof(double) * (size_t)E * n * n * n * 3);
   c->vol = (double*)malloc(sizeof(double) * (size_t)E * n * n * n);
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < E; ++e)
     for (int k = 0; k < n; ++k)
       for (int j = 0; j < n; ++j)
@@ -1518,9 +1519,17 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
         double* kv = c->kv + p * 3;
         double xi[3];
         if (!newton_chain(c, e, x, xi, o->max_newton_it, o->use_mlp, &it_sum, &calls, &nfb)) {
-          c->status[p] = OR_LOST_NEWTON; nlost++; continue;
-        }
-        if (!inside_ref(xi)) {
+          /* Newton diverges in the recorded element: the point left it along
+           * a segment that was not traced (reference-space localisation), and
+           * the map continued beyond a strongly curved element need not be
+           * invertible there.  The paper's localisation: the background-mesh
+           * candidates of the point. */
+          int f = or_locate(c, x, -1, xi);
+          if (f < 0) { c->status[p] = OR_LOST_NEWTON; nlost++; continue; }
+          e = f;
+          c->elem[p] = e;
+          nrec++;
+        } else if (!inside_ref(xi)) {
           if (!recover_elem(c, &e, x, xi, o->max_newton_it, &it_sum, &calls, &nfb)) {
             c->status[p] = OR_LOST_TRACK; nlost++; continue;
           }
@@ -1558,9 +1567,12 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
     int64_t a0 = 0, a1 = 0, a2 = 0;
     int e = c->elem[p];
     if (!newton_chain(c, e, c->x + p * 3, xi, o->max_newton_it, 0, &a0, &a1, &a2)) {
-      c->status[p] = OR_LOST_NEWTON; nlost++; continue;
-    }
-    if (!inside_ref(xi)) {
+      /* as in the stage loop: the background-mesh candidates */
+      int f = or_locate(c, c->x + p * 3, -1, xi);
+      if (f < 0) { c->status[p] = OR_LOST_NEWTON; nlost++; continue; }
+      c->elem[p] = f;
+      nrec++;
+    } else if (!inside_ref(xi)) {
       if (recover_elem(c, &e, c->x + p * 3, xi, o->max_newton_it, &a0, &a1, &a2)) {
         c->elem[p] = e;
         nrec++;

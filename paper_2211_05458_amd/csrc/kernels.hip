@@ -145,7 +145,15 @@ __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64
     int it = 0, calls = 0, fb = 0, e = P.elem[p];
     bool ok = locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb);
     bool inside = ok && inside_ref(xi);
-    if (ok && !inside && recover_elem<NN, NG>(m, e, x, xi, 50, it, calls, fb)) {
+    if (!ok) {
+      // as in the stage: the background-mesh candidates of the point
+      const int f = bgm_locate<NN, NG>(m, x, xi, it, calls, fb);
+      if (f >= 0) {
+        ok = inside = true;
+        nrec++;
+        P.elem[p] = f;
+      }
+    } else if (!inside && recover_elem<NN, NG>(m, e, x, xi, 50, it, calls, fb)) {
       inside = true;
       nrec++;
       P.elem[p] = e;

@@ -8,7 +8,8 @@
 //                update, and the bounding-box test of the element's faces
 //                (Sec. 3.2.4).  Particles whose segment touches a face box go
 //                to the tracking queue; particles that left the task element
-//                in an earlier stage go to the straggler queue.
+//                in an earlier stage, or that Newton does not locate inside
+//                it, go to the straggler queue.
 //  k_stage_lane  the same stage for the straggler queue (or for all particles
 //                when no sort has been done), with per-lane element data.
 //  k_track       physical-space tracking (Sec. 3.2.3/3.2.4) of the queued
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   const int nt = __builtin_amdgcn_readfirstlane(*ntask);
-  int it_sum = 0, calls = 0, fb = 0, nlost = 0;
+  int it_sum = 0, calls = 0, fb = 0;
   bool strag = false, trk = false;
   int64_t p = 0;
   double xs0 = 0, xs1 = 0, xs2 = 0;
@@ -123,11 +124,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const UT* Ue = kStageU ? sU[w] : U + (size_t)e * 5 * NN3;
       double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
       double xi[3];
-      if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb)) {
-        P.status[p] = LOST_NEWTON;
-        nlost++;
-      } else if (!inside_ref(xi)) {
-        strag = true;   // outside its element: the per-lane kernel recovers it
+      if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb) || !inside_ref(xi)) {
+        strag = true;   // not located in its element: the per-lane kernel recovers it
       } else {
         double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
         double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
@@ -174,7 +172,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   wave_add(stats + ST_NEWTON_IT * kStatSlots, it_sum);
   wave_add(stats + ST_NEWTON_CALLS * kStatSlots, calls);
   wave_add(stats + ST_FALLBACK * kStatSlots, fb);
-  wave_add(stats + ST_LOST * kStatSlots, nlost);
 }
 
 // per-lane stage for the straggler queue (list != null) or all n particles;
@@ -202,7 +199,20 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
         bool ok = locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi,
                                            sp.max_it, it_sum, calls, fb);
         bool inside = ok && inside_ref(xi);
-        if (ok && !inside) {
+        if (!ok) {
+          // Newton diverges in the recorded element: the point left it along a
+          // segment that was not traced (reference-space localisation), and the
+          // map continued beyond a strongly curved element need not be
+          // invertible there; the paper's localisation takes the
+          // background-mesh candidates of the point
+          const int f = bgm_locate<NN, NG>(m, x, xi, it_sum, calls, fb);
+          if (f >= 0) {
+            ok = inside = true;
+            e = f;
+            nrec++;
+            P.elem[p] = e;
+          }
+        } else if (!inside) {
           inside = recover_elem<NN, NG>(m, e, x, xi, sp.max_it, it_sum, calls, fb);
           if (inside) {
             nrec++;

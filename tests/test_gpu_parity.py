@@ -290,3 +290,39 @@ def test_reference_space_localisation_parity():
         np.testing.assert_array_equal(r1[k], r0[k])
     assert np.abs(r1["x"] - r0["x"]).max() <= 1e-12
     assert s1["recovered"] > 1000 and s1["crossings"] < 0.8 * s0["crossings"] and s1["lost"] == 0
+
+
+def test_reference_space_localisation_parity_annulus():
+    """Strongly curved annular passage (N_geo = 6): tracking mode 1 against the
+    oracle in the same mode, with the particle whose untraced path ends where
+    Newton on its previous element diverges (background-mesh localisation)
+    among 4000 others; and the same result as physical tracking on the GPU."""
+    import json
+    import os
+    w = W.config4(n_particles=4000)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "annulus_localisation_case.json")) as f:
+        c = json.load(f)
+    x = np.concatenate([w.x, [c["x"]]])
+    v = np.concatenate([w.v, [c["v"]]])
+    d = np.concatenate([w.d, [c["d"]]])
+    h = np.concatenate([w.elem_hint, [c["elem_hint"]]]).astype(np.int32)
+    o = O.Oracle(w.mesh, w.N, w.U)
+    o.push(x, v, d, h)
+    o.step(w.dt, 3, rk=w.rk, drag=w.drag, tracking=1)
+    ro = o.read()
+    so = o.stats()
+    FlexiPart = _gpu()
+    res = []
+    for tracking in (1, 0):
+        g = FlexiPart(w.mesh, w.N, len(x))
+        g.set_fluid_state(w.U)
+        g.push(x, v, d, h)
+        g.step(w.dt, 3, rk=w.rk, drag=w.drag, tracking=tracking)
+        res.append((g.read(), g.stats()))
+    (r1, s1), (r0, s0) = res
+    assert_parity(ro, r1, vscale=5.0)
+    for k in ("status", "elem", "hits"):
+        np.testing.assert_array_equal(r1[k], r0[k])
+    assert np.abs(r1["x"] - r0["x"]).max() <= 1e-12
+    assert so["lost"] == 0 and s1["lost"] == 0 and s1["recovered"] > 0 and s1["fallbacks"] > 0
+

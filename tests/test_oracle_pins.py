@@ -765,6 +765,47 @@ def test_reference_space_localisation_equals_physical_tracking():
     assert sa["wall_hits"] > 100 and sb["crossings"] < 0.8 * sa["crossings"] and sb["recovered"] > 1000
 
 
+def _annulus_localisation_case():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "annulus_localisation_case.json")
+    with open(path) as f:
+        c = json.load(f)
+    return (np.array([c["x"]]), np.array([c["v"]]), np.array([c["d"]]),
+            np.array([c["elem_hint"]], np.int32))
+
+
+def test_reference_space_localises_where_newton_diverges():
+    """Strongly curved annular passage (N_geo = 6), one particle of its seeded
+    workload (fixture written by tests/golden/make_annulus_localisation_case.py):
+    its step crosses two internal faces without coming near a wall, so under
+    reference-space localisation no segment is traced.  Newton on the map of
+    the element it started in diverges at the end point (from every guess),
+    so the location step must fall back to the background-mesh candidates
+    (Sec. 3.2.3); the result equals physical tracking bit for bit."""
+    w = W.config4(n_particles=1)
+    x, v, d, h = _annulus_localisation_case()
+    o = O.Oracle(w.mesh, w.N, w.U)
+    out = []
+    for tracking in (0, 1):
+        o.reset_stats()
+        st, _ = o.push(x, v, d, h)
+        assert st[0] == O.ACTIVE
+        o.step(w.dt, 1, rk=w.rk, drag=w.drag, tracking=tracking)
+        out.append((o.read(), o.stats()))
+    (a, sa), (b, sb) = out
+    for k in ("status", "elem", "hits", "x", "v"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert a["status"][0] == O.ACTIVE and a["elem"][0] != h[0] and sa["crossings"] >= 2
+    assert sb["crossings"] == 0 and sb["recovered"] >= 1 and sb["lost"] == 0
+    # the premise: the start element's map cannot be inverted at the end point
+    xe = a["x"][0]
+    assert not o.newton(int(h[0]), xe, o.guess(int(h[0]), xe))[0]
+    assert not o.newton(int(h[0]), xe, o.guess_faces(int(h[0]), xe))[0]
+    conv, xi, _ = o.newton(int(a["elem"][0]), xe, o.guess(int(a["elem"][0]), xe))
+    assert conv and np.abs(xi).max() <= 1.0
+
+
 def test_boundary_distance_is_a_lower_bound():
     """Brute force: points of each element against dense samples of every wall
     and periodic face; no point is closer to such a face than the element's
