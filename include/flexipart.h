@@ -89,8 +89,23 @@ typedef struct {
                             1: reference-space localisation: a segment that cannot reach a
                             face that is not internal (wall, open, periodic) is not traced,
                             the next location step finds its element */
-  double gravity[3];     /* added body acceleration */
+  int32_t forces;        /* extra terms of the equation of motion (eq. theory:maxey), FP_F_* bits;
+                            0: drag and gravity only (see below) */
+  double gravity[3];     /* body acceleration g */
 } fp_step_opts;
+
+/* Extra terms of the particle equation of motion (Sec. 2.2, eq. theory:maxey)
+ *   m_p dv/dt = F_D + m_f Du/Dt + m_f/2 (Du/Dt - dv/dt) + F_L + g (m_p - m_f)
+ * with m_p = rho_p pi d^3/6 and m_f = rho pi d^3/6 (rho the interpolated fluid
+ * density).  FP_F_BUOYANCY: body force g (m_p - m_f) instead of g m_p.
+ * FP_F_STRESS: undisturbed-flow stress m_f Du/Dt.  FP_F_ADDED_MASS: the added
+ * mass, solved implicitly ((m_p + m_f/2) dv/dt on the left).  FP_F_SAFFMAN:
+ * Saffman lift with Mei's correction (Sec. 2.2.2), directed along (u - v) x w
+ * (w the vorticity).  The fluid state is frozen over a step, so
+ * Du/Dt = (u . grad) u from the interpolant's gradient.  Basset history and
+ * Magnus lift are not provided.  With any of these bits set every particle
+ * runs through the per-lane stage kernel. */
+enum { FP_F_BUOYANCY = 1, FP_F_STRESS = 2, FP_F_ADDED_MASS = 4, FP_F_SAFFMAN = 8 };
 
 /* Create a context bound to a HIP stream (hipStream_t, may be NULL for the
  * null stream) on the current device. */
@@ -138,9 +153,13 @@ int fp_step(fp_ctx* ctx, double dt, int32_t n_steps, const fp_step_opts* opts);
  * the minimum-image distance (0: not periodic).  Each positive period must
  * exceed 2 * radius (FP_EINVAL otherwise), so that at most one image of a node
  * lies within reach of a particle.  Particles with no node within reach deposit
- * nothing.  Sorts the particles by element.  Asynchronous. */
+ * nothing.  F is the fluid force of the equation of motion (eq. theory:source):
+ * the drag law `drag` (as in fp_step_opts) plus the terms of `forces` (FP_F_*;
+ * the added mass needs dv/dt, hence gravity[3], host, may be NULL for zero);
+ * gravity and buoyancy themselves are not part of it.  Sorts the particles by
+ * element.  Asynchronous. */
 int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, double radius,
-                      const double* period, int32_t drag);
+                      const double* period, int32_t drag, int32_t forces, const double* gravity);
 
 /* Copy the quadrature volumes V_ijk = w_i w_j w_k J(xi_ijk) of all DG nodes
  * (device output V[n_elem][(n_dg+1)^3], f64) -- the measure in which the

@@ -88,7 +88,9 @@ def _declare(L):
     L.or_stats.argtypes = [P, P]
     L.or_reset_stats.argtypes = [P]
     L.or_deposit.restype = I
-    L.or_deposit.argtypes = [P, P, I, D, P, I]
+    L.or_deposit.argtypes = [P, P, I, D, P, I, I, P]
+    L.or_fluid_grad.argtypes = [P, I, P, P, P]
+    L.or_particle_accel.argtypes = [P, I, I, P, P, P, D, P, P, P]
     L.or_mlp_n_weights.restype = I64
     L.or_mlp_features.argtypes = [P, I, P, P]
     L.or_mlp_forward.argtypes = [P, I64, P, P]
@@ -104,7 +106,11 @@ def _declare(L):
 class StepOpts(C.Structure):
     _fields_ = [("rk", C.c_int32), ("drag", C.c_int32), ("max_newton_it", C.c_int32),
                 ("max_crossings", C.c_int32), ("use_mlp", C.c_int32), ("tracking", C.c_int32),
-                ("gravity", C.c_double * 3), ("drag_mask", C.c_double * 3)]
+                ("gravity", C.c_double * 3), ("drag_mask", C.c_double * 3), ("forces", C.c_int32)]
+
+
+# extra terms of the equation of motion (bit flags of StepOpts.forces)
+F_BUOYANCY, F_STRESS, F_ADDED_MASS, F_SAFFMAN = 1, 2, 4, 8
 
 
 def _p(a):
@@ -257,6 +263,19 @@ class Oracle:
                             _p(_f64(g)) if g is not None else None, _p(a), _p(fD))
         return a, fD[0]
 
+    def fluid_grad(self, e, xi):
+        """Primitive state (5) and velocity gradient G[i][j] = du_i/dx_j at xi."""
+        prim = np.zeros(5); G = np.zeros(9)
+        lib().or_fluid_grad(self.ctx, int(e), _p(_f64(xi)), _p(prim), _p(G))
+        return prim, G.reshape(3, 3)
+
+    def particle_accel(self, drag, forces, prim, G, v, d, g=None):
+        """dv/dt and the fluid force of the two-way source (equation of motion)."""
+        a = np.zeros(3); F = np.zeros(3)
+        lib().or_particle_accel(self.ctx, int(drag), int(forces), _p(_f64(prim)), _p(_f64(G).ravel()),
+                                _p(_f64(v)), float(d), _p(_f64(g)) if g is not None else None, _p(a), _p(F))
+        return a, F
+
     def face(self, e, f):
         ng = self.n_geo + 1
         cp = np.zeros(ng * ng * 3); t = C.c_int(0)
@@ -296,8 +315,9 @@ class Oracle:
         return st, nbad
 
     def step(self, dt, n_steps=1, rk=0, drag=1, max_newton_it=50, max_crossings=64,
-             gravity=(0, 0, 0), drag_mask=(1, 1, 1), use_mlp=False, tracking=0):
+             gravity=(0, 0, 0), drag_mask=(1, 1, 1), use_mlp=False, tracking=0, forces=0):
         o = StepOpts()
+        o.forces = int(forces)
         o.rk = rk; o.drag = drag; o.max_newton_it = max_newton_it; o.max_crossings = max_crossings
         o.use_mlp = int(bool(use_mlp))
         o.tracking = int(tracking)
@@ -323,12 +343,13 @@ class Oracle:
     def reset_stats(self):
         lib().or_reset_stats(self.ctx)
 
-    def deposit(self, kind=0, radius=0.0, period=None, drag=1, S=None):
+    def deposit(self, kind=0, radius=0.0, period=None, drag=1, S=None, forces=0, gravity=None):
         n3 = (self.N + 1) ** 3
         if S is None:
             S = np.zeros((self.E, 4, n3))
         per = _f64(period) if period is not None else None
-        lib().or_deposit(self.ctx, _p(S), int(kind), float(radius), _p(per), int(drag))
+        g = _f64(gravity) if gravity is not None else None
+        lib().or_deposit(self.ctx, _p(S), int(kind), float(radius), _p(per), int(drag), int(forces), _p(g))
         return S
 
     # learned guess

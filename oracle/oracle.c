@@ -445,6 +445,115 @@ void or_drag_accel(const or_ctx* c, int drag, const double* prim, const double* 
   if (fD_out) *fD_out = (drag == 2) ? 0.0 : fD;
 }
 
+/* Primitive state and physical velocity gradient G[i][j] = du_i/dx_j at xi
+ * (needed by the undisturbed-flow stress, added mass and lift, Sec. 2.2):
+ * derivatives of the interpolant (eq. part_interpolation) with respect to
+ * xi_d, then the chain rule df/dx_j = sum_d df/dxi_d (J^-1)_dj with J the
+ * element map's Jacobian at xi, and u = m / rho:
+ * du_i/dx_j = (dm_i/dx_j - u_i drho/dx_j) / rho. */
+void or_fluid_grad(const or_ctx* c, int e, const double* xi, double* prim, double* G) {
+  int n = c->n, n3 = n * n * n;
+  double l[3][MAXG], dl[3][MAXG];
+  for (int d = 0; d < 3; ++d) or_lagrange(n, c->xdg, xi[d], l[d], dl[d]);
+  const double* U = c->U + (size_t)e * 5 * n3;
+  double Uc[5], dU[4][3];
+  for (int var = 0; var < 5; ++var) {
+    double s = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double u = U[var * n3 + (k * n + j) * n + i];
+          s += u * l[0][i] * l[1][j] * l[2][k];
+          s0 += u * dl[0][i] * l[1][j] * l[2][k];
+          s1 += u * l[0][i] * dl[1][j] * l[2][k];
+          s2 += u * l[0][i] * l[1][j] * dl[2][k];
+        }
+    Uc[var] = s;
+    if (var < 4) { dU[var][0] = s0; dU[var][1] = s1; dU[var][2] = s2; }
+  }
+  cons2prim(c->kappa, Uc, prim);
+  double x[3], Jf[9];
+  or_map(c, e, xi, x, Jf);
+  /* inverse of J by cofactors */
+  double Ji[9];
+  Ji[0] = Jf[4] * Jf[8] - Jf[5] * Jf[7];
+  Ji[1] = Jf[2] * Jf[7] - Jf[1] * Jf[8];
+  Ji[2] = Jf[1] * Jf[5] - Jf[2] * Jf[4];
+  Ji[3] = Jf[5] * Jf[6] - Jf[3] * Jf[8];
+  Ji[4] = Jf[0] * Jf[8] - Jf[2] * Jf[6];
+  Ji[5] = Jf[2] * Jf[3] - Jf[0] * Jf[5];
+  Ji[6] = Jf[3] * Jf[7] - Jf[4] * Jf[6];
+  Ji[7] = Jf[1] * Jf[6] - Jf[0] * Jf[7];
+  Ji[8] = Jf[0] * Jf[4] - Jf[1] * Jf[3];
+  double det = Jf[0] * Ji[0] + Jf[1] * Ji[3] + Jf[2] * Ji[6];
+  for (int q = 0; q < 9; ++q) Ji[q] /= det;
+  double gx[4][3];   /* physical gradients of rho, m1, m2, m3 */
+  for (int var = 0; var < 4; ++var)
+    for (int jx = 0; jx < 3; ++jx)
+      gx[var][jx] = dU[var][0] * Ji[0 * 3 + jx] + dU[var][1] * Ji[1 * 3 + jx] + dU[var][2] * Ji[2 * 3 + jx];
+  for (int i = 0; i < 3; ++i)
+    for (int jx = 0; jx < 3; ++jx) G[i * 3 + jx] = (gx[1 + i][jx] - prim[1 + i] * gx[0][jx]) / prim[0];
+}
+
+/* Particle acceleration and fluid force from the generalised equation of
+ * motion (eq. theory:maxey) with the terms selected in `forces`:
+ *   m_p dv/dt = F_D + m_f Du/Dt + m_f/2 (Du/Dt - dv/dt) + F_L + g (m_p - m_f),
+ * m_p = rho_p pi d^3/6, m_f = rho pi d^3/6 (r = rho/rho_p).  The fluid state
+ * is frozen over a step, so Du/Dt = (u . grad) u.  Basset history and Magnus
+ * lift are not included.  Without OR_F_BUOYANCY the body force is g m_p (the
+ * model of the other configurations); with OR_F_ADDED_MASS the dv/dt term is
+ * moved to the left: (1 + r/2) dv/dt = ...  Saffman lift (Sec. 2.2.2) with
+ * Mei's correction, read as C_S = (1 - 0.3314 sqrt(th)) exp(-Re/10)
+ * + 0.3314 sqrt(th) for Re <= 40 (the bracketing that meets the Re > 40 branch
+ * 0.0524 sqrt(th Re) at Re = 40), th = d |w| / (2 |u - v|) limited to
+ * [0.005, 0.4], and with the direction (u - v) x w (w the vorticity): the
+ * relative velocity of the paper's cross product is read as particle minus
+ * fluid, which turns a particle that lags the fluid in a shear flow towards
+ * the faster fluid (Saffman's result).
+ * a[3]: dv/dt; F[3] (may be NULL): the fluid force of the two-way source
+ * (eq. theory:source): F_D + m_f Du/Dt + m_f/2 (Du/Dt - dv/dt) + F_L. */
+void or_particle_accel(const or_ctx* c, int drag, int forces, const double* prim, const double* G,
+                       const double* v, double d, const double* g, double* a, double* F) {
+  double w[3] = {prim[1] - v[0], prim[2] - v[1], prim[3] - v[2]};
+  double aD[3], fD;
+  or_drag_accel(c, drag, prim, v, d, NULL, aD, &fD);
+  double r = prim[0] / c->rho_p;
+  double DuDt[3] = {0, 0, 0}, aL[3] = {0, 0, 0};
+  if (forces & (OR_F_STRESS | OR_F_ADDED_MASS))
+    for (int i = 0; i < 3; ++i) DuDt[i] = G[i * 3 + 0] * prim[1] + G[i * 3 + 1] * prim[2] + G[i * 3 + 2] * prim[3];
+  if (forces & OR_F_SAFFMAN) {
+    double om[3] = {G[2 * 3 + 1] - G[1 * 3 + 2], G[0 * 3 + 2] - G[2 * 3 + 0], G[1 * 3 + 0] - G[0 * 3 + 1]};
+    double wo = norm3(om), ww = norm3(w);
+    if (wo > 0.0 && ww > 0.0) {
+      double Re = prim[0] * ww * d / c->mu;
+      double th = d * wo / (2.0 * ww);
+      if (th < 0.005) th = 0.005;
+      if (th > 0.4) th = 0.4;
+      double CS = (Re <= 40.0) ? (1.0 - 0.3314 * sqrt(th)) * exp(-0.1 * Re) + 0.3314 * sqrt(th)
+                               : 0.0524 * sqrt(th * Re);
+      double mp = c->rho_p * M_PI * d * d * d / 6.0;
+      double coef = 6.46 / 4.0 * CS * d * d * sqrt(prim[0] * c->mu / wo) / mp;
+      double cr[3];
+      cross3(w, om, cr);
+      for (int q = 0; q < 3; ++q) aL[q] = coef * cr[q];
+    }
+  }
+  double cs = ((forces & OR_F_STRESS) ? 1.0 : 0.0) + ((forces & OR_F_ADDED_MASS) ? 0.5 : 0.0);
+  double den = (forces & OR_F_ADDED_MASS) ? 1.0 + 0.5 * r : 1.0;
+  double gb = (forces & OR_F_BUOYANCY) ? 1.0 - r : 1.0;
+  for (int q = 0; q < 3; ++q) a[q] = (aD[q] + cs * r * DuDt[q] + aL[q] + gb * (g ? g[q] : 0.0)) / den;
+  if (F) {
+    /* drag as in eq. dragforce, the other terms per unit particle mass times m_p */
+    double mp = c->rho_p * M_PI * d * d * d / 6.0;
+    for (int q = 0; q < 3; ++q) {
+      double f = aL[q];
+      if (forces & OR_F_STRESS) f += r * DuDt[q];
+      if (forces & OR_F_ADDED_MASS) f += 0.5 * r * (DuDt[q] - a[q]);
+      F[q] = 3.0 * M_PI * c->mu * d * fD * w[q] + mp * f;
+    }
+  }
+}
+
 /* ======================================================================== */
 /* faces: Lagrange -> Bernstein control points, type, slab bounding box      */
 /* ======================================================================== */
@@ -1538,10 +1647,16 @@ int or_step(or_ctx* c, double dt, int n_steps, const or_step_opts* o) {
         }
         for (int k = 0; k < 3; ++k) c->xi[p * 3 + k] = xi[k];
         double Uc[5], prim[5], a[3];
-        or_interp(c, e, xi, Uc);
-        cons2prim(c->kappa, Uc, prim);
-        or_drag_accel(c, o->drag, prim, v, c->d[p], NULL, a, NULL);
-        for (int k = 0; k < 3; ++k) a[k] = a[k] * o->drag_mask[k] + o->gravity[k];
+        if (o->forces) {
+          double G[9];
+          or_fluid_grad(c, e, xi, prim, G);
+          or_particle_accel(c, o->drag, o->forces, prim, G, v, c->d[p], o->gravity, a, NULL);
+        } else {
+          or_interp(c, e, xi, Uc);
+          cons2prim(c->kappa, Uc, prim);
+          or_drag_accel(c, o->drag, prim, v, c->d[p], NULL, a, NULL);
+          for (int k = 0; k < 3; ++k) a[k] = a[k] * o->drag_mask[k] + o->gravity[k];
+        }
         double xe[3];
         for (int k = 0; k < 3; ++k) {
           kx[k] = A[s] * kx[k] + dt * v[k];
@@ -1614,9 +1729,13 @@ void or_reset_stats(or_ctx* c) {
  * kind 1: polynomial shape kernel K(r) = (1 - (r/R)^2)^2 over all DG nodes
  * within R, discretely normalised so that sum_k S_k V_k = a (not in the
  * paper; a smoother projection operator of the same conservation property).
- * Momentum source S_m = -F_D, energy source S_e = -F_D . v_p.  Output layout
+ * Momentum source S_m = -F (F_D, plus the undisturbed-flow stress, added
+ * mass and lift terms selected in `forces`, as in eq. theory:source; the
+ * added-mass term uses dv/dt, hence the gravity argument), energy source
+ * S_e = -F . v_p.  Output layout
  * [E][4][(N+1)^3]; S is accumulated into. */
-int or_deposit(or_ctx* c, double* S, int kind, double R, const double* period, int drag) {
+int or_deposit(or_ctx* c, double* S, int kind, double R, const double* period, int drag, int forces,
+               const double* gravity) {
   int n = c->n, n3 = n * n * n;
   int64_t np = c->np;
   double* F = (double*)malloc(sizeof(double) * np * 4);
@@ -1630,15 +1749,19 @@ int or_deposit(or_ctx* c, double* S, int kind, double R, const double* period, i
     int64_t a0 = 0, a1 = 0, a2 = 0;
     if (!newton_chain(c, e, c->x + p * 3, xi, 50, 0, &a0, &a1, &a2)) continue;
     double Uc[5], prim[5], a[3], fD;
-    or_interp(c, e, xi, Uc);
-    cons2prim(c->kappa, Uc, prim);
-    or_drag_accel(c, drag, prim, c->v + p * 3, c->d[p], NULL, a, &fD);
     double dd = c->d[p];
     double Fv[3], fdot = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      Fv[k] = 3.0 * M_PI * c->mu * dd * fD * (prim[1 + k] - c->v[p * 3 + k]);
-      fdot += Fv[k] * c->v[p * 3 + k];
+    if (forces) {
+      double G[9];
+      or_fluid_grad(c, e, xi, prim, G);
+      or_particle_accel(c, drag, forces, prim, G, c->v + p * 3, dd, gravity, a, Fv);
+    } else {
+      or_interp(c, e, xi, Uc);
+      cons2prim(c->kappa, Uc, prim);
+      or_drag_accel(c, drag, prim, c->v + p * 3, dd, NULL, a, &fD);
+      for (int k = 0; k < 3; ++k) Fv[k] = 3.0 * M_PI * c->mu * dd * fD * (prim[1 + k] - c->v[p * 3 + k]);
     }
+    for (int k = 0; k < 3; ++k) fdot += Fv[k] * c->v[p * 3 + k];
     for (int k = 0; k < 3; ++k) F[p * 4 + k] = Fv[k];
     F[p * 4 + 3] = fdot;
     for (int k = 0; k < 3; ++k) xi_all[p * 3 + k] = xi[k];

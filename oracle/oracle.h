@@ -49,6 +49,9 @@ int  or_newton(or_ctx*, int e, const double* x, const double* xi0, double* xi, i
 void or_guess(const or_ctx*, int e, const double* x, double* xi0);
 void or_guess_faces(const or_ctx*, int e, const double* x, double* xi0);
 void or_interp(const or_ctx*, int e, const double* xi, double* Uout /*5*/);
+void or_fluid_grad(const or_ctx*, int e, const double* xi, double* prim /*5*/, double* G /*3x3, du_i/dx_j*/);
+void or_particle_accel(const or_ctx*, int drag, int forces, const double* prim, const double* G,
+                       const double* v, double d, const double* g, double* a, double* F /*may be NULL*/);
 void or_drag_accel(const or_ctx*, int drag, const double* prim, const double* v, double d,
                    const double* g, double* a, double* fD);
 int  or_face_info(const or_ctx*, int e, int f, double* cp /*ng*ng*3*/, int* type);
@@ -68,10 +71,13 @@ int  or_push(or_ctx*, int64_t n, const double* x, const double* v, const double*
  * max_newton_it, max_crossings, use_mlp, tracking (0 physical space; 1 reference-space
  * localisation: segments that cannot reach a boundary face are not traced),
  * gravity[3], drag_mask[3] (1 keeps drag in that axis) */
+/* extra terms of the equation of motion (eq. theory:maxey), bit flags */
+enum { OR_F_BUOYANCY = 1, OR_F_STRESS = 2, OR_F_ADDED_MASS = 4, OR_F_SAFFMAN = 8 };
 typedef struct {
   int32_t rk, drag, max_newton_it, max_crossings, use_mlp, tracking;
   double gravity[3];
-  double drag_mask[3];
+  double drag_mask[3];   /* per-axis drag factor, only without extra forces (tests) */
+  int32_t forces;        /* OR_F_* */
 } or_step_opts;
 void or_default_opts(or_step_opts*);
 int  or_step(or_ctx*, double dt, int n_steps, const or_step_opts*);
@@ -82,7 +88,7 @@ void or_reset_stats(or_ctx*);
 
 /* two-way coupling source ------------------------------------------------- */
 int  or_deposit(or_ctx*, double* S /*[E][4][(N+1)^3]*/, int kind, double radius,
-                const double* period, int drag);
+                const double* period, int drag, int forces, const double* gravity /*3 or NULL*/);
 
 /* learned initial guess --------------------------------------------------- */
 #define OR_MLP_NIN 84

@@ -682,7 +682,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   if (!c || !o || n_steps < 0 || !(dt > 0.0)) return FP_EINVAL;
   if (!c->ws || !c->fluid_ok) return fail(c, FP_ESTATE, "fp_step: workspace or fluid state missing");
   if (o->rk < 0 || o->rk > 1 || o->drag < 0 || o->drag > 2 || o->precision < 0 || o->precision > 1 ||
-      o->tracking < 0 || o->tracking > 1)
+      o->tracking < 0 || o->tracking > 1 || (o->forces & ~kForceAll) != 0)
     return fail(c, FP_EINVAL, "fp_step: bad options");
   if (o->precision == 0 && c->fl.f32)
     ;  // FP64 arithmetic on an FP32 state is allowed (values widened on load)
@@ -705,6 +705,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   sp.max_cross = o->max_crossings > 0 ? o->max_crossings : 64;
   sp.use_mlp = (o->guess == 1 && c->mlp_w) ? 1 : 0;
   sp.refspace = o->tracking;
+  sp.forces = o->forces;
   hipStream_t s = c->stream;
   for (int st = 0; st < n_steps; ++st) {
     if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
@@ -753,12 +754,16 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
 }
 
 int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radius, const double* period,
-                      int32_t drag) {
-  if (!c || !S || kind < 0 || kind > 1) return FP_EINVAL;
+                      int32_t drag, int32_t forces, const double* gravity) {
+  if (!c || !S || kind < 0 || kind > 1 || drag < 0 || drag > 2 || (forces & ~kForceAll) != 0) return FP_EINVAL;
   if (!c->ws || !c->fluid_ok) return fail(c, FP_ESTATE, "fp_deposit_source: workspace or fluid state missing");
+  ForceModel fm{};
+  fm.drag = drag;
+  fm.forces = forces;
+  for (int k = 0; k < 3; ++k) fm.gravity[k] = gravity ? gravity[k] : 0.0;
   if (kind == 0) {
     Timed tm(c, 3);
-    HIPCHK(c, launch_deposit_nearest(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, c->stream));
+    HIPCHK(c, launch_deposit_nearest(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, c->stream));
     return FP_OK;
   }
   if (!(radius > 0.0)) return fail(c, FP_EINVAL, "fp_deposit_source: radius must be positive");
@@ -774,7 +779,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   if (rc) return rc;
   {
     Timed tm(c, 4);
-    HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, drag, radius, per,
+    HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
                                    c->node_pad, c->dep_buf, c->sort_start, c->dep_pad, c->stream));
   }
   return FP_OK;

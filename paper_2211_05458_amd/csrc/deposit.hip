@@ -167,12 +167,11 @@ __device__ __forceinline__ void stream_candidates(const MeshView& m, const doubl
 
 // 1. force and validity ------------------------------------------------------
 template <int NN, int NG, typename UT>
-__global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Fluid fl, int64_t n, int drag, double* F,
-                                                   int32_t* ok, unsigned long long* povh) {
+__global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Fluid fl, int64_t n, ForceModel fm,
+                                                   double* F, int32_t* ok, unsigned long long* povh) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0) *povh = 0ull;
   if (p >= n) return;
-  constexpr int N3 = NN * NN * NN;
   double* Fp = F + p * 4;
   Fp[0] = Fp[1] = Fp[2] = Fp[3] = 0.0;
   ok[p] = 0;
@@ -183,18 +182,13 @@ __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Flui
   double xi[3];
   int it = 0, calls = 0, fb = 0;
   if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb)) return;
-  double Uc[kInterpVars];
-  interp<NN, UT>(m, (const UT*)fl.U + (size_t)e * 5 * N3, xi, Uc);
-  double ir = 1.0 / Uc[0];
-  double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
   double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
-  double d = P.d[p], a[3], fD;
-  drag_accel<double>(drag, Uc[0], u, v, d, fl.mu, fl.rho_p, a, fD);
-  double c = 3.0 * M_PI * fl.mu * d * fD;
-  Fp[0] = c * (u[0] - v[0]);
-  Fp[1] = c * (u[1] - v[1]);
-  Fp[2] = c * (u[2] - v[2]);
-  Fp[3] = Fp[0] * v[0] + Fp[1] * v[1] + Fp[2] * v[2];
+  double Fq[3];
+  source_force<NN, NG, UT>(m, fl, fm, e, xi, v, P.d[p], Fq);
+  Fp[0] = Fq[0];
+  Fp[1] = Fq[1];
+  Fp[2] = Fq[2];
+  Fp[3] = Fq[0] * v[0] + Fq[1] * v[1] + Fq[2] * v[2];
   ok[p] = 1;
 }
 
@@ -443,8 +437,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Parti
 #include "fp_shapes.h"
 
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
-                                int s_f32, int drag, double R, const double* period, double node_pad, double* dep,
-                                const int32_t* elem_start, unsigned long long* povh, hipStream_t s) {
+                                int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
+                                double* dep, const int32_t* elem_start, unsigned long long* povh, hipStream_t s) {
   DepGeo g;
   g.R = R;
   g.R2 = R * R;
@@ -457,8 +451,8 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
   dim3 ge((unsigned)(((m.E + kXcd - 1) / kXcd) * kXcd));
 #define FP_L(A, B)                                                                                           \
   if (m.n == A && m.ng == B) {                                                                               \
-    if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, drag, F, ok, povh);                 \
-    else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, drag, F, ok, povh);                       \
+    if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                   \
+    else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                         \
     k_dep_norm<A><<<ge, kNormThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                             \
     if (s_f32) k_dep_gather<A, float><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (float*)S); \
     else k_dep_gather<A, double><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);    \

@@ -529,6 +529,185 @@ __device__ __forceinline__ void drag_accel(int drag, T rho, const T* u, const T*
 }
 
 // ---------------------------------------------------------------------------
+// extra terms of the equation of motion (eq. theory:maxey): buoyancy, the
+// undisturbed-flow stress m_f Du/Dt, added mass and Saffman lift
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__device__ __forceinline__ void lagrange_dt(const T* nodes, const T* cden, T x, T* l, T* dl) {
+  T dx[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) dx[j] = x - nodes[j];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T p = T(1), dp = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j != i) {
+        dp = dp * dx[j] + p;
+        p *= dx[j];
+      }
+    l[i] = cden[i] * p;
+    dl[i] = cden[i] * dp;
+  }
+}
+
+// density and momentum (eq. part_interpolation) and their derivatives along
+// xi_1, xi_2, xi_3, by sum factorisation in precision T
+template <int NN, typename T, typename UT>
+__device__ void interp_grad(const T* xdg, const T* cdg, const UT* __restrict__ U, const double* xi, T* val,
+                            T (*dval)[3]) {
+  T l1[NN], d1[NN], l2[NN], d2[NN], l3[NN], d3[NN];
+  lagrange_dt<NN, T>(xdg, cdg, (T)xi[0], l1, d1);
+  lagrange_dt<NN, T>(xdg, cdg, (T)xi[1], l2, d2);
+  lagrange_dt<NN, T>(xdg, cdg, (T)xi[2], l3, d3);
+  constexpr int N3 = NN * NN * NN;
+#pragma unroll 1
+  for (int var = 0; var < kInterpVars; ++var) {
+    T s = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 1
+    for (int k = 0; k < NN; ++k) {
+      const UT* Uk = U + var * N3 + k * NN * NN;
+      T a = 0, b = 0, c = 0;
+#pragma unroll
+      for (int j = 0; j < NN; ++j) {
+        T p = 0, q = 0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          const T u = (T)Uk[j * NN + i];
+          p += u * l1[i];
+          q += u * d1[i];
+        }
+        a += p * l2[j];
+        b += q * l2[j];
+        c += p * d2[j];
+      }
+      s += a * l3[k];
+      s1 += b * l3[k];
+      s2 += c * l3[k];
+      s3 += a * d3[k];
+    }
+    val[var] = s;
+    dval[var][0] = s1;
+    dval[var][1] = s2;
+    dval[var][2] = s3;
+  }
+}
+
+// velocity u = m / rho and its physical gradient G[i][j] = du_i/dx_j:
+// df/dx_j = sum_d df/dxi_d (J^-1)_dj, du_i = (dm_i - u_i drho) / rho
+template <typename T>
+__device__ void velocity_gradient(const double J[3][3], const T* val, const T (*dval)[3], T* u, T (*G)[3]) {
+  double Ji[3][3];
+  Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double idet = 1.0 / (J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0]);
+  T gx[kInterpVars][3];
+#pragma unroll
+  for (int var = 0; var < kInterpVars; ++var)
+#pragma unroll
+    for (int jx = 0; jx < 3; ++jx)
+      gx[var][jx] = dval[var][0] * (T)(Ji[0][jx] * idet) + dval[var][1] * (T)(Ji[1][jx] * idet) +
+                    dval[var][2] * (T)(Ji[2][jx] * idet);
+  const T ir = T(1) / val[0];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    u[i] = val[1 + i] * ir;
+#pragma unroll
+    for (int jx = 0; jx < 3; ++jx) G[i][jx] = (gx[1 + i][jx] - u[i] * gx[0][jx]) * ir;
+  }
+}
+
+// dv/dt from m_p dv/dt = F_D + m_f Du/Dt + m_f/2 (Du/Dt - dv/dt) + F_L
+// + g (m_p - m_f) with the terms selected in `forces` (m_f = rho pi d^3/6,
+// r = rho / rho_p).  The fluid state is frozen over a step, so
+// Du/Dt = (u . grad) u.  Without kForceBuoyancy the body force is g m_p; with
+// kForceAddedMass the dv/dt term moves to the left, (1 + r/2) dv/dt = ....
+// Saffman lift (Sec. 2.2.2): 6.46/4 C_S d^2 sqrt(rho mu / |w|) (u - v) x w
+// (w the vorticity; the direction that lifts a particle lagging a shear flow
+// towards the faster fluid), Mei's C_S = (1 - 0.3314 sqrt(th)) exp(-Re/10)
+// + 0.3314 sqrt(th) for Re <= 40 and 0.0524 sqrt(th Re) above, with
+// th = d |w| / (2 |u - v|) limited to [0.005, 0.4].  F (may be null): the fluid
+// force of the two-way source (eq. theory:source), F_D + m_f Du/Dt
+// + m_f/2 (Du/Dt - dv/dt) + F_L.
+template <typename T>
+__device__ void particle_accel(int drag, int forces, T rho, const T* u, const T (*G)[3], const T* v, T d, T mu,
+                               T rho_p, const double* g, T* a, T* F) {
+  T aD[3], fD;
+  drag_accel<T>(drag, rho, u, v, d, mu, rho_p, aD, fD);
+  const T w[3] = {u[0] - v[0], u[1] - v[1], u[2] - v[2]};
+  const T r = rho / rho_p;
+  const T mp = rho_p * T(M_PI) * d * d * d / T(6);
+  T DuDt[3] = {0, 0, 0}, aL[3] = {0, 0, 0};
+  if (forces & (kForceStress | kForceAddedMass))
+#pragma unroll
+    for (int i = 0; i < 3; ++i) DuDt[i] = G[i][0] * u[0] + G[i][1] * u[1] + G[i][2] * u[2];
+  if (forces & kForceSaffman) {
+    const T om[3] = {G[2][1] - G[1][2], G[0][2] - G[2][0], G[1][0] - G[0][1]};
+    const T wo = sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]);
+    const T ww = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (wo > T(0) && ww > T(0)) {
+      const T Re = rho * ww * d / mu;
+      const T th = fmin(fmax(d * wo / (T(2) * ww), T(0.005)), T(0.4));
+      const T CS = (Re <= T(40)) ? (T(1) - T(0.3314) * sqrt(th)) * exp(T(-0.1) * Re) + T(0.3314) * sqrt(th)
+                                 : T(0.0524) * sqrt(th * Re);
+      const T coef = T(6.46) / T(4) * CS * d * d * sqrt(rho * mu / wo) / mp;
+      aL[0] = coef * (w[1] * om[2] - w[2] * om[1]);
+      aL[1] = coef * (w[2] * om[0] - w[0] * om[2]);
+      aL[2] = coef * (w[0] * om[1] - w[1] * om[0]);
+    }
+  }
+  const T cs = ((forces & kForceStress) ? T(1) : T(0)) + ((forces & kForceAddedMass) ? T(0.5) : T(0));
+  const T den = (forces & kForceAddedMass) ? T(1) + T(0.5) * r : T(1);
+  const T gb = (forces & kForceBuoyancy) ? T(1) - r : T(1);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) a[q] = (aD[q] + cs * r * DuDt[q] + aL[q] + gb * (T)g[q]) / den;
+  if (F) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      T f = aL[q];
+      if (forces & kForceStress) f += r * DuDt[q];
+      if (forces & kForceAddedMass) f += T(0.5) * r * (DuDt[q] - a[q]);
+      F[q] = T(3) * T(M_PI) * mu * d * fD * w[q] + mp * f;
+    }
+  }
+}
+
+// fluid force on a particle at xi in element e for the two-way source
+// (eq. theory:source): drag F_D = 3 pi mu d f_D (u - v) (eq. dragforce), plus
+// the extra terms of fm.forces (FP64 throughout)
+template <int NN, int NG, typename UT>
+__device__ void source_force(const MeshView& m, const Fluid& fl, const ForceModel& fm, int e, const double* xi,
+                             const double* v, double d, double* F) {
+  constexpr int N3 = NN * NN * NN;
+  const UT* Ue = (const UT*)fl.U + (size_t)e * 5 * N3;
+  if (fm.forces) {
+    double val[kInterpVars], dval[kInterpVars][3], u[3], G[3][3], J[3][3], xm[3], a[3];
+    interp_grad<NN, double, UT>(m.xdg, m.cdg, Ue, xi, val, dval);
+    map_jac<NG>(m, m.X + (size_t)e * NG * NG * NG * 3, xi, xm, J);
+    velocity_gradient<double>(J, val, dval, u, G);
+    particle_accel<double>(fm.drag, fm.forces, val[0], u, G, v, d, fl.mu, fl.rho_p, fm.gravity, a, F);
+  } else {
+    double Uc[kInterpVars];
+    interp<NN, UT>(m, Ue, xi, Uc);
+    double ir = 1.0 / Uc[0];
+    double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+    double a[3], fD;
+    drag_accel<double>(fm.drag, Uc[0], u, v, d, fl.mu, fl.rho_p, a, fD);
+    double c = 3.0 * M_PI * fl.mu * d * fD;
+    F[0] = c * (u[0] - v[0]);
+    F[1] = c * (u[1] - v[1]);
+    F[2] = c * (u[2] - v[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // face intersection (Sec. 3.2.4)
 // ---------------------------------------------------------------------------
 // Bezier control points of local face f of an element (Lagrange geometry

@@ -87,12 +87,23 @@ struct Fluid {
   double mu, kappa, rho_p;
 };
 
+// extra terms of the equation of motion (eq. theory:maxey), bit flags
+constexpr int kForceBuoyancy = 1, kForceStress = 2, kForceAddedMass = 4, kForceSaffman = 8;
+constexpr int kForceAll = 15;
+
 struct StepParams {
   double dt;
   double A, B;          // low-storage coefficients of this stage
   double gravity[3];
   int32_t drag, max_it, max_cross, use_mlp;
   int32_t refspace;     // reference-space localisation of segments that cannot reach a boundary face
+  int32_t forces;       // kForce* terms beyond drag and gravity
+};
+
+// force model of the two-way source (the fluid force of the equation of motion)
+struct ForceModel {
+  double gravity[3];
+  int32_t drag, forces;
 };
 
 }  // namespace fp

@@ -37,10 +37,10 @@ hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, h
 hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, unsigned long long* stats,
                            hipStream_t s);
 hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
-                                  int s_f32, int drag, hipStream_t s);
+                                  int s_f32, const ForceModel& fm, hipStream_t s);
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
-                                int s_f32, int drag, double R, const double* period, double node_pad, double* dep,
-                                const int32_t* elem_start, unsigned long long* povh, hipStream_t s);
+                                int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
+                                double* dep, const int32_t* elem_start, unsigned long long* povh, hipStream_t s);
 hipError_t launch_sort(const Particles& src, const Particles& dst, int64_t n, int E, int32_t* count,
                        int32_t* start, int32_t* rank, int32_t* block_sums, hipStream_t s);
 hipError_t launch_elem_start(const Particles& P, int64_t n, int E, int32_t* elem_start, hipStream_t s);

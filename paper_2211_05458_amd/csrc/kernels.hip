@@ -168,11 +168,12 @@ __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64
 }
 
 // ---------------------------------------------------------------------------
-// two-way source at the nearest DOF (Sec. 2.3): S = -F / V_ijk, S_e = -F.v / V
+// two-way source at the nearest DOF (Sec. 2.3): S = -F / V_ijk, S_e = -F.v / V,
+// F the fluid force of the particle's equation of motion
 // ---------------------------------------------------------------------------
 template <int NN, int NG, typename UT, typename ST>
 __global__ __launch_bounds__(256) void k_deposit_nearest(MeshView m, Particles P, Fluid fl, int64_t n, ST* S,
-                                                         int drag) {
+                                                         ForceModel fm) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n || P.status[p] != ACTIVE) return;
   constexpr int N3 = NN * NN * NN;
@@ -182,15 +183,9 @@ __global__ __launch_bounds__(256) void k_deposit_nearest(MeshView m, Particles P
   double xi[3];
   int it = 0, calls = 0, fb = 0;
   if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb)) return;
-  double Uc[kInterpVars];
-  interp<NN, UT>(m, (const UT*)fl.U + (size_t)e * 5 * N3, xi, Uc);
-  double ir = 1.0 / Uc[0];
-  double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
   double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
-  double d = P.d[p], a[3], fD;
-  drag_accel<double>(drag, Uc[0], u, v, d, fl.mu, fl.rho_p, a, fD);
-  double c = 3.0 * M_PI * fl.mu * d * fD;
-  double F[3] = {c * (u[0] - v[0]), c * (u[1] - v[1]), c * (u[2] - v[2])};
+  double F[3];
+  source_force<NN, NG, UT>(m, fl, fm, e, xi, v, P.d[p], F);
   double Fv = F[0] * v[0] + F[1] * v[1] + F[2] * v[2];
   int idx[3];
   for (int k = 0; k < 3; ++k) {
@@ -275,15 +270,15 @@ hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, uns
 }
 
 hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
-                                  int s_f32, int drag, hipStream_t s) {
+                                  int s_f32, const ForceModel& fm, hipStream_t s) {
   if (n == 0) return hipSuccess;
   dim3 g = grid_for(n);
 #define FP_L(A, B)                                                                                              \
   if (m.n == A && m.ng == B) {                                                                                  \
-    if (fl.f32 && s_f32) k_deposit_nearest<A, B, float, float><<<g, 256, 0, s>>>(m, P, fl, n, (float*)S, drag);    \
-    else if (fl.f32) k_deposit_nearest<A, B, float, double><<<g, 256, 0, s>>>(m, P, fl, n, (double*)S, drag);      \
-    else if (s_f32) k_deposit_nearest<A, B, double, float><<<g, 256, 0, s>>>(m, P, fl, n, (float*)S, drag);        \
-    else k_deposit_nearest<A, B, double, double><<<g, 256, 0, s>>>(m, P, fl, n, (double*)S, drag);                 \
+    if (fl.f32 && s_f32) k_deposit_nearest<A, B, float, float><<<g, 256, 0, s>>>(m, P, fl, n, (float*)S, fm);      \
+    else if (fl.f32) k_deposit_nearest<A, B, float, double><<<g, 256, 0, s>>>(m, P, fl, n, (double*)S, fm);        \
+    else if (s_f32) k_deposit_nearest<A, B, double, float><<<g, 256, 0, s>>>(m, P, fl, n, (float*)S, fm);          \
+    else k_deposit_nearest<A, B, double, double><<<g, 256, 0, s>>>(m, P, fl, n, (double*)S, fm);                   \
     return hipGetLastError();                                                                                   \
   }
   FP_FOR_EACH_SHAPE(FP_L)

@@ -20,38 +20,65 @@
 
 namespace fp {
 
-// interpolation, drag and the low-storage update for one particle
-template <int NN, typename UT, bool MIXED>
-__device__ __forceinline__ void stage_update(const MeshView& m, const UT* __restrict__ Ue, const double* xi,
-                                             const double* x, double* v, double* kx, double* kv, double d,
-                                             const Fluid& fl, const StepParams& sp, double* xe) {
+// interpolation, drag and the low-storage update for one particle.  FORCES:
+// the extra terms of the equation of motion selected in sp.forces (they need
+// the velocity gradient, hence the element's geometry nodes Xe).
+template <int NN, int NG, typename UT, bool MIXED, bool FORCES>
+__device__ __forceinline__ void stage_update(const MeshView& m, const UT* __restrict__ Ue,
+                                             const double* __restrict__ Xe, const double* xi, const double* x,
+                                             double* v, double* kx, double* kv, double d, const Fluid& fl,
+                                             const StepParams& sp, double* xe) {
+  double Jg[3][3];
+  if (FORCES) {
+    double xm[3];
+    map_jac<NG>(m, Xe, xi, xm, Jg);
+  }
   if (!MIXED) {
-    double Uc[kInterpVars];
-    interp<NN, UT>(m, Ue, xi, Uc);
-    double rho = Uc[0], ir = 1.0 / rho;
-    double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
-    double a[3], fD;
-    drag_accel<double>(sp.drag, rho, u, v, d, fl.mu, fl.rho_p, a, fD);
+    double a[3];
+    if (FORCES) {
+      double val[kInterpVars], dval[kInterpVars][3], u[3], G[3][3];
+      interp_grad<NN, double, UT>(m.xdg, m.cdg, Ue, xi, val, dval);
+      velocity_gradient<double>(Jg, val, dval, u, G);
+      particle_accel<double>(sp.drag, sp.forces, val[0], u, G, v, d, fl.mu, fl.rho_p, sp.gravity, a, nullptr);
+    } else {
+      double Uc[kInterpVars];
+      interp<NN, UT>(m, Ue, xi, Uc);
+      double rho = Uc[0], ir = 1.0 / rho;
+      double u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+      double fD;
+      drag_accel<double>(sp.drag, rho, u, v, d, fl.mu, fl.rho_p, a, fD);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a[k] += sp.gravity[k];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      a[k] += sp.gravity[k];
       kx[k] = sp.A * kx[k] + sp.dt * v[k];
       kv[k] = sp.A * kv[k] + sp.dt * a[k];
       xe[k] = x[k] + sp.B * kx[k];
       v[k] = v[k] + sp.B * kv[k];
     }
   } else {
-    float Uc[kInterpVars];
-    interp_f32<NN, UT>(m, Ue, xi, Uc);
-    float ir = 1.0f / Uc[0];
-    float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
     float vf[3] = {(float)v[0], (float)v[1], (float)v[2]};
-    float a[3], fD;
-    drag_accel<float>(sp.drag, Uc[0], u, vf, (float)d, (float)fl.mu, (float)fl.rho_p, a, fD);
+    float a[3];
+    if (FORCES) {
+      float val[kInterpVars], dval[kInterpVars][3], u[3], G[3][3];
+      interp_grad<NN, float, UT>(m.xdgf, m.cdgf, Ue, xi, val, dval);
+      velocity_gradient<float>(Jg, val, dval, u, G);
+      particle_accel<float>(sp.drag, sp.forces, val[0], u, G, vf, (float)d, (float)fl.mu, (float)fl.rho_p,
+                            sp.gravity, a, nullptr);
+    } else {
+      float Uc[kInterpVars];
+      interp_f32<NN, UT>(m, Ue, xi, Uc);
+      float ir = 1.0f / Uc[0];
+      float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+      float fD;
+      drag_accel<float>(sp.drag, Uc[0], u, vf, (float)d, (float)fl.mu, (float)fl.rho_p, a, fD);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a[k] += (float)sp.gravity[k];
+    }
     const float A = (float)sp.A, B = (float)sp.B, dt = (float)sp.dt;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      a[k] += (float)sp.gravity[k];
       float kxf = A * (float)kx[k] + dt * vf[k];
       float kvf = A * (float)kv[k] + dt * a[k];
       kx[k] = kxf;
@@ -131,7 +158,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
         double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
         double xe[3];
-        stage_update<NN, UT, MIXED>(m, Ue, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
+        stage_update<NN, NG, UT, MIXED, false>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
         const FaceRec* Fe = faces + (size_t)e * 6;
         bool any = false;
         // reference-space localisation: a segment that cannot reach a
@@ -230,8 +257,10 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
           double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
           double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
           double xe[3];
-          stage_update<NN, UT, MIXED>(m, (const UT*)fl.U + (size_t)e * 5 * NN3, xi, x, v, kx, kv, P.d[p], fl, sp,
-                                      xe);
+          const UT* Ue = (const UT*)fl.U + (size_t)e * 5 * NN3;
+          const double* Xe = m.X + (size_t)e * NG3 * 3;
+          if (sp.forces) stage_update<NN, NG, UT, MIXED, true>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
+          else stage_update<NN, NG, UT, MIXED, false>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             P.x[k * cap + p] = xe[k];
@@ -348,7 +377,9 @@ static void run_stage(const StageLaunch& L, hipStream_t s) {
   k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   int64_t lane_blocks;
   auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
-  if (L.tasks) {
+  // the extra forces run through the per-lane kernel, which keeps their
+  // registers out of the element kernel
+  if (L.tasks && !L.sp.forces) {
     int64_t waves = (int64_t)m.E + L.P.cap / 64 + 1;
     rec(0);
     k_stage_elem<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(

@@ -45,7 +45,11 @@ class FluidParams(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("rk", C.c_int32), ("drag", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32),
                 ("sort_every", C.c_int32), ("max_newton_it", C.c_int32), ("max_crossings", C.c_int32),
-                ("tracking", C.c_int32), ("gravity", C.c_double * 3)]
+                ("tracking", C.c_int32), ("forces", C.c_int32), ("gravity", C.c_double * 3)]
+
+
+# extra terms of the equation of motion (fp_step_opts.forces bits)
+F_BUOYANCY, F_STRESS, F_ADDED_MASS, F_SAFFMAN = 1, 2, 4, 8
 
 
 _lib = None
@@ -71,7 +75,7 @@ def load():
     L.fp_set_fluid_state.argtypes = [P, P, C.c_int, C.POINTER(FluidParams)]
     L.fp_push_particles.argtypes = [P, I64, P, P, P, P, P]
     L.fp_step.argtypes = [P, D, I32, C.POINTER(StepOpts)]
-    L.fp_deposit_source.argtypes = [P, P, C.c_int, I32, D, P, I32]
+    L.fp_deposit_source.argtypes = [P, P, C.c_int, I32, D, P, I32, I32, P]
     L.fp_read_particles.argtypes = [P, C.POINTER(I64), P, P, P, P, P, P]
     L.fp_get_stats.argtypes = [P, P]
     L.fp_reset_stats.argtypes = [P]
@@ -187,19 +191,20 @@ class FlexiPart:
         return st, rc
 
     def step(self, dt, n_steps=1, rk=1, drag=1, precision=0, guess=0, sort_every=1, max_newton_it=50,
-             max_crossings=64, gravity=(0.0, 0.0, 0.0), tracking=0):
+             max_crossings=64, gravity=(0.0, 0.0, 0.0), tracking=0, forces=0):
         o = StepOpts(rk, drag, precision, guess, sort_every, max_newton_it, max_crossings, int(tracking),
-                     (C.c_double * 3)(*gravity))
+                     int(forces), (C.c_double * 3)(*gravity))
         return self._check(self.L.fp_step(self.ctx, float(dt), int(n_steps), C.byref(o)), "fp_step")
 
-    def deposit(self, S=None, kind=0, radius=0.0, period=None, drag=1, dtype=None):
+    def deposit(self, S=None, kind=0, radius=0.0, period=None, drag=1, dtype=None, forces=0, gravity=None):
         t = self.torch
         if S is None:
             S = t.zeros((self.E, 4, self.n3), dtype=dtype or t.float64, device=self.device)
         per = np.ascontiguousarray(period, np.float64) if period is not None else None
+        g = np.ascontiguousarray(gravity, np.float64) if gravity is not None else None
         dt = F64 if S.dtype == t.float64 else F32
-        self._check(self.L.fp_deposit_source(self.ctx, _ptr(S), dt, int(kind), float(radius), _ptr(per), int(drag)),
-                    "fp_deposit_source")
+        self._check(self.L.fp_deposit_source(self.ctx, _ptr(S), dt, int(kind), float(radius), _ptr(per), int(drag),
+                                             int(forces), _ptr(g)), "fp_deposit_source")
         return S
 
     def node_volumes(self):

@@ -58,7 +58,7 @@ def test_host_validation_without_gpu():
     assert b"reciprocal" in L.fp_last_error(ctx)
     # calls out of order
     assert L.fp_init_mesh(ctx, ctypes.byref(desc)) == 0
-    o = lib.StepOpts(1, 1, 0, 0, 1, 50, 64, 0, (ctypes.c_double * 3)(0, 0, 0))
+    o = lib.StepOpts(1, 1, 0, 0, 1, 50, 64, 0, 0, (ctypes.c_double * 3)(0, 0, 0))
     assert L.fp_step(ctx, 1e-3, 1, ctypes.byref(o)) == lib.FP_ESTATE
     sz = ctypes.c_size_t(0)
     assert L.fp_workspace_size(ctx, 1000, ctypes.byref(sz)) == 0 and sz.value > 0
