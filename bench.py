@@ -79,7 +79,8 @@ def bytes_per_particle_stage(n, ng, ppe):
     return soa + elem / ppe
 
 
-def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False, tracking=0):
+def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False, tracking=0, forces=0,
+            gravity=(0.0, 0.0, 0.0)):
     """Push w's particles, run `warmup` untimed then `steps` timed fp_step(dt, 1)
     calls (each followed by deposit(g) if given); returns timings and the state."""
     import numpy as np
@@ -90,7 +91,8 @@ def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None,
     st, nrej = g.push(w.x, w.v, w.d, w.elem_hint)
     n_active = int((st == 0).sum())
     n_flagged = g.mlp_set_weights(weights) if weights is not None else 0
-    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1, guess=guess, tracking=tracking)
+    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1, guess=guess, tracking=tracking,
+                forces=forces, gravity=gravity)
     for _ in range(warmup):
         g.step(w.dt, 1, **opts)
         if deposit:
@@ -284,6 +286,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-refspace", action="store_true", help="skip the reference-space localisation run")
+    ap.add_argument("--no-forces", action="store_true", help="skip the extra-forces run")
     ap.add_argument("--cpu-every", type=int, default=25, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
@@ -358,6 +361,15 @@ def main():
         extras["fp64_refspace"].update({"crossings_traced": rr["stats"]["crossings"],
                                         "localised": rr["stats"]["recovered"],
                                         "track_queue": rr["stats"]["track_queue"]})
+
+    if not args.no_forces:
+        # the extra terms of the equation of motion (buoyancy, undisturbed-flow
+        # stress, added mass, Saffman lift) with gravity; they run through the
+        # per-lane stage kernel
+        print("[bench] extra-forces run", file=sys.stderr, flush=True)
+        rf = run_gpu(w, U64, 0, args.steps, args.warmup, forces=15, gravity=(0.0, -9.81, 0.0))
+        extras["fp64_forces"] = summary(rf, K)
+        extras["fp64_forces"].update({"forces": "buoyancy+stress+added_mass+saffman", "gravity": [0.0, -9.81, 0.0]})
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -103,8 +103,8 @@ typedef struct {
  * Saffman lift with Mei's correction (Sec. 2.2.2), directed along (u - v) x w
  * (w the vorticity).  The fluid state is frozen over a step, so
  * Du/Dt = (u . grad) u from the interpolant's gradient.  Basset history and
- * Magnus lift are not provided.  With any of these bits set every particle
- * runs through the per-lane stage kernel. */
+ * Magnus lift are not provided.  Together with the learned guess (guess = 1)
+ * these terms run through the per-lane stage kernel (slower). */
 enum { FP_F_BUOYANCY = 1, FP_F_STRESS = 2, FP_F_ADDED_MASS = 4, FP_F_SAFFMAN = 8 };
 
 /* Create a context bound to a HIP stream (hipStream_t, may be NULL for the

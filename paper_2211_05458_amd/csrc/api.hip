@@ -735,7 +735,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
         for (int k = 0; k < 6; ++k) Lc.ev[k] = take_event(c);
       HIPCHK(c, launch_stage(Lc, s));
       if (c->timing) {
-        if (Lc.tasks && Lc.ev[0] && Lc.ev[1]) c->recs.push_back({1, Lc.ev[0], Lc.ev[1]});
+        if (stage_uses_tasks(Lc) && Lc.ev[0] && Lc.ev[1]) c->recs.push_back({1, Lc.ev[0], Lc.ev[1]});
         if (Lc.ev[2] && Lc.ev[3]) c->recs.push_back({5, Lc.ev[2], Lc.ev[3]});
         if (Lc.ev[4] && Lc.ev[5]) c->recs.push_back({6, Lc.ev[4], Lc.ev[5]});
       }

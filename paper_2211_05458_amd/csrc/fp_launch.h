@@ -30,6 +30,7 @@ struct StageLaunch {
   hipEvent_t ev[6];         // optional (start, end) pairs around the elem, lane and track kernels
 };
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
+bool stage_uses_tasks(const StageLaunch& L);   // k_stage_elem runs (else all particles go per lane)
 hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int32_t* tcount, int32_t* tstart,
                         int32_t* sums, void* tasks, int32_t* ntask, int64_t max_tasks, hipStream_t s);
 size_t task_bytes();

@@ -101,7 +101,7 @@ struct Queues {
 // Four wavefronts per SIMD (at most 128 VGPRs): the Newton and interpolation
 // loops wait on LDS reads, and the fourth wavefront hides more of that latency
 // than the few spilled registers cost.
-template <int NN, int NG, typename UT, bool MIXED, bool MLP>
+template <int NN, int NG, typename UT, bool MIXED, bool MLP, bool FORCES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_stage_elem(MeshView m, const double* __restrict__ X,
                                                     const double* __restrict__ XN, const UT* __restrict__ U,
                                                     const FaceRec* __restrict__ faces, const Task* __restrict__ tasks,
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
         double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
         double xe[3];
-        stage_update<NN, NG, UT, MIXED, false>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
+        stage_update<NN, NG, UT, MIXED, FORCES>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
         const FaceRec* Fe = faces + (size_t)e * 6;
         bool any = false;
         // reference-space localisation: a segment that cannot reach a
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // per-lane stage for the straggler queue (list != null) or all n particles;
-// every updated particle goes to the tracking queue
+// updated particles whose segment touches a face box go to the tracking queue
 template <int NN, int NG, typename UT, bool MIXED, bool MLP>
 __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* __restrict__ list, int64_t n_all,
                                                     Particles P, Fluid fl, StepParams sp, Queues q,
@@ -268,10 +268,16 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
             P.kx[k * cap + p] = kx[k];
             P.kv[k * cap + p] = kv[k];
           }
+          // the same prefilter as the element kernel: reference-space skip,
+          // then the bounding boxes of the element's faces
           const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
                             (xe[2] - x[2]) * (xe[2] - x[2]);
           const double ds = m.dsafe[e];
-          trk = !(sp.refspace && L2 < ds * ds);
+          if (!(sp.refspace && L2 < ds * ds)) {
+            const FaceRec* Fe = m.faces + (size_t)e * 6;
+#pragma unroll 1
+            for (int f = 0; f < 6 && !trk; ++f) trk = bbox_hit(Fe[f], x, xe);
+          }
           xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
         }
       }
@@ -370,6 +376,10 @@ size_t task_bytes() { return sizeof(Task); }
 
 #include "fp_shapes.h"
 
+// the element kernel runs when tasks exist (with the extra forces it has an
+// instantiation of its own, except together with the learned guess)
+bool stage_uses_tasks(const StageLaunch& L) { return L.tasks != nullptr && (L.sp.forces == 0 || !L.mlp); }
+
 template <int NN, int NG, typename UT, bool MIXED, bool MLP>
 static void run_stage(const StageLaunch& L, hipStream_t s) {
   const MeshView& m = L.m;
@@ -377,13 +387,16 @@ static void run_stage(const StageLaunch& L, hipStream_t s) {
   k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   int64_t lane_blocks;
   auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
-  // the extra forces run through the per-lane kernel, which keeps their
-  // registers out of the element kernel
-  if (L.tasks && !L.sp.forces) {
+  if (stage_uses_tasks(L)) {
     int64_t waves = (int64_t)m.E + L.P.cap / 64 + 1;
     rec(0);
-    k_stage_elem<NN, NG, UT, MIXED, MLP><<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(
-        m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (!MLP && L.sp.forces)
+      k_stage_elem<NN, NG, UT, MIXED, false, true><<<grid, 256, 0, s>>>(
+          m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
+    else
+      k_stage_elem<NN, NG, UT, MIXED, MLP, false><<<grid, 256, 0, s>>>(
+          m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
     rec(1);
     lane_blocks = std::min<int64_t>((L.n + 255) / 256, 256);
     rec(2);
