@@ -50,7 +50,9 @@ enum fp_err {
   FP_WDT = 1        /* warning: dt exceeds the stability bound of the drag term */
 };
 typedef enum { FP_F32 = 0, FP_F64 = 1 } fp_dtype;
-typedef enum { FP_BC_INTERNAL = 0, FP_BC_OPEN = 1, FP_BC_REFLECT = 2, FP_BC_PERIODIC = 3 } fp_bc;
+/* FP_BC_MORTAR: the big side of a non-conforming face (Sec. 3.2.3), matched
+ * by two or four small faces of neighbouring elements (fp_mesh_desc.mortar) */
+typedef enum { FP_BC_INTERNAL = 0, FP_BC_OPEN = 1, FP_BC_REFLECT = 2, FP_BC_PERIODIC = 3, FP_BC_MORTAR = 4 } fp_bc;
 /* per-particle status (not errors) */
 enum { FP_ACTIVE = 0, FP_OPEN_EXIT = 1, FP_LOST_NEWTON = 2, FP_LOST_TRACK = 3,
        FP_MAX_CROSS = 4, FP_REJECTED = 5 };
@@ -68,6 +70,12 @@ typedef struct {
   const double* periodic_shift;/* [n_elem][6][3], added to a particle crossing a periodic face */
   int32_t n_dg;                /* DG degree N, 1..7 */
   int32_t dg_nodes;            /* 0: Legendre-Gauss, 1: Legendre-Gauss-Lobatto */
+  int32_t n_mortar;            /* number of big mortar faces (0: conforming mesh) */
+  const int32_t* mortar;       /* [n_mortar][4][2]: (element, local face) of the small faces that tile
+                                  big face m, (-1, -1) where unused (2:1); may be NULL if n_mortar = 0.
+                                  A big face has bc FP_BC_MORTAR and nbr_elem = m (nbr_face unused);
+                                  each small face is FP_BC_INTERNAL with the big element and face as its
+                                  neighbour.  The small faces must tile the big one geometrically. */
 } fp_mesh_desc;
 
 /* Fluid and particle-material constants (Sec. 2.1, 2.2). */

@@ -90,6 +90,8 @@ def _declare(L):
     L.or_deposit.restype = I
     L.or_deposit.argtypes = [P, P, I, D, P, I, I, P]
     L.or_fluid_grad.argtypes = [P, I, P, P, P]
+    L.or_set_mortar.argtypes = [P, I, P]
+    L.or_set_mortar.restype = I
     L.or_particle_accel.argtypes = [P, I, I, P, P, P, D, P, P, P]
     L.or_mlp_n_weights.restype = I64
     L.or_mlp_features.argtypes = [P, I, P, P]
@@ -211,6 +213,12 @@ class Oracle:
         self.ctx = L.or_create(self.E, mesh.n_geo, *[_p(a) for a in self._keep], N, dg_nodes)
         if not self.ctx:
             raise ValueError("oracle: invalid mesh")
+        mortar = getattr(mesh, "mortar", None)
+        if mortar is not None and len(mortar):
+            tab = np.ascontiguousarray(mortar, np.int32)
+            self._keep.append(tab)
+            if L.or_set_mortar(self.ctx, int(tab.shape[0]), _p(tab)) != 0:
+                raise ValueError("oracle: inconsistent mortar table")
         self.U = None
         if U is not None:
             self.set_fluid(U, mu, kappa, rho_p)

@@ -69,6 +69,9 @@ struct or_ctx {
   int *bstart, *blist;
   double *elo, *ehi;      /* padded element AABB [E][3] */
   double *dsafe;          /* [E] lower bound of the distance to a boundary face */
+  /* non-conforming faces: per big mortar face, (small element, face) x 4 */
+  int n_mortar;
+  int32_t *mortar;
   /* fluid */
   const double *U;
   double mu, kappa, rho_p;
@@ -1384,7 +1387,7 @@ void or_destroy(or_ctx* c) {
   free(c->X); free(c->nbr_elem); free(c->nbr_face); free(c->bc); free(c->shift);
   free(c->xnode); free(c->vol); free(c->hE); free(c->cp); free(c->ftype); free(c->fframe);
   free(c->forig); free(c->flo); free(c->fhi); free(c->fdiam); free(c->bstart); free(c->blist);
-  free(c->elo); free(c->ehi); free(c->dsafe);
+  free(c->elo); free(c->ehi); free(c->dsafe); free(c->mortar);
   free(c->x); free(c->v); free(c->kx); free(c->kv); free(c->d); free(c->xi); free(c->elem);
   free(c->hits); free(c->status); free(c->mlp_w); free(c->mlp_flag);
   free(c);
@@ -1533,6 +1536,45 @@ static void track(or_ctx* c, int64_t p, double* xs_in, double* xe, double* v, do
       excl = (c->ftype[ne * 6 + nf] == OR_FACE_PLANAR) ? nf : -1;
       entry = (c->ftype[ne * 6 + nf] == OR_FACE_PLANAR) ? -1 : nf;
       for (int q = 0; q < 3; ++q) xs[q] = xh[q];
+    } else if (bc == OR_BC_MORTAR) {
+      /* Non-conforming side (Sec. 3.2.3): the big face is matched by two or
+       * four small faces of neighbouring elements.  As in the paper, the
+       * trajectory is inverted (from the leg end back towards its start) and
+       * intersected with the small faces: a root where the inverted path
+       * leaves a small element is where the forward path enters it.  Of those
+       * roots the one nearest the big-face crossing (alpha = best) is the
+       * crossing; the particle continues from it in that small element.  If
+       * none is found (rounding at the seam of two small faces) the leg ends
+       * in the big element and the next location step finds the element. */
+      int m = c->nbr_elem[fid];
+      double tb[3] = {-t[0], -t[1], -t[2]};
+      double bd = INFINITY, sa = 0.0;
+      int se = -1, sf = -1;
+      for (int j = 0; j < 4; ++j) {
+        int s = c->mortar[m * 8 + 2 * j], fs = c->mortar[m * 8 + 2 * j + 1];
+        if (s < 0) continue;
+        int sfid = s * 6 + fs;
+        double al[8], uv[16];
+        int nr = (c->ftype[sfid] == OR_FACE_CURVED)
+                     ? bezier_band(c->ng, c->cp + (size_t)sfid * c->ng * c->ng * 3, xe, tb, -1e-9 * c->fdiam[sfid],
+                                   L + 1e-9 * c->fdiam[sfid], al, uv, 8)
+                     : or_face_intersect(c, s, fs, xe, tb, al, uv, 8);
+        for (int r = 0; r < nr; ++r) {
+          double pad = 1e-9 * c->fdiam[sfid];
+          if (!(al[r] >= -pad && al[r] <= L + pad)) continue;
+          if (fabs(uv[2 * r]) > 1.0 + UV_EPS || fabs(uv[2 * r + 1]) > 1.0 + UV_EPS) continue;
+          double nrm[3];
+          face_normal(c, sfid, uv[2 * r], uv[2 * r + 1], nrm);
+          if (!(FACE_SIGN[fs] * dot3(nrm, tb) > 0.0)) continue;
+          double a = L - al[r];
+          if (fabs(a - best) < bd) { bd = fabs(a - best); sa = a; se = s; sf = fs; }
+        }
+      }
+      if (se < 0) { for (int q = 0; q < 3; ++q) xs[q] = xh[q]; excl = -1; entry = bf; continue; }
+      e = se;
+      excl = (c->ftype[se * 6 + sf] == OR_FACE_PLANAR) ? sf : -1;
+      entry = (c->ftype[se * 6 + sf] == OR_FACE_PLANAR) ? -1 : sf;
+      for (int q = 0; q < 3; ++q) xs[q] = xs[q] + sa * t[q];
     } else if (bc == 2) {
       double nrm[3];
       face_normal(c, fid, bu, bv, nrm);
@@ -1600,6 +1642,34 @@ static int recover_elem(or_ctx* c, int* e, double* x, double* xi, int max_it, in
 }
 
 double or_boundary_distance(const or_ctx* c, int e) { return c->dsafe[e]; }
+
+/* Non-conforming (mortar) faces: table[m][4][2] lists the (element, local
+ * face) of the small faces that tile big face m, (-1, -1) where unused; a big
+ * face has bc OR_BC_MORTAR and nbr_elem = m, each small face bc internal with
+ * the big element and face as neighbour.  Returns 0, or -1 on an inconsistent
+ * table (then nothing is stored). */
+int or_set_mortar(or_ctx* c, int n, const int32_t* table) {
+  for (int m = 0; m < n; ++m) {
+    int big = -1, nsmall = 0;
+    for (int e = 0; e < c->E && big < 0; ++e)
+      for (int f = 0; f < 6; ++f)
+        if (c->bc[e * 6 + f] == OR_BC_MORTAR && c->nbr_elem[e * 6 + f] == m) { big = e * 6 + f; break; }
+    if (big < 0) return -1;
+    for (int j = 0; j < 4; ++j) {
+      int s = table[m * 8 + 2 * j], fs = table[m * 8 + 2 * j + 1];
+      if (s < 0) continue;
+      if (s >= c->E || fs < 0 || fs > 5) return -1;
+      if (c->bc[s * 6 + fs] != 0 || c->nbr_elem[s * 6 + fs] * 6 + c->nbr_face[s * 6 + fs] != big) return -1;
+      nsmall++;
+    }
+    if (nsmall != 2 && nsmall != 4) return -1;
+  }
+  free(c->mortar);
+  c->mortar = (int32_t*)malloc(sizeof(int32_t) * 8 * (n > 0 ? n : 1));
+  memcpy(c->mortar, table, sizeof(int32_t) * 8 * n);
+  c->n_mortar = n;
+  return 0;
+}
 
 void or_default_opts(or_step_opts* o) {
   memset(o, 0, sizeof(*o));

@@ -28,6 +28,9 @@ typedef struct or_ctx or_ctx;
 enum { OR_ACTIVE = 0, OR_OPEN_EXIT = 1, OR_LOST_NEWTON = 2, OR_LOST_TRACK = 3,
        OR_MAX_CROSS = 4, OR_REJECTED = 5 };
 enum { OR_FACE_PLANAR = 0, OR_FACE_BILINEAR = 1, OR_FACE_CURVED = 2 };
+/* face boundary codes: 0 internal, 1 open, 2 reflective, 3 periodic, 4 big side of a mortar */
+enum { OR_BC_MORTAR = 4 };
+int or_set_mortar(or_ctx*, int n_mortar, const int32_t* table /*[n][4][2] (element, face), -1 unused*/);
 
 /* basis ------------------------------------------------------------------ */
 void or_gauss_nodes(int n, double* x, double* w);          /* Legendre-Gauss, n points */

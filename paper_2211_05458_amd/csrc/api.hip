@@ -17,7 +17,8 @@ struct fp_ctx {
   bool mesh_ok = false;
   int E = 0, n_geo = 0, ng = 0, N = 0, n = 0, dg_nodes = 0;
   std::vector<double> X, shift, elo, ehi, dsafe;
-  std::vector<int32_t> nbr_elem, nbr_face, bstart, blist;
+  std::vector<int32_t> nbr_elem, nbr_face, bstart, blist, mortar;
+  int n_mortar = 0;
   std::vector<int8_t> bc;
   std::vector<double> Minv;
   double blo[3], bdx[3];
@@ -206,7 +207,8 @@ struct Timed {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, nbr_elem, nbr_face, bc, shift, bstart, blist, mlp_flag, stats,
+  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
+      mlp_flag, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, part[2], total;
   size_t part_bytes;
@@ -227,6 +229,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.ehi = take(E * 3 * 8);
   L.nbox = take(E * 6 * 8);
   L.dsafe = take(E * 8);
+  L.mortar = take(std::max<size_t>(1, c->mortar.size()) * 4);
   L.nbr_elem = take(E * 6 * 4);
   L.nbr_face = take(E * 6 * 4);
   L.bc = take(E * 6);
@@ -427,17 +430,49 @@ int fp_init_mesh(fp_ctx* c, const fp_mesh_desc* d) {
   if (!supported(d->n_dg + 1, d->n_geo + 1))
     return fail(c, FP_EINVAL, "fp_init_mesh: no compiled kernels for this (N, Ngeo)");
   int E = d->n_elem;
-  // neighbour reciprocity
+  const int NM = d->n_mortar;
+  if (NM < 0 || (NM > 0 && !d->mortar)) return fail(c, FP_EINVAL, "fp_init_mesh: bad mortar table");
+  // small face (e, f) listed under big mortar face m
+  auto listed = [&](int m, int e, int f) {
+    for (int j = 0; j < 4; ++j)
+      if (d->mortar[m * 8 + 2 * j] == e && d->mortar[m * 8 + 2 * j + 1] == f) return true;
+    return false;
+  };
+  // neighbour reciprocity (a small face points to its big face, which lists it)
+  std::vector<int> mortar_owner(NM, -1);
   for (int e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f) {
       int nb = d->nbr_elem[e * 6 + f], nf = d->nbr_face[e * 6 + f], b = d->bc[e * 6 + f];
-      if (b < 0 || b > 3) return fail(c, FP_EMESH, "fp_init_mesh: bad boundary code");
-      if (b == FP_BC_INTERNAL || b == FP_BC_PERIODIC) {
+      if (b < 0 || b > 4) return fail(c, FP_EMESH, "fp_init_mesh: bad boundary code");
+      if (b == FP_BC_MORTAR) {
+        if (nb < 0 || nb >= NM || mortar_owner[nb] >= 0) return fail(c, FP_EMESH, "fp_init_mesh: bad mortar index");
+        mortar_owner[nb] = e * 6 + f;
+      } else if (b == FP_BC_INTERNAL || b == FP_BC_PERIODIC) {
         if (nb < 0 || nb >= E || nf < 0 || nf > 5) return fail(c, FP_EMESH, "fp_init_mesh: bad neighbour");
-        if (d->nbr_elem[nb * 6 + nf] != e || d->nbr_face[nb * 6 + nf] != f)
+        if (d->bc[nb * 6 + nf] == FP_BC_MORTAR) {
+          const int m = d->nbr_elem[nb * 6 + nf];
+          if (b != FP_BC_INTERNAL || m < 0 || m >= NM || !listed(m, e, f))
+            return fail(c, FP_EMESH, "fp_init_mesh: small face not listed by its mortar");
+        } else if (d->nbr_elem[nb * 6 + nf] != e || d->nbr_face[nb * 6 + nf] != f) {
           return fail(c, FP_EMESH, "fp_init_mesh: non-reciprocal neighbour table");
+        }
       }
     }
+  for (int m = 0; m < NM; ++m) {
+    if (mortar_owner[m] < 0) return fail(c, FP_EMESH, "fp_init_mesh: mortar without a big face");
+    int nsmall = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int s = d->mortar[m * 8 + 2 * j], fs = d->mortar[m * 8 + 2 * j + 1];
+      if (s < 0) continue;
+      if (s >= E || fs < 0 || fs > 5 || d->bc[s * 6 + fs] != FP_BC_INTERNAL ||
+          d->nbr_elem[s * 6 + fs] * 6 + d->nbr_face[s * 6 + fs] != mortar_owner[m])
+        return fail(c, FP_EMESH, "fp_init_mesh: mortar lists a face that does not point back");
+      nsmall++;
+    }
+    if (nsmall != 2 && nsmall != 4) return fail(c, FP_EMESH, "fp_init_mesh: a mortar needs 2 or 4 small faces");
+  }
+  c->n_mortar = NM;
+  c->mortar.assign(NM ? d->mortar : nullptr, NM ? d->mortar + (size_t)NM * 8 : nullptr);
   c->E = E; c->n_geo = d->n_geo; c->ng = d->n_geo + 1; c->N = d->n_dg; c->n = d->n_dg + 1;
   c->dg_nodes = d->dg_nodes;
   size_t ng3 = (size_t)c->ng * c->ng * c->ng;
@@ -544,6 +579,8 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   HIPCHK(c, hipMemcpyAsync(b + L.X, c->X.data(), E * ng3 * 3 * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.elo, c->elo.data(), E * 3 * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.dsafe, c->dsafe.data(), E * 8, hipMemcpyHostToDevice, s));
+  if (!c->mortar.empty())
+    HIPCHK(c, hipMemcpyAsync(b + L.mortar, c->mortar.data(), c->mortar.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.ehi, c->ehi.data(), E * 3 * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.nbr_elem, c->nbr_elem.data(), E * 6 * 4, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(b + L.nbr_face, c->nbr_face.data(), E * 6 * 4, hipMemcpyHostToDevice, s));
@@ -567,6 +604,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   m.ehi = (const double*)(b + L.ehi);
   m.nbox = (const double*)(b + L.nbox);
   m.dsafe = (const double*)(b + L.dsafe);
+  m.mortar = (const int32_t*)(b + L.mortar);
   for (int i = 0; i < kMaxNodes; ++i) {
     m.xgeo[i] = i < c->ng ? c->xgeo[i] : 0.0;
     m.cgeo[i] = i < c->ng ? c->cgeo[i] : 0.0;

@@ -1134,7 +1134,7 @@ template <int NG>
 __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
                       int max_cross, int8_t& status, int& hits, int& ncross) {
   constexpr double kBoxTol = 1e-7;
-  enum { NEW_LEG, NEXT_FACE, POP, CLIP, LEG_END, DONE };
+  enum { NEW_LEG, NEXT_FACE, POP, CLIP, LEG_END, MORT_FACE, MORT_END, DONE };
   double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
   // excl: planar face just entered through (no further root possible);
   // entry: non-planar face just entered through, whose root at the entry point
@@ -1144,6 +1144,11 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
   double t[3] = {0, 0, 0}, n1[3] = {0, 0, 0}, n2[3] = {0, 0, 0}, L = 0.0, eps = 0.0;
   double best = 1e300, bu = 0.0, bv = 0.0, amin = 0.0, bmin = 0.0, bmax = 0.0;
   int bf = -1, f = 0;
+  int fl = 0;   // local index of the face under test (its outward-normal sign)
+  // non-conforming side: mortar index, cursor over its small faces, the
+  // big-face crossing and the small-face root nearest it
+  int mort = -1, mj = 0, mbig = -1, ms = -1, mf = -1, mse = -1, msf = -1;
+  double astar = 0.0, mbd = 1e300, msa = 0.0;
   const double* cpf = m.cp;
   double stk[kClipStack][4];
   int sp = 0, budget = 0;
@@ -1153,8 +1158,16 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
   // the element there: tn = t . outward normal > 0 (a root where the path
   // enters, at a tangential touch or the entry point, is not a crossing)
   auto consider = [&](double a, double uu, double vv, double tn) {
-    if (!(a > amin && a <= L)) return;
     if (fabs(uu) > 1.0 + kUVEps || fabs(vv) > 1.0 + kUVEps) return;
+    if (mort >= 0) {
+      // small face of a mortar: a root where the path enters the small element
+      // (where the inverted path leaves it), the one nearest the big-face crossing
+      if (!(a >= bmin && a <= bmax) || !(tn < 0.0)) return;
+      const double dd = fabs(a - astar);
+      if (dd < mbd) { mbd = dd; msa = a; mse = ms; msf = mf; }
+      return;
+    }
+    if (!(a > amin && a <= L)) return;
     if (!(tn > 0.0)) return;
     if (a < best) { best = a; bf = f; bu = uu; bv = vv; }
   };
@@ -1183,6 +1196,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         mode = LEG_END;
       } else {
         const FaceRec& F = m.faces[e * 6 + f];
+        fl = f;
         amin = (f == entry) ? fmax(eps, kEntryRel * F.diam) : eps;
         if (F.type != FACE_CURVED) {
           double al[2], uv[4];
@@ -1210,10 +1224,52 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         }
       }
     }
+    if (mode == MORT_FACE) {
+      // the small faces of the big mortar face just crossed (Sec. 3.2.3)
+      while (mj < 4 && (m.mortar[mort * 8 + 2 * mj] < 0 ||
+                        !bbox_hit(m.faces[m.mortar[mort * 8 + 2 * mj] * 6 + m.mortar[mort * 8 + 2 * mj + 1]], xs, xe)))
+        mj++;
+      if (mj == 4) {
+        mode = MORT_END;
+      } else {
+        ms = m.mortar[mort * 8 + 2 * mj];
+        mf = m.mortar[mort * 8 + 2 * mj + 1];
+        fl = mf;
+        const FaceRec& F = m.faces[ms * 6 + mf];
+        const double pad = 1e-9 * F.diam;
+        bmin = -pad;
+        bmax = L + pad;
+        if (F.type != FACE_CURVED) {
+          double al[2], uv[4];
+          int nr = (F.type == FACE_PLANAR) ? planar_hit(F, xs, t, al, uv) : bilinear_hit(F, xs, t, al, uv);
+          for (int r = 0; r < nr; ++r) {
+            double pu[3], pv[3], nrm[3];
+            for (int k = 0; k < 3; ++k) {
+              pu[k] = F.A[k] * uv[2 * r + 1] + F.B[k];
+              pv[k] = F.A[k] * uv[2 * r] + F.C[k];
+            }
+            cross3(pu, pv, nrm);
+            consider(al[r], uv[2 * r], uv[2 * r + 1], kFaceSign[mf] * dot3(nrm, t));
+          }
+          mj++;
+        } else {
+          cpf = m.cp + (size_t)(ms * 6 + mf) * (NG * NG * 3);
+          stk[0][0] = 0.0; stk[0][1] = 1.0; stk[0][2] = 0.0; stk[0][3] = 1.0;
+          sp = 1;
+          budget = kClipSteps;
+          mode = POP;
+        }
+      }
+    }
     if (mode == POP) {
       if (sp == 0 || budget <= 0) {
-        f++;
-        mode = NEXT_FACE;
+        if (mort >= 0) {
+          mj++;
+          mode = MORT_FACE;
+        } else {
+          f++;
+          mode = NEXT_FACE;
+        }
       } else {
         --sp;
         u0 = stk[sp][0]; u1 = stk[sp][1]; v0 = stk[sp][2]; v1 = stk[sp][3];
@@ -1260,7 +1316,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
             bezier_eval<NG>(cpf, u, vv, pp, pu, pv);
             double r3[3] = {pp[0] - xs[0], pp[1] - xs[1], pp[2] - xs[2]}, nrm[3];
             cross3(pu, pv, nrm);
-            consider(dot3(r3, t), u, vv, kFaceSign[f] * dot3(nrm, t));
+            consider(dot3(r3, t), u, vv, kFaceSign[fl] * dot3(nrm, t));
           } else if (su || sv) {
             const int dir = (su && sv) ? (wu >= wv ? 0 : 1) : (su ? 0 : 1);
             if (dir == 0) {
@@ -1301,6 +1357,15 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
           excl = planar ? nf : -1;
           entry = planar ? -1 : nf;
           xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
+        } else if (bc == BC_MORTAR) {
+          // non-conforming side: find the small face the path enters through
+          mort = F.nbr_elem;
+          mj = 0;
+          mse = -1;
+          mbd = 1e300;
+          astar = best;
+          mbig = bf;
+          mode = MORT_FACE;
         } else if (bc == BC_REFLECT) {
           double nrm[3];
           if (F.type == FACE_CURVED) {
@@ -1332,6 +1397,24 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
           mode = DONE;
         }
       }
+    }
+    if (mode == MORT_END) {
+      if (mse >= 0) {
+        // continue from the small-face crossing in the small element
+        e = mse;
+        const bool planar = m.faces[mse * 6 + msf].type == FACE_PLANAR;
+        excl = planar ? msf : -1;
+        entry = planar ? -1 : msf;
+        xs[0] += msa * t[0]; xs[1] += msa * t[1]; xs[2] += msa * t[2];
+      } else {
+        // no small face found (rounding at a seam): the leg ends in the big
+        // element and the next location step finds the particle
+        xs[0] += astar * t[0]; xs[1] += astar * t[1]; xs[2] += astar * t[2];
+        excl = -1;
+        entry = mbig;
+      }
+      mort = -1;
+      mode = NEW_LEG;
     }
   }
 }

@@ -27,7 +27,7 @@ constexpr int kRecoverHops = 3;      // neighbour hops when a located particle l
 
 enum { ACTIVE = 0, OPEN_EXIT = 1, LOST_NEWTON = 2, LOST_TRACK = 3, MAX_CROSS = 4, REJECTED = 5 };
 enum { FACE_PLANAR = 0, FACE_BILINEAR = 1, FACE_CURVED = 2 };
-enum { BC_INTERNAL = 0, BC_OPEN = 1, BC_REFLECT = 2, BC_PERIODIC = 3 };
+enum { BC_INTERNAL = 0, BC_OPEN = 1, BC_REFLECT = 2, BC_PERIODIC = 3, BC_MORTAR = 4 };
 enum { ST_NEWTON_IT = 0, ST_NEWTON_CALLS, ST_CROSS, ST_HITS, ST_LOST, ST_FALLBACK, ST_STRAG, ST_TRACKQ, ST_RECOVER, ST_N };
 constexpr int kStatSlots = 64;   // each counter is spread over slots (blockIdx % 64) to avoid atomic contention
 
@@ -55,6 +55,7 @@ struct MeshView {
   const double* ehi;
   const double* nbox;     // [E][6] box of the DG nodes (lo xyz, hi xyz)
   const double* dsafe;    // [E] lower bound of the distance to a face that is not internal
+  const int32_t* mortar;  // [n_mortar][4][2] (small element, local face) per big mortar face, -1 unused
   double xgeo[kMaxNodes], cgeo[kMaxNodes];  // geometry nodes, 1/prod(x_i - x_j)
   double xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
   float xdgf[kMaxNodes], cdgf[kMaxNodes];

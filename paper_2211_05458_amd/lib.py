@@ -35,7 +35,8 @@ class FPError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("n_elem", C.c_int32), ("n_geo", C.c_int32), ("X", C.c_void_p),
                 ("nbr_elem", C.c_void_p), ("nbr_face", C.c_void_p), ("bc", C.c_void_p),
-                ("periodic_shift", C.c_void_p), ("n_dg", C.c_int32), ("dg_nodes", C.c_int32)]
+                ("periodic_shift", C.c_void_p), ("n_dg", C.c_int32), ("dg_nodes", C.c_int32),
+                ("n_mortar", C.c_int32), ("mortar", C.c_void_p)]
 
 
 class FluidParams(C.Structure):
@@ -138,7 +139,11 @@ class FlexiPart:
         keep = [np.ascontiguousarray(mesh.X, np.float64), np.ascontiguousarray(mesh.nbr_elem, np.int32),
                 np.ascontiguousarray(mesh.nbr_face, np.int32), np.ascontiguousarray(mesh.bc, np.int8),
                 np.ascontiguousarray(mesh.shift, np.float64)]
-        desc = MeshDesc(self.E, mesh.n_geo, *[_ptr(a) for a in keep], N, dg_nodes)
+        mortar = getattr(mesh, "mortar", None)
+        mortar = np.ascontiguousarray(mortar if mortar is not None else np.zeros((0, 4, 2)), np.int32)
+        keep.append(mortar)
+        desc = MeshDesc(self.E, mesh.n_geo, *[_ptr(a) for a in keep[:5]], N, dg_nodes, int(mortar.shape[0]),
+                        _ptr(mortar) if mortar.shape[0] else None)
         self._check(self.L.fp_init_mesh(self.ctx, C.byref(desc)), "fp_init_mesh")
         sz = C.c_size_t(0)
         self._check(self.L.fp_workspace_size(self.ctx, int(max_particles), C.byref(sz)), "fp_workspace_size")

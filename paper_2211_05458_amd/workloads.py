@@ -37,7 +37,7 @@ RHO_F = 1.2
 P0 = 1.0e5
 RHO_P = 2500.0
 
-BC_INTERNAL, BC_OPEN, BC_REFLECT, BC_PERIODIC = 0, 1, 2, 3
+BC_INTERNAL, BC_OPEN, BC_REFLECT, BC_PERIODIC, BC_MORTAR = 0, 1, 2, 3, 4
 
 VERBOSE = False   # report generation progress on stderr (large workloads)
 
@@ -58,6 +58,7 @@ class Mesh:
     shift: np.ndarray      # [E][6][3] f64
     h: float               # nominal element width
     cells: tuple = ()      # logical lattice size (n1, n2, n3) when structured
+    mortar: np.ndarray = None  # [n_mortar][4][2] i32: (small element, its face) per big mortar face, -1 unused
 
     @property
     def n_elem(self) -> int:
@@ -387,6 +388,113 @@ def config4(n_particles=10_000_000, cells=(48, 24, 48), n_steps=100, seed=1004):
     x, v, d, e = _particles(rng, mesh.cells, n_particles, annulus_logical, field)
     return Workload("config4_annulus%dx%dx%d_N5_Ng6" % tuple(cells), mesh, 5, U, x, v, d, e,
                     dt=1e-3, n_steps=n_steps, rk=1, drag=1, velocity=field)
+
+
+# ----------------------------------------------------------------------------
+# non-conforming mesh (mortar faces)
+# ----------------------------------------------------------------------------
+def _mortar_map(n_geo, amp):
+    if n_geo == 1:
+        # trilinear: twisted (bilinear) faces
+        def phi(s):
+            x, y, z = s[..., 0], s[..., 1], s[..., 2]
+            return np.stack([x + amp * y * z, y + amp * x * z, z + amp * x * y], axis=-1)
+    else:
+        # quadratic: curved faces, reproduced exactly by any geometry degree >= 2
+        def phi(s):
+            x, y, z = s[..., 0], s[..., 1], s[..., 2]
+            return np.stack([x + amp * ((y - 0.5) ** 2 + z * (1.0 - z)), y + amp * x * (2.0 - x) * 0.5,
+                             z + amp * x * y], axis=-1)
+    return phi
+
+
+def mortar_box(n_geo=4, N=3, refine=(2, 2), n_particles=2000, seed=51, amp=0.05, vscale=1.0):
+    """Box [0,2]x[0,1]x[0,1] (logical) with walls all round: a coarse block
+    (x < 1) of 2x2x2 elements and a fine block (x > 1) of 2 x 2ry x 2rz
+    elements.  Each coarse face on x = 1 is a big mortar face matched by
+    ry*rz small faces (refine (2, 2): 4:1, (2, 1): 2:1).  The map is trilinear
+    (n_geo = 1) or quadratic (n_geo >= 2), so every element represents it
+    exactly and the small faces tile the big ones exactly."""
+    rng = np.random.default_rng(seed)
+    ry, rz = refine
+    boxes = []
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                boxes.append(((i / 2, j / 2, k / 2), ((i + 1) / 2, (j + 1) / 2, (k + 1) / 2)))
+    for k in range(2 * rz):
+        for j in range(2 * ry):
+            for i in range(2):
+                lo = (1.0 + i / 2, j / (2 * ry), k / (2 * rz))
+                hi = (1.0 + (i + 1) / 2, (j + 1) / (2 * ry), (k + 1) / (2 * rz))
+                boxes.append((lo, hi))
+    E = len(boxes)
+    lo = np.array([b[0] for b in boxes])
+    hi = np.array([b[1] for b in boxes])
+    phi = _mortar_map(n_geo, amp)
+    ng = n_geo + 1
+    r = np.linspace(-1.0, 1.0, ng)
+    kk, jj, ii = np.meshgrid(r, r, r, indexing="ij")
+    xi = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    X = np.ascontiguousarray(phi(lo[:, None, :] + 0.5 * (xi[None] + 1.0) * (hi - lo)[:, None, :]))
+    nbr_elem = np.full((E, 6), -1, np.int32)
+    nbr_face = np.full((E, 6), -1, np.int32)
+    bc = np.full((E, 6), BC_REFLECT, np.int8)
+    shift = np.zeros((E, 6, 3))
+
+    def rect(e, f):
+        a, side = f // 2, f % 2
+        fr = [b for b in range(3) if b != a]
+        pos = hi[e, a] if side else lo[e, a]
+        return a, pos, (lo[e, fr[0]], hi[e, fr[0]]), (lo[e, fr[1]], hi[e, fr[1]])
+
+    tol = 1e-12
+    mortars = []
+    for e in range(E):
+        for f in range(6):
+            a, pos, u, v = rect(e, f)
+            same, inner, outer = None, [], None
+            for o in range(E):
+                if o == e:
+                    continue
+                fo = 2 * a + (1 - f % 2)
+                ao, po, uo, vo = rect(o, fo)
+                if abs(po - pos) > tol:
+                    continue
+                if abs(uo[0] - u[0]) < tol and abs(uo[1] - u[1]) < tol and abs(vo[0] - v[0]) < tol and \
+                        abs(vo[1] - v[1]) < tol:
+                    same = (o, fo)
+                elif uo[0] >= u[0] - tol and uo[1] <= u[1] + tol and vo[0] >= v[0] - tol and vo[1] <= v[1] + tol:
+                    inner.append((vo[0], uo[0], o, fo))
+                elif u[0] >= uo[0] - tol and u[1] <= uo[1] + tol and v[0] >= vo[0] - tol and v[1] <= vo[1] + tol:
+                    outer = (o, fo)
+            if same is not None:
+                nbr_elem[e, f], nbr_face[e, f], bc[e, f] = same[0], same[1], BC_INTERNAL
+            elif outer is not None:
+                nbr_elem[e, f], nbr_face[e, f], bc[e, f] = outer[0], outer[1], BC_INTERNAL
+            elif inner:
+                inner.sort()
+                tab = np.full((4, 2), -1, np.int32)
+                for q, (_, _, o, fo) in enumerate(inner):
+                    tab[q] = (o, fo)
+                nbr_elem[e, f], nbr_face[e, f], bc[e, f] = len(mortars), -1, BC_MORTAR
+                mortars.append(tab)
+    mesh = Mesh(n_geo, X, nbr_elem, nbr_face, bc, shift, h=0.25, mortar=np.array(mortars, np.int32))
+    field = fourier_field(rng)
+    n = N + 1
+    g = gauss_nodes(n)
+    kk, jj, ii = np.meshgrid(g, g, g, indexing="ij")
+    xq = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    xd = phi(lo[:, None, :] + 0.5 * (xq[None] + 1.0) * (hi - lo)[:, None, :])
+    U = np.ascontiguousarray(conservative(field(xd.reshape(-1, 3)) * vscale).reshape(E, n ** 3, 5)
+                             .transpose(0, 2, 1))
+    e = rng.integers(0, E, size=n_particles)
+    xs = rng.uniform(-1.0, 1.0, size=(n_particles, 3))
+    d = rng.lognormal(mean=-9.2, sigma=0.3, size=n_particles)
+    x = phi(lo[e] + 0.5 * (xs + 1.0) * (hi - lo)[e])
+    v = field(x) * vscale
+    return Workload("mortar_box_ng%d_N%d_%dx%d" % (n_geo, N, ry, rz), mesh, N, U, x, v, d, e.astype(np.int32),
+                    dt=1e-3, n_steps=1, rk=1, drag=1, velocity=field)
 
 
 # ----------------------------------------------------------------------------

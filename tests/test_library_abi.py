@@ -71,3 +71,27 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(lib.FPError):
         lib.load()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_mortar_table_validation_without_gpu():
+    """A non-conforming mesh is accepted with its mortar table; a table that
+    lists a small face of another big face, or a missing table, is rejected."""
+    import numpy as np
+    from paper_2211_05458_amd import lib, workloads as W
+    L = lib.load()
+    ctx = ctypes.c_void_p()
+    assert L.fp_create(ctypes.byref(ctx), None) == 0
+    mesh = W.mortar_box(n_geo=1, N=1, refine=(2, 2), n_particles=1).mesh
+    keep = [np.ascontiguousarray(mesh.X), mesh.nbr_elem.copy(), mesh.nbr_face.copy(), mesh.bc.copy(),
+            np.ascontiguousarray(mesh.shift)]
+    tab = np.ascontiguousarray(mesh.mortar, np.int32)
+    desc = lib.MeshDesc(mesh.n_elem, 1, *[lib._ptr(a) for a in keep], 1, 0, tab.shape[0], lib._ptr(tab))
+    assert L.fp_init_mesh(ctx, ctypes.byref(desc)) == 0
+    wrong = tab.copy()
+    wrong[0, 1] = wrong[1, 1]
+    bad = lib.MeshDesc(mesh.n_elem, 1, *[lib._ptr(a) for a in keep], 1, 0, wrong.shape[0], lib._ptr(wrong))
+    assert L.fp_init_mesh(ctx, ctypes.byref(bad)) == lib.FP_EMESH
+    bad = lib.MeshDesc(mesh.n_elem, 1, *[lib._ptr(a) for a in keep], 1, 0, 0, None)
+    assert L.fp_init_mesh(ctx, ctypes.byref(bad)) == lib.FP_EMESH
+    L.fp_destroy(ctx)
