@@ -80,7 +80,7 @@ def bytes_per_particle_stage(n, ng, ppe):
 
 
 def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False, tracking=0, forces=0,
-            gravity=(0.0, 0.0, 0.0)):
+            gravity=(0.0, 0.0, 0.0), sort_every=1):
     """Push w's particles, run `warmup` untimed then `steps` timed fp_step(dt, 1)
     calls (each followed by deposit(g) if given); returns timings and the state."""
     import numpy as np
@@ -91,7 +91,7 @@ def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None,
     st, nrej = g.push(w.x, w.v, w.d, w.elem_hint)
     n_active = int((st == 0).sum())
     n_flagged = g.mlp_set_weights(weights) if weights is not None else 0
-    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=1, guess=guess, tracking=tracking,
+    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=sort_every, guess=guess, tracking=tracking,
                 forces=forces, gravity=gravity)
     for _ in range(warmup):
         g.step(w.dt, 1, **opts)
@@ -261,6 +261,38 @@ def bench_twoway(args):
     print(json.dumps(out))
 
 
+def bench_mortar(args):
+    """Non-conforming mesh: a coarse block of 16^3 curved elements (Ngeo=4)
+    against a fine block refined 4:1 across the interface (16x32x32), DG N=5,
+    walls all round, 1e6 particles, FP64.  Every coarse face on the interface
+    is a big mortar face."""
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+    n = args.particles or 1_000_000
+    K, Wm = args.steps or 100, args.warmup
+    print("[bench] generating mortar workload", file=sys.stderr, flush=True)
+    w = W.mortar_box(n_geo=4, N=5, refine=(2, 2), n_particles=n, cells=(16, 16, 16), seed=1006)
+    U64 = torch.from_numpy(w.U).cuda()
+    runs = {}
+    for name, tr in (("fp64", 0), ("fp64_refspace", 1)):
+        print("[bench] run", name, file=sys.stderr, flush=True)
+        runs[name] = run_gpu(w, U64, 0, K, Wm, tracking=tr)
+    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
+           "value": summary(runs["fp64"], K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
+           "warmup": Wm, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "non-conforming box: 16^3 coarse + 16x32x32 fine curved elements (4:1 mortar "
+                                  "interface, %d big faces), Ngeo=4, DG N=5, %d particles, Schiller-Naumann, "
+                                  "3-stage LSERK, dt=1e-3, FP64" % (len(w.mesh.mortar), n),
+                      "elements": w.mesh.n_elem}}
+    for k, r in runs.items():
+        out[k] = summary(r, K)
+        out[k].update({"crossings": r["stats"]["crossings"], "wall_hits": r["stats"]["wall_hits"],
+                       "recovered": r["stats"]["recovered"], "active_end": r["active_end"]})
+    out["fp64_refspace"].update(pos_error(runs["fp64"], runs["fp64_refspace"], w.mesh.h))
+    print(json.dumps(out))
+
+
 def copy_calibration(gib=2, reps=5):
     """Device-to-device copy of a known byte count (counter calibration)."""
     import torch
@@ -280,13 +312,14 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--particles", type=int, default=None)
-    ap.add_argument("--workload", choices=["curved32", "annulus", "precision", "twoway"], default="curved32",
+    ap.add_argument("--workload", choices=["curved32", "annulus", "precision", "twoway", "mortar"], default="curved32",
                     help="curved32: the benchmark line; the others measure the remaining workloads")
     ap.add_argument("--epochs", type=int, default=20, help="learned-guess training epochs (annulus)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-refspace", action="store_true", help="skip the reference-space localisation run")
     ap.add_argument("--no-forces", action="store_true", help="skip the extra-forces run")
+    ap.add_argument("--sort-every", type=int, default=1, help="counting sort by element every k steps")
     ap.add_argument("--cpu-every", type=int, default=25, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
@@ -302,7 +335,8 @@ def main():
     from paper_2211_05458_amd import workloads as W
     W.VERBOSE = True
     if args.workload != "curved32":
-        {"annulus": bench_annulus, "precision": bench_precision, "twoway": bench_twoway}[args.workload](args)
+        {"annulus": bench_annulus, "precision": bench_precision, "twoway": bench_twoway,
+         "mortar": bench_mortar}[args.workload](args)
         return
     args.steps = args.steps or 100
     args.particles = args.particles or 1_000_000
@@ -316,7 +350,7 @@ def main():
     n, ng = w.N + 1, w.mesh.n_geo + 1
     U64 = torch.from_numpy(w.U).cuda()
     print("[bench] FP64 run", file=sys.stderr, flush=True)
-    r64 = run_gpu(w, U64, 0, args.steps, args.warmup)
+    r64 = run_gpu(w, U64, 0, args.steps, args.warmup, sort_every=args.sort_every)
     K = args.steps
     value = r64["n_active"] * K / (r64["ms"] * 1e-3)
     stages = 3

@@ -605,6 +605,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   m.nbox = (const double*)(b + L.nbox);
   m.dsafe = (const double*)(b + L.dsafe);
   m.mortar = (const int32_t*)(b + L.mortar);
+  m.n_mortar = c->n_mortar;
   for (int i = 0; i < kMaxNodes; ++i) {
     m.xgeo[i] = i < c->ng ? c->xgeo[i] : 0.0;
     m.cgeo[i] = i < c->ng ? c->cgeo[i] : 0.0;

@@ -1130,7 +1130,7 @@ __device__ __forceinline__ bool outside_band(const double* q, double amin, doubl
 // test different faces, need different iteration counts or cross different
 // numbers of faces all share the clipping iteration that dominates the cost,
 // instead of the wavefront running every face to the slowest lane.
-template <int NG>
+template <int NG, bool MORT>
 __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
                       int max_cross, int8_t& status, int& hits, int& ncross) {
   constexpr double kBoxTol = 1e-7;
@@ -1159,7 +1159,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
   // enters, at a tangential touch or the entry point, is not a crossing)
   auto consider = [&](double a, double uu, double vv, double tn) {
     if (fabs(uu) > 1.0 + kUVEps || fabs(vv) > 1.0 + kUVEps) return;
-    if (mort >= 0) {
+    if (MORT && mort >= 0) {
       // small face of a mortar: a root where the path enters the small element
       // (where the inverted path leaves it), the one nearest the big-face crossing
       if (!(a >= bmin && a <= bmax) || !(tn < 0.0)) return;
@@ -1224,7 +1224,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         }
       }
     }
-    if (mode == MORT_FACE) {
+    if (MORT && mode == MORT_FACE) {
       // the small faces of the big mortar face just crossed (Sec. 3.2.3)
       while (mj < 4 && (m.mortar[mort * 8 + 2 * mj] < 0 ||
                         !bbox_hit(m.faces[m.mortar[mort * 8 + 2 * mj] * 6 + m.mortar[mort * 8 + 2 * mj + 1]], xs, xe)))
@@ -1263,7 +1263,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
     }
     if (mode == POP) {
       if (sp == 0 || budget <= 0) {
-        if (mort >= 0) {
+        if (MORT && mort >= 0) {
           mj++;
           mode = MORT_FACE;
         } else {
@@ -1357,7 +1357,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
           excl = planar ? nf : -1;
           entry = planar ? -1 : nf;
           xs[0] = xh[0]; xs[1] = xh[1]; xs[2] = xh[2];
-        } else if (bc == BC_MORTAR) {
+        } else if (MORT && bc == BC_MORTAR) {
           // non-conforming side: find the small face the path enters through
           mort = F.nbr_elem;
           mj = 0;
@@ -1398,7 +1398,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         }
       }
     }
-    if (mode == MORT_END) {
+    if (MORT && mode == MORT_END) {
       if (mse >= 0) {
         // continue from the small-face crossing in the small element
         e = mse;

@@ -56,6 +56,7 @@ struct MeshView {
   const double* nbox;     // [E][6] box of the DG nodes (lo xyz, hi xyz)
   const double* dsafe;    // [E] lower bound of the distance to a face that is not internal
   const int32_t* mortar;  // [n_mortar][4][2] (small element, local face) per big mortar face, -1 unused
+  int32_t n_mortar;
   double xgeo[kMaxNodes], cgeo[kMaxNodes];  // geometry nodes, 1/prod(x_i - x_j)
   double xdg[kMaxNodes], cdg[kMaxNodes], wdg[kMaxNodes];
   float xdgf[kMaxNodes], cdgf[kMaxNodes];

@@ -297,7 +297,9 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
   wave_add(stats + ST_LOST * kStatSlots, nlost);
 }
 
-template <int NG>
+// MORT: the mesh has non-conforming (mortar) faces; conforming meshes run the
+// variant without that part of the state machine (fewer registers)
+template <int NG, bool MORT>
 __global__ __launch_bounds__(256) void k_track(MeshView m, Particles P, Queues q, StepParams sp,
                                                unsigned long long* stats) {
   const int64_t count = q.counters[1];
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(256) void k_track(MeshView m, Particles P, Queues q
     double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
     int e = P.elem[p], e0 = e, h = 0, nc = 0;
     int8_t st = ACTIVE;
-    track<NG>(m, e, xs, xe, v, kx, kv, sp.max_cross, st, h, nc);
+    track<NG, MORT>(m, e, xs, xe, v, kx, kv, sp.max_cross, st, h, nc);
     ncross += nc;
     nhits += h;
     if (nc || st != ACTIVE) {
@@ -412,7 +414,8 @@ static void run_stage(const StageLaunch& L, hipStream_t s) {
   }
   int64_t trk_blocks = std::max<int64_t>(1, std::min<int64_t>((L.n + 255) / 256, 1024));
   rec(4);
-  k_track<NG><<<dim3((unsigned)trk_blocks), 256, 0, s>>>(m, L.P, q, L.sp, L.stats);
+  if (m.n_mortar > 0) k_track<NG, true><<<dim3((unsigned)trk_blocks), 256, 0, s>>>(m, L.P, q, L.sp, L.stats);
+  else k_track<NG, false><<<dim3((unsigned)trk_blocks), 256, 0, s>>>(m, L.P, q, L.sp, L.stats);
   rec(5);
 }
 

@@ -408,29 +408,31 @@ def _mortar_map(n_geo, amp):
     return phi
 
 
-def mortar_box(n_geo=4, N=3, refine=(2, 2), n_particles=2000, seed=51, amp=0.05, vscale=1.0):
+def mortar_box(n_geo=4, N=3, refine=(2, 2), n_particles=2000, seed=51, amp=0.05, vscale=1.0, cells=(2, 2, 2)):
     """Box [0,2]x[0,1]x[0,1] (logical) with walls all round: a coarse block
-    (x < 1) of 2x2x2 elements and a fine block (x > 1) of 2 x 2ry x 2rz
-    elements.  Each coarse face on x = 1 is a big mortar face matched by
-    ry*rz small faces (refine (2, 2): 4:1, (2, 1): 2:1).  The map is trilinear
-    (n_geo = 1) or quadratic (n_geo >= 2), so every element represents it
-    exactly and the small faces tile the big ones exactly."""
+    (x < 1) of cx x cy x cz elements and a fine block (x > 1) of
+    cx x (ry cy) x (rz cz) elements.  Each coarse face on x = 1 is a big mortar
+    face matched by ry*rz small faces (refine (2, 2): 4:1, (2, 1): 2:1), listed
+    z-major.  Elements: coarse i + cx (j + cy k), then fine.  The map is
+    trilinear (n_geo = 1) or quadratic (n_geo >= 2), so every element
+    represents it exactly and the small faces tile the big ones exactly."""
     rng = np.random.default_rng(seed)
     ry, rz = refine
-    boxes = []
-    for k in range(2):
-        for j in range(2):
-            for i in range(2):
-                boxes.append(((i / 2, j / 2, k / 2), ((i + 1) / 2, (j + 1) / 2, (k + 1) / 2)))
-    for k in range(2 * rz):
-        for j in range(2 * ry):
-            for i in range(2):
-                lo = (1.0 + i / 2, j / (2 * ry), k / (2 * rz))
-                hi = (1.0 + (i + 1) / 2, (j + 1) / (2 * ry), (k + 1) / (2 * rz))
-                boxes.append((lo, hi))
-    E = len(boxes)
-    lo = np.array([b[0] for b in boxes])
-    hi = np.array([b[1] for b in boxes])
+    cx, cy, cz = cells
+    fx, fy, fz = cx, ry * cy, rz * cz
+    nc, nf_ = cx * cy * cz, fx * fy * fz
+    E = nc + nf_
+
+    def block(n1, n2, n3, x0, dx):
+        idx = np.arange(n1 * n2 * n3)
+        i, j, k = idx % n1, (idx // n1) % n2, idx // (n1 * n2)
+        lo = np.stack([x0 + i * dx[0], j * dx[1], k * dx[2]], axis=1)
+        return lo, lo + np.asarray(dx), (i, j, k)
+
+    loc, hic, (ic, jc, kc) = block(cx, cy, cz, 0.0, (1.0 / cx, 1.0 / cy, 1.0 / cz))
+    lof, hif, (i_f, j_f, k_f) = block(fx, fy, fz, 1.0, (1.0 / fx, 1.0 / fy, 1.0 / fz))
+    lo = np.concatenate([loc, lof])
+    hi = np.concatenate([hic, hif])
     phi = _mortar_map(n_geo, amp)
     ng = n_geo + 1
     r = np.linspace(-1.0, 1.0, ng)
@@ -441,60 +443,48 @@ def mortar_box(n_geo=4, N=3, refine=(2, 2), n_particles=2000, seed=51, amp=0.05,
     nbr_face = np.full((E, 6), -1, np.int32)
     bc = np.full((E, 6), BC_REFLECT, np.int8)
     shift = np.zeros((E, 6, 3))
-
-    def rect(e, f):
-        a, side = f // 2, f % 2
-        fr = [b for b in range(3) if b != a]
-        pos = hi[e, a] if side else lo[e, a]
-        return a, pos, (lo[e, fr[0]], hi[e, fr[0]]), (lo[e, fr[1]], hi[e, fr[1]])
-
-    tol = 1e-12
-    mortars = []
-    for e in range(E):
-        for f in range(6):
-            a, pos, u, v = rect(e, f)
-            same, inner, outer = None, [], None
-            for o in range(E):
-                if o == e:
-                    continue
-                fo = 2 * a + (1 - f % 2)
-                ao, po, uo, vo = rect(o, fo)
-                if abs(po - pos) > tol:
-                    continue
-                if abs(uo[0] - u[0]) < tol and abs(uo[1] - u[1]) < tol and abs(vo[0] - v[0]) < tol and \
-                        abs(vo[1] - v[1]) < tol:
-                    same = (o, fo)
-                elif uo[0] >= u[0] - tol and uo[1] <= u[1] + tol and vo[0] >= v[0] - tol and vo[1] <= v[1] + tol:
-                    inner.append((vo[0], uo[0], o, fo))
-                elif u[0] >= uo[0] - tol and u[1] <= uo[1] + tol and v[0] >= vo[0] - tol and v[1] <= vo[1] + tol:
-                    outer = (o, fo)
-            if same is not None:
-                nbr_elem[e, f], nbr_face[e, f], bc[e, f] = same[0], same[1], BC_INTERNAL
-            elif outer is not None:
-                nbr_elem[e, f], nbr_face[e, f], bc[e, f] = outer[0], outer[1], BC_INTERNAL
-            elif inner:
-                inner.sort()
-                tab = np.full((4, 2), -1, np.int32)
-                for q, (_, _, o, fo) in enumerate(inner):
-                    tab[q] = (o, fo)
-                nbr_elem[e, f], nbr_face[e, f], bc[e, f] = len(mortars), -1, BC_MORTAR
-                mortars.append(tab)
-    mesh = Mesh(n_geo, X, nbr_elem, nbr_face, bc, shift, h=0.25, mortar=np.array(mortars, np.int32))
+    # structured neighbours inside each block
+    for off, (n1, n2, n3), (i, j, k) in ((0, (cx, cy, cz), (ic, jc, kc)), (nc, (fx, fy, fz), (i_f, j_f, k_f))):
+        idx = np.arange(n1 * n2 * n3)
+        cnt, coords, strides = (n1, n2, n3), (i, j, k), (1, n1, n1 * n2)
+        for a in range(3):
+            for side in (0, 1):
+                f = 2 * a + side
+                step = -1 if side == 0 else 1
+                inside = (coords[a] + step >= 0) & (coords[a] + step < cnt[a])
+                nbr_elem[off + idx[inside], f] = off + idx[inside] + step * strides[a]
+                nbr_face[off + idx[inside], f] = 2 * a + (1 - side)
+                bc[off + idx[inside], f] = BC_INTERNAL
+    # the interface x = 1: coarse +x faces are big mortar faces
+    big = np.nonzero(ic == cx - 1)[0]
+    mortar = np.full((len(big), 4, 2), -1, np.int32)
+    for m, e in enumerate(big):
+        q = 0
+        for dz in range(rz):
+            for dy in range(ry):
+                s = nc + 0 + fx * ((ry * jc[e] + dy) + fy * (rz * kc[e] + dz))
+                mortar[m, q] = (s, 0)
+                nbr_elem[s, 0], nbr_face[s, 0], bc[s, 0] = e, 1, BC_INTERNAL
+                q += 1
+        nbr_elem[e, 1], nbr_face[e, 1], bc[e, 1] = m, -1, BC_MORTAR
+    mesh = Mesh(n_geo, X, nbr_elem, nbr_face, bc, shift, h=1.0 / (2 * max(cx, cy, cz)), mortar=mortar)
     field = fourier_field(rng)
     n = N + 1
     g = gauss_nodes(n)
     kk, jj, ii = np.meshgrid(g, g, g, indexing="ij")
     xq = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
-    xd = phi(lo[:, None, :] + 0.5 * (xq[None] + 1.0) * (hi - lo)[:, None, :])
-    U = np.ascontiguousarray(conservative(field(xd.reshape(-1, 3)) * vscale).reshape(E, n ** 3, 5)
-                             .transpose(0, 2, 1))
+    U = np.empty((E, 5, n ** 3))
+    for s0 in range(0, E, 4096):
+        sl = slice(s0, min(E, s0 + 4096))
+        xd = phi(lo[sl, None, :] + 0.5 * (xq[None] + 1.0) * (hi - lo)[sl, None, :])
+        U[sl] = conservative(field(xd.reshape(-1, 3)) * vscale).reshape(-1, n ** 3, 5).transpose(0, 2, 1)
     e = rng.integers(0, E, size=n_particles)
     xs = rng.uniform(-1.0, 1.0, size=(n_particles, 3))
     d = rng.lognormal(mean=-9.2, sigma=0.3, size=n_particles)
     x = phi(lo[e] + 0.5 * (xs + 1.0) * (hi - lo)[e])
     v = field(x) * vscale
-    return Workload("mortar_box_ng%d_N%d_%dx%d" % (n_geo, N, ry, rz), mesh, N, U, x, v, d, e.astype(np.int32),
-                    dt=1e-3, n_steps=1, rk=1, drag=1, velocity=field)
+    return Workload("mortar_box_ng%d_N%d_%dx%d_%dx%dx%d" % (n_geo, N, ry, rz, cx, cy, cz), mesh, N, U, x, v, d,
+                    e.astype(np.int32), dt=1e-3, n_steps=1, rk=1, drag=1, velocity=field)
 
 
 # ----------------------------------------------------------------------------
