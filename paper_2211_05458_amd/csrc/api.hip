@@ -18,6 +18,7 @@ struct fp_ctx {
   int E = 0, n_geo = 0, ng = 0, N = 0, n = 0, dg_nodes = 0;
   std::vector<double> X, shift, elo, ehi, dsafe;
   std::vector<int32_t> nbr_elem, nbr_face, bstart, blist, mortar;
+  int task_tp = 64;          // particles per element task of the last sort
   int n_mortar = 0;
   std::vector<int8_t> bc;
   std::vector<double> Minv;
@@ -249,7 +250,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   size_t pc1 = (size_t)std::max<int64_t>(cap, 1);
   L.tcount = take((E + 1) * 4);
   L.tstart = take((E + 1) * 4);
-  L.tasks = take((E + pc1 / 64 + 2) * task_bytes());
+  L.tasks = take((E + pc1 / kMinTaskParticles + 2) * task_bytes());
   L.qcnt = take(64);
   L.strag = take(pc1 * 4);
   L.trk_p = take(pc1 * 4);
@@ -387,7 +388,8 @@ void boundary_distance(fp_ctx* c) {
   }
 }
 
-int sort_particles(fp_ctx* c) {
+// counting sort by element, then the element tasks of tp particles each
+int sort_particles(fp_ctx* c, int tp) {
   hipStream_t s = c->stream;
   if (c->np == 0) {   // nothing to bucket: no histogram is computed, so no tasks either
     c->tasks_valid = false;
@@ -397,9 +399,10 @@ int sort_particles(fp_ctx* c) {
                         c->sort_sums, s));
   c->cur = 1 - c->cur;
   c->sorts++;
-  HIPCHK(c, launch_tasks(c->sort_count, c->sort_start, c->E, c->tcount, c->tstart, c->sort_sums, c->tasks,
-                         c->qcnt + 4, (int64_t)c->E + c->cap / 64 + 2, s));
+  HIPCHK(c, launch_tasks(c->sort_count, c->sort_start, c->E, tp, c->tcount, c->tstart, c->sort_sums, c->tasks,
+                         c->qcnt + 4, (int64_t)c->E + c->cap / tp + 2, s));
   c->tasks_valid = true;
+  c->task_tp = tp;
   return FP_OK;
 }
 }  // namespace
@@ -749,7 +752,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   for (int st = 0; st < n_steps; ++st) {
     if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
       Timed tm(c, 0);
-      int rc = sort_particles(c);
+      int rc = sort_particles(c, task_particles(c->n, c->ng, o->precision == 1));
       if (rc) return rc;
     }
     for (int i = 0; i < S; ++i) {
@@ -764,6 +767,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
       Lc.mixed = o->precision;
       Lc.mlp = sp.use_mlp;
       Lc.tasks = c->tasks_valid ? c->tasks : nullptr;
+      Lc.task_tp = c->task_tp;
       Lc.ntask = c->qcnt + 4;
       Lc.counters = c->qcnt;
       Lc.strag = c->strag;
@@ -813,8 +817,9 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
     if (per[k] > 0.0 && per[k] <= 2.0 * radius)
       return fail(c, FP_EINVAL, "fp_deposit_source: a period must exceed twice the kernel radius");
   if (c->np == 0) return FP_OK;
-  // gather needs the particles bucketed by their current element
-  int rc = sort_particles(c);
+  // gather needs the particles bucketed by their current element (tasks for
+  // the stage that ran last)
+  int rc = sort_particles(c, c->task_tp);
   if (rc) return rc;
   {
     Timed tm(c, 4);

@@ -446,9 +446,9 @@ __device__ inline int bgm_locate(const MeshView& m, const double* x, double* xi,
 // ---------------------------------------------------------------------------
 // interpolation of the conservative variables (eq. part_interpolation).  The
 // drag law reads density and momentum only (constant viscosity), so the
-// energy, the fifth variable of each element's block, is not interpolated.
+// energy, the fifth variable of each element's block, is not interpolated
+// (kInterpVars).
 // ---------------------------------------------------------------------------
-constexpr int kInterpVars = 4;
 
 template <int NN, typename UT>
 __device__ __forceinline__ void interp(const MeshView& m, const UT* __restrict__ U, const double* xi, double* out) {
@@ -1440,20 +1440,23 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, long long v) {
   if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(dst + (blockIdx.x & (kStatSlots - 1)), (unsigned long long)v);
 }
 
-// workgroup-aggregated queue append (blockDim.x == 256): one atomic per
+// workgroup-aggregated queue append (blockDim.x == 64 * NW): one atomic per
 // workgroup; returns each predicated thread's slot (-1 otherwise).  Must be
 // reached by every thread of the workgroup.
-__device__ __forceinline__ int block_push(int32_t* counter, bool pred, int* sh /* [5] shared */) {
+template <int NW = 4>
+__device__ __forceinline__ int block_push(int32_t* counter, bool pred, int* sh /* [NW + 1] shared */) {
   unsigned long long mask = __ballot(pred);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) sh[wid] = (int)__popcll(mask);
   __syncthreads();
   if (threadIdx.x == 0) {
-    int tot = sh[0] + sh[1] + sh[2] + sh[3];
-    sh[4] = tot ? atomicAdd(counter, tot) : 0;
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += sh[w];
+    sh[NW] = tot ? atomicAdd(counter, tot) : 0;
   }
   __syncthreads();
-  int base = sh[4];
+  int base = sh[NW];
   for (int w = 0; w < wid; ++w) base += sh[w];
   int r = pred ? base + (int)__popcll(mask & ((1ull << lane) - 1ull)) : -1;
   __syncthreads();

@@ -89,6 +89,19 @@ struct Fluid {
   double mu, kappa, rho_p;
 };
 
+// conservative variables the drag law reads (density, momentum): with
+// constant viscosity the energy is never used
+constexpr int kInterpVars = 4;
+
+// particles per element task after the counting sort: two tasks per
+// wavefront, one per half (32), when the stage is mixed and four elements'
+// geometry nodes and FP32 state fit in 27 KB of LDS (three two-wavefront
+// workgroups per SIMD); one task per wavefront (64) otherwise
+__host__ __device__ constexpr int task_particles(int nn, int ng, bool mixed) {
+  return (mixed && 4 * (ng * ng * ng * 3 * 8 + kInterpVars * nn * nn * nn * 4) <= 27 * 1024) ? 32 : 64;
+}
+constexpr int kMinTaskParticles = 32;
+
 // extra terms of the equation of motion (eq. theory:maxey), bit flags
 constexpr int kForceBuoyancy = 1, kForceStress = 2, kForceAddedMass = 4, kForceSaffman = 8;
 constexpr int kForceAll = 15;

@@ -21,6 +21,7 @@ struct StageLaunch {
   int64_t n;
   int mixed, mlp;
   const void* tasks;        // element tasks from the last sort, or null
+  int task_tp;              // particles per task of those tasks
   const int32_t* ntask;
   int32_t* counters;        // queue counters [2]
   int32_t* strag;           // [cap]
@@ -31,7 +32,7 @@ struct StageLaunch {
 };
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
 bool stage_uses_tasks(const StageLaunch& L);   // k_stage_elem runs (else all particles go per lane)
-hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int32_t* tcount, int32_t* tstart,
+hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int tp, int32_t* tcount, int32_t* tstart,
                         int32_t* sums, void* tasks, int32_t* ntask, int64_t max_tasks, hipStream_t s);
 size_t task_bytes();
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s);

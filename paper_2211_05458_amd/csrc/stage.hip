@@ -98,25 +98,38 @@ struct Queues {
   double* trk_x;      // [3][cap] segment start
 };
 
-// Four wavefronts per SIMD (at most 128 VGPRs): the Newton and interpolation
-// loops wait on LDS reads, and the fourth wavefront hides more of that latency
-// than the few spilled registers cost.
+// Tasks of up to 64 particles: one per wavefront, four wavefronts per
+// workgroup, four per SIMD (at most 128 VGPRs: the Newton and interpolation
+// loops wait on LDS reads, and the fourth wavefront hides more of that
+// latency than the few spilled registers cost).  Tasks of up to 32 particles
+// (mixed stage, small elements): two per wavefront, one per half, each with
+// its own element in LDS, two wavefronts per workgroup, three per SIMD:
+// elements hold about 30 particles, so one element per wavefront leaves half
+// of every LDS broadcast and VALU instruction idle.  (Two FP64 elements per
+// wavefront leave room for only two wavefronts per SIMD, which measured
+// slower, and so do FP32 elements of N = 7 or N_geo = 6.)
+constexpr int elem_waves(int tp) { return tp == 64 ? 4 : 2; }
+
 template <int NN, int NG, typename UT, bool MIXED, bool MLP, bool FORCES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_stage_elem(MeshView m, const double* __restrict__ X,
-                                                    const double* __restrict__ XN, const UT* __restrict__ U,
-                                                    const FaceRec* __restrict__ faces, const Task* __restrict__ tasks,
-                                                    const int32_t* __restrict__ ntask, Particles P, Fluid fl,
-                                                    StepParams sp, Queues q, unsigned long long* stats) {
+__global__ __launch_bounds__(64 * elem_waves(task_particles(NN, NG, MIXED)))
+__attribute__((amdgpu_waves_per_eu(task_particles(NN, NG, MIXED) == 64 ? 4 : 3)))
+void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __restrict__ XN, const UT* __restrict__ U,
+                  const FaceRec* __restrict__ faces, const Task* __restrict__ tasks, const int32_t* __restrict__ ntask,
+                  Particles P, Fluid fl, StepParams sp, Queues q, unsigned long long* stats) {
   constexpr int NG3 = NG * NG * NG, NN3 = NN * NN * NN;
-  // the task element's geometry nodes and fluid state, staged once per
-  // wavefront with coalesced vector loads and read as LDS broadcasts by every
-  // Newton iteration and the interpolation; U stays in global memory when both
-  // would not fit three to four wavefronts per SIMD
+  constexpr int TP = task_particles(NN, NG, MIXED), kElemWaves = elem_waves(TP), PER = 64 / TP;
+  constexpr int SLOTS = kElemWaves * PER;
+  // the task element's geometry nodes and fluid state, staged once per task
+  // with coalesced vector loads and read as LDS broadcasts by every Newton
+  // iteration and the interpolation; U stays in global memory when both would
+  // not fit four elements per workgroup in 40 KB
   constexpr bool kStageU = NG3 * 3 * 8 + kInterpVars * NN3 * (int)sizeof(UT) <= 12 * 1024;
-  __shared__ double sX[4][NG3 * 3];
-  __shared__ UT sU[4][kStageU ? kInterpVars * NN3 : 1];
+  __shared__ double sX[SLOTS][NG3 * 3];
+  __shared__ UT sU[SLOTS][kStageU ? kInterpVars * NN3 : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  const int half = (TP == 64) ? 0 : lane / TP, tl = lane % TP, slot = w * PER + half;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kElemWaves + w));
+  const int ti = wid * PER + half;
   const int nt = __builtin_amdgcn_readfirstlane(*ntask);
   int it_sum = 0, calls = 0, fb = 0;
   bool strag = false, trk = false;
@@ -124,31 +137,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   double xs0 = 0, xs1 = 0, xs2 = 0;
   const int64_t cap = P.cap;
   Task t{0, 0, 0, 0};
-  if (wid < nt) {
-    t = tasks[wid];
-    const int e = __builtin_amdgcn_readfirstlane(t.e);
+  if (ti < nt) {
+    t = tasks[ti];
+    const int e = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.e) : t.e;
     const double* Xg = X + (size_t)e * NG3 * 3;
-    for (int i = lane; i < NG3 * 3; i += 64) sX[w][i] = Xg[i];
+    for (int i = tl; i < NG3 * 3; i += TP) sX[slot][i] = Xg[i];
     if (kStageU) {
       const UT* Ug = U + (size_t)e * 5 * NN3;
-      for (int i = lane; i < kInterpVars * NN3; i += 64) sU[w][i] = Ug[i];
+      for (int i = tl; i < kInterpVars * NN3; i += TP) sU[slot][i] = Ug[i];
     }
   }
   __syncthreads();
-  if (wid < nt) {
-    const int e = __builtin_amdgcn_readfirstlane(t.e);
-    const int p0 = __builtin_amdgcn_readfirstlane(t.p0);
-    const int cnt = __builtin_amdgcn_readfirstlane(t.cnt);
-    p = (int64_t)p0 + lane;
-    bool act = lane < cnt && P.status[p] == ACTIVE;
+  if (ti < nt) {
+    const int e = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.e) : t.e;
+    const int p0 = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.p0) : t.p0;
+    const int cnt = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.cnt) : t.cnt;
+    p = (int64_t)p0 + tl;
+    bool act = tl < cnt && P.status[p] == ACTIVE;
     if (act && P.elem[p] != e) {
       strag = true;
       act = false;
     }
     if (act) {
-      const double* Xe = sX[w];
+      const double* Xe = sX[slot];
       const double* XNe = XN + (size_t)e * NN3 * 3;
-      const UT* Ue = kStageU ? sU[w] : U + (size_t)e * 5 * NN3;
+      const UT* Ue = kStageU ? sU[slot] : U + (size_t)e * 5 * NN3;
       double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
       double xi[3];
       if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb) || !inside_ref(xi)) {
@@ -184,12 +197,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
     }
   }
-  __shared__ int sh[5];
-  int s1 = block_push(q.counters + 0, strag, sh);
+  __shared__ int sh[kElemWaves + 1];
+  int s1 = block_push<kElemWaves>(q.counters + 0, strag, sh);
   if (strag) q.strag[s1] = (int32_t)p;
   wave_add(stats + ST_STRAG * kStatSlots, strag ? 1 : 0);
   wave_add(stats + ST_TRACKQ * kStatSlots, trk ? 1 : 0);
-  int s2 = block_push(q.counters + 1, trk, sh);
+  int s2 = block_push<kElemWaves>(q.counters + 1, trk, sh);
   if (trk) {
     q.trk_p[s2] = (int32_t)p;
     q.trk_x[s2] = xs0;
@@ -338,24 +351,24 @@ __global__ void k_reset_counters(int32_t* c) {
   if (threadIdx.x < 2) c[threadIdx.x] = 0;
 }
 
-// tasks of <= 64 particles per element after the counting sort
-__global__ void k_task_count(const int32_t* __restrict__ count, int E, int32_t* tcount) {
+// tasks of <= tp particles per element after the counting sort
+__global__ void k_task_count(const int32_t* __restrict__ count, int E, int tp, int32_t* tcount) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < E) tcount[e] = (count[e] + 63) / 64;
+  if (e < E) tcount[e] = (count[e] + tp - 1) / tp;
   else if (e == E) tcount[E] = 0;
 }
 
 __global__ void k_task_fill(const int32_t* __restrict__ count, const int32_t* __restrict__ start,
-                            const int32_t* __restrict__ tstart, int E, Task* tasks, int32_t* ntask,
+                            const int32_t* __restrict__ tstart, int E, int tp, Task* tasks, int32_t* ntask,
                             int64_t max_tasks) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   int c = count[e], t0 = tstart[e], s0 = start[e];
-  for (int j = 0; 64 * j < c && (int64_t)t0 + j < max_tasks; ++j) {
+  for (int j = 0; tp * j < c && (int64_t)t0 + j < max_tasks; ++j) {
     Task t;
     t.e = e;
-    t.p0 = s0 + 64 * j;
-    t.cnt = min(64, c - 64 * j);
+    t.p0 = s0 + tp * j;
+    t.cnt = min(tp, c - tp * j);
     t.pad = 0;
     tasks[t0 + j] = t;
   }
@@ -364,13 +377,13 @@ __global__ void k_task_fill(const int32_t* __restrict__ count, const int32_t* __
 
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s);
 
-hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int32_t* tcount, int32_t* tstart,
+hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int tp, int32_t* tcount, int32_t* tstart,
                         int32_t* sums, void* tasks, int32_t* ntask, int64_t max_tasks, hipStream_t s) {
   dim3 g((unsigned)((E + 1 + 255) / 256));
-  k_task_count<<<g, 256, 0, s>>>(count, E, tcount);
+  k_task_count<<<g, 256, 0, s>>>(count, E, tp, tcount);
   hipError_t err = scan_i32(tcount, tstart, E + 1, sums, s);
   if (err != hipSuccess) return err;
-  k_task_fill<<<g, 256, 0, s>>>(count, start, tstart, E, (Task*)tasks, ntask, max_tasks);
+  k_task_fill<<<g, 256, 0, s>>>(count, start, tstart, E, tp, (Task*)tasks, ntask, max_tasks);
   return hipGetLastError();
 }
 
@@ -378,9 +391,12 @@ size_t task_bytes() { return sizeof(Task); }
 
 #include "fp_shapes.h"
 
-// the element kernel runs when tasks exist (with the extra forces it has an
-// instantiation of its own, except together with the learned guess)
-bool stage_uses_tasks(const StageLaunch& L) { return L.tasks != nullptr && (L.sp.forces == 0 || !L.mlp); }
+// the element kernel runs when tasks of its size exist (with the extra forces
+// it has an instantiation of its own, except together with the learned guess)
+bool stage_uses_tasks(const StageLaunch& L) {
+  return L.tasks != nullptr && L.task_tp == task_particles(L.m.n, L.m.ng, L.mixed != 0) &&
+         (L.sp.forces == 0 || !L.mlp);
+}
 
 template <int NN, int NG, typename UT, bool MIXED, bool MLP>
 static void run_stage(const StageLaunch& L, hipStream_t s) {
@@ -390,14 +406,17 @@ static void run_stage(const StageLaunch& L, hipStream_t s) {
   int64_t lane_blocks;
   auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
   if (stage_uses_tasks(L)) {
-    int64_t waves = (int64_t)m.E + L.P.cap / 64 + 1;
+    // at most E + cap / tp + 1 tasks, 64 / tp per wavefront
+    constexpr int tp = task_particles(NN, NG, MIXED), nw = elem_waves(tp);
+    const int64_t max_tasks = (int64_t)m.E + L.P.cap / tp + 1;
+    const int64_t waves = (max_tasks * tp + 63) / 64;
     rec(0);
-    const dim3 grid((unsigned)((waves + 3) / 4));
+    const dim3 grid((unsigned)((waves + nw - 1) / nw));
     if (!MLP && L.sp.forces)
-      k_stage_elem<NN, NG, UT, MIXED, false, true><<<grid, 256, 0, s>>>(
+      k_stage_elem<NN, NG, UT, MIXED, false, true><<<grid, 64 * nw, 0, s>>>(
           m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
     else
-      k_stage_elem<NN, NG, UT, MIXED, MLP, false><<<grid, 256, 0, s>>>(
+      k_stage_elem<NN, NG, UT, MIXED, MLP, false><<<grid, 64 * nw, 0, s>>>(
           m, m.X, m.xnode, (const UT*)L.fl.U, m.faces, (const Task*)L.tasks, L.ntask, L.P, L.fl, L.sp, q, L.stats);
     rec(1);
     lane_blocks = std::min<int64_t>((L.n + 255) / 256, 256);
