@@ -320,7 +320,7 @@ def main():
     ap.add_argument("--no-refspace", action="store_true", help="skip the reference-space localisation run")
     ap.add_argument("--no-forces", action="store_true", help="skip the extra-forces run")
     ap.add_argument("--sort-every", type=int, default=1, help="counting sort by element every k steps")
-    ap.add_argument("--cpu-every", type=int, default=25, help="oracle sample: every k-th particle")
+    ap.add_argument("--cpu-every", type=int, default=2, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: a plain device copy of known size, the calibration for HBM counters")
@@ -438,7 +438,7 @@ def main():
                    "elements": w.mesh.n_elem, "particles": w.n_particles, "N": w.N, "n_geo": w.mesh.n_geo},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "k_stage_elem<6,5,double,false,false>", "avg_launch_ms": avg_stage_ms,
+                     "kernel": "k_stage_elem<6,5,double,false,false,false>", "avg_launch_ms": avg_stage_ms,
                      "particles_per_launch": per_launch_particles,
                      "flops_per_particle_stage": fl_ps, "newton_it_per_particle_stage": it_per_ps,
                      "algorithmic_bytes_per_launch": per_launch_bytes,
