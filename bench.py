@@ -417,7 +417,7 @@ def main():
         el = time.perf_counter() - t0
         cpu = {"value": len(idx) * args.cpu_steps / el, "unit": "particle-steps/s", "cores": O.num_threads(),
                "kind": "oracle",
-               "sample": "every %dth particle (%d of %d) for %d steps of the same workload, FP64, "
+               "sample": "one particle in %d (%d of %d) for %d steps of the same workload, FP64, "
                          "%.1f s wall" % (args.cpu_every, len(idx), w.n_particles, args.cpu_steps, el)}
 
     out = {

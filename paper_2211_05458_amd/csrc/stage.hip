@@ -122,8 +122,11 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
   // the task element's geometry nodes and fluid state, staged once per task
   // with coalesced vector loads and read as LDS broadcasts by every Newton
   // iteration and the interpolation; U stays in global memory when both would
-  // not fit four elements per workgroup in 40 KB
-  constexpr bool kStageU = NG3 * 3 * 8 + kInterpVars * NN3 * (int)sizeof(UT) <= 12 * 1024;
+  // not fit four elements per workgroup in 48 KB, or when the geometry nodes
+  // alone take more than 4 KB (N_geo = 6: with U as well, three workgroups per
+  // CU and one wavefront per SIMD)
+  constexpr bool kStageU =
+      NG3 * 3 * 8 + kInterpVars * NN3 * (int)sizeof(UT) <= 12 * 1024 && NG3 * 3 * 8 <= 4096;
   __shared__ double sX[SLOTS][NG3 * 3];
   __shared__ UT sU[SLOTS][kStageU ? kInterpVars * NN3 : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
