@@ -419,6 +419,19 @@ def main():
                "kind": "oracle",
                "sample": "one particle in %d (%d of %d) for %d steps of the same workload, FP64, "
                          "%.1f s wall" % (args.cpu_every, len(idx), w.n_particles, args.cpu_steps, el)}
+        # the same oracle on one core, over a sixteenth of that sample
+        n_all = O.num_threads()
+        idx1 = idx[::16]
+        o1 = O.Oracle(w.mesh, w.N, w.U)
+        o1.push(w.x[idx1], w.v[idx1], w.d[idx1], w.elem_hint[idx1])
+        O.set_num_threads(1)
+        t0 = time.perf_counter()
+        o1.step(w.dt, args.cpu_steps, rk=w.rk, drag=w.drag)
+        el1 = time.perf_counter() - t0
+        O.set_num_threads(n_all)
+        cpu.update({"value_1core": len(idx1) * args.cpu_steps / el1,
+                    "sample_1core": "%d particles for %d steps on one thread, %.1f s wall" % (len(idx1), args.cpu_steps,
+                                                                                         el1)})
 
     out = {
         "metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",

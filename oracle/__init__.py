@@ -54,6 +54,7 @@ def _declare(L):
     L.or_create.argtypes = [I, I, P, P, P, P, P, I, I]
     L.or_destroy.argtypes = [P]
     L.or_num_threads.restype = I
+    L.or_set_num_threads.argtypes = [I]
     L.or_set_fluid.argtypes = [P, P, D, D, D]
     L.or_gauss_nodes.argtypes = [I, P, P]
     L.or_lobatto_nodes.argtypes = [I, P, P]
@@ -196,6 +197,10 @@ def mlp_train_epoch(w, m, v, t, inp, target, order, batch, lr):
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n):
+    lib().or_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

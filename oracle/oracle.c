@@ -1150,6 +1150,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* threads of the parallel particle loops from now on (timing on one core) */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static void build_bgm(or_ctx* c) {
   int E = c->E, ng = c->ng;
   double glo[3] = {INFINITY, INFINITY, INFINITY}, ghi[3] = {-INFINITY, -INFINITY, -INFINITY};

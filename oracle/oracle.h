@@ -44,6 +44,7 @@ or_ctx* or_create(int n_elem, int n_geo, const double* X, const int32_t* nbr_ele
                   int N, int dg_nodes);
 void    or_destroy(or_ctx*);
 int     or_num_threads(void);
+void    or_set_num_threads(int n);
 void    or_set_fluid(or_ctx*, const double* U, double mu, double kappa, double rho_p);
 
 /* components (pins) ------------------------------------------------------- */
