@@ -31,7 +31,7 @@ constexpr int kNormChunk = 32;       // particles per normalisation pass
 constexpr int kXcd = 8;
 
 struct DepGeo {
-  double R, R2, iR2;
+  double R, R2, iR;   // radius, its square and its inverse
   double node_pad;     // largest distance of a DG node outside its element box
   double period[3];
 };
@@ -193,16 +193,21 @@ __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Flui
 }
 
 // 2. normalisation per source element ---------------------------------------
-// Each lane keeps its partial sums in its own LDS column (s_acc[wave][i][lane]),
-// so the particle loop stays dynamic and no per-pair reduction is needed; the
-// two wavefronts split the candidate target elements, and the next target's
-// nodes are loaded while the current one is evaluated.
+// For each window of candidate targets the chunk's particles are first tested
+// against every target's node box (two targets per wave instruction, one
+// particle per lane); targets with no particle within R go no further, and
+// the others form a list that the wavefronts share, so node data is fetched
+// only for targets that contribute.  Each lane keeps its partial sums in its
+// own LDS column (s_acc[wave][i][lane]), and the next listed target's nodes
+// are loaded while the current one is evaluated.  Distances are taken in
+// units of R, so K = max(1 - |d|^2, 0)^2 needs no cut-off test.
 template <int NN>
 __global__ __launch_bounds__(kNormThreads) void k_dep_norm(MeshView m, Particles P,
                                                            const int32_t* __restrict__ elem_start, DepGeo g,
                                                            double* F, const int32_t* __restrict__ ok,
                                                            unsigned long long* povh) {
   constexpr int TH = kNormThreads, NW = TH / 64, CH = kNormChunk;
+  static_assert(CH <= 32, "a ballot holds the masks of two targets");
   const int es = xcd_element(blockIdx.x, m.E);
   if (es >= m.E) return;
   const int p0 = elem_start[es], p1 = elem_start[es + 1];
@@ -212,8 +217,11 @@ __global__ __launch_bounds__(kNormThreads) void k_dep_norm(MeshView m, Particles
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t cap = P.cap;
   __shared__ CandLds<TH> L;
-  __shared__ double s_x[CH][3];
+  __shared__ double s_x[CH][3];     // positions
+  __shared__ double s_xs[CH][3];    // positions / R
   __shared__ double s_acc[NW][CH][64];
+  __shared__ uint32_t s_mask[kDepCand];
+  __shared__ int32_t s_list[kDepCand];
   __shared__ double s_q[6];
   __shared__ int s_any;
   for (int c0 = p0; c0 < p1; c0 += CH) {
@@ -229,7 +237,10 @@ __global__ __launch_bounds__(kNormThreads) void k_dep_norm(MeshView m, Particles
           ov = fmax(ov, fmax(m.elo[es * 3 + k] - x[k], x[k] - m.ehi[es * 3 + k]));
         if (ov > 0.0) atomicMax(povh, (unsigned long long)__double_as_longlong(ov));
       }
-      for (int k = 0; k < 3; ++k) s_x[i][k] = x[k];
+      for (int k = 0; k < 3; ++k) {
+        s_x[i][k] = x[k];
+        s_xs[i][k] = x[k] * g.iR;
+      }
     }
     for (int i = 0; i < CH; ++i) s_acc[wave][i][lane] = 0.0;
     __syncthreads();
@@ -248,54 +259,87 @@ __global__ __launch_bounds__(kNormThreads) void k_dep_norm(MeshView m, Particles
     if (!s_any) continue;   // uniform
     double qlo[3] = {s_q[0], s_q[1], s_q[2]}, qhi[3] = {s_q[3], s_q[4], s_q[5]};
     stream_candidates<TH>(m, g.period, qlo, qhi, g.R + g.node_pad, L, [&](int nc) {
-      double xn[NPL][3], vn[NPL], xn2[NPL][3], vn2[NPL];
-      // nodes of candidate T for this lane, shifted into the particles' image
-#define FP_LOAD_NODES(T, XN, VN)                                                                  \
-  {                                                                                               \
-    const int e_ = L.e[T];                                                                        \
-    double sh_[3];                                                                                \
-    image_shift(L.img[T], g.period, sh_);                                                         \
-    _Pragma("unroll") for (int j = 0; j < NPL; ++j) {                                             \
-      const int q = lane + 64 * j;                                                                \
-      if (q < N3) {                                                                               \
-        const double* src = m.xnode + ((size_t)e_ * N3 + q) * 3;                                  \
-        XN[j][0] = src[0] - sh_[0]; XN[j][1] = src[1] - sh_[1]; XN[j][2] = src[2] - sh_[2];       \
-        VN[j] = m.vol[(size_t)e_ * N3 + q];                                                       \
-      } else {                                                                                    \
-        XN[j][0] = XN[j][1] = XN[j][2] = 1e300;                                                   \
-        VN[j] = 0.0;                                                                              \
-      }                                                                                           \
-    }                                                                                             \
-  }
-      if (wave < nc) FP_LOAD_NODES(wave, xn, vn)
-      for (int t = wave; t < nc; t += NW) {
-        if (t + NW < nc) FP_LOAD_NODES(t + NW, xn2, vn2)
-        const int e = L.e[t];
-        double sh[3];
-        image_shift(L.img[t], g.period, sh);
-        const double* nb = m.nbox + (size_t)e * 6;
-        const double blo[3] = {nb[0] - sh[0], nb[1] - sh[1], nb[2] - sh[2]};
-        const double bhi[3] = {nb[3] - sh[0], nb[4] - sh[1], nb[5] - sh[2]};
-        for (int i = 0; i < cnt; ++i) {
+      // particle masks: lanes 0..31 test target t0, lanes 32..63 target t0 + 1
+      for (int t0 = 2 * wave; t0 < nc; t0 += 2 * NW) {
+        const int t = t0 + (lane >> 5), i = lane & 31;
+        bool near = false;
+        if (t < nc && i < CH) {
+          double sh[3];
+          image_shift(L.img[t], g.period, sh);
+          const double* nb = m.nbox + (size_t)L.e[t] * 6;
+          const double blo[3] = {nb[0] - sh[0], nb[1] - sh[1], nb[2] - sh[2]};
+          const double bhi[3] = {nb[3] - sh[0], nb[4] - sh[1], nb[5] - sh[2]};
           const double px[3] = {s_x[i][0], s_x[i][1], s_x[i][2]};
-          if (!(box_dist2(px, blo, bhi) < g.R2)) continue;   // wave-uniform
+          near = box_dist2(px, blo, bhi) < g.R2;
+        }
+        const unsigned long long bal = __ballot(near);
+        if (lane == 0) s_mask[t0] = (uint32_t)bal;
+        if (lane == 32 && t < nc) s_mask[t] = (uint32_t)(bal >> 32);
+      }
+      __syncthreads();
+      int nl = 0;
+      for (int cb = 0; cb < nc; cb += TH) {
+        const int c = cb + threadIdx.x;
+        const int f = (c < nc && s_mask[c] != 0u) ? 1 : 0;
+        int tot = 0;
+        const int off = block_excl_scan<TH>(f, L.wsum, tot);
+        if (f) s_list[nl + off] = c;
+        nl += tot;
+      }
+      __syncthreads();
+      // two register sets in turn: one target is evaluated while the next
+      // one's nodes are in flight
+      // Lanes past the last node load the last node again (every lane issues
+      // the same loads, so the wait for one set never waits for the other)
+      // and contribute with zero volume.
+      double xa[NPL][3], va[NPL], xb[NPL][3], vb[NPL];
+      auto load = [&](int t, double (&X)[NPL][3], double (&V)[NPL]) {
+        const size_t e = (size_t)L.e[t];
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          const int q = min(lane + 64 * j, N3 - 1);
+          const double* src = m.xnode + (e * N3 + q) * 3;
+          X[j][0] = src[0]; X[j][1] = src[1]; X[j][2] = src[2];
+          V[j] = m.vol[e * N3 + q];
+        }
+      };
+      auto eval = [&](int t, const double (&X)[NPL][3], const double (&V)[NPL]) {
+        // nodes in units of R, shifted into the particles' periodic image
+        double sh[3], xs[NPL][3], vv[NPL];
+        image_shift(L.img[t], g.period, sh);
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) xs[j][k] = (X[j][k] - sh[k]) * g.iR;
+          vv[j] = (lane + 64 * j < N3) ? V[j] : 0.0;
+        }
+        uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[t]);
+        for (; mask; mask &= mask - 1u) {
+          const int i = __builtin_ctz(mask);
+          const double ps0 = s_xs[i][0], ps1 = s_xs[i][1], ps2 = s_xs[i][2];
           double a = 0.0;
 #pragma unroll
           for (int j = 0; j < NPL; ++j) {
-            const double r0 = xn[j][0] - px[0], r1 = xn[j][1] - px[1], r2 = xn[j][2] - px[2];
-            const double rr = r0 * r0 + r1 * r1 + r2 * r2;
-            const double s = 1.0 - rr * g.iR2;
-            a += (rr < g.R2) ? s * s * vn[j] : 0.0;
+            const double d0 = xs[j][0] - ps0, d1 = xs[j][1] - ps1, d2 = xs[j][2] - ps2;
+            double w = fma(-d0, d0, fma(-d1, d1, fma(-d2, d2, 1.0)));
+            w = fmax(w, 0.0);
+            a = fma(w * vv[j], w, a);
           }
-          s_acc[wave][i][lane] += a;
+          // each lane owns its column, so the no-return LDS add keeps the
+          // summation order fixed while hiding the read-modify-write latency
+          __hip_atomic_fetch_add(&s_acc[wave][i][lane], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-#pragma unroll
-        for (int j = 0; j < NPL; ++j) {
-          xn[j][0] = xn2[j][0]; xn[j][1] = xn2[j][1]; xn[j][2] = xn2[j][2];
-          vn[j] = vn2[j];
-        }
+      };
+      // the prefetch is issued on every path (past the list's end it loads
+      // the last target again), so its loads are always the newest in flight
+      if (wave < nl) load(s_list[wave], xa, va);
+      for (int jl = wave; jl < nl; jl += 2 * NW) {
+        load(s_list[min(jl + NW, nl - 1)], xb, vb);
+        eval(s_list[jl], xa, va);
+        if (jl + NW >= nl) break;
+        load(s_list[min(jl + 2 * NW, nl - 1)], xa, va);
+        eval(s_list[jl + NW], xb, vb);
       }
-#undef FP_LOAD_NODES
     });
     // sum over waves and lanes: TH / CH threads per particle, fixed order
     {
@@ -320,7 +364,7 @@ __global__ __launch_bounds__(kNormThreads) void k_dep_norm(MeshView m, Particles
 
 // 3. gather per target element ----------------------------------------------
 // Each thread holds PER target nodes, so every staged particle read from LDS
-// serves PER kernel evaluations.
+// serves PER kernel evaluations.  Nodes and particles are held in units of R.
 template <int NN, typename ST>
 __global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Particles P,
                                                                const int32_t* __restrict__ elem_start, DepGeo g,
@@ -345,7 +389,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Parti
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[s][k] = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) xn[s][k] = (q < N3) ? m.xnode[((size_t)t * N3 + q) * 3 + k] : 1e300;
+    for (int k = 0; k < 3; ++k) xn[s][k] = (q < N3) ? m.xnode[((size_t)t * N3 + q) * 3 + k] * g.iR : 1e300;
   }
   const double* nb = m.nbox + (size_t)t * 6;
   const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
@@ -396,7 +440,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Parti
       if (keep) {
         const int slot = base + lane_rank(bal);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s_px[slot][k] = px[k];
+        for (int k = 0; k < 3; ++k) s_px[slot][k] = px[k] * g.iR;
 #pragma unroll
         for (int k = 0; k < 4; ++k) s_pg[slot][k] = pg[k];
       }
@@ -407,10 +451,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Parti
         const double g0 = s_pg[k][0], g1 = s_pg[k][1], g2 = s_pg[k][2], g3 = s_pg[k][3];
 #pragma unroll
         for (int s = 0; s < PER; ++s) {
-          const double r0 = xn[s][0] - x0, r1 = xn[s][1] - x1, r2 = xn[s][2] - x2;
-          const double rr = r0 * r0 + r1 * r1 + r2 * r2;
-          double w = 1.0 - rr * g.iR2;
-          w = (rr < g.R2) ? w * w : 0.0;
+          const double d0 = xn[s][0] - x0, d1 = xn[s][1] - x1, d2 = xn[s][2] - x2;
+          double w = fmax(fma(-d0, d0, fma(-d1, d1, fma(-d2, d2, 1.0))), 0.0);
+          w = w * w;
           acc[s][0] += w * g0;
           acc[s][1] += w * g1;
           acc[s][2] += w * g2;
@@ -442,7 +485,7 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
   DepGeo g;
   g.R = R;
   g.R2 = R * R;
-  g.iR2 = 1.0 / (R * R);
+  g.iR = 1.0 / R;
   g.node_pad = node_pad;
   for (int k = 0; k < 3; ++k) g.period[k] = period[k];
   double* F = dep;
