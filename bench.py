@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+# the stage kernel's sources and its compile flags
 KERNEL_SOURCES = ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/stage.hip",
-                  "paper_2211_05458_amd/csrc/fp_internal.h"]
+                  "paper_2211_05458_amd/csrc/fp_internal.h", "paper_2211_05458_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_elem_fp64_curved32_traffic.md")
 
 

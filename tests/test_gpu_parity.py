@@ -295,8 +295,13 @@ def test_reference_space_localisation_parity():
 def test_reference_space_localisation_parity_annulus():
     """Strongly curved annular passage (N_geo = 6): tracking mode 1 against the
     oracle in the same mode, with the particle whose untraced path ends where
-    Newton on its previous element diverges (background-mesh localisation)
-    among 4000 others; and the same result as physical tracking on the GPU."""
+    Newton on its previous element diverges in the oracle (background-mesh
+    localisation) among 4000 others; and the same result as physical tracking
+    on the GPU.  The divergence there is marginal (the |xi| > 2 test after the
+    third iteration), so whether the GPU's Newton, which sums the map in
+    another order, also diverges depends on rounding: the GPU must reach the
+    oracle's element and position either through the background mesh or
+    through the neighbour hops."""
     import json
     import os
     w = W.config4(n_particles=4000)
@@ -324,5 +329,5 @@ def test_reference_space_localisation_parity_annulus():
     for k in ("status", "elem", "hits"):
         np.testing.assert_array_equal(r1[k], r0[k])
     assert np.abs(r1["x"] - r0["x"]).max() <= 1e-12
-    assert so["lost"] == 0 and s1["lost"] == 0 and s1["recovered"] > 0 and s1["fallbacks"] > 0
+    assert so["lost"] == 0 and s1["lost"] == 0 and s1["recovered"] > 0
 
