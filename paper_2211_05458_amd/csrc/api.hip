@@ -208,7 +208,7 @@ struct Timed {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
+  size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, gxi, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
       mlp_flag, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, part[2], total;
@@ -230,6 +230,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.ehi = take(E * 3 * 8);
   L.nbox = take(E * 6 * 8);
   L.dsafe = take(E * 8);
+  L.gxi = take(E * 3 * 8);
   L.mortar = take(std::max<size_t>(1, c->mortar.size()) * 4);
   L.nbr_elem = take(E * 6 * 4);
   L.nbr_face = take(E * 6 * 4);
@@ -607,6 +608,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   m.ehi = (const double*)(b + L.ehi);
   m.nbox = (const double*)(b + L.nbox);
   m.dsafe = (const double*)(b + L.dsafe);
+  m.gxi = (const double*)(b + L.gxi);
   m.mortar = (const int32_t*)(b + L.mortar);
   m.n_mortar = c->n_mortar;
   for (int i = 0; i < kMaxNodes; ++i) {
@@ -649,7 +651,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
                               (const int8_t*)(b + L.bc), (const double*)(b + L.shift), c->Minv.data(),
                               (FaceRec*)(b + L.faces), (double*)(b + L.cp), s));
   HIPCHK(c, launch_nodes(m, (double*)(b + L.xnode), (double*)(b + L.vol), (double*)(b + L.hE), (double*)(b + L.nbox),
-                         c->scratch_i32, (unsigned long long*)(b + L.scratch + 8), s));
+                         (double*)(b + L.gxi), c->scratch_i32, (unsigned long long*)(b + L.scratch + 8), s));
   int32_t bad = 0;
   unsigned long long pad_bits = 0;
   HIPCHK(c, hipMemcpyAsync(&bad, c->scratch_i32, 4, hipMemcpyDeviceToHost, s));

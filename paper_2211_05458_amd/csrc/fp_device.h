@@ -800,6 +800,21 @@ __device__ inline void face_setup(const double* __restrict__ Xe, int f, const do
   F.type = (planar && bilin && tw <= tol) ? FACE_PLANAR : (bilin ? FACE_BILINEAR : FACE_CURVED);
 }
 
+// A segment of squared length L2 that starts at reference point xi of element
+// e stays inside e: along a path inside the element xi_i changes by at most
+// gxi[e][i] per unit length, and no coordinate can reach +-1 within L.  Such
+// a segment crosses no face, so tracking it would find nothing.
+__device__ __forceinline__ bool stays_inside(const MeshView& m, int e, const double* xi, double L2) {
+  const double* g = m.gxi + (size_t)e * 3;
+  bool in = true;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double r = 1.0 - fabs(xi[i]);
+    in = in && r > 0.0 && L2 * g[i] * g[i] < r * r;
+  }
+  return in;
+}
+
 __device__ inline bool bbox_hit(const FaceRec& F, const double* xs, const double* xe) {
   double pad = 1e-9 * F.diam;
   double r0[3] = {xs[0] - F.org[0], xs[1] - F.org[1], xs[2] - F.org[2]};

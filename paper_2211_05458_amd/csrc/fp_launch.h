@@ -10,8 +10,8 @@ bool supported(int n, int ng);
 hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* nbr_elem, const int32_t* nbr_face,
                              const int8_t* bc, const double* shift, const double* Minv, FaceRec* faces, double* cp,
                              hipStream_t s);
-hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, int32_t* bad,
-                        unsigned long long* node_pad, hipStream_t s);
+hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, double* gxi,
+                        int32_t* bad, unsigned long long* node_pad, hipStream_t s);
 hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* hint, int64_t n, hipStream_t s);
 struct StageLaunch {
   MeshView m;

@@ -89,6 +89,52 @@ __global__ __launch_bounds__(64) void k_node_box(MeshView m, const double* xnode
   }
 }
 
+// Upper bound G_i of |grad xi_i| = |row i of J^-1| over each element (one wave
+// per element): the largest value on a (2 n_g + 2)^3 lattice of reference
+// points that includes the element's faces, edges and corners, times
+// kGxiMargin; +inf where the sampled Jacobian is not positive.  Along a path
+// inside the element xi_i changes by at most G_i per unit length, so a
+// segment of length L from xi with L G_i < 1 - |xi_i| for every i stays
+// inside and crosses no face.
+constexpr double kGxiMargin = 1.5;
+
+template <int NG>
+__global__ __launch_bounds__(64) void k_gxi_bound(MeshView m, double* gxi) {
+  constexpr int S = 2 * NG + 2;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const double* X = m.X + (size_t)e * NG * NG * NG * 3;
+  double g[3] = {0.0, 0.0, 0.0};
+  bool bad = false;
+  for (int q = lane; q < S * S * S; q += 64) {
+    const double xi[3] = {-1.0 + 2.0 * (q % S) / (S - 1), -1.0 + 2.0 * ((q / S) % S) / (S - 1),
+                          -1.0 + 2.0 * (q / (S * S)) / (S - 1)};
+    double x[3], J[3][3];
+    map_jac<NG>(m, X, xi, x, J);
+    const double dj = det3(J);
+    if (!(dj > 0.0)) {
+      bad = true;
+      continue;
+    }
+    // rows of J^-1 = rows of the adjugate / det
+    double inv[3][3];
+    inv[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    inv[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    inv[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    inv[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    inv[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    inv[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    inv[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    inv[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    inv[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    for (int i = 0; i < 3; ++i) g[i] = fmax(g[i], sqrt(dot3(inv[i], inv[i])) / dj);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int off = 32; off > 0; off >>= 1) g[i] = fmax(g[i], __shfl_xor(g[i], off, 64));
+  bad = __any(bad);
+  if (lane == 0)
+    for (int i = 0; i < 3; ++i) gxi[(size_t)e * 3 + i] = bad ? 1e300 : kGxiMargin * g[i];
+}
+
 // ---------------------------------------------------------------------------
 // particle location (push): hint element, else background-mesh candidates
 // ---------------------------------------------------------------------------
@@ -236,13 +282,14 @@ hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, int32_t* bad,
-                        unsigned long long* node_pad, hipStream_t s) {
+hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, double* gxi,
+                        int32_t* bad, unsigned long long* node_pad, hipStream_t s) {
   int64_t tot = (int64_t)m.E * m.n * m.n * m.n;
 #define FP_L(A, B)                                                                           \
   if (m.n == A && m.ng == B) {                                                               \
     k_nodes<A, B><<<grid_for(tot), 256, 0, s>>>(m, xnode, vol, hE, bad);                     \
     k_node_box<A><<<m.E, 64, 0, s>>>(m, xnode, nbox, node_pad);                              \
+    k_gxi_bound<B><<<m.E, 64, 0, s>>>(m, gxi);                                               \
     return hipGetLastError();                                                                \
   }
   FP_FOR_EACH_SHAPE(FP_L)

@@ -178,11 +178,12 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
         const FaceRec* Fe = faces + (size_t)e * 6;
         bool any = false;
         // reference-space localisation: a segment that cannot reach a
-        // boundary face is not traced (the next location step finds it)
+        // boundary face is not traced (the next location step finds it);
+        // nor, in either mode, one that cannot leave the element
         const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
                           (xe[2] - x[2]) * (xe[2] - x[2]);
         const double ds = m.dsafe[e];
-        if (!(sp.refspace && L2 < ds * ds)) {
+        if (!(sp.refspace && L2 < ds * ds) && !stays_inside(m, e, xi, L2)) {
 #pragma unroll 1
           for (int f = 0; f < 6; ++f) any = any || bbox_hit(Fe[f], x, xe);
         }
@@ -285,11 +286,12 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
             P.kv[k * cap + p] = kv[k];
           }
           // the same prefilter as the element kernel: reference-space skip,
-          // then the bounding boxes of the element's faces
+          // segments that cannot leave the element, then the bounding boxes
+          // of the element's faces
           const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
                             (xe[2] - x[2]) * (xe[2] - x[2]);
           const double ds = m.dsafe[e];
-          if (!(sp.refspace && L2 < ds * ds)) {
+          if (!(sp.refspace && L2 < ds * ds) && !stays_inside(m, e, xi, L2)) {
             const FaceRec* Fe = m.faces + (size_t)e * 6;
 #pragma unroll 1
             for (int f = 0; f < 6 && !trk; ++f) trk = bbox_hit(Fe[f], x, xe);

@@ -331,3 +331,30 @@ def test_reference_space_localisation_parity_annulus():
     assert np.abs(r1["x"] - r0["x"]).max() <= 1e-12
     assert so["lost"] == 0 and s1["lost"] == 0 and s1["recovered"] > 0
 
+
+
+def test_segments_kept_inside_are_not_tracked_annulus():
+    """Strongly curved annular passage (N_geo = 6), physical tracking.  A
+    segment whose length times the element's bound of |grad xi_i| stays below
+    1 - |xi_i| for every i cannot leave its element, and the stage kernels do
+    not queue it for tracking.  Nothing may change: the GPU counts exactly the
+    oracle's crossings, wall hits and recoveries and ends every particle where
+    the oracle does, while tracking far fewer segments than it runs."""
+    w = W.config4(n_particles=3000)
+    v = w.v * 6.0
+    o = O.Oracle(w.mesh, w.N, w.U)
+    o.push(w.x, v, w.d, w.elem_hint)
+    o.step(w.dt, 4, rk=w.rk, drag=w.drag)
+    ro, so = o.read(), o.stats()
+    FlexiPart = _gpu()
+    g = FlexiPart(w.mesh, w.N, len(w.x))
+    g.set_fluid_state(w.U)
+    g.push(w.x, v, w.d, w.elem_hint)
+    g.step(w.dt, 4, rk=w.rk, drag=w.drag)
+    rg, sg = g.read(), g.stats()
+    assert_parity(ro, rg, vscale=10.0)
+    assert so["crossings"] > 500
+    for k in ("crossings", "wall_hits", "recovered", "lost"):
+        assert sg[k] == so[k], k
+    print("crossings", sg["crossings"], "track queue", sg["track_queue"], "of", len(w.x) * 4 * 3, "segments")
+    assert sg["track_queue"] < 0.9 * len(w.x) * 4 * 3
