@@ -45,6 +45,7 @@ struct fp_ctx {
   int32_t *tcount = nullptr, *tstart = nullptr, *qcnt = nullptr, *strag = nullptr, *trk_p = nullptr;
   void* tasks = nullptr;
   double* trk_x = nullptr;
+  uint8_t* trk_m = nullptr;
   bool tasks_valid = false;
   // fluid
   Fluid fl{};
@@ -211,7 +212,7 @@ struct Layout {
   size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, gxi, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
       mlp_flag, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
-      strag, trk_p, trk_x, part[2], total;
+      strag, trk_p, trk_x, trk_m, part[2], total;
   size_t part_bytes;
 };
 
@@ -256,6 +257,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.strag = take(pc1 * 4);
   L.trk_p = take(pc1 * 4);
   L.trk_x = take(pc1 * 3 * 8);
+  L.trk_m = take(pc1);
   size_t pc = (size_t)std::max<int64_t>(cap, 1);
   L.part_bytes = align256(pc * 15 * 8) + align256(pc * 8) + 3 * align256(pc * 4) + align256(pc);
   L.part[0] = take(L.part_bytes);
@@ -642,6 +644,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   c->strag = (int32_t*)(b + L.strag);
   c->trk_p = (int32_t*)(b + L.trk_p);
   c->trk_x = (double*)(b + L.trk_x);
+  c->trk_m = (uint8_t*)(b + L.trk_m);
   c->tasks_valid = false;
   c->P[0] = carve(b + L.part[0], c->cap);
   c->P[1] = carve(b + L.part[1], c->cap);
@@ -775,6 +778,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
       Lc.strag = c->strag;
       Lc.trk_p = c->trk_p;
       Lc.trk_x = c->trk_x;
+      Lc.trk_m = c->trk_m;
       Lc.stats = c->stats;
       if (c->timing)
         for (int k = 0; k < 6; ++k) Lc.ev[k] = take_event(c);

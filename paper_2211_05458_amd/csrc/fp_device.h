@@ -800,19 +800,23 @@ __device__ inline void face_setup(const double* __restrict__ Xe, int f, const do
   F.type = (planar && bilin && tw <= tol) ? FACE_PLANAR : (bilin ? FACE_BILINEAR : FACE_CURVED);
 }
 
-// A segment of squared length L2 that starts at reference point xi of element
-// e stays inside e: along a path inside the element xi_i changes by at most
-// gxi[e][i] per unit length, and no coordinate can reach +-1 within L.  Such
-// a segment crosses no face, so tracking it would find nothing.
-__device__ __forceinline__ bool stays_inside(const MeshView& m, int e, const double* xi, double L2) {
+// Local faces that a segment of squared length L2 starting at reference
+// point xi of element e could reach (bit f; face f lies at xi_{f/2} = -1 for
+// even f, +1 for odd f): along a path inside the element xi_i changes by at
+// most gxi[e][i] per unit length, so face f is out of reach when that times
+// L stays below its reference distance.  A segment that reaches no face stays
+// inside and crosses nothing.
+__device__ __forceinline__ unsigned reachable_faces(const MeshView& m, int e, const double* xi, double L2) {
   const double* g = m.gxi + (size_t)e * 3;
-  bool in = true;
+  unsigned mask = 0u;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double r = 1.0 - fabs(xi[i]);
-    in = in && r > 0.0 && L2 * g[i] * g[i] < r * r;
+    const double gl2 = L2 * g[i] * g[i];
+    const double rm = 1.0 + xi[i], rp = 1.0 - xi[i];
+    if (!(rm > 0.0 && gl2 < rm * rm)) mask |= 1u << (2 * i);
+    if (!(rp > 0.0 && gl2 < rp * rp)) mask |= 1u << (2 * i + 1);
   }
-  return in;
+  return mask;
 }
 
 __device__ inline bool bbox_hit(const FaceRec& F, const double* xs, const double* xe) {
@@ -1147,7 +1151,7 @@ __device__ __forceinline__ bool outside_band(const double* q, double amin, doubl
 // instead of the wavefront running every face to the slowest lane.
 template <int NG, bool MORT>
 __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
-                      int max_cross, int8_t& status, int& hits, int& ncross) {
+                      int max_cross, int8_t& status, int& hits, int& ncross, unsigned reach = 0x3Fu) {
   constexpr double kBoxTol = 1e-7;
   enum { NEW_LEG, NEXT_FACE, POP, CLIP, LEG_END, MORT_FACE, MORT_END, DONE };
   double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
@@ -1206,7 +1210,8 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       }
     }
     if (mode == NEXT_FACE) {
-      while (f < 6 && (f == excl || !bbox_hit(m.faces[e * 6 + f], xs, xe))) f++;
+      // reach: the faces the first leg can reach (all of them on later legs)
+      while (f < 6 && (f == excl || !((reach >> f) & 1u) || !bbox_hit(m.faces[e * 6 + f], xs, xe))) f++;
       if (f == 6) {
         mode = LEG_END;
       } else {
@@ -1363,6 +1368,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         const FaceRec& F = m.faces[fid];
         const int bc = F.bc;
         mode = NEW_LEG;
+        reach = 0x3Fu;
         if (bc == BC_INTERNAL || bc == BC_PERIODIC) {
           const int ne = F.nbr_elem, nf = F.nbr_face;
           if (bc == BC_PERIODIC)
@@ -1430,6 +1436,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       }
       mort = -1;
       mode = NEW_LEG;
+      reach = 0x3Fu;
     }
   }
 }

@@ -27,6 +27,7 @@ struct StageLaunch {
   int32_t* strag;           // [cap]
   int32_t* trk_p;           // [cap]
   double* trk_x;            // [3][cap]
+  uint8_t* trk_m;           // [cap] faces the first leg can reach
   unsigned long long* stats;
   hipEvent_t ev[6];         // optional (start, end) pairs around the elem, lane and track kernels
 };

@@ -96,6 +96,7 @@ struct Queues {
   int32_t* strag;     // [cap]
   int32_t* trk_p;     // [cap]
   double* trk_x;      // [3][cap] segment start
+  uint8_t* trk_m;     // [cap] local faces the segment can reach (bit f)
 };
 
 // Tasks of up to 64 particles: one per wavefront, four wavefronts per
@@ -138,6 +139,7 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
   bool strag = false, trk = false;
   int64_t p = 0;
   double xs0 = 0, xs1 = 0, xs2 = 0;
+  unsigned reach = 0x3Fu;
   const int64_t cap = P.cap;
   Task t{0, 0, 0, 0};
   if (ti < nt) {
@@ -178,14 +180,15 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
         const FaceRec* Fe = faces + (size_t)e * 6;
         bool any = false;
         // reference-space localisation: a segment that cannot reach a
-        // boundary face is not traced (the next location step finds it);
-        // nor, in either mode, one that cannot leave the element
+        // boundary face is not traced (the next location step finds it); in
+        // either mode only the boxes of the faces the segment can reach count
         const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
                           (xe[2] - x[2]) * (xe[2] - x[2]);
         const double ds = m.dsafe[e];
-        if (!(sp.refspace && L2 < ds * ds) && !stays_inside(m, e, xi, L2)) {
+        if (!(sp.refspace && L2 < ds * ds)) {
+          reach = reachable_faces(m, e, xi, L2);
 #pragma unroll 1
-          for (int f = 0; f < 6; ++f) any = any || bbox_hit(Fe[f], x, xe);
+          for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -209,6 +212,7 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
   int s2 = block_push<kElemWaves>(q.counters + 1, trk, sh);
   if (trk) {
     q.trk_p[s2] = (int32_t)p;
+    q.trk_m[s2] = (uint8_t)reach;
     q.trk_x[s2] = xs0;
     q.trk_x[cap + s2] = xs1;
     q.trk_x[2 * cap + s2] = xs2;
@@ -234,6 +238,7 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
     bool trk = false;
     int64_t p = 0;
     double xs0 = 0, xs1 = 0, xs2 = 0;
+    unsigned reach = 0x3Fu;
     if (i < count) {
       p = list ? (int64_t)list[i] : i;
       if (P.status[p] == ACTIVE) {
@@ -286,15 +291,15 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
             P.kv[k * cap + p] = kv[k];
           }
           // the same prefilter as the element kernel: reference-space skip,
-          // segments that cannot leave the element, then the bounding boxes
-          // of the element's faces
+          // then the bounding boxes of the faces the segment can reach
           const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
                             (xe[2] - x[2]) * (xe[2] - x[2]);
           const double ds = m.dsafe[e];
-          if (!(sp.refspace && L2 < ds * ds) && !stays_inside(m, e, xi, L2)) {
+          if (!(sp.refspace && L2 < ds * ds)) {
             const FaceRec* Fe = m.faces + (size_t)e * 6;
+            reach = reachable_faces(m, e, xi, L2);
 #pragma unroll 1
-            for (int f = 0; f < 6 && !trk; ++f) trk = bbox_hit(Fe[f], x, xe);
+            for (int f = 0; f < 6 && !trk; ++f) trk = ((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe);
           }
           xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
         }
@@ -303,6 +308,7 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
     int s = wave_push(q.counters + 1, trk);
     if (trk) {
       q.trk_p[s] = (int32_t)p;
+      q.trk_m[s] = (uint8_t)reach;
       q.trk_x[s] = xs0;
       q.trk_x[cap + s] = xs1;
       q.trk_x[2 * cap + s] = xs2;
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(256) void k_track(MeshView m, Particles P, Queues q
     double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
     int e = P.elem[p], e0 = e, h = 0, nc = 0;
     int8_t st = ACTIVE;
-    track<NG, MORT>(m, e, xs, xe, v, kx, kv, sp.max_cross, st, h, nc);
+    track<NG, MORT>(m, e, xs, xe, v, kx, kv, sp.max_cross, st, h, nc, q.trk_m[i]);
     ncross += nc;
     nhits += h;
     if (nc || st != ACTIVE) {
@@ -406,7 +412,7 @@ bool stage_uses_tasks(const StageLaunch& L) {
 template <int NN, int NG, typename UT, bool MIXED, bool MLP>
 static void run_stage(const StageLaunch& L, hipStream_t s) {
   const MeshView& m = L.m;
-  Queues q{L.counters, L.strag, L.trk_p, L.trk_x};
+  Queues q{L.counters, L.strag, L.trk_p, L.trk_x, L.trk_m};
   k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   int64_t lane_blocks;
   auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
