@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64) void k_node_box(MeshView m, const double* xnode
 // inside the element xi_i changes by at most G_i per unit length, so a
 // segment of length L from xi with L G_i < 1 - |xi_i| for every i stays
 // inside and crosses no face.
-constexpr double kGxiMargin = 1.5;
+constexpr double kGxiMargin = 1.2;
 
 template <int NG>
 __global__ __launch_bounds__(64) void k_gxi_bound(MeshView m, double* gxi) {

@@ -1,0 +1,73 @@
+"""The stage kernels queue a segment for tracking only if it can reach a face
+of its element.  Along a path inside element e, xi_i changes by at most G_i
+per unit length, where G_i bounds |grad xi_i| = |row i of J^-1| over the
+element; the library takes the largest value on a (2 n_g + 2)^3 reference
+lattice that includes the element's faces, edges and corners, times 1.2.  A
+segment of length L from xi reaches face (i, +-1) only if L G_i >= 1 -+ xi_i.
+
+These tests check that sampled bound with the oracle's map on the most
+strongly curved meshes of the workloads (the annular passage with N_geo = 6
+and the sine box with N_geo = 4): lattices twice as dense stay well inside
+the margin, and straight segments just shorter than the bound allows end
+inside their element.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2211_05458_amd import workloads as W
+
+MARGIN = 1.2
+
+
+def _grad_xi_max(o, e, S):
+    g = np.zeros(3)
+    t = np.linspace(-1.0, 1.0, S)
+    for a in t:
+        for b in t:
+            for c in t:
+                _, J = o.map(e, np.array([a, b, c]))
+                assert np.linalg.det(J) > 0.0
+                g = np.maximum(g, np.linalg.norm(np.linalg.inv(J), axis=1))
+    return g
+
+
+def _mesh(kind):
+    if kind == "annulus":
+        w = W.config4(n_particles=1)
+    else:
+        w = W.curved_box(cells=6, N=3, n_particles=1, n_steps=1, seed=3)
+    return w, O.Oracle(w.mesh, w.N, None)
+
+
+@pytest.mark.parametrize("kind", ["annulus", "sine"])
+def test_denser_lattice_stays_within_margin(kind):
+    w, o = _mesh(kind)
+    ng = w.mesh.n_geo + 1
+    rng = np.random.default_rng(7)
+    for e in rng.choice(w.mesh.n_elem, 6, replace=False):
+        g = _grad_xi_max(o, int(e), 2 * ng + 2)
+        gd = _grad_xi_max(o, int(e), 4 * ng + 3)
+        assert np.all(gd <= 1.05 * g), (e, g, gd)
+
+
+def test_segments_within_the_bound_end_inside_annulus():
+    w, o = _mesh("annulus")
+    ng = w.mesh.n_geo + 1
+    rng = np.random.default_rng(8)
+    elems = rng.choice(w.mesh.n_elem, 8, replace=False)
+    G = {int(e): MARGIN * _grad_xi_max(o, int(e), 2 * ng + 2) for e in elems}
+    worst = 0.0
+    for k in range(800):
+        e = int(elems[k % len(elems)])
+        xi = rng.uniform(-0.999, 0.999, 3)
+        dirn = rng.normal(size=3)
+        dirn /= np.linalg.norm(dirn)
+        L = 0.999 * np.min((1.0 - np.abs(xi)) / G[e])
+        x0, _ = o.map(e, xi)
+        conv, xi1, _ = o.newton(e, x0 + L * dirn, xi)
+        assert conv
+        worst = max(worst, np.abs(xi1).max())
+        assert np.abs(xi1).max() < 1.0, (e, xi, xi1)
+    # the bound is not vacuous: some segments end close to a face
+    assert worst > 0.9
