@@ -231,7 +231,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.ehi = take(E * 3 * 8);
   L.nbox = take(E * 6 * 8);
   L.dsafe = take(E * 8);
-  L.gxi = take(E * 3 * 8);
+  L.gxi = take(E * 6 * 8);
   L.mortar = take(std::max<size_t>(1, c->mortar.size()) * 4);
   L.nbr_elem = take(E * 6 * 4);
   L.nbr_face = take(E * 6 * 4);

@@ -58,6 +58,27 @@ __device__ __forceinline__ void lagrange_d(const double* nodes, const double* cd
   }
 }
 
+// l_i, l_i' and l_i'' at x (product rule over the factors (x - x_j))
+template <int N>
+__device__ __forceinline__ void lagrange_d2(const double* nodes, const double* cden, double x, double* l,
+                                            double* dl, double* d2l) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double p = 1.0, dp = 0.0, d2p = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j != i) {
+        const double dx = x - nodes[j];
+        d2p = d2p * dx + 2.0 * dp;
+        dp = dp * dx + p;
+        p *= dx;
+      }
+    l[i] = cden[i] * p;
+    dl[i] = cden[i] * dp;
+    d2l[i] = cden[i] * d2p;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // chi_e(xi) and J = d chi / d xi by sum factorisation over i, then j, then k
 // ---------------------------------------------------------------------------
@@ -807,7 +828,7 @@ __device__ inline void face_setup(const double* __restrict__ Xe, int f, const do
 // L stays below its reference distance.  A segment that reaches no face stays
 // inside and crosses nothing.
 __device__ __forceinline__ unsigned reachable_faces(const MeshView& m, int e, const double* xi, double L2) {
-  const double* g = m.gxi + (size_t)e * 3;
+  const double* g = m.gxi + (size_t)e * 6;
   unsigned mask = 0u;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -817,6 +838,42 @@ __device__ __forceinline__ unsigned reachable_faces(const MeshView& m, int e, co
     if (!(rp > 0.0 && gl2 < rp * rp)) mask |= 1u << (2 * i + 1);
   }
   return mask;
+}
+
+// Refinement of reachable_faces for a segment x -> xe from reference point xi
+// (x = chi_e(xi)): along the segment, while inside the element, xi_i moves by
+// at most s (grad xi_i(x) . t) + s^2 H_i / 2 after a length s, where H_i
+// bounds the Hessian of xi_i over the element (gxi[e][3 + i]); the bound is
+// convex in s, so face (i, +1) is out of reach when it stays below 1 - xi_i at
+// s = L (face (i, -1) likewise with the sign of the first term reversed).
+// grad xi_i(x) is row i of J^-1 at xi.  The 1e-9 slack covers xi being
+// Newton's solution (to 1e-10) rather than the exact preimage of x.
+template <int NG>
+__device__ __forceinline__ unsigned reachable_faces_taylor(const MeshView& m, int e, const double* __restrict__ Xe,
+                                                           const double* xi, const double* x, const double* xe,
+                                                           double L2, unsigned reach) {
+  double xm[3], J[3][3];
+  map_jac<NG>(m, Xe, xi, xm, J);
+  const double dj = det3(J);
+  if (!(dj > 0.0)) return reach;
+  const double d[3] = {xe[0] - x[0], xe[1] - x[1], xe[2] - x[2]};
+  // rows of the adjugate dotted with d, over det: first-order change of xi_i
+  double a[3];
+  a[0] = ((J[1][1] * J[2][2] - J[1][2] * J[2][1]) * d[0] + (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * d[1] +
+          (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * d[2]) / dj;
+  a[1] = ((J[1][2] * J[2][0] - J[1][0] * J[2][2]) * d[0] + (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * d[1] +
+          (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * d[2]) / dj;
+  a[2] = ((J[1][0] * J[2][1] - J[1][1] * J[2][0]) * d[0] + (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * d[1] +
+          (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * d[2]) / dj;
+  const double* h = m.gxi + (size_t)e * 6 + 3;
+  unsigned out = 0u;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double q = 0.5 * L2 * h[i] + 1e-9;
+    if (-a[i] + q >= 1.0 + xi[i]) out |= 1u << (2 * i);
+    if (a[i] + q >= 1.0 - xi[i]) out |= 1u << (2 * i + 1);
+  }
+  return reach & out;
 }
 
 __device__ inline bool bbox_hit(const FaceRec& F, const double* xs, const double* xe) {

@@ -55,7 +55,8 @@ struct MeshView {
   const double* ehi;
   const double* nbox;     // [E][6] box of the DG nodes (lo xyz, hi xyz)
   const double* dsafe;    // [E] lower bound of the distance to a face that is not internal
-  const double* gxi;      // [E][3] upper bound of |grad xi_i| over the element (sampled, with a margin)
+  const double* gxi;      // [E][6] upper bounds over the element of |grad xi_i| (0..2) and of the norm of
+                          // the Hessian of xi_i (3..5) (sampled, with margins)
   const int32_t* mortar;  // [n_mortar][4][2] (small element, local face) per big mortar face, -1 unused
   int32_t n_mortar;
   double xgeo[kMaxNodes], cgeo[kMaxNodes];  // geometry nodes, 1/prod(x_i - x_j)

@@ -89,50 +89,109 @@ __global__ __launch_bounds__(64) void k_node_box(MeshView m, const double* xnode
   }
 }
 
-// Upper bound G_i of |grad xi_i| = |row i of J^-1| over each element (one wave
-// per element): the largest value on a (2 n_g + 2)^3 lattice of reference
-// points that includes the element's faces, edges and corners, times
-// kGxiMargin; +inf where the sampled Jacobian is not positive.  Along a path
-// inside the element xi_i changes by at most G_i per unit length, so a
-// segment of length L from xi with L G_i < 1 - |xi_i| for every i stays
-// inside and crosses no face.
+// Upper bounds over each element (one wave per element) of G_i = |grad xi_i|
+// = |row i of J^-1| and of H_i = |Hessian of xi_i| (Frobenius norm): the
+// largest values on reference lattices that include the element's faces,
+// edges and corners ((2 n_g + 2)^3 points for G, (n_g + 3)^3 for H), times
+// kGxiMargin and kHxiMargin; +inf where the sampled Jacobian is not positive.
+// Along a path inside the element xi_i changes by at most G_i per unit
+// length, so a segment of length L from xi with L G_i < 1 - |xi_i| for every i
+// stays inside and crosses no face; H_i bounds the second-order term of the
+// same change (Hessian of xi_i = -J^-T (sum_k (J^-1)_ik d2 chi_k) J^-1).
 constexpr double kGxiMargin = 1.2;
+constexpr double kHxiMargin = 2.0;
+
+__device__ inline bool inv3(const double J[3][3], double K[3][3]) {
+  const double dj = det3(J);
+  if (!(dj > 0.0)) return false;
+  const double id = 1.0 / dj;
+  K[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+  K[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+  K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+  K[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+  K[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+  K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+  K[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+  K[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+  K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  return true;
+}
 
 template <int NG>
 __global__ __launch_bounds__(64) void k_gxi_bound(MeshView m, double* gxi) {
-  constexpr int S = 2 * NG + 2;
   const int e = blockIdx.x, lane = threadIdx.x;
   const double* X = m.X + (size_t)e * NG * NG * NG * 3;
-  double g[3] = {0.0, 0.0, 0.0};
+  double g[3] = {0.0, 0.0, 0.0}, h[3] = {0.0, 0.0, 0.0};
   bool bad = false;
+  constexpr int S = 2 * NG + 2;
   for (int q = lane; q < S * S * S; q += 64) {
     const double xi[3] = {-1.0 + 2.0 * (q % S) / (S - 1), -1.0 + 2.0 * ((q / S) % S) / (S - 1),
                           -1.0 + 2.0 * (q / (S * S)) / (S - 1)};
-    double x[3], J[3][3];
+    double x[3], J[3][3], K[3][3];
     map_jac<NG>(m, X, xi, x, J);
-    const double dj = det3(J);
-    if (!(dj > 0.0)) {
+    if (!inv3(J, K)) {
       bad = true;
       continue;
     }
-    // rows of J^-1 = rows of the adjugate / det
-    double inv[3][3];
-    inv[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    inv[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    inv[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    inv[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    inv[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    inv[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    inv[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    inv[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    inv[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    for (int i = 0; i < 3; ++i) g[i] = fmax(g[i], sqrt(dot3(inv[i], inv[i])) / dj);
+    for (int i = 0; i < 3; ++i) g[i] = fmax(g[i], sqrt(dot3(K[i], K[i])));
+  }
+  constexpr int SH = NG + 3;
+  for (int q = lane; q < SH * SH * SH; q += 64) {
+    const double xi[3] = {-1.0 + 2.0 * (q % SH) / (SH - 1), -1.0 + 2.0 * ((q / SH) % SH) / (SH - 1),
+                          -1.0 + 2.0 * (q / (SH * SH)) / (SH - 1)};
+    double l[3][NG], dl[3][NG], d2l[3][NG];
+    for (int a = 0; a < 3; ++a) lagrange_d2<NG>(m.xgeo, m.cgeo, xi[a], l[a], dl[a], d2l[a]);
+    // first and second derivatives of the map: J[k][p], M[k][pq] (pq: 00 11 22 01 02 12)
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, M[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0},
+                                                                   {0, 0, 0, 0, 0, 0}};
+    for (int kk = 0; kk < NG; ++kk)
+      for (int jj = 0; jj < NG; ++jj)
+        for (int ii = 0; ii < NG; ++ii) {
+          const double* P = X + ((kk * NG + jj) * NG + ii) * 3;
+          const double b1[3] = {dl[0][ii] * l[1][jj] * l[2][kk], l[0][ii] * dl[1][jj] * l[2][kk],
+                                l[0][ii] * l[1][jj] * dl[2][kk]};
+          const double b2[6] = {d2l[0][ii] * l[1][jj] * l[2][kk], l[0][ii] * d2l[1][jj] * l[2][kk],
+                                l[0][ii] * l[1][jj] * d2l[2][kk], dl[0][ii] * dl[1][jj] * l[2][kk],
+                                dl[0][ii] * l[1][jj] * dl[2][kk], l[0][ii] * dl[1][jj] * dl[2][kk]};
+          for (int k = 0; k < 3; ++k) {
+            for (int p = 0; p < 3; ++p) J[k][p] += P[k] * b1[p];
+            for (int r = 0; r < 6; ++r) M[k][r] += P[k] * b2[r];
+          }
+        }
+    double K[3][3];
+    if (!inv3(J, K)) {
+      bad = true;
+      continue;
+    }
+    for (int i = 0; i < 3; ++i) {
+      // T = sum_k K[i][k] M_k (symmetric), H = K^T T K
+      double T[3][3];
+      const int idx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+      for (int p = 0; p < 3; ++p)
+        for (int r = 0; r < 3; ++r)
+          T[p][r] = K[i][0] * M[0][idx[p][r]] + K[i][1] * M[1][idx[p][r]] + K[i][2] * M[2][idx[p][r]];
+      double f2 = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double v = 0.0;
+          for (int p = 0; p < 3; ++p)
+            for (int r = 0; r < 3; ++r) v += K[p][a] * T[p][r] * K[r][b];
+          f2 += v * v;
+        }
+      h[i] = fmax(h[i], sqrt(f2));
+    }
   }
   for (int i = 0; i < 3; ++i)
-    for (int off = 32; off > 0; off >>= 1) g[i] = fmax(g[i], __shfl_xor(g[i], off, 64));
+    for (int off = 32; off > 0; off >>= 1) {
+      g[i] = fmax(g[i], __shfl_xor(g[i], off, 64));
+      h[i] = fmax(h[i], __shfl_xor(h[i], off, 64));
+    }
   bad = __any(bad);
   if (lane == 0)
-    for (int i = 0; i < 3; ++i) gxi[(size_t)e * 3 + i] = bad ? 1e300 : kGxiMargin * g[i];
+    for (int i = 0; i < 3; ++i) {
+      gxi[(size_t)e * 6 + i] = bad ? 1e300 : kGxiMargin * g[i];
+      gxi[(size_t)e * 6 + 3 + i] = bad ? 1e300 : kHxiMargin * h[i];
+    }
 }
 
 // ---------------------------------------------------------------------------

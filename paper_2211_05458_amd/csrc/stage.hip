@@ -20,6 +20,16 @@
 
 namespace fp {
 
+// The second-order reach test (reachable_faces_taylor) costs the stage
+// kernels a map evaluation per wavefront and registers; it pays where the
+// tracking queue keeps the tracker throughput-bound, measured on the
+// strongly curved geometry of degree 6 (N_geo = 6: tracking queue -63 %, step
+// time -40 % on the annular passage), not on degree 4 (32^3 sine box: the
+// shorter queue left the latency-bound tracker as slow and the stage kernel
+// 5 % slower).
+template <int NG>
+constexpr bool kReach2 = NG >= 7;
+
 // interpolation, drag and the low-storage update for one particle.  FORCES:
 // the extra terms of the equation of motion selected in sp.forces (they need
 // the velocity gradient, hence the element's geometry nodes Xe).
@@ -189,6 +199,12 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
           reach = reachable_faces(m, e, xi, L2);
 #pragma unroll 1
           for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
+          if (kReach2<NG> && any) {
+            reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach);
+            any = false;
+#pragma unroll 1
+            for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
+          }
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -300,6 +316,12 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
             reach = reachable_faces(m, e, xi, L2);
 #pragma unroll 1
             for (int f = 0; f < 6 && !trk; ++f) trk = ((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe);
+            if (kReach2<NG> && trk) {
+              reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach);
+              trk = false;
+#pragma unroll 1
+              for (int f = 0; f < 6 && !trk; ++f) trk = ((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe);
+            }
           }
           xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
         }
