@@ -92,7 +92,7 @@ __global__ __launch_bounds__(64) void k_node_box(MeshView m, const double* xnode
 // Upper bounds over each element (one wave per element) of G_i = |grad xi_i|
 // = |row i of J^-1| and of H_i = |Hessian of xi_i| (Frobenius norm): the
 // largest values on reference lattices that include the element's faces,
-// edges and corners ((2 n_g + 2)^3 points for G, (n_g + 3)^3 for H), times
+// edges and corners ((2 n_g + 2)^3 points), times
 // kGxiMargin and kHxiMargin; +inf where the sampled Jacobian is not positive.
 // Along a path inside the element xi_i changes by at most G_i per unit
 // length, so a segment of length L from xi with L G_i < 1 - |xi_i| for every i
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64) void k_gxi_bound(MeshView m, double* gxi) {
     }
     for (int i = 0; i < 3; ++i) g[i] = fmax(g[i], sqrt(dot3(K[i], K[i])));
   }
-  constexpr int SH = NG + 3;
+  constexpr int SH = 2 * NG + 2;
   for (int q = lane; q < SH * SH * SH; q += 64) {
     const double xi[3] = {-1.0 + 2.0 * (q % SH) / (SH - 1), -1.0 + 2.0 * ((q / SH) % SH) / (SH - 1),
                           -1.0 + 2.0 * (q / (SH * SH)) / (SH - 1)};
