@@ -62,7 +62,10 @@ INTERP_VARS = 4
 
 
 def flops_per_particle_stage(n, ng, newton_it):
-    """Algorithmic flops of one particle-stage (measurement)."""
+    """Algorithmic flops of one particle-stage: Newton iterations on the
+    geometry map and Jacobian (sum factorisation), interpolation of the drag
+    law's variables, the nearest-node guess, and the drag, update and box
+    tests."""
     f_newton = 6 * (2 * ng ** 3 + 3 * ng ** 2 + 4 * ng) + 160
     f_interp = 2 * INTERP_VARS * (n ** 3 + n ** 2 + n) + 9 * n ** 2
     f_guess = 8 * ng ** 3
@@ -330,7 +333,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     from paper_2211_05458_amd import workloads as W

@@ -1,8 +1,8 @@
 """Learned Newton initial guess (extension of Sec. 3.2.1's guess approaches):
 training pairs from the GPU Newton solver, training with the library's own
 forward/backward/Adam kernels, use as the initial guess on strongly curved
-elements with the paper's guess as fallback.  Converged Newton stays the judge,
-so trajectories must not change."""
+elements with the paper's guess as fallback.  Converged Newton decides the
+location, so trajectories must not change."""
 import numpy as np
 import pytest
 
