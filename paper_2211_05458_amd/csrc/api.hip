@@ -210,7 +210,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, gxi, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
-      mlp_flag, stats,
+      mlp_flag, mlp_h1, mlp_ctr, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, trk_m, part[2], total;
   size_t part_bytes;
@@ -240,6 +240,8 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.bstart = take(c->bstart.size() * 4);
   L.blist = take(std::max<size_t>(1, c->blist.size()) * 4);
   L.mlp_flag = take(E);
+  L.mlp_h1 = take(E * 64 * 4);
+  L.mlp_ctr = take(E * 4 * 8);
   L.stats = take(16 * kStatSlots * 8);
   L.sort_count = take((E + 1) * 4);
   L.sort_start = take((E + 1) * 4);
@@ -627,6 +629,8 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   m.blist = (const int32_t*)(b + L.blist);
   m.mlp_flag = (const uint8_t*)(b + L.mlp_flag);
   m.mlp_w = nullptr;
+  m.mlp_h1 = (const float*)(b + L.mlp_h1);
+  m.mlp_ctr = (const double*)(b + L.mlp_ctr);
   c->mlp_flag = (uint8_t*)(b + L.mlp_flag);
   c->stats = (unsigned long long*)(b + L.stats);
   c->sort_count = (int32_t*)(b + L.sort_count);
@@ -995,6 +999,7 @@ int fp_mlp_set_weights(fp_ctx* c, const float* w, double thresh) {
   if (!w) { c->n_flagged = 0; return FP_OK; }
   HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 4, c->stream));
   HIPCHK(c, launch_curved_flags(c->mv, thresh, c->mlp_flag, c->scratch_i32, c->stream));
+  HIPCHK(c, launch_mlp_elem_table(c->mv, w, (float*)c->mv.mlp_h1, (double*)c->mv.mlp_ctr, c->stream));
   int32_t cnt = 0;
   HIPCHK(c, hipMemcpyAsync(&cnt, c->scratch_i32, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -274,7 +274,7 @@ __device__ __forceinline__ bool inside_ref(const double* xi) {
 // points of the {-1,0,1}^3 lattice (57; zero for straight elements), and the
 // point (3); lengths divided by the mean corner-edge length.
 template <int NG>
-__device__ void mlp_features(const MeshView& m, int e, const double* x, float* feat) {
+__device__ void mlp_features(const MeshView& m, int e, const double* x, float* feat, double* ctr_ih = nullptr) {
   const double* P = m.X + (size_t)e * (NG * NG * NG * 3);
   constexpr int G = NG - 1;
   double cor[8][3], ctr[3] = {0, 0, 0};
@@ -296,6 +296,9 @@ __device__ void mlp_features(const MeshView& m, int e, const double* x, float* f
       hs += sqrt(dx * dx + dy * dy + dz * dz);
     }
   double ih = 12.0 / hs;
+  if (ctr_ih) {
+    ctr_ih[0] = ctr[0]; ctr_ih[1] = ctr[1]; ctr_ih[2] = ctr[2]; ctr_ih[3] = ih;
+  }
 #pragma unroll
   for (int a = 0; a < 8; ++a)
     for (int r = 0; r < 3; ++r) feat[a * 3 + r] = (float)((cor[a][r] - ctr[r]) * ih);
@@ -323,6 +326,59 @@ __device__ void mlp_features(const MeshView& m, int e, const double* x, float* f
 }
 
 __device__ __forceinline__ float fast_tanh(float s) { return tanhf(s); }
+
+// Layers 2..4 of the 84-64-64-64-3 network from the first layer's
+// pre-activation s1 (64 values).
+__device__ inline void mlp_forward_tail(const float* __restrict__ w, const float* s1, float* out) {
+  constexpr int H = 64, NI = kMlpIn;
+  const float* W2 = w + H * NI + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H * H;
+  const float* W4 = b3 + H;
+  const float* b4 = W4 + 3 * H;
+  float h1[H], h2[H];
+#pragma unroll
+  for (int o = 0; o < H; ++o) h1[o] = fast_tanh(s1[o]);
+#pragma unroll 2
+  for (int o = 0; o < H; ++o) {
+    float s = b2[o];
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += W2[o * H + i] * h1[i];
+    h2[o] = fast_tanh(s);
+  }
+#pragma unroll 2
+  for (int o = 0; o < H; ++o) {
+    float s = b3[o];
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += W3[o * H + i] * h2[i];
+    h1[o] = fast_tanh(s);
+  }
+  for (int o = 0; o < 3; ++o) {
+    float s = b4[o];
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += W4[o * H + i] * h1[i];
+    out[o] = s;
+  }
+}
+
+// The learned guess at x in element e: 81 of the 84 inputs depend on the
+// element only, so the first layer's element part is taken from the table
+// filled when the weights are set (mlp_h1) and only the point's three inputs
+// are added per particle.
+__device__ inline void mlp_guess(const MeshView& m, int e, const double* x, float* out) {
+  constexpr int H = 64, NI = kMlpIn;
+  const float* W1 = m.mlp_w;
+  const float* h1e = m.mlp_h1 + (size_t)e * H;
+  const double* c = m.mlp_ctr + (size_t)e * 4;
+  const float p0 = (float)((x[0] - c[0]) * c[3]), p1 = (float)((x[1] - c[1]) * c[3]),
+              p2 = (float)((x[2] - c[2]) * c[3]);
+  float s1[H];
+#pragma unroll
+  for (int o = 0; o < H; ++o)
+    s1[o] = h1e[o] + W1[o * NI + 81] * p0 + W1[o * NI + 82] * p1 + W1[o * NI + 83] * p2;
+  mlp_forward_tail(m.mlp_w, s1, out);
+}
 
 // 84-64-64-64-3 forward for one row; weights read through the scalar path
 // (uniform addresses).
@@ -373,9 +429,8 @@ __device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__
                             const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks) {
   double g[3];
   if (MLP && m.mlp_flag[e]) {
-    float feat[kMlpIn], o[3];
-    mlp_features<NG>(m, e, x, feat);
-    mlp_forward_row(m.mlp_w, feat, o);
+    float o[3];
+    mlp_guess(m, e, x, o);
     g[0] = o[0]; g[1] = o[1]; g[2] = o[2];
     calls++;
     if (newton_e<NG>(m, Xe, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }

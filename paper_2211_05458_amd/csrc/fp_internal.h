@@ -68,6 +68,8 @@ struct MeshView {
   const int32_t* blist;
   const uint8_t* mlp_flag;// [E] learned guess enabled
   const float* mlp_w;     // weights (device), or null
+  const float* mlp_h1;    // [E][64] first layer's pre-activation from the element inputs (bias included)
+  const double* mlp_ctr;  // [E][4] corner mean (xyz) and length scale of the inputs (1 / mean corner edge)
 };
 
 // Particle state, structure of arrays, capacity cap.

@@ -59,5 +59,6 @@ hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, cons
 hipError_t launch_adam(float* w, float* m, float* v, const float* g, int64_t nw, int64_t t, float lr,
                        hipStream_t s);
 hipError_t launch_curved_flags(const MeshView& m, double thresh, uint8_t* flag, int32_t* count, hipStream_t s);
+hipError_t launch_mlp_elem_table(const MeshView& m, const float* w, float* h1, double* ctr, hipStream_t s);
 
 }  // namespace fp

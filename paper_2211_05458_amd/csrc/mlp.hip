@@ -232,6 +232,35 @@ hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n,
   return hipErrorInvalidValue;
 }
 
+// Per element (one 64-thread workgroup, one hidden unit per thread): the first
+// layer's pre-activation from the 81 inputs that depend on the element only,
+// bias included, summed in the order of the full forward pass, and the corner
+// mean and length scale that turn a point into the last three inputs.
+template <int NG>
+__global__ __launch_bounds__(64) void k_mlp_elem_table(MeshView m, const float* __restrict__ w, float* h1,
+                                                      double* ctr) {
+  const int e = blockIdx.x, o = threadIdx.x;
+  float feat[kMlpIn];
+  double ci[4];
+  const double x0[3] = {0.0, 0.0, 0.0};
+  mlp_features<NG>(m, e, x0, feat, ci);
+  float s = w[64 * kMlpIn + o];
+  for (int i = 0; i < kMlpIn - 3; ++i) s += w[o * kMlpIn + i] * feat[i];
+  h1[(size_t)e * 64 + o] = s;
+  if (o < 4) ctr[(size_t)e * 4 + o] = ci[o];
+}
+
+hipError_t launch_mlp_elem_table(const MeshView& m, const float* w, float* h1, double* ctr, hipStream_t s) {
+  switch (m.ng) {
+    case 2: k_mlp_elem_table<2><<<m.E, 64, 0, s>>>(m, w, h1, ctr); break;
+    case 3: k_mlp_elem_table<3><<<m.E, 64, 0, s>>>(m, w, h1, ctr); break;
+    case 5: k_mlp_elem_table<5><<<m.E, 64, 0, s>>>(m, w, h1, ctr); break;
+    case 7: k_mlp_elem_table<7><<<m.E, 64, 0, s>>>(m, w, h1, ctr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_curved_flags(const MeshView& m, double thresh, uint8_t* flag, int32_t* count, hipStream_t s) {
   dim3 g((unsigned)((m.E + 255) / 256));
   switch (m.ng) {
