@@ -23,10 +23,12 @@
  *    fp_mlp_set_weights must stay valid and unmodified until they are
  *    replaced or the context is destroyed.
  *  - The library never allocates device memory: all device state lives in the
- *    caller-allocated workspace (fp_workspace_size / fp_bind_workspace).
+ *    caller-allocated workspace (fp_workspace_size / fp_bind_workspace), or in
+ *    a caller-allocated particle block (fp_bind_particles).
  *  - All device work is enqueued on the stream given to fp_create, in order.
- *    Only fp_push_particles, fp_read_particles, fp_get_stats and
- *    fp_bind_workspace synchronise that stream.
+ *    Only fp_push_particles, fp_read_particles, fp_get_stats,
+ *    fp_bind_workspace, fp_newton_pairs, fp_mlp_set_weights and fp_mlp_train
+ *    synchronise that stream.
  *  - Element local faces: 0: xi1=-1, 1: xi1=+1, 2: xi2=-1, 3: xi2=+1,
  *    4: xi3=-1, 5: xi3=+1.  Volume node index i + n*(j + n*k), i along xi1.
  */
@@ -134,15 +136,50 @@ int fp_workspace_size(fp_ctx* ctx, int64_t max_particles, size_t* bytes);
  * (Sec. 4.1.2).  Synchronises the stream. */
 int fp_bind_workspace(fp_ctx* ctx, void* dev_ptr, size_t bytes);
 
-/* Borrow the DG state U (device) [n_elem][5][(n_dg+1)^3] of conservative
- * variables (rho, rho u, rho e) in FP64 or FP32. */
+/* Borrow the DG state U (device) [n_elem][5][(n_dg+1)^3]: the nodal values
+ * U_ijk of the conservative variables (rho, rho u, rho e) of Sec. 2.1 that
+ * the tensor-product Lagrange polynomial of Sec. 3.1 (eq.
+ * dgsem_interpolation) interpolates, in FP64 or FP32; node index
+ * i + n (j + n k).  params: viscosity, ratio of specific heats and particle
+ * density (Sec. 2.1, 2.2).  The pointer must stay valid and unmodified until
+ * it is replaced.  FP_EINVAL for a null pointer or a non-positive viscosity
+ * or density. */
 int fp_set_fluid_state(fp_ctx* ctx, const void* U_dev, fp_dtype dtype, const fp_fluid_params* params);
 
-/* Insert n particles (host arrays x[n][3], v[n][3], d[n]; elem_hint[n] or
- * NULL) replacing any previous set.  Each is located by Newton in its hint
- * element, else in the background-mesh candidates in element order; status_out
- * (host, may be NULL) receives FP_ACTIVE or FP_REJECTED.  Returns the number of
- * rejected particles (>= 0) or an error. */
+/* ---- particle block owned by the caller ----------------------------------
+ * The particle state of Sec. 2.2 (position, velocity, diameter) together with
+ * the low-storage Runge-Kutta registers of Sec. 3.2.2 and the reference
+ * position of Sec. 3.2.1, as one structure-of-arrays block of capacity `cap`:
+ *   offsets[0] x [3][cap] f64     offsets[1] v [3][cap] f64
+ *   offsets[2] kx [3][cap] f64    offsets[3] kv [3][cap] f64 (RK registers)
+ *   offsets[4] xi [3][cap] f64    offsets[5] d [cap] f64
+ *   offsets[6] elem [cap] i32     offsets[7] wall hits [cap] i32
+ *   offsets[8] id [cap] i32 (index in push order)
+ *   offsets[9] status [cap] i8 (FP_ACTIVE, ...)
+ * fp_particle_block_layout writes the ten byte offsets (host, may be NULL)
+ * and the block size; the block is FP64 in both precisions (FP_EINVAL for
+ * FP_F32: mixed precision rounds on load). */
+int fp_particle_block_layout(int64_t capacity, fp_dtype dtype, int64_t* offsets, size_t* bytes);
+/* Bind a caller-allocated device block of that layout (256-byte aligned,
+ * 0 < capacity <= the workspace's particle capacity) as the context's
+ * particle state, replacing the workspace's own buffer; soa_dev = NULL returns
+ * to it.  Any particle set is dropped (push again).  After fp_push_particles,
+ * fp_step and fp_deposit_source the block holds the current state, rows in
+ * element order (id gives the push order); the sort's second buffer stays in
+ * the workspace.  The block is borrowed: it must stay valid until it is
+ * replaced or the context is destroyed. */
+int fp_bind_particles(fp_ctx* ctx, int64_t capacity, fp_dtype dtype, void* soa_dev);
+
+/* Insert n particles replacing any previous set: positions, velocities and
+ * diameters (Sec. 2.2) as host arrays x[n][3], v[n][3], d[n]; or, with a
+ * bound particle block, x = v = d = NULL to take the block's first n entries
+ * of x, v and d as they are.  elem_hint[n] (host) or NULL.  Each particle is
+ * located by Newton for its reference position (Sec. 3.2.1) in its hint
+ * element, else in the candidates of the Cartesian background mesh (Sec.
+ * 4.1.2) in element order; status_out (host, may be NULL) receives
+ * FP_ACTIVE or FP_REJECTED (outside every element).  Returns the number of
+ * rejected particles (>= 0), FP_EINVAL for n above the capacity or a
+ * non-positive diameter.  Synchronises the stream. */
 int fp_push_particles(fp_ctx* ctx, int64_t n, const double* x, const double* v, const double* d,
                       const int32_t* elem_hint, int32_t* status_out);
 
@@ -175,7 +212,10 @@ int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, do
 int fp_node_volumes(fp_ctx* ctx, double* V_dev);
 
 /* Copy the particle state to host buffers (any may be NULL) in the order of
- * fp_push_particles.  xi is the reference position in elem.  Synchronises. */
+ * fp_push_particles: position and velocity (Sec. 2.2), element, reference
+ * position xi with chi_elem(xi) = x (Sec. 3.2.1; every active particle is
+ * located first), wall-hit count (reflections, Sec. 2.4) and status.
+ * Synchronises. */
 int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* elem, double* xi,
                       int32_t* wall_hits, int8_t* status);
 
@@ -227,8 +267,24 @@ int fp_mlp_loss_grad(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in
 int fp_mlp_train_epoch(fp_ctx* ctx, float* w_dev, float* m_dev, float* v_dev, int64_t* t,
                        const float* in_dev, const float* target_dev, const int32_t* order_dev,
                        int64_t n, int32_t batch, float lr, float* loss_dev);
-/* Enable the learned guess with weights (device, borrowed) on elements whose
- * geometry deviates from the trilinear corner map by > thresh * h_e. */
+/* Train the network from scratch on n (features, xi) rows (device
+ * in[n][84], target[n][3], e.g. from fp_newton_pairs): Xavier-uniform initial
+ * weights and zero biases, then `epochs` epochs of minibatch Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, step lr) on the mean squared error in batches of
+ * `batch` rows (the last n mod batch rows of each epoch's order are left
+ * out).  Every random draw comes from SplitMix64 seeded with `seed`: one
+ * uniform per weight in layout order, then one Fisher-Yates shuffle of the
+ * rows per epoch (a draw for i = n-1 down to 1, j = floor(u64 * (i+1) / 2^64)).
+ * w_out (device, fp_mlp_n_weights floats) receives the trained weights;
+ * loss_hist (host [epochs], may be NULL) the mean batch loss of each epoch.
+ * FP_EINVAL for batch > 8192, n < batch or n above the workspace's particle
+ * capacity.  Synchronises. */
+int fp_mlp_train(fp_ctx* ctx, const float* in_dev, const float* target_dev, int64_t n, int32_t epochs,
+                 int32_t batch, float lr, uint64_t seed, float* w_out_dev, float* loss_hist);
+/* Enable the learned guess with weights w_dev (device; copied into the
+ * workspace, so later changes of w_dev have no effect until the next call;
+ * NULL disables the guess) on elements whose geometry deviates from the
+ * trilinear corner map by > thresh * h_e. */
 int fp_mlp_set_weights(fp_ctx* ctx, const float* w_dev, double thresh);
 int fp_mlp_num_flagged(fp_ctx* ctx, int64_t* n);
 

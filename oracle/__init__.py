@@ -104,6 +104,7 @@ def _declare(L):
     L.or_mlp_train.argtypes = [P, P, P, P, P, P, P, I64, I, D, P]
     L.or_set_mlp.argtypes = [P, P, P]
     L.or_curved_flags.argtypes = [P, D, P]
+    L.or_mlp_draws.argtypes = [C.c_uint64, I64, I, P, P]
 
 
 class StepOpts(C.Structure):
@@ -193,6 +194,14 @@ def mlp_train_epoch(w, m, v, t, inp, target, order, batch, lr):
     mean = lib().or_mlp_train(_p(w), _p(m), _p(v), C.byref(tt), _p(_f64(inp)), _p(_f64(target)),
                               _p(order), len(order), batch, lr, _p(hist))
     return mean, tt.value, hist[:nb]
+
+
+def mlp_draws(seed, n, epochs):
+    """Initial weights and per-epoch row orders of a seeded training run."""
+    w0 = np.zeros(mlp_n_weights())
+    orders = np.zeros((max(epochs, 1), n), np.int32)
+    lib().or_mlp_draws(int(seed), int(n), int(epochs), _p(w0), _p(orders))
+    return w0, orders[:epochs]
 
 
 def num_threads():

@@ -2148,6 +2148,50 @@ double or_mlp_train(double* w, double* m, double* v, int64_t* t, const double* i
   return nb ? tot / nb : 0.0;
 }
 
+/* The draws of a seeded training run.  Generator: SplitMix64 (Steele, Lea and
+ * Flood, OOPSLA 2014), the i-th output of stream `seed` being the finaliser
+ * applied to seed + i * 0x9E3779B97F4A7C15 (i = 1, 2, ...).  Uniform in [0, 1):
+ * the top 53 bits times 2^-53.  Order of the draws: one uniform per weight in
+ * layout order (Xavier-uniform matrices, a * (2u - 1) with
+ * a = sqrt(6 / (fan_in + fan_out)); biases zero, no draw), then for each
+ * epoch a Fisher-Yates shuffle of 0..n-1: for i = n-1 down to 1 swap a[i]
+ * with a[j], j = floor(z (i + 1) / 2^64) for the next output z.
+ * orders: [epochs][n]. */
+static uint64_t sm64_next(uint64_t* st) {
+  uint64_t z;
+  *st += 0x9E3779B97F4A7C15ull;
+  z = *st;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void or_mlp_draws(uint64_t seed, int64_t n, int epochs, double* w0, int32_t* orders) {
+  const int rows[4] = {OR_MLP_H, OR_MLP_H, OR_MLP_H, OR_MLP_NOUT};
+  const int cols[4] = {OR_MLP_NIN, OR_MLP_H, OR_MLP_H, OR_MLP_H};
+  uint64_t st = seed;
+  int64_t o = 0;
+  for (int l = 0; l < 4; ++l) {
+    double a = sqrt(6.0 / (double)(rows[l] + cols[l]));
+    for (int i = 0; i < rows[l] * cols[l]; ++i) {
+      double u = (double)(sm64_next(&st) >> 11) * (1.0 / 9007199254740992.0);
+      w0[o++] = a * (2.0 * u - 1.0);
+    }
+    for (int i = 0; i < rows[l]; ++i) w0[o++] = 0.0;
+  }
+  for (int ep = 0; ep < epochs; ++ep) {
+    int32_t* a = orders + (int64_t)ep * n;
+    for (int64_t i = 0; i < n; ++i) a[i] = (int32_t)i;
+    for (int64_t i = n - 1; i >= 1; --i) {
+      uint64_t z = sm64_next(&st);
+      int64_t j = (int64_t)(((unsigned __int128)z * (unsigned __int128)(i + 1)) >> 64);
+      int32_t t = a[i];
+      a[i] = a[j];
+      a[j] = t;
+    }
+  }
+}
+
 void or_set_mlp(or_ctx* c, const double* w, const uint8_t* flag) {
   free(c->mlp_w); free(c->mlp_flag);
   c->mlp_w = NULL; c->mlp_flag = NULL;

@@ -108,6 +108,8 @@ void or_adam(double* w, double* m, double* v, const double* grad, int64_t nw, in
 double or_mlp_train(double* w, double* m, double* v, int64_t* t, const double* in,
                     const double* target, const int32_t* order, int64_t n, int batch,
                     double lr, double* loss_hist);
+/* initial weights and per-epoch row orders of a seeded run (SplitMix64) */
+void or_mlp_draws(uint64_t seed, int64_t n, int epochs, double* w0, int32_t* orders);
 void or_set_mlp(or_ctx*, const double* w, const uint8_t* flag);
 void or_curved_flags(const or_ctx*, double thresh, uint8_t* flag);
 

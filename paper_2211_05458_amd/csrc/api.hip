@@ -56,8 +56,16 @@ struct fp_ctx {
   bool xi_dirty = false;
   bool sorted_valid = false;
   int64_t steps_done = 0, sorts = 0;
-  // learned guess
+  // caller-owned particle block (fp_bind_particles): P[0] then lives there and
+  // holds the current state after every call that moves particles
+  bool bound = false;
+  char* part0 = nullptr;          // the workspace's first particle buffer
+  // learned guess: the weights in use are the workspace copy mlp_wbuf
   const float* mlp_w = nullptr;
+  float* mlp_wbuf = nullptr;
+  float* mlp_adam = nullptr;      // Adam moments m, v of fp_mlp_train [2][nw]
+  int32_t* mlp_order = nullptr;   // row order of one epoch [cap]
+  float* mlp_bloss = nullptr;     // batch losses of one epoch [cap]
   int64_t n_flagged = 0;
   // timing
   bool timing = false;
@@ -208,9 +216,23 @@ struct Timed {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Byte offsets of the particle arrays in one block of capacity cap (the
+// layout fp_particle_block_layout documents): x, v, kx, kv, xi [3][cap] f64,
+// d [cap] f64, elem, hits, id [cap] i32, status [cap] i8, each array starting
+// on a 256-byte boundary.
+void particle_offsets(int64_t cap, int64_t* off, size_t* total) {
+  size_t pc = (size_t)std::max<int64_t>(cap, 1), o = 0;
+  for (int a = 0; a < 5; ++a) { off[a] = (int64_t)o; o += align256(pc * 3 * 8); }
+  off[5] = (int64_t)o; o += align256(pc * 8);
+  for (int a = 6; a < 9; ++a) { off[a] = (int64_t)o; o += align256(pc * 4); }
+  off[9] = (int64_t)o; o += align256(pc);
+  *total = o;
+}
+
+
 struct Layout {
   size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, gxi, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
-      mlp_flag, mlp_h1, mlp_ctr, stats,
+      mlp_flag, mlp_h1, mlp_ctr, mlp_w, mlp_adam, mlp_order, mlp_bloss, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, trk_m, part[2], total;
   size_t part_bytes;
@@ -242,6 +264,10 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.mlp_flag = take(E);
   L.mlp_h1 = take(E * 64 * 4);
   L.mlp_ctr = take(E * 4 * 8);
+  L.mlp_w = take((size_t)kMlpWeights * 4);
+  L.mlp_adam = take((size_t)kMlpWeights * 2 * 4);
+  L.mlp_order = take((size_t)std::max<int64_t>(cap, 1) * 4);
+  L.mlp_bloss = take((size_t)std::max<int64_t>(cap, 1) * 4);
   L.stats = take(16 * kStatSlots * 8);
   L.sort_count = take((E + 1) * 4);
   L.sort_start = take((E + 1) * 4);
@@ -260,8 +286,10 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.trk_p = take(pc1 * 4);
   L.trk_x = take(pc1 * 3 * 8);
   L.trk_m = take(pc1);
-  size_t pc = (size_t)std::max<int64_t>(cap, 1);
-  L.part_bytes = align256(pc * 15 * 8) + align256(pc * 8) + 3 * align256(pc * 4) + align256(pc);
+  {
+    int64_t off[10];
+    particle_offsets(cap, off, &L.part_bytes);
+  }
   L.part[0] = take(L.part_bytes);
   L.part[1] = take(L.part_bytes);
   L.total = o;
@@ -270,18 +298,20 @@ Layout layout(const fp_ctx* c, int64_t cap) {
 
 Particles carve(char* base, int64_t cap) {
   Particles P{};
-  size_t pc = (size_t)std::max<int64_t>(cap, 1);
+  int64_t off[10];
+  size_t total;
+  particle_offsets(cap, off, &total);
   P.cap = cap;
-  char* p = base;
-  P.x = (double*)p; P.v = P.x + 3 * pc; P.kx = P.v + 3 * pc; P.kv = P.kx + 3 * pc; P.xi = P.kv + 3 * pc;
-  p += align256(pc * 15 * 8);
-  P.d = (double*)p; p += align256(pc * 8);
-  P.elem = (int32_t*)p; p += align256(pc * 4);
-  P.hits = (int32_t*)p; p += align256(pc * 4);
-  P.id = (int32_t*)p; p += align256(pc * 4);
-  P.status = (int8_t*)p;
+  P.x = (double*)(base + off[0]); P.v = (double*)(base + off[1]); P.kx = (double*)(base + off[2]);
+  P.kv = (double*)(base + off[3]); P.xi = (double*)(base + off[4]); P.d = (double*)(base + off[5]);
+  P.elem = (int32_t*)(base + off[6]); P.hits = (int32_t*)(base + off[7]); P.id = (int32_t*)(base + off[8]);
+  P.status = (int8_t*)(base + off[9]);
   return P;
 }
+
+// A caller-owned block holds the current state: after a sort left it in the
+// workspace buffer, copy it back (same indices, so element tasks stay valid).
+int sync_bound(fp_ctx* c);
 
 }  // namespace
 
@@ -409,6 +439,60 @@ int sort_particles(fp_ctx* c, int tp) {
   c->tasks_valid = true;
   c->task_tp = tp;
   return FP_OK;
+}
+
+int sync_bound(fp_ctx* c) {
+  if (!c->bound || c->cur == 0 || c->np == 0) return FP_OK;
+  const Particles& S = c->P[1];
+  const Particles& D = c->P[0];
+  const size_t n = (size_t)c->np;
+  hipStream_t s = c->stream;
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(c, hipMemcpyAsync(D.x + k * D.cap, S.x + k * S.cap, n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(D.v + k * D.cap, S.v + k * S.cap, n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(D.kx + k * D.cap, S.kx + k * S.cap, n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(D.kv + k * D.cap, S.kv + k * S.cap, n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(D.xi + k * D.cap, S.xi + k * S.cap, n * 8, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(D.d, S.d, n * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(D.elem, S.elem, n * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(D.hits, S.hits, n * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(D.id, S.id, n * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(D.status, S.status, n, hipMemcpyDeviceToDevice, s));
+  c->cur = 0;
+  return FP_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): output i of stream `seed` is the mix of
+// seed + (i + 1) * 0x9E3779B97F4A7C15.  Draws of fp_mlp_train: the initial
+// weights first (one per weight, in layout order), then one Fisher-Yates
+// shuffle per epoch (draws for i = n-1 down to 1).
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }                       // [0, 1)
+  uint32_t below(uint32_t k) { return (uint32_t)(((unsigned __int128)next() * k) >> 64); }  // [0, k)
+};
+
+// Xavier-uniform weights (limit sqrt(6 / (fan_in + fan_out))), zero biases
+void mlp_xavier(SplitMix64& g, std::vector<float>& w) {
+  const int shapes[4][2] = {{64, kMlpIn}, {64, 64}, {64, 64}, {3, 64}};
+  size_t o = 0;
+  for (auto& sh : shapes) {
+    const double a = std::sqrt(6.0 / (sh[0] + sh[1]));
+    for (int i = 0; i < sh[0] * sh[1]; ++i) w[o++] = (float)(a * (2.0 * g.uniform() - 1.0));
+    for (int i = 0; i < sh[0]; ++i) w[o++] = 0.0f;
+  }
+}
+
+void shuffle(SplitMix64& g, std::vector<int32_t>& a) {
+  for (int64_t i = (int64_t)a.size() - 1; i >= 1; --i) std::swap(a[i], a[g.below((uint32_t)(i + 1))]);
 }
 }  // namespace
 
@@ -650,9 +734,16 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   c->trk_x = (double*)(b + L.trk_x);
   c->trk_m = (uint8_t*)(b + L.trk_m);
   c->tasks_valid = false;
+  c->part0 = b + L.part[0];
   c->P[0] = carve(b + L.part[0], c->cap);
   c->P[1] = carve(b + L.part[1], c->cap);
   c->cur = 0;
+  c->bound = false;
+  c->mlp_wbuf = (float*)(b + L.mlp_w);
+  c->mlp_adam = (float*)(b + L.mlp_adam);
+  c->mlp_order = (int32_t*)(b + L.mlp_order);
+  c->mlp_bloss = (float*)(b + L.mlp_bloss);
+  c->mlp_w = nullptr;
   HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 64, s));
   HIPCHK(c, launch_face_setup(m, m.X, (const int32_t*)(b + L.nbr_elem), (const int32_t*)(b + L.nbr_face),
                               (const int8_t*)(b + L.bc), (const double*)(b + L.shift), c->Minv.data(),
@@ -685,28 +776,51 @@ int fp_set_fluid_state(fp_ctx* c, const void* U, fp_dtype dt, const fp_fluid_par
 
 int fp_push_particles(fp_ctx* c, int64_t n, const double* x, const double* v, const double* d,
                       const int32_t* hint, int32_t* status_out) {
-  if (!c || n < 0 || (n > 0 && (!x || !v || !d))) return FP_EINVAL;
+  if (!c || n < 0) return FP_EINVAL;
+  const bool in_place = !x && !v && !d;
+  if (n > 0 && !in_place && (!x || !v || !d)) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_push_particles: no workspace");
-  if (n > c->cap) return fail(c, FP_EINVAL, "fp_push_particles: more particles than workspace capacity");
+  if (in_place && n > 0 && !c->bound)
+    return fail(c, FP_EINVAL, "fp_push_particles: x, v, d may be NULL only with a bound particle block");
   hipStream_t s = c->stream;
   c->cur = 0;
   Particles& P = c->P[0];
-  int64_t cap = c->cap;
-  std::vector<double> tx((size_t)n * 3), tv((size_t)n * 3);
+  int64_t cap = P.cap;
+  if (n > cap) return fail(c, FP_EINVAL, "fp_push_particles: more particles than capacity");
   double dmin = 1e300;
-  for (int64_t p = 0; p < n; ++p) {
-    for (int k = 0; k < 3; ++k) {
-      tx[k * n + p] = x[p * 3 + k];
-      tv[k * n + p] = v[p * 3 + k];
+  if (in_place) {
+    // x, v and d are already in the bound block: smallest diameter (and a
+    // check that every one is positive) on the device
+    if (n > 0) {
+      HIPCHK(c, hipMemsetAsync(c->scratch_i32 + 8, 0, 24, s));
+      HIPCHK(c, launch_min_positive(P.d, n, (unsigned long long*)(c->scratch_i32 + 8), c->scratch_i32 + 12, s));
+      unsigned long long bits = 0;
+      int32_t bad = 0;
+      HIPCHK(c, hipMemcpyAsync(&bits, c->scratch_i32 + 8, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(&bad, c->scratch_i32 + 12, 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (bad) return fail(c, FP_EINVAL, "fp_push_particles: non-positive diameter");
+      bits = ~bits;
+      std::memcpy(&dmin, &bits, 8);
     }
-    dmin = std::min(dmin, d[p]);
-    if (!(d[p] > 0.0)) return fail(c, FP_EINVAL, "fp_push_particles: non-positive diameter");
+  } else {
+    std::vector<double> tx((size_t)n * 3), tv((size_t)n * 3);
+    for (int64_t p = 0; p < n; ++p) {
+      for (int k = 0; k < 3; ++k) {
+        tx[k * n + p] = x[p * 3 + k];
+        tv[k * n + p] = v[p * 3 + k];
+      }
+      dmin = std::min(dmin, d[p]);
+      if (!(d[p] > 0.0)) return fail(c, FP_EINVAL, "fp_push_particles: non-positive diameter");
+    }
+    for (int k = 0; k < 3 && n > 0; ++k) {
+      HIPCHK(c, hipMemcpyAsync(P.x + k * cap, tx.data() + k * n, n * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(P.v + k * cap, tv.data() + k * n, n * 8, hipMemcpyHostToDevice, s));
+    }
+    if (n > 0) HIPCHK(c, hipMemcpyAsync(P.d, d, n * 8, hipMemcpyHostToDevice, s));
+    // the copies read pageable host memory: finish them before tx, tv go
+    HIPCHK(c, hipStreamSynchronize(s));
   }
-  for (int k = 0; k < 3 && n > 0; ++k) {
-    HIPCHK(c, hipMemcpyAsync(P.x + k * cap, tx.data() + k * n, n * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(P.v + k * cap, tv.data() + k * n, n * 8, hipMemcpyHostToDevice, s));
-  }
-  if (n > 0) HIPCHK(c, hipMemcpyAsync(P.d, d, n * 8, hipMemcpyHostToDevice, s));
   const int32_t* dh = nullptr;
   if (hint && n > 0) {
     HIPCHK(c, hipMemcpyAsync(c->sort_rank, hint, n * 4, hipMemcpyHostToDevice, s));
@@ -796,6 +910,10 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
     c->steps_done++;
   }
   c->xi_dirty = true;
+  {
+    int rc = sync_bound(c);
+    if (rc) return rc;
+  }
   // stability of the drag term: dt * f_D / tau_p within the real-axis bound of the scheme
   double tau_min = c->fl.rho_p * c->d_min * c->d_min / (18.0 * c->fl.mu);
   double bound = o->rk == 0 ? 4.65 : 2.51;
@@ -814,18 +932,28 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   fm.drag = drag;
   fm.forces = forces;
   for (int k = 0; k < 3; ++k) fm.gravity[k] = gravity ? gravity[k] : 0.0;
+  if (kind == 1) {
+    if (!(radius > 0.0)) return fail(c, FP_EINVAL, "fp_deposit_source: radius must be positive");
+    for (int k = 0; k < 3; ++k)
+      if (period && period[k] > 0.0 && period[k] <= 2.0 * radius)
+        return fail(c, FP_EINVAL, "fp_deposit_source: a period must exceed twice the kernel radius");
+  }
+  // the source belongs to the element that contains each particle at the end
+  // of the last step: locate them first (a segment that was not traced, or a
+  // crossing the face intersection missed, leaves the old element recorded)
+  if (c->xi_dirty && c->np > 0) {
+    Timed tm(c, 2);
+    HIPCHK(c, launch_finalize(c->mv, c->P[c->cur], c->np, c->stats, c->stream));
+    c->xi_dirty = false;
+  }
   if (kind == 0) {
     Timed tm(c, 3);
     HIPCHK(c, launch_deposit_nearest(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, c->stream));
     return FP_OK;
   }
-  if (!(radius > 0.0)) return fail(c, FP_EINVAL, "fp_deposit_source: radius must be positive");
   double per[3] = {0, 0, 0};
   if (period)
     for (int k = 0; k < 3; ++k) per[k] = period[k];
-  for (int k = 0; k < 3; ++k)
-    if (per[k] > 0.0 && per[k] <= 2.0 * radius)
-      return fail(c, FP_EINVAL, "fp_deposit_source: a period must exceed twice the kernel radius");
   if (c->np == 0) return FP_OK;
   // gather needs the particles bucketed by their current element (tasks for
   // the stage that ran last)
@@ -836,7 +964,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
     HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
                                    c->node_pad, c->dep_buf, c->sort_start, c->dep_pad, c->stream));
   }
-  return FP_OK;
+  return sync_bound(c);
 }
 
 int fp_node_volumes(fp_ctx* c, double* V) {
@@ -852,10 +980,11 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
   if (!c) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_read_particles: no workspace");
   hipStream_t s = c->stream;
-  int64_t n = c->np, cap = c->cap;
+  int64_t n = c->np;
   if (n_out) *n_out = n;
   if (n == 0) return FP_OK;
   Particles& P = c->P[c->cur];
+  const int64_t cap = P.cap;
   if (c->xi_dirty) {
     Timed tm(c, 2);
     HIPCHK(c, launch_finalize(c->mv, P, n, c->stats, s));
@@ -994,16 +1123,101 @@ int fp_mlp_train_epoch(fp_ctx* c, float* w, float* m, float* v, int64_t* t, cons
 int fp_mlp_set_weights(fp_ctx* c, const float* w, double thresh) {
   if (!c) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_set_weights: no workspace");
-  c->mlp_w = w;
-  c->mv.mlp_w = w;
-  if (!w) { c->n_flagged = 0; return FP_OK; }
+  if (!w) {
+    c->mlp_w = nullptr;
+    c->mv.mlp_w = nullptr;
+    c->n_flagged = 0;
+    return FP_OK;
+  }
+  // the guess uses a copy: later changes of w (training in place) do not
+  // reach the stage kernels or the per-element first-layer table
+  if (w != c->mlp_wbuf)
+    HIPCHK(c, hipMemcpyAsync(c->mlp_wbuf, w, (size_t)kMlpWeights * 4, hipMemcpyDeviceToDevice, c->stream));
+  c->mlp_w = c->mlp_wbuf;
+  c->mv.mlp_w = c->mlp_wbuf;
   HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 4, c->stream));
   HIPCHK(c, launch_curved_flags(c->mv, thresh, c->mlp_flag, c->scratch_i32, c->stream));
-  HIPCHK(c, launch_mlp_elem_table(c->mv, w, (float*)c->mv.mlp_h1, (double*)c->mv.mlp_ctr, c->stream));
+  HIPCHK(c, launch_mlp_elem_table(c->mv, c->mlp_wbuf, (float*)c->mv.mlp_h1, (double*)c->mv.mlp_ctr, c->stream));
   int32_t cnt = 0;
   HIPCHK(c, hipMemcpyAsync(&cnt, c->scratch_i32, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->n_flagged = cnt;
+  return FP_OK;
+}
+
+int fp_mlp_train(fp_ctx* c, const float* in, const float* target, int64_t n, int32_t epochs, int32_t batch,
+                 float lr, uint64_t seed, float* w_out, float* loss_hist) {
+  if (!c || !in || !target || !w_out || n <= 0 || epochs < 0 || batch <= 0) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_train: no workspace");
+  if (batch > kMlpMaxBatch) return fail(c, FP_EINVAL, "fp_mlp_train: batch above 8192");
+  if (n > c->cap) return fail(c, FP_EINVAL, "fp_mlp_train: more rows than the workspace's particle capacity");
+  if (n < batch) return fail(c, FP_EINVAL, "fp_mlp_train: fewer rows than one batch");
+  hipStream_t s = c->stream;
+  const int64_t nw = kMlpWeights, nb = n / batch;
+  SplitMix64 g{seed};
+  std::vector<float> w0((size_t)nw);
+  mlp_xavier(g, w0);
+  HIPCHK(c, hipMemcpyAsync(w_out, w0.data(), nw * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(c->mlp_adam, 0, (size_t)nw * 2 * 4, s));
+  std::vector<int32_t> order((size_t)n);
+  std::vector<float> bl((size_t)nb);
+  int64_t t = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+    shuffle(g, order);
+    // the previous epoch's copy of `order` must be done before it is reused
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipMemcpyAsync(c->mlp_order, order.data(), n * 4, hipMemcpyHostToDevice, s));
+    for (int64_t bi = 0; bi < nb; ++bi) {
+      HIPCHK(c, launch_mlp_loss_grad(w_out, batch, in, target, c->mlp_order + bi * batch, c->mlp_grad,
+                                     c->mlp_bloss + bi, c->mlp_rows, s));
+      ++t;
+      HIPCHK(c, launch_adam(w_out, c->mlp_adam, c->mlp_adam + nw, c->mlp_grad, nw, t, lr, s));
+    }
+    if (loss_hist) {
+      HIPCHK(c, hipMemcpyAsync(bl.data(), c->mlp_bloss, nb * 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      double sum = 0.0;
+      for (int64_t bi = 0; bi < nb; ++bi) sum += bl[bi];
+      loss_hist[ep] = (float)(sum / nb);
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  return FP_OK;
+}
+
+int fp_particle_block_layout(int64_t capacity, fp_dtype dtype, int64_t* offsets, size_t* bytes) {
+  if (capacity <= 0 || !bytes || dtype != FP_F64) return FP_EINVAL;
+  int64_t off[10];
+  size_t total;
+  particle_offsets(capacity, off, &total);
+  if (offsets)
+    for (int a = 0; a < 10; ++a) offsets[a] = off[a];
+  *bytes = total;
+  return FP_OK;
+}
+
+int fp_bind_particles(fp_ctx* c, int64_t capacity, fp_dtype dtype, void* soa) {
+  if (!c) return FP_EINVAL;
+  if (!c->ws) return fail(c, FP_ESTATE, "fp_bind_particles: no workspace");
+  if (!soa) {   // back to the workspace's own particle buffer
+    c->P[0] = carve(c->part0, c->cap);
+    c->bound = false;
+    c->np = 0;
+    c->cur = 0;
+    c->tasks_valid = false;
+    return FP_OK;
+  }
+  if (dtype != FP_F64)
+    return fail(c, FP_EINVAL, "fp_bind_particles: the particle block is FP64 in both precisions");
+  if (capacity <= 0 || capacity > c->cap)
+    return fail(c, FP_EINVAL, "fp_bind_particles: capacity must be in (0, workspace particle capacity]");
+  if (((uintptr_t)soa) & 255) return fail(c, FP_EINVAL, "fp_bind_particles: block not 256-byte aligned");
+  c->P[0] = carve((char*)soa, capacity);
+  c->bound = true;
+  c->np = 0;
+  c->cur = 0;
+  c->tasks_valid = false;
   return FP_OK;
 }
 

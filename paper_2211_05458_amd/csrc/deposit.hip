@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Flui
   double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
   double xi[3];
   int it = 0, calls = 0, fb = 0;
-  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb)) return;
+  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb) || !inside_ref(xi)) return;
   double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
   double Fq[3];
   source_force<NN, NG, UT>(m, fl, fm, e, xi, v, P.d[p], Fq);

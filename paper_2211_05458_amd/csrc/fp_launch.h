@@ -13,6 +13,11 @@ hipError_t launch_face_setup(const MeshView& m, const double* X, const int32_t* 
 hipError_t launch_nodes(const MeshView& m, double* xnode, double* vol, double* hE, double* nbox, double* gxi,
                         int32_t* bad, unsigned long long* node_pad, hipStream_t s);
 hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* hint, int64_t n, hipStream_t s);
+// smallest of n doubles that are all positive, as the complement of its bit
+// pattern (*inv_bits, zeroed by the caller, receives the largest complement),
+// and the count of entries that are not positive and finite (*bad, zeroed)
+hipError_t launch_min_positive(const double* d, int64_t n, unsigned long long* inv_bits, int32_t* bad,
+                               hipStream_t s);
 struct StageLaunch {
   MeshView m;
   Particles P;

@@ -238,6 +238,37 @@ __global__ __launch_bounds__(256) void k_locate(MeshView m, Particles P, const i
   }
 }
 
+// positive doubles order like their bit patterns, so the largest complement
+// of the bits is the complement of the smallest value's bits
+__global__ __launch_bounds__(256) void k_min_positive(const double* __restrict__ d, int64_t n,
+                                                      unsigned long long* inv_bits, int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long m = 0;
+  int b = 0;
+  if (i < n) {
+    const double v = d[i];
+    if (v > 0.0 && v < INFINITY) m = ~(unsigned long long)__double_as_longlong(v);
+    else b = 1;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+    b += __shfl_xor(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (m) atomicMax(inv_bits, m);
+    if (b) atomicAdd(bad, b);
+  }
+}
+
+hipError_t launch_min_positive(const double* d, int64_t n, unsigned long long* inv_bits, int32_t* bad,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_min_positive<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(d, n, inv_bits, bad);
+  return hipGetLastError();
+}
+
 // reference coordinates of the current positions, with the inside check
 template <int NN, int NG>
 __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, unsigned long long* stats) {
@@ -287,7 +318,9 @@ __global__ __launch_bounds__(256) void k_deposit_nearest(MeshView m, Particles P
   double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
   double xi[3];
   int it = 0, calls = 0, fb = 0;
-  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb)) return;
+  // the source is taken in the element that contains the particle (the
+  // caller locates every particle before the deposit)
+  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb) || !inside_ref(xi)) return;
   double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
   double F[3];
   source_force<NN, NG, UT>(m, fl, fm, e, xi, v, P.d[p], F);

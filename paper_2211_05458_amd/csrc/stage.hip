@@ -196,10 +196,14 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
                           (xe[2] - x[2]) * (xe[2] - x[2]);
         const double ds = m.dsafe[e];
         if (!(sp.refspace && L2 < ds * ds)) {
-          reach = reachable_faces(m, e, xi, L2);
+          // the sampled reach bounds only drop faces of segments that cannot
+          // reach a wall, open or periodic face (certified distance dsafe):
+          // a crossing they miss is then an internal one, which the location
+          // step repairs exactly by following xi to the neighbour
+          reach = L2 < ds * ds ? reachable_faces(m, e, xi, L2) : 0x3Fu;
 #pragma unroll 1
           for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
-          if (kReach2<NG> && any) {
+          if (kReach2<NG> && any && L2 < ds * ds) {
             reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach);
             any = false;
 #pragma unroll 1
@@ -313,10 +317,10 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
           const double ds = m.dsafe[e];
           if (!(sp.refspace && L2 < ds * ds)) {
             const FaceRec* Fe = m.faces + (size_t)e * 6;
-            reach = reachable_faces(m, e, xi, L2);
+            reach = L2 < ds * ds ? reachable_faces(m, e, xi, L2) : 0x3Fu;
 #pragma unroll 1
             for (int f = 0; f < 6 && !trk; ++f) trk = ((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe);
-            if (kReach2<NG> && trk) {
+            if (kReach2<NG> && trk && L2 < ds * ds) {
               reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach);
               trk = false;
 #pragma unroll 1

@@ -24,7 +24,8 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_deposit_source", "fp_read_particles", "fp_get_stats", "fp_reset_stats",
            "fp_mlp_n_weights", "fp_mlp_features", "fp_newton_pairs", "fp_mlp_forward",
            "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged",
-           "fp_set_timing", "fp_get_timing", "fp_node_volumes"]
+           "fp_set_timing", "fp_get_timing", "fp_node_volumes", "fp_bind_particles",
+           "fp_particle_block_layout", "fp_mlp_train"]
 TIMING_CLASSES = ("sort", "stage_elem", "finalize", "deposit_nearest", "deposit_shape", "stage_lane", "track")
 
 
@@ -92,6 +93,9 @@ def load():
     L.fp_set_timing.argtypes = [P, I32]
     L.fp_node_volumes.argtypes = [P, P]
     L.fp_get_timing.argtypes = [P, P]
+    L.fp_particle_block_layout.argtypes = [I64, C.c_int, P, C.POINTER(C.c_size_t)]
+    L.fp_bind_particles.argtypes = [P, I64, C.c_int, P]
+    L.fp_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, P, P]
     for name in EXPORTS:       # every documented entry point must resolve
         getattr(L, name)
     _lib = L
@@ -183,17 +187,39 @@ class FlexiPart:
         dt = F64 if U.dtype == t.float64 else F32
         self._check(self.L.fp_set_fluid_state(self.ctx, _ptr(U), dt, C.byref(prm)), "fp_set_fluid_state")
 
-    def push(self, x, v, d, elem_hint=None):
-        x = np.ascontiguousarray(x, np.float64)
-        v = np.ascontiguousarray(v, np.float64)
-        d = np.ascontiguousarray(d, np.float64)
-        n = x.shape[0]
+    def push(self, x, v, d, elem_hint=None, n=None):
+        """Host arrays x, v, d; or x = v = d = None with a bound particle block
+        whose first n entries of x, v and d are already filled."""
+        if x is None:
+            xp = vp = dp = None
+        else:
+            x = np.ascontiguousarray(x, np.float64)
+            v = np.ascontiguousarray(v, np.float64)
+            d = np.ascontiguousarray(d, np.float64)
+            n = x.shape[0]
+            xp, vp, dp = _ptr(x), _ptr(v), _ptr(d)
         h = np.ascontiguousarray(elem_hint, np.int32) if elem_hint is not None else None
         st = np.zeros(n, np.int32)
-        rc = self._check(self.L.fp_push_particles(self.ctx, n, _ptr(x), _ptr(v), _ptr(d), _ptr(h), _ptr(st)),
-                         "fp_push_particles")
+        rc = self._check(self.L.fp_push_particles(self.ctx, n, xp, vp, dp, _ptr(h), _ptr(st)), "fp_push_particles")
         self.np = n
         return st, rc
+
+    @staticmethod
+    def particle_block_layout(capacity):
+        """(byte offsets of the 10 arrays, block bytes) of a caller-owned particle block."""
+        off = np.zeros(10, np.int64)
+        nb = C.c_size_t(0)
+        rc = load().fp_particle_block_layout(int(capacity), F64, _ptr(off), C.byref(nb))
+        if rc != 0:
+            raise FPError("fp_particle_block_layout failed (%d)" % rc)
+        return off, nb.value
+
+    def bind_particles(self, block, capacity):
+        """Bind a caller-owned device block (uint8 tensor of the documented layout),
+        or None to return to the workspace's own particle buffer."""
+        self.block = block
+        self._check(self.L.fp_bind_particles(self.ctx, int(capacity), F64, _ptr(block)), "fp_bind_particles")
+        self.np = 0
 
     def step(self, dt, n_steps=1, rk=1, drag=1, precision=0, guess=0, sort_every=1, max_newton_it=50,
              max_crossings=64, gravity=(0.0, 0.0, 0.0), tracking=0, forces=0):
@@ -295,24 +321,15 @@ class FlexiPart:
                     "fp_mlp_train_epoch")
         return tt.value, losses[:n // batch]
 
-    def mlp_train(self, feat, target, epochs=20, batch=4096, lr=1e-3, seed=4, w0=None):
-        """Minibatch Adam on the GPU kernels; returns (weights, mean loss per epoch).
-
-        The initial weights (Xavier-uniform, zero biases) and the per-epoch row
-        order are drawn on the host from `seed` and passed in."""
+    def mlp_train(self, feat, target, epochs=20, batch=4096, lr=1e-3, seed=4):
+        """Train from scratch with fp_mlp_train (initial weights and row orders
+        drawn by the library from `seed`); returns (weights, mean loss per epoch)."""
         t = self.torch
-        rng = np.random.default_rng(seed)
-        w = t.tensor(xavier_init(rng) if w0 is None else np.asarray(w0), dtype=t.float32, device=self.device)
-        m = t.zeros_like(w)
-        v = t.zeros_like(w)
-        step = 0
-        hist = []
-        n = feat.shape[0]
-        for _ in range(epochs):
-            order = t.tensor(rng.permutation(n).astype(np.int32), device=self.device)
-            step, losses = self.mlp_train_epoch(w, m, v, step, feat, target, order, batch, lr)
-            hist.append(float(losses.mean().item()) if losses.numel() else float("nan"))
-        return w, hist
+        w = t.empty(self.mlp_n_weights(), dtype=t.float32, device=self.device)
+        hist = np.zeros(max(int(epochs), 1), np.float32)
+        self._check(self.L.fp_mlp_train(self.ctx, _ptr(feat), _ptr(target), int(feat.shape[0]), int(epochs),
+                                        int(batch), float(lr), int(seed), _ptr(w), _ptr(hist)), "fp_mlp_train")
+        return w, [float(v) for v in hist[:epochs]]
 
     def mlp_set_weights(self, w, thresh=0.05):
         self.mlp_w = w

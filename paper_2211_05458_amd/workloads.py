@@ -292,7 +292,7 @@ def sine_map_logical(s, amp=0.05):
     return out
 
 
-def sine_mesh(cells, n_geo=4, amp=0.05):
+def sine_mesh(cells, n_geo=4, amp=0.05, wall_bc=BC_REFLECT):
     def node_map(I1, I2, I3, M):
         shp = np.broadcast_shapes(I1.shape, I2.shape, I3.shape)
         s1 = np.broadcast_to(I1 / M[0], shp)
@@ -308,15 +308,16 @@ def sine_mesh(cells, n_geo=4, amp=0.05):
         return out
     cc = (cells, cells, cells)
     X, ne, nf, bc, sh, _ = structured_mesh(cc, n_geo, node_map, (True, False, True),
-                                           periods=np.eye(3))
+                                           periods=np.eye(3), wall_bc=wall_bc)
     return Mesh(n_geo, X, ne, nf, bc, sh, h=1.0 / cells, cells=cc)
 
 
 def curved_box(cells=32, N=5, n_particles=1_000_000, n_steps=500, seed=1002, name="config2",
-               n_geo=4):
-    """Sine-mapped periodic (x, z) box with curved reflective walls at logical y=0/1."""
+               n_geo=4, wall_bc=BC_REFLECT):
+    """Sine-mapped periodic (x, z) box with curved walls (reflective, or open
+    with wall_bc=BC_OPEN) at logical y=0/1."""
     rng = np.random.default_rng(seed)
-    mesh = sine_mesh(cells, n_geo)
+    mesh = sine_mesh(cells, n_geo, wall_bc=wall_bc)
     cc = mesh.cells
     field = fourier_field(rng)
     U = _dg_state(cc, N, sine_map_logical, field)

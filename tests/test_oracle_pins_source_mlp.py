@@ -261,3 +261,24 @@ def test_curved_flags_affine_zero_and_bulge_threshold(n_geo):
     mesh = W.single_element(n_geo, lambda xi: xi @ A.T)
     o = O.Oracle(mesh, 1, W.uniform_state(1, 1, (0.0, 0.0, 0.0)))
     assert int(o.curved_flags(1e-9)[0]) == 0
+
+
+# --------------------------------------------------------------------------
+# seeded draws of a training run (SplitMix64, Steele, Lea and Flood 2014)
+# --------------------------------------------------------------------------
+def test_training_draws_follow_the_published_generator():
+    """The first outputs of SplitMix64 seeded with 1234567 are the published
+    test values 6457827717110365317, 3203168211198807973, 9817491932198370423;
+    the first weights are the Xavier-uniform values they give, biases are zero,
+    and every epoch order is a permutation."""
+    published = [6457827717110365317, 3203168211198807973, 9817491932198370423]
+    w0, orders = O.mlp_draws(1234567, 1000, 3)
+    a = math.sqrt(6.0 / (H + NI))
+    ref = [a * (2.0 * ((z >> 11) * 2.0 ** -53) - 1.0) for z in published]
+    np.testing.assert_allclose(w0[:3], ref, rtol=0, atol=1e-16)
+    W1, b1, W2, b2, W3, b3, W4, b4 = _split(w0)
+    assert not b1.any() and not b2.any() and not b3.any() and not b4.any()
+    assert np.abs(W2).max() <= math.sqrt(6.0 / 128) and np.abs(W4).max() <= math.sqrt(6.0 / 67)
+    for ep in range(3):
+        assert sorted(orders[ep].tolist()) == list(range(1000))
+    assert (orders[0] != orders[1]).any()
