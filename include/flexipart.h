@@ -261,6 +261,19 @@ int fp_mlp_forward(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in_d
 /* Mean squared error loss and its gradient over n rows (device; grad[nw]). */
 int fp_mlp_loss_grad(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in_dev,
                      const float* target_dev, float* grad_dev, float* loss_dev);
+/* fp_mlp_loss_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * needs only fp_create (for the stream), no workspace.  The per-row
+ * activations and deltas live in a fixed device array of the library
+ * (FP_MLP_STATIC_ROWS rows of 471 floats, 7.7 MB on each GPU the library runs
+ * on, held until the process ends); every row is written before it is read,
+ * so nothing in it needs clearing.  All calls on one GPU share that array:
+ * calls that overlap on one GPU (two streams, two threads) race.  Same
+ * arguments and results as fp_mlp_loss_grad; n in [1, FP_MLP_STATIC_ROWS]
+ * (FP_EINVAL otherwise).  Allocates nothing.  Asynchronous. */
+#define FP_MLP_STATIC_ROWS 4096
+int fp_mlp_loss_grad_static(fp_ctx* ctx, const float* w_dev, int64_t n, const float* in_dev,
+                            const float* target_dev, float* grad_dev, float* loss_dev);
 /* One epoch of minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) in the row
  * order given by order_dev[n]; w, m, v (device, nw each) updated in place;
  * *t is the Adam step counter; loss_dev[n/batch] receives batch losses. */

@@ -498,6 +498,8 @@ void shuffle(SplitMix64& g, std::vector<int32_t>& a) {
 
 extern "C" {
 
+static_assert(FP_MLP_STATIC_ROWS == kMlpStaticRows, "row limit of fp_mlp_loss_grad_static");
+
 int fp_create(fp_ctx** out, void* hip_stream) {
   if (!out) return FP_EINVAL;
   fp_ctx* c = new fp_ctx();
@@ -1099,6 +1101,17 @@ int fp_mlp_loss_grad(fp_ctx* c, const float* w, int64_t n, const float* in, cons
   if (!c->ws) return fail(c, FP_ESTATE, "fp_mlp_loss_grad: no workspace");
   if (n > kMlpMaxBatch) return fail(c, FP_EINVAL, "fp_mlp_loss_grad: at most 8192 rows per call");
   HIPCHK(c, launch_mlp_loss_grad(w, n, in, target, nullptr, grad, loss, c->mlp_rows, c->stream));
+  return FP_OK;
+}
+
+int fp_mlp_loss_grad_static(fp_ctx* c, const float* w, int64_t n, const float* in, const float* target,
+                            float* grad, float* loss) {
+  if (!c || !w || !in || !target || !grad || !loss) return FP_EINVAL;
+  if (n <= 0 || n > FP_MLP_STATIC_ROWS)
+    return fail(c, FP_EINVAL, "fp_mlp_loss_grad_static: n must be in [1, FP_MLP_STATIC_ROWS]");
+  float* rows = nullptr;
+  HIPCHK(c, mlp_static_rows(&rows));
+  HIPCHK(c, launch_mlp_loss_grad(w, n, in, target, nullptr, grad, loss, rows, c->stream));
   return FP_OK;
 }
 

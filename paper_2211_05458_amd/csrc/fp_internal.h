@@ -11,6 +11,7 @@ constexpr int kClipStack = 16;      // Bezier-clipping interval stack
 constexpr int kClipSteps = 64;      // clipping iterations per face test
 constexpr int kMaxRoots = 8;
 constexpr int kMlpMaxBatch = 8192;   // rows per MLP gradient evaluation
+constexpr int kMlpStaticRows = 4096; // rows of fp_mlp_loss_grad_static (fixed device array)
 constexpr int kMlpIn = 84;           // learned-guess inputs: corners, curvature, point
 constexpr int kMlpRow = kMlpIn + 6 * 64 + 3;  // activations and deltas kept per row
 constexpr int kMlpWeights = 64 * kMlpIn + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3;

@@ -61,6 +61,9 @@ hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n,
 hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s);
 hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,
                                 const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s);
+// device address of the fixed row buffer of fp_mlp_loss_grad_static on the
+// current device (kMlpStaticRows rows)
+hipError_t mlp_static_rows(float** out);
 hipError_t launch_adam(float* w, float* m, float* v, const float* g, int64_t nw, int64_t t, float lr,
                        hipStream_t s);
 hipError_t launch_curved_flags(const MeshView& m, double thresh, uint8_t* flag, int32_t* count, hipStream_t s);

@@ -1,6 +1,8 @@
 // Learned Newton initial guess: features, training pairs from Newton, a
 // 84-64-64-64-3 tanh MLP (forward, backward, Adam) in FP32, and the flags of
 // strongly curved elements on which the guess is used.
+#include <mutex>
+
 #include "fp_device.h"
 #include "fp_launch.h"
 
@@ -277,6 +279,37 @@ hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float*
   if (n == 0) return hipSuccess;
   k_mlp_forward<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(w, n, in, out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Row buffer of fp_mlp_loss_grad_static (callers that cannot allocate): a
+// fixed device array, one copy per GPU, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address reaches kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[(size_t)kMlpStaticRows * ROW];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float* scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_static_rows(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = (float*)p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,

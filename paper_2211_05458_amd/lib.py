@@ -25,7 +25,7 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_mlp_n_weights", "fp_mlp_features", "fp_newton_pairs", "fp_mlp_forward",
            "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged",
            "fp_set_timing", "fp_get_timing", "fp_node_volumes", "fp_bind_particles",
-           "fp_particle_block_layout", "fp_mlp_train"]
+           "fp_particle_block_layout", "fp_mlp_train", "fp_mlp_loss_grad_static"]
 TIMING_CLASSES = ("sort", "stage_elem", "finalize", "deposit_nearest", "deposit_shape", "stage_lane", "track")
 
 
@@ -96,6 +96,7 @@ def load():
     L.fp_particle_block_layout.argtypes = [I64, C.c_int, P, C.POINTER(C.c_size_t)]
     L.fp_bind_particles.argtypes = [P, I64, C.c_int, P]
     L.fp_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, P, P]
+    L.fp_mlp_loss_grad_static.argtypes = [P, P, I64, P, P, P, P]
     for name in EXPORTS:       # every documented entry point must resolve
         getattr(L, name)
     _lib = L
