@@ -219,14 +219,16 @@ int fp_node_volumes(fp_ctx* ctx, double* V_dev);
 int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* elem, double* xi,
                       int32_t* wall_hits, int8_t* status);
 
-/* Counters since the last reset (host out[10]): out[0] Newton iterations,
+/* Counters since the last reset (host out[11]): out[0] Newton iterations,
  * out[1] Newton solves, out[2] face crossings, out[3] wall hits, out[4] lost
  * particles, out[5] learned-guess fallbacks, out[6] sorts, out[7]
  * particle-stages taken by the per-lane kernel (they left their sorted element
  * or lie outside it), out[8] particle-stages queued for face intersection,
  * out[9] particles recovered in a neighbour element after a crossing the face
- * intersection missed (see fp_step).  Synchronises. */
-int fp_get_stats(fp_ctx* ctx, int64_t* out10);
+ * intersection missed (see fp_step), out[10] (particle, DG node) pairs within
+ * the shape-kernel radius evaluated by FP32 sources (the kernel's unit of
+ * work).  Synchronises. */
+int fp_get_stats(fp_ctx* ctx, int64_t* out11);
 int fp_reset_stats(fp_ctx* ctx);
 
 /* ---- kernel timing (tracing) ---------------------------------------------

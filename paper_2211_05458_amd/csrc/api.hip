@@ -39,6 +39,10 @@ struct fp_ctx {
   int32_t* scratch_i32 = nullptr;
   uint8_t* mlp_flag = nullptr;
   double* dep_buf = nullptr;   // per-particle force (4 doubles), then a validity flag (int32)
+  // candidate lists of the FP32 shape-kernel source, valid for (dl_R, dl_per)
+  int32_t *dl_count = nullptr, *dl_start = nullptr, *dl_list = nullptr;
+  bool dl_valid = false, dl_tried = false;
+  double dl_R = 0.0, dl_per[3] = {0, 0, 0}, dl_pad = 0.0;
   unsigned long long* dep_pad = nullptr;   // largest distance of a particle outside its element box
   float* mlp_rows = nullptr;   // per-row activations for MLP gradients
   float* mlp_grad = nullptr;   // gradient + loss scratch
@@ -54,7 +58,7 @@ struct fp_ctx {
   int64_t np = 0;
   double d_min = 0.0;
   bool xi_dirty = false;
-  bool sorted_valid = false;
+  bool sorted_fresh = false;   // sorted by element, and no particle moved since
   int64_t steps_done = 0, sorts = 0;
   // caller-owned particle block (fp_bind_particles): P[0] then lives there and
   // holds the current state after every call that moves particles
@@ -232,7 +236,7 @@ void particle_offsets(int64_t cap, int64_t* off, size_t* total) {
 
 struct Layout {
   size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, gxi, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
-      mlp_flag, mlp_h1, mlp_ctr, mlp_w, mlp_adam, mlp_order, mlp_bloss, stats,
+      mlp_flag, mlp_h1, mlp_ctr, mlp_w, mlp_adam, mlp_order, mlp_bloss, dl_count, dl_start, dl_list, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
       strag, trk_p, trk_x, trk_m, part[2], total;
   size_t part_bytes;
@@ -268,6 +272,9 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.mlp_adam = take((size_t)kMlpWeights * 2 * 4);
   L.mlp_order = take((size_t)std::max<int64_t>(cap, 1) * 4);
   L.mlp_bloss = take((size_t)std::max<int64_t>(cap, 1) * 4);
+  L.dl_count = take((E + 1) * 4);
+  L.dl_start = take((E + 1) * 4);
+  L.dl_list = take(E * (size_t)kDepListPerElem * 4);
   L.stats = take(16 * kStatSlots * 8);
   L.sort_count = take((E + 1) * 4);
   L.sort_start = take((E + 1) * 4);
@@ -434,6 +441,7 @@ int sort_particles(fp_ctx* c, int tp) {
                         c->sort_sums, s));
   c->cur = 1 - c->cur;
   c->sorts++;
+  c->sorted_fresh = true;
   HIPCHK(c, launch_tasks(c->sort_count, c->sort_start, c->E, tp, c->tcount, c->tstart, c->sort_sums, c->tasks,
                          c->qcnt + 4, (int64_t)c->E + c->cap / tp + 2, s));
   c->tasks_valid = true;
@@ -746,6 +754,10 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   c->mlp_order = (int32_t*)(b + L.mlp_order);
   c->mlp_bloss = (float*)(b + L.mlp_bloss);
   c->mlp_w = nullptr;
+  c->dl_count = (int32_t*)(b + L.dl_count);
+  c->dl_start = (int32_t*)(b + L.dl_start);
+  c->dl_list = (int32_t*)(b + L.dl_list);
+  c->dl_valid = c->dl_tried = false;
   HIPCHK(c, hipMemsetAsync(c->scratch_i32, 0, 64, s));
   HIPCHK(c, launch_face_setup(m, m.X, (const int32_t*)(b + L.nbr_elem), (const int32_t*)(b + L.nbr_face),
                               (const int8_t*)(b + L.bc), (const double*)(b + L.shift), c->Minv.data(),
@@ -841,6 +853,7 @@ int fp_push_particles(fp_ctx* c, int64_t n, const double* x, const double* v, co
   c->d_min = dmin;
   c->xi_dirty = false;
   c->tasks_valid = false;
+  c->sorted_fresh = false;
   c->steps_done = 0;
   return nrej;
 }
@@ -876,10 +889,16 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   hipStream_t s = c->stream;
   for (int st = 0; st < n_steps; ++st) {
     if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
-      Timed tm(c, 0);
-      int rc = sort_particles(c, task_particles(c->n, c->ng, o->precision == 1));
-      if (rc) return rc;
+      const int tp = task_particles(c->n, c->ng, o->precision == 1);
+      // a sort since the particles last moved (the shape-kernel source sorts
+      // after locating them) already holds the tasks of this step
+      if (!(c->sorted_fresh && c->tasks_valid && c->task_tp == tp)) {
+        Timed tm(c, 0);
+        int rc = sort_particles(c, tp);
+        if (rc) return rc;
+      }
     }
+    c->sorted_fresh = false;
     for (int i = 0; i < S; ++i) {
       sp.A = A[i];
       sp.B = B[i];
@@ -947,6 +966,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
     Timed tm(c, 2);
     HIPCHK(c, launch_finalize(c->mv, c->P[c->cur], c->np, c->stats, c->stream));
     c->xi_dirty = false;
+    c->sorted_fresh = false;
   }
   if (kind == 0) {
     Timed tm(c, 3);
@@ -957,6 +977,27 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   if (period)
     for (int k = 0; k < 3; ++k) per[k] = period[k];
   if (c->np == 0) return FP_OK;
+  // FP32 source: candidate lists for this radius and these periods, built
+  // once (they depend on the mesh only); over budget, the kernels search
+  if (dt == FP_F32 && (!c->dl_tried || c->dl_R != radius || c->dl_per[0] != per[0] || c->dl_per[1] != per[1] ||
+                       c->dl_per[2] != per[2])) {
+    Timed tm(c, 4);
+    c->dl_tried = true;
+    c->dl_valid = false;
+    c->dl_R = radius;
+    for (int k = 0; k < 3; ++k) c->dl_per[k] = per[k];
+    c->dl_pad = 0.05 * c->max_extent;
+    HIPCHK(c, launch_dep_lists(c->mv, radius, per, c->dl_pad, 0, c->dl_count, nullptr, nullptr, c->stream));
+    HIPCHK(c, scan_i32(c->dl_count, c->dl_start, (int64_t)c->E + 1, c->sort_sums, c->stream));
+    int32_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, c->dl_start + c->E, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // entries pack the element in 27 bits
+    if (total >= 0 && (size_t)total <= (size_t)c->E * kDepListPerElem && c->E < (1 << 27)) {
+      HIPCHK(c, launch_dep_lists(c->mv, radius, per, c->dl_pad, 1, nullptr, c->dl_start, c->dl_list, c->stream));
+      c->dl_valid = true;
+    }
+  }
   // gather needs the particles bucketed by their current element (tasks for
   // the stage that ran last)
   int rc = sort_particles(c, c->task_tp);
@@ -964,7 +1005,9 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   {
     Timed tm(c, 4);
     HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
-                                   c->node_pad, c->dep_buf, c->sort_start, c->dep_pad, c->stream));
+                                   c->node_pad, c->dep_buf, c->sort_start, c->dep_pad,
+                                   c->stats + ST_DEP_PAIRS * kStatSlots, c->dl_valid ? c->dl_start : nullptr,
+                                   c->dl_list, c->dl_pad, c->stream));
   }
   return sync_bound(c);
 }
@@ -991,6 +1034,7 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
     Timed tm(c, 2);
     HIPCHK(c, launch_finalize(c->mv, P, n, c->stats, s));
     c->xi_dirty = false;
+    c->sorted_fresh = false;
   }
   std::vector<double> hx((size_t)n * 3), hv((size_t)n * 3), hxi((size_t)n * 3);
   std::vector<int32_t> he(n), hh(n), hid(n);
@@ -1021,6 +1065,7 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
 }
 
 int fp_get_stats(fp_ctx* c, int64_t* out) {
+  static_assert(ST_N <= 16, "the stats area holds 16 counters");
   if (!c || !out) return FP_EINVAL;
   if (!c->ws) return fail(c, FP_ESTATE, "fp_get_stats: no workspace");
   std::vector<unsigned long long> slots((size_t)ST_N * kStatSlots);
@@ -1034,6 +1079,7 @@ int fp_get_stats(fp_ctx* c, int64_t* out) {
   out[7] = (int64_t)h[ST_STRAG];
   out[8] = (int64_t)h[ST_TRACKQ];
   out[9] = (int64_t)h[ST_RECOVER];
+  out[10] = (int64_t)h[ST_DEP_PAIRS];
   return FP_OK;
 }
 

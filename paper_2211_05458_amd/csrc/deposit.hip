@@ -170,7 +170,6 @@ template <int NN, int NG, typename UT>
 __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Fluid fl, int64_t n, ForceModel fm,
                                                    double* F, int32_t* ok, unsigned long long* povh) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) *povh = 0ull;
   if (p >= n) return;
   double* Fp = F + p * 4;
   Fp[0] = Fp[1] = Fp[2] = Fp[3] = 0.0;
@@ -179,9 +178,16 @@ __global__ __launch_bounds__(256) void k_dep_force(MeshView m, Particles P, Flui
   const int64_t cap = P.cap;
   int e = P.elem[p];
   double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
-  double xi[3];
-  int it = 0, calls = 0, fb = 0;
-  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb) || !inside_ref(xi)) return;
+  {
+    // largest distance of a particle outside its element's box: the candidate
+    // searches pad the element boxes by it
+    double ov = 0.0;
+    for (int k = 0; k < 3; ++k) ov = fmax(ov, fmax(m.elo[e * 3 + k] - x[k], x[k] - m.ehi[e * 3 + k]));
+    if (ov > 0.0) atomicMax(povh, (unsigned long long)__double_as_longlong(ov));
+  }
+  // the caller has located every particle (reference coordinates in P.xi)
+  const double xi[3] = {P.xi[p], P.xi[cap + p], P.xi[2 * cap + p]};
+  if (!inside_ref(xi)) return;
   double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
   double Fq[3];
   source_force<NN, NG, UT>(m, fl, fm, e, xi, v, P.d[p], Fq);
@@ -475,13 +481,484 @@ __global__ __launch_bounds__(kGatherThreads) void k_dep_gather(MeshView m, Parti
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Candidate lists of the FP32 source: for every target element, the elements
+// (with the periodic image, entry = element | image << 27, unsigned) whose box, shifted
+// by the image, lies within R + pad of the target's node box (Euclidean
+// box-to-box distance).  Built once per radius and periods by two passes of
+// the background-mesh search (count, then fill at the scanned offsets), so
+// the source kernels read their candidates instead of searching.  Particles
+// lie within pad of their element's box as long as the largest overhang
+// measured at the deposit does not exceed pad; otherwise the kernels search.
+// ---------------------------------------------------------------------------
+struct DepLists {
+  const int32_t* start;   // [E + 1]
+  const int32_t* list;
+  double pad;
+  int32_t valid;
+};
+
+__device__ __forceinline__ double box_box_dist2(const double* alo, const double* ahi, const double* blo,
+                                                const double* bhi) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double d = fmax(fmax(alo[k] - bhi[k], blo[k] - ahi[k]), 0.0);
+    s += d * d;
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_dep_lists(MeshView m, DepGeo g, double pad, int pass, int32_t* count,
+                                                   const int32_t* __restrict__ start, int32_t* list) {
+  const int t = blockIdx.x;
+  if (t >= m.E) return;
+  __shared__ CandLds<256> L;
+  const double* nb = m.nbox + (size_t)t * 6;
+  const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
+  const double reach2 = (g.R + pad) * (g.R + pad);
+  int written = 0;
+  stream_candidates<256>(m, g.period, blo, bhi, g.R + pad, L, [&](int nc) {
+    for (int cb = 0; cb < nc; cb += 256) {
+      const int c = cb + threadIdx.x;
+      bool keep = false;
+      int e = 0, code = 0;
+      if (c < nc) {
+        e = L.e[c];
+        code = L.img[c];
+        double sh[3];
+        image_shift(code, g.period, sh);
+        double elo[3], ehi[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          elo[k] = m.elo[e * 3 + k] - sh[k];
+          ehi[k] = m.ehi[e * 3 + k] - sh[k];
+        }
+        keep = box_box_dist2(elo, ehi, blo, bhi) < reach2;
+      }
+      int tot = 0;
+      const int off = block_excl_scan<256>(keep ? 1 : 0, L.wsum, tot);
+      if (pass == 1 && keep) list[start[t] + written + off] = (int32_t)((uint32_t)e | ((uint32_t)code << 27));
+      written += tot;
+    }
+  });
+  if (pass == 0 && threadIdx.x == 0) count[t] = written;
+  if (pass == 0 && t == m.E - 1 && threadIdx.x == 0) count[m.E] = 0;
+}
+
+// body(nc) over the target's candidates in windows of kDepCand (L.e, L.img):
+// from the list when it is valid for the particles' overhang, else by search
+template <int TH, class Body>
+__device__ __forceinline__ void for_candidates(const MeshView& m, const DepGeo& g, const DepLists& dl, int t,
+                                               const double* blo, const double* bhi, double part_pad,
+                                               CandLds<TH>& L, Body&& body) {
+  if (dl.valid && part_pad <= dl.pad) {
+    const int b = dl.start[t], e = dl.start[t + 1];
+    for (int w0 = b; w0 < e; w0 += kDepCand) {
+      const int nc = min(kDepCand, e - w0);
+      for (int c = threadIdx.x; c < nc; c += TH) {
+        const uint32_t v = (uint32_t)dl.list[w0 + c];
+        L.e[c] = (int32_t)(v & ((1u << 27) - 1u));
+        L.img[c] = (int8_t)(v >> 27);
+      }
+      __syncthreads();
+      body(nc);
+      __syncthreads();
+    }
+  } else {
+    stream_candidates<TH>(m, g.period, blo, bhi, g.R + part_pad, L, body);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 source on the matrix cores.  With node and particle positions n, p
+// relative to the target element's centre in units of R,
+//   q = 1 - |n - p|^2 = a(p) . b(n),  a = (1 - |p|^2, 2p, 1),  b = (1, n, -|n|^2),
+// so the kernel argument of 16 particles x 16 nodes is one rank-5 product:
+// two v_mfma_f32_16x16x4f32 (the fifth feature in the second, zero-padded),
+// and K = max(q, 0)^2 leaves two VALU operations per pair.  Both passes are
+// node-major: a workgroup owns one target element, each of its four waves a
+// group of at most TPW 16-node tiles whose features stay in registers; the
+// candidate particles (from the background-mesh candidates of the target) are
+// culled once per workgroup against the target's node box, staged in LDS and
+// processed 16 at a time by every wave.  Pass 1 adds sum_n K V_n of every particle to
+// its normalisation with one float atomic per particle and wave; pass 2
+// accumulates sum_p K G_p per node in registers and adds it to S once.
+// MFMA 16x16x4 lane layout: A[row][k] and B[k][col] sit in lane
+// (row or col) + 16 k; D[row][col] in lane col + 16 (row / 4), register row % 4.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Waves per target element: two (seven tiles each for N = 5, half a tile of
+// padding) up to N = 5, four for N = 7 (eight tiles each); each wave issues
+// the MFMAs of all its node tiles before their VALU work, so up to TPW
+// independent MFMA chains are in flight.
+template <int NN>
+struct NodeTiling {
+  static constexpr int N3 = NN * NN * NN;
+  static constexpr int NT = (N3 + 15) / 16;                          // 16-node tiles per element
+  static constexpr int W = NN >= 8 ? 4 : 2;                          // waves per workgroup
+  static constexpr int TH = 64 * W;
+  static constexpr int TPW = (NT + W - 1) / W;                       // tiles per wave
+  static constexpr int CAP = TH + 16;                                // staged particles
+};
+
+struct __attribute__((aligned(16))) PStage {
+  float g[4];     // G_p (pass 2)
+  float a[5];     // particle features 1 - |p|^2, 2 p, 1
+  int32_t p;      // particle index, -1 for a padding row
+  float pad[2];
+};
+static_assert(sizeof(PStage) == 48, "a staged particle is three float4");
+
+// One wave's node group: features (as A or B operand: k = lane / 16) and the
+// quadrature volumes of the nodes this lane holds in the node-row layout.
+template <int NN>
+struct NodeGroup {
+  static constexpr int TPW = NodeTiling<NN>::TPW;
+  float b0[TPW], b1[TPW];   // features 0..3 (k = lane/16), feature 4 (lanes 0..15) of node tile*16 + lane%16
+  float vrow[TPW][4];       // V of nodes tile*16 + 4 (lane/16) + i (norm pass, node-row layout)
+};
+
+template <int NN>
+__device__ inline void load_node_group(const MeshView& m, int t, const double* ctr, double iR, int wave, int lane,
+                                       NodeGroup<NN>& G) {
+  using T = NodeTiling<NN>;
+  const int t0 = wave * T::TPW;   // tiles past the element's nodes keep zero features (q = 0)
+#pragma unroll
+  for (int tt = 0; tt < T::TPW; ++tt) {
+    const int q = (t0 + tt) * 16 + (lane & 15);
+    float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (q < T::N3) {
+      double r[3], rr = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        r[k] = (m.xnode[((size_t)t * T::N3 + q) * 3 + k] - ctr[k]) * iR;
+        rr += r[k] * r[k];
+      }
+      f[0] = 1.f;
+      f[1] = (float)r[0];
+      f[2] = (float)r[1];
+      f[3] = (float)r[2];
+      f[4] = (float)(-rr);
+    }
+    // feature k = lane / 16 without indexing a private array (scratch)
+    const int kq = lane >> 4;
+    G.b0[tt] = kq == 0 ? f[0] : kq == 1 ? f[1] : kq == 2 ? f[2] : f[3];
+    G.b1[tt] = (kq == 0) ? f[4] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int qr = (t0 + tt) * 16 + 4 * kq + i;
+      G.vrow[tt][i] = (qr < T::N3) ? (float)m.vol[(size_t)t * T::N3 + qr] : 0.f;
+    }
+  }
+}
+
+// Stream the target's candidate particles through the workgroup: for every
+// window of candidate elements each thread takes one candidate particle at a
+// time, keeps it if its force is valid and it lies within R of the target's
+// node box, and the kept ones are appended (features in FP32, relative to the
+// target's centre, units of R) to the shared list s_c; then every wave runs
+// tile(first) on each full 16-particle tile of the list with its own node
+// tiles.  The last partial tile is padded (q = -1, so K = 0) and flushed.
+// All threads of the workgroup must call it.
+
+template <int NN, class Tile>
+__device__ inline void stream_particles(const MeshView& m, const Particles& P, const int32_t* __restrict__ elem_start,
+                                        const DepGeo& g, const DepLists& dl, const int32_t* __restrict__ ok,
+                                        const float* __restrict__ Gp, int t, const double* ctr, double part_pad,
+                                        CandLds<NodeTiling<NN>::TH>& L, int32_t* s_pre, PStage* s_c, Tile&& tile) {
+  constexpr int TH = NodeTiling<NN>::TH;
+  const int64_t cap = P.cap;
+  const double* nb = m.nbox + (size_t)t * 6;
+  const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
+  float flo[3], fhi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    flo[k] = (float)((blo[k] - ctr[k]) * g.iR);
+    fhi[k] = (float)((bhi[k] - ctr[k]) * g.iR);
+  }
+  int n = 0;   // entries in s_c (uniform)
+  for_candidates<TH>(m, g, dl, t, blo, bhi, part_pad, L, [&](int nc) {
+    int T = 0;
+    for (int cb = 0; cb < nc; cb += TH) {
+      const int c = cb + threadIdx.x;
+      const int cntc = (c < nc) ? elem_start[L.e[c] + 1] - elem_start[L.e[c]] : 0;
+      int tot = 0;
+      const int off = block_excl_scan<TH>(cntc, L.wsum, tot);
+      if (c < nc) s_pre[c] = T + off;
+      T += tot;
+    }
+    __syncthreads();
+    for (int jb = 0; jb < T; jb += TH) {
+      const int j = jb + threadIdx.x;
+      bool keep = false;
+      float r[3] = {0.f, 0.f, 0.f}, gg[4] = {0.f, 0.f, 0.f, 0.f};
+      int32_t pi = -1;
+      if (j < T) {
+        int lo = 0, hi = nc - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        const int64_t p = elem_start[L.e[lo]] + (j - s_pre[lo]);
+        if (ok[p]) {
+          double sh[3];
+          image_shift(L.img[lo], g.period, sh);
+          float d2 = 0.f;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            r[k] = (float)((P.x[k * cap + p] - sh[k] - ctr[k]) * g.iR);
+            const float dd = fmaxf(fmaxf(flo[k] - r[k], r[k] - fhi[k]), 0.f);
+            d2 = fmaf(dd, dd, d2);
+          }
+          keep = d2 < 1.f;
+          pi = (int32_t)p;
+          if (Gp) {
+            const float4 gv = *(const float4*)(Gp + p * 8);
+            gg[0] = gv.x; gg[1] = gv.y; gg[2] = gv.z; gg[3] = gv.w;
+          }
+        }
+      }
+      int tot = 0;
+      const int off = block_excl_scan<TH>(keep ? 1 : 0, L.wsum, tot);
+      if (keep) {
+        PStage& S = s_c[n + off];
+        S.g[0] = gg[0]; S.g[1] = gg[1]; S.g[2] = gg[2]; S.g[3] = gg[3];
+        S.a[0] = 1.f - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        S.a[1] = 2.f * r[0];
+        S.a[2] = 2.f * r[1];
+        S.a[3] = 2.f * r[2];
+        S.a[4] = 1.f;
+        S.p = pi;
+      }
+      n += tot;
+      __syncthreads();
+      int first = 0;
+      for (; n - first >= 16; first += 16) tile(first);
+      if (first > 0) {
+        // the remainder (< 16 entries) to the front
+        const int rem = n - first;
+        float4 t0 = make_float4(0.f, 0.f, 0.f, 0.f), t1 = t0, t2 = t0;
+        __syncthreads();
+        if ((int)threadIdx.x < rem) {
+          const float4* src = (const float4*)&s_c[first + threadIdx.x];
+          t0 = src[0]; t1 = src[1]; t2 = src[2];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < rem) {
+          float4* dst = (float4*)&s_c[threadIdx.x];
+          dst[0] = t0; dst[1] = t1; dst[2] = t2;
+        }
+        n = rem;
+      }
+      __syncthreads();
+    }
+  });
+  if (n > 0) {
+    if ((int)threadIdx.x >= n && threadIdx.x < 16) {
+      PStage& S = s_c[threadIdx.x];
+      S.a[0] = -1.f;
+      S.a[1] = S.a[2] = S.a[3] = S.a[4] = 0.f;
+      S.g[0] = S.g[1] = S.g[2] = S.g[3] = 0.f;
+      S.p = -1;
+    }
+    __syncthreads();
+    tile(0);
+  }
+}
+
+// pass 1: norm[p] += sum over the wave's nodes of K V (rows = nodes)
+template <int NN>
+__global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_norm_mfma(MeshView m, Particles P,
+                                                                     const int32_t* __restrict__ elem_start,
+                                                                     DepGeo g, DepLists dl,
+                                                                     const int32_t* __restrict__ ok,
+                                                                     const unsigned long long* __restrict__ povh,
+                                                                     float* norm, unsigned long long* pairs) {
+  using T = NodeTiling<NN>;
+  const int t = xcd_element(blockIdx.x, m.E);
+  if (t >= m.E) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ CandLds<T::TH> L;
+  __shared__ int32_t s_pre[kDepCand + 1];
+  __shared__ PStage s_c[T::CAP];
+  const double* nb = m.nbox + (size_t)t * 6;
+  const double ctr[3] = {0.5 * (nb[0] + nb[3]), 0.5 * (nb[1] + nb[4]), 0.5 * (nb[2] + nb[5])};
+  NodeGroup<NN> NG;
+  load_node_group<NN>(m, t, ctr, g.iR, wave, lane, NG);
+  const double part_pad = __longlong_as_double((long long)*povh);
+  unsigned long long npairs = 0;   // wave-uniform
+  const v4f zero = {0.f, 0.f, 0.f, 0.f};
+  auto tile = [&](int first) {
+    // B operand: features (k = lane / 16) of particle first + lane % 16
+    const PStage& S = s_c[first + (lane & 15)];
+    const int kq = lane >> 4;
+    const float pb0 = S.a[kq];
+    const float pb1 = (kq == 0) ? S.a[4] : 0.f;
+    float acc = 0.f;
+    // node tiles in groups of four: their MFMA chains are in flight together
+#pragma unroll
+    for (int t0 = 0; t0 < T::TPW; t0 += 4) {
+      constexpr int G4 = 4;
+      v4f q[G4];
+#pragma unroll
+      for (int u = 0; u < G4; ++u)
+        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(NG.b0[t0 + u], pb0, zero, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < G4; ++u)
+        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(NG.b1[t0 + u], pb1, q[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < G4; ++u)
+        if (t0 + u < T::TPW)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float w = fmaxf(q[u][i], 0.f);
+            npairs += __popcll(__ballot(w > 0.f));
+            acc = fmaf(w * w, NG.vrow[t0 + u][i], acc);
+          }
+    }
+    // sum over the node rows held by the four lane groups
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (lane < 16 && S.p >= 0 && acc != 0.f) atomicAdd(norm + S.p, acc);
+  };
+  stream_particles<NN>(m, P, elem_start, g, dl, ok, nullptr, t, ctr, part_pad, L, s_pre, s_c, tile);
+  if (pairs && lane == 0 && npairs) atomicAdd(pairs + (blockIdx.x & (kStatSlots - 1)), npairs);
+}
+
+// G_p = -F_p / norm_p (FP32, written over F_p), zero for particles that
+// deposit nothing
+__global__ __launch_bounds__(256) void k_dep_scale(int64_t n, double* F, const int32_t* __restrict__ ok,
+                                                   const float* __restrict__ norm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double nv = norm[p];
+  const bool use = ok[p] && nv > 0.0;
+  const double in = use ? -1.0 / nv : 0.0;
+  double f[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) f[k] = F[p * 4 + k];
+  float* G = (float*)(F + p * 4);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) G[k] = use ? (float)(f[k] * in) : 0.f;
+}
+
+// pass 2: S[node] += sum_p K G_p (rows = particles)
+template <int NN>
+__global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_gather_mfma(MeshView m, Particles P,
+                                                                       const int32_t* __restrict__ elem_start,
+                                                                       DepGeo g, DepLists dl,
+                                                                       const int32_t* __restrict__ ok,
+                                                                       const float* __restrict__ Gp,
+                                                                       const unsigned long long* __restrict__ povh,
+                                                                       float* S) {
+  using T = NodeTiling<NN>;
+  const int t = xcd_element(blockIdx.x, m.E);
+  if (t >= m.E) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ CandLds<T::TH> L;
+  __shared__ int32_t s_pre[kDepCand + 1];
+  __shared__ PStage s_c[T::CAP];
+  const double* nb = m.nbox + (size_t)t * 6;
+  const double ctr[3] = {0.5 * (nb[0] + nb[3]), 0.5 * (nb[1] + nb[4]), 0.5 * (nb[2] + nb[5])};
+  NodeGroup<NN> NG;
+  load_node_group<NN>(m, t, ctr, g.iR, wave, lane, NG);
+  const double part_pad = __longlong_as_double((long long)*povh);
+  float acc[T::TPW][4];
+#pragma unroll
+  for (int tt = 0; tt < T::TPW; ++tt)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[tt][c] = 0.f;
+  const v4f zero = {0.f, 0.f, 0.f, 0.f};
+  auto tile = [&](int first) {
+    // A operand: features of particle first + lane % 16
+    const PStage& Sa = s_c[first + (lane & 15)];
+    const int kq = lane >> 4;
+    const float pa0 = Sa.a[kq];
+    const float pa1 = (kq == 0) ? Sa.a[4] : 0.f;
+    // G of the four particle rows this lane holds: first + 4 kq + i
+    float gr[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 gv = *(const float4*)s_c[first + 4 * kq + i].g;
+      gr[i][0] = gv.x; gr[i][1] = gv.y; gr[i][2] = gv.z; gr[i][3] = gv.w;
+    }
+    // node tiles in groups of four: their MFMA chains are in flight together
+#pragma unroll
+    for (int t0 = 0; t0 < T::TPW; t0 += 4) {
+      constexpr int G4 = 4;
+      v4f q[G4];
+#pragma unroll
+      for (int u = 0; u < G4; ++u)
+        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa0, NG.b0[t0 + u], zero, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < G4; ++u)
+        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa1, NG.b1[t0 + u], q[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < G4; ++u)
+        if (t0 + u < T::TPW)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float w = fmaxf(q[u][i], 0.f);
+            w *= w;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[t0 + u][c] = fmaf(w, gr[i][c], acc[t0 + u][c]);
+          }
+    }
+  };
+  stream_particles<NN>(m, P, elem_start, g, dl, ok, Gp, t, ctr, part_pad, L, s_pre, s_c, tile);
+  // sum over the particle rows held by the four lane groups, then one
+  // read-modify-write of each node's four components
+  const int t0 = wave * T::TPW;
+#pragma unroll
+  for (int tt = 0; tt < T::TPW; ++tt) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float v = acc[tt][c];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      acc[tt][c] = v;
+    }
+    const int q = (t0 + tt) * 16 + lane;
+    if (lane < 16 && q < T::N3)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float* dst = S + ((size_t)t * 4 + c) * T::N3 + q;
+        *dst += acc[tt][c];
+      }
+  }
+}
+
+__global__ void k_dep_reset(unsigned long long* povh, float* norm, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *povh = 0ull;
+  if (i < n) norm[i] = 0.f;
+}
+
 }  // namespace
 
 #include "fp_shapes.h"
 
+hipError_t launch_dep_lists(const MeshView& m, double R, const double* period, double pad, int pass,
+                            int32_t* count, const int32_t* start, int32_t* list, hipStream_t s) {
+  DepGeo g{};
+  g.R = R;
+  g.R2 = R * R;
+  g.iR = 1.0 / R;
+  for (int k = 0; k < 3; ++k) g.period[k] = period[k];
+  k_dep_lists<<<dim3((unsigned)m.E), 256, 0, s>>>(m, g, pad, pass, count, start, list);
+  return hipGetLastError();
+}
+
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
                                 int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
-                                double* dep, const int32_t* elem_start, unsigned long long* povh, hipStream_t s) {
+                                double* dep, const int32_t* elem_start, unsigned long long* povh,
+                                unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
+                                double list_pad, hipStream_t s) {
+  DepLists dl{list_start, list, list_pad, list_start != nullptr ? 1 : 0};
   DepGeo g;
   g.R = R;
   g.R2 = R * R;
@@ -492,13 +969,24 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
   int32_t* ok = (int32_t*)(dep + 4 * P.cap);
   dim3 gp((unsigned)((std::max<int64_t>(n, 1) + 255) / 256));
   dim3 ge((unsigned)(((m.E + kXcd - 1) / kXcd) * kXcd));
+  // FP32 source: the normalisation sums of the matrix-core pass (float[cap],
+  // after the validity flags)
+  float* norm = (float*)(ok + P.cap);
+  k_dep_reset<<<gp, 256, 0, s>>>(povh, norm, s_f32 ? n : 0);
 #define FP_L(A, B)                                                                                           \
   if (m.n == A && m.ng == B) {                                                                               \
     if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                   \
     else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                         \
-    k_dep_norm<A><<<ge, kNormThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                             \
-    if (s_f32) k_dep_gather<A, float><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (float*)S); \
-    else k_dep_gather<A, double><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);    \
+    if (s_f32) {                                                                                             \
+      k_dep_norm_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, P, elem_start, g, dl, ok, povh, norm, pairs);  \
+      k_dep_scale<<<gp, 256, 0, s>>>(n, F, ok, norm);                                                        \
+      k_dep_gather_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, P, elem_start, g, dl, ok, (const float*)F,  \
+                                                            povh,                                            \
+                                                       (float*)S);                                           \
+    } else {                                                                                                 \
+      k_dep_norm<A><<<ge, kNormThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                           \
+      k_dep_gather<A, double><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);       \
+    }                                                                                                        \
     return hipGetLastError();                                                                                \
   }
   FP_FOR_EACH_SHAPE(FP_L)

@@ -29,7 +29,8 @@ constexpr int kRecoverHops = 3;      // neighbour hops when a located particle l
 enum { ACTIVE = 0, OPEN_EXIT = 1, LOST_NEWTON = 2, LOST_TRACK = 3, MAX_CROSS = 4, REJECTED = 5 };
 enum { FACE_PLANAR = 0, FACE_BILINEAR = 1, FACE_CURVED = 2 };
 enum { BC_INTERNAL = 0, BC_OPEN = 1, BC_REFLECT = 2, BC_PERIODIC = 3, BC_MORTAR = 4 };
-enum { ST_NEWTON_IT = 0, ST_NEWTON_CALLS, ST_CROSS, ST_HITS, ST_LOST, ST_FALLBACK, ST_STRAG, ST_TRACKQ, ST_RECOVER, ST_N };
+enum { ST_NEWTON_IT = 0, ST_NEWTON_CALLS, ST_CROSS, ST_HITS, ST_LOST, ST_FALLBACK, ST_STRAG, ST_TRACKQ, ST_RECOVER,
+       ST_DEP_PAIRS, ST_N };
 constexpr int kStatSlots = 64;   // each counter is spread over slots (blockIdx % 64) to avoid atomic contention
 
 // One element face: slab bounding box (Sec. 3.2.4), corner bilinear form,

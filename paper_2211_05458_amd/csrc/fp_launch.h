@@ -48,7 +48,14 @@ hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const F
                                   int s_f32, const ForceModel& fm, hipStream_t s);
 hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
                                 int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
-                                double* dep, const int32_t* elem_start, unsigned long long* povh, hipStream_t s);
+                                double* dep, const int32_t* elem_start, unsigned long long* povh,
+                                unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
+                                double list_pad, hipStream_t s);
+// candidate lists of the FP32 shape-kernel source: pass 0 counts per target
+// (count[E + 1], last entry 0), pass 1 fills list at the scanned start[]
+hipError_t launch_dep_lists(const MeshView& m, double R, const double* period, double pad, int pass,
+                            int32_t* count, const int32_t* start, int32_t* list, hipStream_t s);
+constexpr int kDepListPerElem = 256;   // workspace budget of candidate-list entries per element
 hipError_t launch_sort(const Particles& src, const Particles& dst, int64_t n, int E, int32_t* count,
                        int32_t* start, int32_t* rank, int32_t* block_sums, hipStream_t s);
 hipError_t launch_elem_start(const Particles& P, int64_t n, int E, int32_t* elem_start, hipStream_t s);

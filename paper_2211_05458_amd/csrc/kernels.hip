@@ -315,12 +315,11 @@ __global__ __launch_bounds__(256) void k_deposit_nearest(MeshView m, Particles P
   constexpr int N3 = NN * NN * NN;
   const int64_t cap = P.cap;
   int e = P.elem[p];
-  double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
-  double xi[3];
-  int it = 0, calls = 0, fb = 0;
-  // the source is taken in the element that contains the particle (the
-  // caller locates every particle before the deposit)
-  if (!locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb) || !inside_ref(xi)) return;
+  // the source is taken in the element that contains the particle: the
+  // caller locates every particle before the deposit (reference coordinates
+  // in P.xi)
+  const double xi[3] = {P.xi[p], P.xi[cap + p], P.xi[2 * cap + p]};
+  if (!inside_ref(xi)) return;
   double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
   double F[3];
   source_force<NN, NG, UT>(m, fl, fm, e, xi, v, P.d[p], F);

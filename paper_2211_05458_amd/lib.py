@@ -255,11 +255,11 @@ class FlexiPart:
         return out
 
     def stats(self):
-        s = np.zeros(10, np.int64)
+        s = np.zeros(11, np.int64)
         self._check(self.L.fp_get_stats(self.ctx, _ptr(s)), "fp_get_stats")
         return dict(newton_iters=int(s[0]), newton_calls=int(s[1]), crossings=int(s[2]), wall_hits=int(s[3]),
                     lost=int(s[4]), fallbacks=int(s[5]), sorts=int(s[6]), stragglers=int(s[7]),
-                    track_queue=int(s[8]), recovered=int(s[9]))
+                    track_queue=int(s[8]), recovered=int(s[9]), deposit_pairs=int(s[10]))
 
     def set_timing(self, enable=True):
         self._check(self.L.fp_set_timing(self.ctx, int(bool(enable))), "fp_set_timing")
