@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the per-particle Lagrangian step on one MI355X.
 
-Workload: curved sine-mapped periodic box with curved reflective walls,
-32^3 hexahedra of geometry degree 4, DG degree 5 random-Fourier fluid state,
-1e6 particles, Schiller-Naumann drag, 3-stage low-storage RK, dt = 1e-3, FP64.
-One timed step = one fp_step(dt, 1): counting sort by element, then three fused
-RK-stage launches (guess, Newton, interpolation, drag, update, tracking with
-face intersection, hand-off and wall reflection, inside verification).
+Default line (the largest single-GPU workload): two-way coupling at scale, a
+96^3 curved sine box of geometry degree 4, DG degree 5 random-Fourier state,
+2e7 particles, Schiller-Naumann drag, 3-stage low-storage RK, dt = 1e-3, and
+the polynomial shape-kernel source (R = 1.5 h) deposited after every step.
+One timed step = one fp_step(dt, 1) (counting sort, three stage launches:
+guess, Newton, interpolation, drag, update, tracking) plus the zeroed source
+and one fp_deposit_source.  `value` is the FP32 + learned-guess form (FP32
+interpolation, drag and update, FP64 Newton tail and tracking, the learned
+Newton guess on strongly curved elements, FP32 source on the matrix cores);
+the plain FP64 form (FP64 throughout, FP64 source) runs beside it.  A second
+leg compares the same forms on the annular passage (geometry degree 6, 1e7
+particles), where the learned guess acts.  Every leg states its position
+error against the FP64 oracle after the workload's full step count on a
+fixed subset of its particles, and carries the roofline of its dominant
+kernel; cpu_baseline times the oracle on a bounded sample.
 
-Prints one JSON line.  Also measured: the mixed-precision form (FP32 fluid
-state, FP32 interpolation/drag/RK) with its position error against the FP64
-form, the dominant kernel against its roofline, and the FP64 CPU oracle on a
-bounded sample of the same workload.
+Other workloads for manual runs: --workload curved32 | annulus | precision |
+twoway | mortar; --mode copy is the calibration of the HBM counters.
 """
 from __future__ import annotations
 
@@ -19,80 +26,110 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
-PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
-# the stage kernel's sources and its compile flags
-KERNEL_SOURCES = ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/stage.hip",
-                  "paper_2211_05458_amd/csrc/fp_internal.h", "paper_2211_05458_amd/build.py"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_elem_fp64_curved32_traffic.md")
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (and unpacked FP32 vector)
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+METRIC = "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error"
+INTERP_VARS = 4              # variables the drag law reads (density, momentum)
+# algorithmic flops per (particle, node) pair within R of the shape-kernel
+# source: |x_n - x_p|^2 (8), 1 - r^2/R^2 (2), K = q^2 (1), then K V summed
+# (2, normalisation pass) or K G for four components (8, node-sum pass)
+DEP_FLOPS_NORM = 13
+DEP_FLOPS_GATHER = 19
+TRAFFIC = {   # committed counter summaries: kernel -> (file, sources its hash covers)
+    "k_dep_norm_mfma": ("profiles/k_dep_norm_mfma_twoway96_traffic.md",
+                        ["paper_2211_05458_amd/csrc/deposit.hip", "paper_2211_05458_amd/csrc/fp_internal.h",
+                         "paper_2211_05458_amd/build.py"]),
+    "k_stage_elem": ("profiles/k_stage_elem_fp64_curved32_traffic.md",
+                     ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/stage.hip",
+                      "paper_2211_05458_amd/csrc/fp_internal.h", "paper_2211_05458_amd/build.py"]),
+}
 
 
-def stage_source_hash():
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash(files):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """Per-launch HBM bytes of the stage kernel from the committed counter summary,
-    only if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` from its committed counter summary, only
+    if the summary was taken on the current kernel sources (else None)."""
+    if kernel not in TRAFFIC:
+        return None
+    path, files = TRAFFIC[kernel]
+    path = os.path.join(ROOT, path)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("source_hash:"):
             vals["hash"] = line.split(":", 1)[1].strip()
         if line.startswith("hbm_bytes_per_launch:"):
             vals["bytes"] = float(line.split(":", 1)[1].strip())
-    if vals.get("hash") != stage_source_hash() or "bytes" not in vals:
+    if vals.get("hash") != source_hash(files) or "bytes" not in vals:
         return None
     return vals["bytes"]
 
 
-# variables the drag law reads (density, momentum); the energy is not needed
-INTERP_VARS = 4
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
+# ---------------------------------------------------------------------------
+# algorithmic work per unit
+# ---------------------------------------------------------------------------
 def flops_per_particle_stage(n, ng, newton_it):
-    """Algorithmic flops of one particle-stage: Newton iterations on the
-    geometry map and Jacobian (sum factorisation), interpolation of the drag
-    law's variables, the nearest-node guess, and the drag, update and box
-    tests."""
+    """Newton iterations on the geometry map and Jacobian (sum factorisation),
+    interpolation of the drag law's variables, the nearest-node guess, and the
+    drag, update and box tests."""
     f_newton = 6 * (2 * ng ** 3 + 3 * ng ** 2 + 4 * ng) + 160
     f_interp = 2 * INTERP_VARS * (n ** 3 + n ** 2 + n) + 9 * n ** 2
     f_guess = 8 * ng ** 3
-    f_rest = 300
-    return newton_it * f_newton + f_interp + f_guess + f_rest
+    return newton_it * f_newton + f_interp + f_guess + 300
 
 
-def bytes_per_particle_stage(n, ng, ppe):
-    """Algorithmic HBM bytes of one particle-stage, FP64 state: particle SoA read
-    (x, v, kx, kv, d, elem, status) and write (x, v, kx, kv, elem), plus the
-    element's fluid state (the variables read), geometry and face records amortised
-    over its particles."""
+def bytes_per_particle_stage(n, ng, ppe, ubytes=8):
+    """Particle SoA read (x, v, kx, kv, d, elem, status) and write (x, v, kx, kv,
+    elem), plus the element's fluid state (the variables read), geometry and
+    face records amortised over its particles."""
     soa = (12 * 8 + 8 + 4 + 1) + (12 * 8 + 4)
-    elem = INTERP_VARS * n ** 3 * 8 + 3 * ng ** 3 * 8 + 336
-    return soa + elem / ppe
+    return soa + (INTERP_VARS * n ** 3 * ubytes + 3 * ng ** 3 * 8 + 336) / ppe
 
 
+# ---------------------------------------------------------------------------
+# GPU runs
+# ---------------------------------------------------------------------------
 def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None, keep=False, tracking=0, forces=0,
-            gravity=(0.0, 0.0, 0.0), sort_every=1):
-    """Push w's particles, run `warmup` untimed then `steps` timed fp_step(dt, 1)
-    calls (each followed by deposit(g) if given); returns timings and the state."""
+            gravity=(0.0, 0.0, 0.0), sort_every=1, idx=None):
+    """Push w's particles (or the subset idx), run `warmup` untimed then `steps`
+    timed fp_step(dt, 1) calls, each followed by deposit(g) if given."""
     import numpy as np
     import torch
     from paper_2211_05458_amd.lib import FlexiPart
-    g = FlexiPart(w.mesh, w.N, w.n_particles)
+    x, v, d, h = (w.x, w.v, w.d, w.elem_hint) if idx is None else (w.x[idx], w.v[idx], w.d[idx], w.elem_hint[idx])
+    g = FlexiPart(w.mesh, w.N, len(x))
     g.set_fluid_state(U)
-    st, nrej = g.push(w.x, w.v, w.d, w.elem_hint)
+    st, nrej = g.push(x, v, d, h)
     n_active = int((st == 0).sum())
     n_flagged = g.mlp_set_weights(weights) if weights is not None else 0
     opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=sort_every, guess=guess, tracking=tracking,
@@ -132,8 +169,298 @@ def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None,
     return out
 
 
+def summary(r, K):
+    return {"value": r["n_active"] * K / (r["ms"] * 1e-3), "ms_per_step": r["ms"] / K,
+            "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items() if v > 0},
+            "newton_it_per_solve": r["stats"]["newton_iters"] / max(r["stats"]["newton_calls"], 1),
+            "fallbacks": r["stats"]["fallbacks"], "lost": r["stats"]["lost"]}
+
+
+def stage_roofline(r, w, K, stages, ubytes=8):
+    """k_stage_elem: algorithmic flops (and bytes) of the particle-stages it
+    processed per launch, over its live HIP-event average."""
+    n, ng = w.N + 1, w.mesh.n_geo + 1
+    n_launch, tot_ms = r["timing"]["stage_elem"]
+    if not n_launch:
+        return None
+    avg = tot_ms / n_launch
+    ps = r["n_active"] * stages * K
+    it = r["stats"]["newton_iters"] / max(ps, 1)
+    per_launch = (ps - r["stats"]["stragglers"]) / n_launch
+    fl = flops_per_particle_stage(n, ng, it) * per_launch
+    by = bytes_per_particle_stage(n, ng, r["n_active"] / w.mesh.n_elem, ubytes) * per_launch
+    ach = fl / (avg * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "k_stage_elem", "avg_launch_ms": avg,
+            "particles_per_launch": per_launch, "newton_it_per_particle_stage": it,
+            "algorithmic_bytes_per_launch": by, "hbm_frac": by / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+
+def deposit_roofline(r, pairs_per_deposit, fp32):
+    """Shape-kernel source, normalisation pass (the larger of its two node
+    passes): algorithmic flops of the (particle, node) pairs within R per
+    launch over its live HIP-event average.  The FP32 pass runs on the matrix
+    cores (peak FP32 MFMA), the FP64 pass on the vector units."""
+    n_launch, tot_ms = r["timing"]["deposit_norm"]
+    if not n_launch or not pairs_per_deposit:
+        return None
+    avg = tot_ms / n_launch
+    ach = pairs_per_deposit * DEP_FLOPS_NORM / (avg * 1e-3) / 1e12
+    kern = "k_dep_norm_mfma" if fp32 else "k_dep_norm"
+    peak = PEAK_FP32_MFMA_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    g_launch, g_ms = r["timing"]["deposit_gather"]
+    out = {"bound": "mfma" if fp32 else "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+           "traffic": read_traffic(kern) if fp32 else None, "kernel": kern, "avg_launch_ms": avg,
+           "pairs_within_R_per_launch": pairs_per_deposit, "flops_per_pair": DEP_FLOPS_NORM}
+    if g_launch:
+        ga = g_ms / g_launch
+        gach = pairs_per_deposit * DEP_FLOPS_GATHER / (ga * 1e-3) / 1e12
+        out["node_sum_pass"] = {"kernel": "k_dep_gather_mfma" if fp32 else "k_dep_gather", "avg_launch_ms": ga,
+                                "achieved": gach, "frac": gach / peak, "flops_per_pair": DEP_FLOPS_GATHER}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# error against the oracle after the full step count
+# ---------------------------------------------------------------------------
+TRAPPED_HITS = 20   # particles pressed against a wall bounce this often or more in the oracle run
+
+
+def error_statement(ro, rg, h):
+    """Element and hit-count mismatch fractions and position errors (in element
+    widths h) of the GPU run against the oracle.  Particles pressed against a
+    curved wall by the field's normal component bounce off it every few stages,
+    which amplifies rounding differences of any summation order; they are
+    reported separately."""
+    import numpy as np
+    trapped = ro["hits"] >= TRAPPED_HITS
+    same = (rg["elem"] == ro["elem"]) & (rg["status"] == ro["status"]) & (ro["status"] == 0)
+    dx = np.linalg.norm(rg["x"] - ro["x"], axis=1) / h
+    free = same & ~trapped
+    return {"particles": int(len(ro["x"])), "elem_mismatch_frac": float((rg["elem"] != ro["elem"]).mean()),
+            "status_mismatch": int((rg["status"] != ro["status"]).sum()),
+            "free_hits_mismatch_frac": float((rg["hits"] != ro["hits"])[~trapped].mean()) if (~trapped).any() else 0.0,
+            "free_max_err_h": float(dx[free].max(initial=0.0)),
+            "free_rms_err_h": float(np.sqrt((dx[free] ** 2).mean())) if free.any() else 0.0,
+            "wall_trapped": int(trapped.sum()),
+            "trapped_hits_mismatch_frac": float((rg["hits"] != ro["hits"])[trapped].mean()) if trapped.any() else 0.0,
+            "trapped_max_err_h": float(dx[same & trapped].max(initial=0.0))}
+
+
+def oracle_run(w, idx, steps):
+    import oracle as O
+    o = O.Oracle(w.mesh, w.N, w.U)
+    o.push(w.x[idx], w.v[idx], w.d[idx], w.elem_hint[idx])
+    o.step(w.dt, steps, rk=w.rk, drag=w.drag)
+    return o
+
+
+def errors_vs_oracle(w, idx, steps, forms):
+    """forms: name -> (U, precision, guess, weights); each GPU form runs the
+    particle subset idx for `steps` steps and is compared with the oracle."""
+    o = oracle_run(w, idx, steps)
+    ro = o.read()
+    out = {}
+    for name, (U, prec, guess, wts) in forms.items():
+        rg = run_gpu(w, U, prec, steps, 0, guess=guess, weights=wts, idx=idx)
+        out[name] = error_statement(ro, rg["read"], w.mesh.h)
+        out[name]["after_steps"] = steps
+    return out, o
+
+
+# ---------------------------------------------------------------------------
+# learned guess
+# ---------------------------------------------------------------------------
+def train_guess(w, U, n_pairs, epochs, batch=1024, lr=2e-3, seed=4):
+    """Newton-solved (features, xi) pairs from the first n_pairs particles, then
+    fp_mlp_train on the GPU; returns weights and a training record."""
+    import torch
+    from paper_2211_05458_amd.lib import FlexiPart
+    t0 = time.perf_counter()
+    n = min(n_pairs, w.n_particles)
+    g = FlexiPart(w.mesh, w.N, n)
+    g.set_fluid_state(U)
+    g.push(w.x[:n], w.v[:n], w.d[:n], w.elem_hint[:n])
+    feat, xi = g.newton_pairs()
+    wts, hist = g.mlp_train(feat, xi, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    pred = g.mlp_forward(wts, feat)
+    med = float((pred - xi).abs().max(dim=1).values.median().item())
+    g.close()
+    return wts, {"pairs": int(feat.shape[0]), "epochs": epochs, "batch": batch, "seconds": time.perf_counter() - t0,
+                 "loss_first_epoch": hist[0] if hist else None, "loss_last_epoch": hist[-1] if hist else None,
+                 "median_guess_error": med}
+
+
+# ---------------------------------------------------------------------------
+# the default line
+# ---------------------------------------------------------------------------
+def bench_composite(args):
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+    import oracle as O
+    K, Wm = args.steps, args.warmup
+    log("generating the 96^3 two-way workload")
+    t0 = time.perf_counter()
+    w = W.config5(n_particles=args.particles or 20_000_000)
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+    R = 1.5 * w.mesh.h
+    per = np.array([1.0, 0.0, 1.0])
+    S = {}
+
+    def depositor(dtype):
+        def dep(g):
+            if "S" not in S or S["S"].dtype != dtype:
+                S.clear()
+                S["S"] = torch.zeros((g.E, 4, g.n3), dtype=dtype, device="cuda")
+            S["S"].zero_()
+            g.deposit(S["S"], kind=1, radius=R, period=per)
+        return dep
+
+    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+    log("learned guess: Newton pairs and training")
+    wts, train = train_guess(w, U32, 1_000_000, args.epochs5)
+    log("FP32 + learned-guess run")
+    rv = run_gpu(w, U32, 1, K, Wm, guess=1, weights=wts, deposit=depositor(torch.float32), keep=True)
+    g = rv.pop("ctx")
+    V = g.node_volumes()
+    tot_shape = (S["S"].double() * V[:, None, :]).sum(dim=(0, 2))
+    Sn = g.deposit(None, kind=0, dtype=torch.float64)
+    tot_near = (Sn * V[:, None, :]).sum(dim=(0, 2))
+    cons = float(((tot_shape - tot_near).abs().max() / tot_near.abs().max()).item())
+    g.close()
+    del Sn, V
+    S.clear()
+    pairs = rv["stats"]["deposit_pairs"] / K
+    value = summary(rv, K)
+    value.update({"flagged_elements": rv["n_flagged"], "deposit_conservation_rel_err": cons,
+                  "learned_guess": "enabled on the elements whose geometry deviates from the trilinear corner map "
+                                   "by more than 0.05 h; %d of %d elements are that curved here"
+                                   % (rv["n_flagged"], w.mesh.n_elem)})
+    del U32
+    torch.cuda.empty_cache()
+    log("plain FP64 run")
+    U64 = torch.from_numpy(w.U).cuda()
+    r64 = run_gpu(w, U64, 0, K, Wm, deposit=depositor(torch.float64))
+    S.clear()
+    fp64 = summary(r64, K)
+    fp64["roofline"] = deposit_roofline(r64, pairs, False)
+    fp64["roofline_stage"] = stage_roofline(r64, w, K, 3)
+    torch.cuda.empty_cache()
+    log("error against the oracle (particle subset, %d steps)" % w.n_steps)
+    idx = np.arange(0, w.n_particles, args.err_every)
+    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+    errs, o = errors_vs_oracle(w, idx, w.n_steps, {"fp32_learned": (U32, 1, 1, wts), "fp64": (U64, 0, 0, None)})
+    # the FP32 source of the same subset after the full run (FP64 stepping, so
+    # that only the source's arithmetic differs) against the oracle's source
+    from paper_2211_05458_amd.lib import FlexiPart
+    So = o.deposit(kind=1, radius=R, period=per)
+    gs = FlexiPart(w.mesh, w.N, len(idx))
+    gs.set_fluid_state(U64)
+    gs.push(w.x[idx], w.v[idx], w.d[idx], w.elem_hint[idx])
+    gs.step(w.dt, w.n_steps, rk=w.rk, drag=w.drag, precision=0)
+    Sg = gs.deposit(None, kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy()
+    src_err = float(np.abs(Sg - So).max() / np.abs(So).max())
+    gs.close()
+    del U32, U64
+    torch.cuda.empty_cache()
+    value["error_vs_oracle"] = errs["fp32_learned"]
+    value["error_vs_oracle"]["fp32_source_max_rel_err"] = src_err
+    fp64["error_vs_oracle"] = errs["fp64"]
+    value["roofline_stage"] = stage_roofline(rv, w, K, 3, ubytes=4)
+    roof = deposit_roofline(rv, pairs, True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle sample")
+        cidx = np.arange(0, w.n_particles, args.cpu_every)
+        oc = O.Oracle(w.mesh, w.N, w.U)
+        oc.push(w.x[cidx], w.v[cidx], w.d[cidx], w.elem_hint[cidx])
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_steps):
+            oc.step(w.dt, 1, rk=w.rk, drag=w.drag)
+            oc.deposit(kind=1, radius=R, period=per)
+        el = time.perf_counter() - t0
+        cpu = {"value": len(cidx) * args.cpu_steps / el, "unit": "particle-steps/s", "cores": O.num_threads(),
+               "kind": "oracle", "cpu": cpu_model(),
+               "sample": "one particle in %d (%d of %d) for %d steps of the same workload, each step followed by "
+                         "the shape-kernel source, FP64, %.1f s wall (the oracle's step uses %d threads, its "
+                         "source one)" % (args.cpu_every, len(cidx), w.n_particles, args.cpu_steps, el,
+                                          O.num_threads())}
+    del w
+    annulus = None if args.no_annulus else bench_annulus_leg(args)
+    out = {
+        "metric": METRIC,
+        "value": value["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": value["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "two-way coupling at scale: curved sine box 96^3 Ngeo=4, DG N=5 random-Fourier "
+                               "state, %d particles, Schiller-Naumann, 3-stage LSERK, dt=1e-3, shape-kernel source "
+                               "R=1.5h after every step; FP32 + learned-guess form" % rv["n_active"],
+                   "elements": 884736, "particles": rv["n_active"], "N": 5, "n_geo": 4},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp32_learned": value,
+        "fp64": fp64,
+        "speedup_fp32_learned_vs_fp64": value["value"] / fp64["value"],
+        "training": train,
+        "annulus": annulus,
+    }
+    print(json.dumps(out))
+
+
+def bench_annulus_leg(args):
+    """Annular passage 48x24x48, Ngeo=6, N=5, 1e7 particles: plain FP64 against
+    FP32 + learned guess (and the two halves of that change)."""
+    import numpy as np
+    import torch
+    from paper_2211_05458_amd import workloads as W
+    K, Wm = min(args.steps, args.annulus_steps), min(args.warmup, 2)
+    log("generating the annulus workload")
+    w = W.config4(n_particles=args.annulus_particles)
+    U64 = torch.from_numpy(w.U).cuda()
+    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
+    log("annulus: training")
+    wts, train = train_guess(w, U64, 1_000_000, args.epochs)
+    runs = {}
+    for name, U, prec, guess in [("fp64", U64, 0, 0), ("fp64_learned", U64, 0, 1), ("fp32", U32, 1, 0),
+                                 ("fp32_learned", U32, 1, 1)]:
+        log("annulus run", name)
+        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None)
+    out = {"config": {"workload": "annular passage 48x24x48 Ngeo=6, DG N=5, %d particles, Schiller-Naumann, "
+                                  "3-stage LSERK, dt=1e-3" % w.n_particles, "elements": w.mesh.n_elem},
+           "steps": K, "warmup": Wm, "training": train}
+    for k, r in runs.items():
+        out[k] = summary(r, K)
+        out[k]["flagged_elements"] = r["n_flagged"]
+        out[k]["roofline"] = stage_roofline(r, w, K, 3, ubytes=4 if k.startswith("fp32") else 8)
+        km = r["kernel_ms"]
+        out[k]["dominant_kernel"] = max(("stage_elem", "stage_lane", "track"), key=lambda c: km.get(c, 0.0))
+    log("annulus: error against the oracle (particle subset, %d steps)" % w.n_steps)
+    idx = np.arange(0, w.n_particles, args.err_every // 2)
+    errs, _ = errors_vs_oracle(w, idx, w.n_steps, {"fp32_learned": (U32, 1, 1, wts), "fp64": (U64, 0, 0, None)})
+    out["fp32_learned"]["error_vs_oracle"] = errs["fp32_learned"]
+    out["fp64"]["error_vs_oracle"] = errs["fp64"]
+    out["speedup_fp32_learned_vs_fp64"] = out["fp32_learned"]["value"] / out["fp64"]["value"]
+    del U64, U32
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# other workloads (manual runs)
+# ---------------------------------------------------------------------------
 def pos_error(ref, other, h):
-    """Position difference of two runs from the same initial state."""
+    """Position difference of two GPU runs from the same initial state."""
     import numpy as np
     both = (ref["read"]["status"] == 0) & (other["read"]["status"] == 0)
     dx = np.linalg.norm(other["read"]["x"][both] - ref["read"]["x"][both], axis=1)
@@ -143,157 +470,55 @@ def pos_error(ref, other, h):
             "hits_mismatch_frac": float((other["read"]["hits"] != ref["read"]["hits"]).mean())}
 
 
-def summary(r, K):
-    return {"value": r["n_active"] * K / (r["ms"] * 1e-3), "ms_per_step": r["ms"] / K,
-            "kernel_ms": r["kernel_ms"],
-            "newton_it_per_solve": r["stats"]["newton_iters"] / max(r["stats"]["newton_calls"], 1),
-            "fallbacks": r["stats"]["fallbacks"], "lost": r["stats"]["lost"]}
-
-
-def bench_annulus(args):
-    """Annular-sector passage 48x24x48, Ngeo=6, N=5: plain FP64 against the
-    mixed form with the learned Newton guess trained on the GPU."""
+def bench_single(args):
+    """One workload, FP64 and the alternative forms, per-kernel times."""
     import numpy as np
     import torch
     from paper_2211_05458_amd import workloads as W
-    from paper_2211_05458_amd.lib import FlexiPart
-    n = args.particles or 10_000_000
-    K, Wm = args.steps or 10, args.warmup
-    print("[bench] generating annulus workload", file=sys.stderr, flush=True)
-    w = W.config4(n_particles=n)
+    K, Wm = args.steps, args.warmup
+    name = args.workload
+    if name == "curved32":
+        w = W.config2(n_particles=args.particles or 1_000_000)
+    elif name == "precision":
+        w = W.config3(n_particles=args.particles or 10_000_000)
+    elif name == "annulus":
+        w = W.config4(n_particles=args.particles or 10_000_000)
+    elif name == "twoway":
+        w = W.config5(n_particles=args.particles or 20_000_000)
+    else:
+        w = W.mortar_box(n_geo=4, N=5, refine=(2, 2), n_particles=args.particles or 1_000_000,
+                         cells=(16, 16, 16), seed=1006)
     U64 = torch.from_numpy(w.U).cuda()
     U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
-    print("[bench] training pairs and training", file=sys.stderr, flush=True)
-    n_train = min(n, 1_000_000)
-    t0 = time.perf_counter()
-    g = FlexiPart(w.mesh, w.N, n_train)
-    g.set_fluid_state(U64)
-    g.push(w.x[:n_train], w.v[:n_train], w.d[:n_train], w.elem_hint[:n_train])
-    feat, xi = g.newton_pairs()
-    wts, hist = g.mlp_train(feat, xi, epochs=args.epochs, batch=1024, lr=2e-3, seed=4)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    pred = g.mlp_forward(wts, feat)
-    guess_err = float((pred - xi).abs().max(dim=1).values.median().item())
-    g.close()
+    dep = None
+    if name == "twoway":
+        R, per, S = 1.5 * w.mesh.h, np.array([1.0, 0.0, 1.0]), {}
+
+        def dep(g):
+            if "S" not in S:
+                S["S"] = torch.zeros((g.E, 4, g.n3), dtype=torch.float32, device="cuda")
+            S["S"].zero_()
+            g.deposit(S["S"], kind=1, radius=R, period=per)
+    forms = [("fp64", U64, 0, 0)] if name != "twoway" else []
+    forms += [("fp32", U32, 1, 0)]
+    if name == "mortar":
+        forms = [("fp64", U64, 0, 0), ("fp64_refspace", U64, 0, 0)]
     runs = {}
-    for name, U, prec, guess, tr in [("fp64", U64, 0, 0, 0), ("fp64_learned", U64, 0, 1, 0), ("mixed", U32, 1, 0, 0),
-                                     ("mixed_learned", U32, 1, 1, 0), ("mixed_learned_refspace", U32, 1, 1, 1)]:
-        print("[bench] run", name, file=sys.stderr, flush=True)
-        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None, tracking=tr)
-    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
-           "value": summary(runs["mixed_learned"], K)["value"], "unit": "particle-steps/s", "n_gpus": 1,
-           "steps": K, "warmup": Wm, "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": "annular passage 48x24x48 Ngeo=6, DG N=5, %d particles, Schiller-Naumann, "
-                                  "3-stage LSERK, dt=1e-3" % n, "elements": w.mesh.n_elem},
-           "training": {"pairs": int(feat.shape[0]), "epochs": args.epochs, "batch": 1024, "seconds": train_s,
-                        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-                        "median_guess_error": guess_err, "flagged_elements": runs["fp64_learned"]["n_flagged"]}}
+    for fname, U, prec, guess in forms:
+        log("run", fname)
+        runs[fname] = run_gpu(w, U, prec, K, Wm, guess=guess, deposit=dep,
+                              tracking=1 if fname.endswith("refspace") else 0)
+    out = {"metric": METRIC, "workload": name, "steps": K, "warmup": Wm, "particles": w.n_particles,
+           "elements": w.mesh.n_elem}
+    first = None
     for k, r in runs.items():
         out[k] = summary(r, K)
-        if k != "fp64":
-            out[k].update(pos_error(runs["fp64"], r, w.mesh.h))
-    out["speedup_mixed_learned_vs_fp64"] = out["mixed_learned"]["value"] / out["fp64"]["value"]
-    out["speedup_mixed_learned_refspace_vs_fp64"] = out["mixed_learned_refspace"]["value"] / out["fp64"]["value"]
-    print(json.dumps(out))
-
-
-def bench_precision(args):
-    """64^3 curved box, Ngeo=4, N=7, FP32 fluid state: FP64 against mixed."""
-    import numpy as np
-    import torch
-    from paper_2211_05458_amd import workloads as W
-    n = args.particles or 10_000_000
-    K, Wm = args.steps or 10, args.warmup
-    print("[bench] generating 64^3 N=7 workload", file=sys.stderr, flush=True)
-    w = W.config3(n_particles=n)
-    U64 = torch.from_numpy(w.U).cuda()
-    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
-    del w.U
-    r64 = run_gpu(w, U64, 0, K, Wm)
-    del U64
-    r32 = run_gpu(w, U32, 1, K, Wm)
-    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
-           "value": summary(r32, K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
-           "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": "curved sine box 64^3 Ngeo=4, DG N=7 (fluid state FP32), %d particles, "
-                                  "Schiller-Naumann, 3-stage LSERK, dt=1e-3" % n, "elements": w.mesh.n_elem},
-           "fp64": summary(r64, K), "mixed": summary(r32, K)}
-    out["mixed"].update(pos_error(r64, r32, w.mesh.h))
-    out["mixed"]["after_steps"] = K + Wm
-    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    print(json.dumps(out))
-
-
-def bench_twoway(args):
-    """96^3 curved box, Ngeo=4, N=5, 2e7 particles, mixed form, shape-kernel
-    source (R = 1.5 h) deposited after every step."""
-    import numpy as np
-    import torch
-    from paper_2211_05458_amd import workloads as W
-    n = args.particles or 20_000_000
-    K, Wm = args.steps or 5, min(args.warmup, 2)
-    print("[bench] generating 96^3 workload", file=sys.stderr, flush=True)
-    w = W.config5(n_particles=n)
-    U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
-    del w.U
-    R = 1.5 * w.mesh.h
-    per = np.array([1.0, 0.0, 1.0])
-    S = {}
-
-    def dep(g):
-        if "S" not in S:
-            S["S"] = torch.zeros((g.E, 4, g.n3), dtype=torch.float32, device="cuda")
-        S["S"].zero_()
-        g.deposit(S["S"], kind=1, radius=R, period=per)
-
-    r = run_gpu(w, U32, 1, K, Wm, deposit=dep, keep=True)
-    g = r["ctx"]
-    V = g.node_volumes()
-    tot_shape = (S["S"].double() * V[:, None, :]).sum(dim=(0, 2))
-    Sn = g.deposit(None, kind=0, dtype=torch.float64)
-    tot_near = (Sn * V[:, None, :]).sum(dim=(0, 2))
-    cons = float(((tot_shape - tot_near).abs().max() / tot_near.abs().max()).item())
-    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
-           "value": summary(r, K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
-           "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": "curved sine box 96^3 Ngeo=4, DG N=5, %d particles, mixed form, shape-kernel "
-                                  "two-way source R=1.5h every step" % n, "elements": w.mesh.n_elem},
-           "run": summary(r, K),
-           "conservation_rel_err_fp32": cons,
-           "deposited_momentum": [float(v) for v in tot_near[:3].tolist()]}
-    print(json.dumps(out))
-
-
-def bench_mortar(args):
-    """Non-conforming mesh: a coarse block of 16^3 curved elements (Ngeo=4)
-    against a fine block refined 4:1 across the interface (16x32x32), DG N=5,
-    walls all round, 1e6 particles, FP64.  Every coarse face on the interface
-    is a big mortar face."""
-    import numpy as np
-    import torch
-    from paper_2211_05458_amd import workloads as W
-    n = args.particles or 1_000_000
-    K, Wm = args.steps or 100, args.warmup
-    print("[bench] generating mortar workload", file=sys.stderr, flush=True)
-    w = W.mortar_box(n_geo=4, N=5, refine=(2, 2), n_particles=n, cells=(16, 16, 16), seed=1006)
-    U64 = torch.from_numpy(w.U).cuda()
-    runs = {}
-    for name, tr in (("fp64", 0), ("fp64_refspace", 1)):
-        print("[bench] run", name, file=sys.stderr, flush=True)
-        runs[name] = run_gpu(w, U64, 0, K, Wm, tracking=tr)
-    out = {"metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
-           "value": summary(runs["fp64"], K)["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
-           "warmup": Wm, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "non-conforming box: 16^3 coarse + 16x32x32 fine curved elements (4:1 mortar "
-                                  "interface, %d big faces), Ngeo=4, DG N=5, %d particles, Schiller-Naumann, "
-                                  "3-stage LSERK, dt=1e-3, FP64" % (len(w.mesh.mortar), n),
-                      "elements": w.mesh.n_elem}}
-    for k, r in runs.items():
-        out[k] = summary(r, K)
-        out[k].update({"crossings": r["stats"]["crossings"], "wall_hits": r["stats"]["wall_hits"],
-                       "recovered": r["stats"]["recovered"], "active_end": r["active_end"]})
-    out["fp64_refspace"].update(pos_error(runs["fp64"], runs["fp64_refspace"], w.mesh.h))
+        out[k]["roofline"] = stage_roofline(r, w, K, 3 if w.rk == 1 else 5, ubytes=4 if k.startswith("fp32") else 8)
+        out[k]["stats"] = r["stats"]
+        if first is None:
+            first = r
+        else:
+            out[k].update(pos_error(first, r, w.mesh.h))
     print(json.dumps(out))
 
 
@@ -313,19 +538,20 @@ def copy_calibration(gib=2, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--particles", type=int, default=None)
-    ap.add_argument("--workload", choices=["curved32", "annulus", "precision", "twoway", "mortar"], default="curved32",
-                    help="curved32: the benchmark line; the others measure the remaining workloads")
-    ap.add_argument("--epochs", type=int, default=20, help="learned-guess training epochs (annulus)")
+    ap.add_argument("--workload", choices=["default", "curved32", "annulus", "precision", "twoway", "mortar"],
+                    default="default", help="default: the benchmark line; the others measure one workload")
+    ap.add_argument("--epochs", type=int, default=20, help="learned-guess training epochs (annulus leg)")
+    ap.add_argument("--epochs5", type=int, default=3, help="learned-guess training epochs (two-way workload)")
+    ap.add_argument("--annulus-particles", type=int, default=10_000_000)
+    ap.add_argument("--annulus-steps", type=int, default=10, help="timed steps of the annulus leg")
+    ap.add_argument("--no-annulus", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-refspace", action="store_true", help="skip the reference-space localisation run")
-    ap.add_argument("--no-forces", action="store_true", help="skip the extra-forces run")
-    ap.add_argument("--sort-every", type=int, default=1, help="counting sort by element every k steps")
-    ap.add_argument("--cpu-every", type=int, default=2, help="oracle sample: every k-th particle")
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--err-every", type=int, default=10000, help="error subset: every k-th particle")
+    ap.add_argument("--cpu-every", type=int, default=2500, help="oracle sample: every k-th particle")
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: a plain device copy of known size, the calibration for HBM counters")
     args = ap.parse_args()
@@ -338,134 +564,10 @@ def main():
         sys.exit(2)
     from paper_2211_05458_amd import workloads as W
     W.VERBOSE = True
-    if args.workload != "curved32":
-        {"annulus": bench_annulus, "precision": bench_precision, "twoway": bench_twoway,
-         "mortar": bench_mortar}[args.workload](args)
-        return
-    args.steps = args.steps or 100
-    args.particles = args.particles or 1_000_000
-
-    import numpy as np
-    import torch
-    from paper_2211_05458_amd import workloads as W
-
-    print("[bench] generating workload", file=sys.stderr, flush=True)
-    w = W.config2(n_particles=args.particles)
-    n, ng = w.N + 1, w.mesh.n_geo + 1
-    U64 = torch.from_numpy(w.U).cuda()
-    print("[bench] FP64 run", file=sys.stderr, flush=True)
-    r64 = run_gpu(w, U64, 0, args.steps, args.warmup, sort_every=args.sort_every)
-    K = args.steps
-    value = r64["n_active"] * K / (r64["ms"] * 1e-3)
-    stages = 3
-    n_launch, stage_ms = r64["timing"]["stage_elem"]
-    sort_launch, sort_ms = r64["timing"]["sort"]
-    avg_stage_ms = stage_ms / max(n_launch, 1)
-    ps = r64["n_active"] * stages * K                       # particle-stages timed
-    it_per_ps = r64["stats"]["newton_iters"] / ps
-    fl_ps = flops_per_particle_stage(n, ng, it_per_ps)
-    ppe = r64["n_active"] / w.mesh.n_elem
-    by_ps = bytes_per_particle_stage(n, ng, ppe)
-    # particles handled by the element-wise kernel per launch (the rest left
-    # their sorted element and go through the per-lane kernel)
-    per_launch_particles = (ps - r64["stats"]["stragglers"]) / max(n_launch, 1)
-    per_launch_flops = fl_ps * per_launch_particles
-    per_launch_bytes = by_ps * per_launch_particles
-    kern_ms = r64["kernel_ms"]
-    achieved_tf = per_launch_flops / (avg_stage_ms * 1e-3) / 1e12
-    achieved_gbs = per_launch_bytes / (avg_stage_ms * 1e-3) / 1e9
-    traffic = read_traffic()
-
-    extras = {}
-    if not args.no_mixed:
-        print("[bench] mixed-precision run", file=sys.stderr, flush=True)
-        U32 = torch.from_numpy(w.U.astype(np.float32)).cuda()
-        r32 = run_gpu(w, U32, 1, args.steps, args.warmup)
-        extras["mixed_fp32"] = summary(r32, K)
-        extras["mixed_fp32"].update(pos_error(r64, r32, w.mesh.h))
-        extras["mixed_fp32"].update({
-            "after_steps": args.warmup + K,
-            "learned_guess": "no element of this mesh deviates from its trilinear corner map by "
-                             "more than 0.05 h, so the learned guess is never used here",
-        })
-
-    if not args.no_refspace:
-        # the paper's reference-space localisation: segments that cannot reach a
-        # wall or periodic face are localised by Newton instead of traced
-        print("[bench] reference-space localisation run", file=sys.stderr, flush=True)
-        rr = run_gpu(w, U64, 0, args.steps, args.warmup, tracking=1)
-        extras["fp64_refspace"] = summary(rr, K)
-        extras["fp64_refspace"].update(pos_error(r64, rr, w.mesh.h))
-        extras["fp64_refspace"].update({"crossings_traced": rr["stats"]["crossings"],
-                                        "localised": rr["stats"]["recovered"],
-                                        "track_queue": rr["stats"]["track_queue"]})
-
-    if not args.no_forces:
-        # the extra terms of the equation of motion (buoyancy, undisturbed-flow
-        # stress, added mass, Saffman lift) with gravity; they run through the
-        # per-lane stage kernel
-        print("[bench] extra-forces run", file=sys.stderr, flush=True)
-        rf = run_gpu(w, U64, 0, args.steps, args.warmup, forces=15, gravity=(0.0, -9.81, 0.0))
-        extras["fp64_forces"] = summary(rf, K)
-        extras["fp64_forces"].update({"forces": "buoyancy+stress+added_mass+saffman", "gravity": [0.0, -9.81, 0.0]})
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle as O
-        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        idx = np.arange(0, w.n_particles, args.cpu_every)
-        o = O.Oracle(w.mesh, w.N, w.U)
-        o.push(w.x[idx], w.v[idx], w.d[idx], w.elem_hint[idx])
-        t0 = time.perf_counter()
-        o.step(w.dt, args.cpu_steps, rk=w.rk, drag=w.drag)
-        el = time.perf_counter() - t0
-        cpu = {"value": len(idx) * args.cpu_steps / el, "unit": "particle-steps/s", "cores": O.num_threads(),
-               "kind": "oracle",
-               "sample": "one particle in %d (%d of %d) for %d steps of the same workload, FP64, "
-                         "%.1f s wall" % (args.cpu_every, len(idx), w.n_particles, args.cpu_steps, el)}
-        # the same oracle on one core, over a sixteenth of that sample
-        n_all = O.num_threads()
-        idx1 = idx[::16]
-        o1 = O.Oracle(w.mesh, w.N, w.U)
-        o1.push(w.x[idx1], w.v[idx1], w.d[idx1], w.elem_hint[idx1])
-        O.set_num_threads(1)
-        t0 = time.perf_counter()
-        o1.step(w.dt, args.cpu_steps, rk=w.rk, drag=w.drag)
-        el1 = time.perf_counter() - t0
-        O.set_num_threads(n_all)
-        cpu.update({"value_1core": len(idx1) * args.cpu_steps / el1,
-                    "sample_1core": "%d particles for %d steps on one thread, %.1f s wall" % (len(idx1), args.cpu_steps,
-                                                                                         el1)})
-
-    out = {
-        "metric": "particle-steps/sec/GPU (plain FP64 vs FP32+MLP-guess) at stated position error",
-        "value": value,
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": r64["ms"] / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "curved sine box 32^3 Ngeo=4, DG N=5 random-Fourier state, %d particles, "
-                               "Schiller-Naumann, 3-stage LSERK, dt=1e-3, FP64, one-way" % w.n_particles,
-                   "elements": w.mesh.n_elem, "particles": w.n_particles, "N": w.N, "n_geo": w.mesh.n_geo},
-        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "k_stage_elem<6,5,double,false,false,false>", "avg_launch_ms": avg_stage_ms,
-                     "particles_per_launch": per_launch_particles,
-                     "flops_per_particle_stage": fl_ps, "newton_it_per_particle_stage": it_per_ps,
-                     "algorithmic_bytes_per_launch": per_launch_bytes,
-                     "algorithmic_GBs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS},
-        "kernel_ms": kern_ms,
-        "stats": r64["stats"],
-        "cpu_baseline": cpu,
-    }
-    out.update(extras)
-    print(json.dumps(out))
+    if args.workload == "default":
+        bench_composite(args)
+    else:
+        bench_single(args)
 
 
 if __name__ == "__main__":

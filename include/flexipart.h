@@ -235,10 +235,11 @@ int fp_reset_stats(fp_ctx* ctx);
  * When enabled, HIP events on the context stream bracket every launch of the
  * step and source kernels.  fp_get_timing synchronises and writes, for each
  * class (0 sort, 1 element-wise stage kernel, 2 final reference coordinates,
- * 3 nearest-DOF source, 4 shape-kernel source, 5 per-lane stage kernel,
- * 6 tracking kernel), out[2*k] = launches and out[2*k+1] = total milliseconds
- * since the last call; the counters are then cleared. */
-#define FP_TIMING_CLASSES 7
+ * 3 nearest-DOF source, 4 shape-kernel source (all of its kernels), 5 per-lane
+ * stage kernel, 6 tracking kernel, 7 the shape-kernel source's normalisation
+ * pass, 8 its node-sum pass), out[2*k] = launches and out[2*k+1] = total
+ * milliseconds since the last call; the counters are then cleared. */
+#define FP_TIMING_CLASSES 9
 int fp_set_timing(fp_ctx* ctx, int32_t enable);
 int fp_get_timing(fp_ctx* ctx, double* out /* [2*FP_TIMING_CLASSES] */);
 

@@ -1003,11 +1003,20 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   int rc = sort_particles(c, c->task_tp);
   if (rc) return rc;
   {
-    Timed tm(c, 4);
-    HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
-                                   c->node_pad, c->dep_buf, c->sort_start, c->dep_pad,
-                                   c->stats + ST_DEP_PAIRS * kStatSlots, c->dl_valid ? c->dl_start : nullptr,
-                                   c->dl_list, c->dl_pad, c->stream));
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (c->timing)
+      for (int k = 0; k < 4; ++k) ev[k] = take_event(c);
+    {
+      Timed tm(c, 4);
+      HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
+                                     c->node_pad, c->dep_buf, c->sort_start, c->dep_pad,
+                                     c->stats + ST_DEP_PAIRS * kStatSlots, c->dl_valid ? c->dl_start : nullptr,
+                                     c->dl_list, c->dl_pad, ev, c->stream));
+    }
+    if (c->timing && ev[0] && ev[1] && ev[2] && ev[3]) {
+      c->recs.push_back({7, ev[0], ev[1]});
+      c->recs.push_back({8, ev[2], ev[3]});
+    }
   }
   return sync_bound(c);
 }

@@ -957,8 +957,9 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
                                 double* dep, const int32_t* elem_start, unsigned long long* povh,
                                 unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
-                                double list_pad, hipStream_t s) {
+                                double list_pad, hipEvent_t* ev, hipStream_t s) {
   DepLists dl{list_start, list, list_pad, list_start != nullptr ? 1 : 0};
+  auto rec = [&](int i) { if (ev && ev[i]) hipEventRecord(ev[i], s); };
   DepGeo g;
   g.R = R;
   g.R2 = R * R;
@@ -978,14 +979,21 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
     if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                   \
     else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                         \
     if (s_f32) {                                                                                             \
+      rec(0);                                                                                                \
       k_dep_norm_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, P, elem_start, g, dl, ok, povh, norm, pairs);  \
+      rec(1);                                                                                                \
       k_dep_scale<<<gp, 256, 0, s>>>(n, F, ok, norm);                                                        \
+      rec(2);                                                                                                \
       k_dep_gather_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, P, elem_start, g, dl, ok, (const float*)F,  \
-                                                            povh,                                            \
-                                                       (float*)S);                                           \
+                                                            povh, (float*)S);                                \
+      rec(3);                                                                                                \
     } else {                                                                                                 \
+      rec(0);                                                                                                \
       k_dep_norm<A><<<ge, kNormThreads, 0, s>>>(m, P, elem_start, g, F, ok, povh);                           \
+      rec(1);                                                                                                \
+      rec(2);                                                                                                \
       k_dep_gather<A, double><<<ge, kGatherThreads, 0, s>>>(m, P, elem_start, g, F, povh, (double*)S);       \
+      rec(3);                                                                                                \
     }                                                                                                        \
     return hipGetLastError();                                                                                \
   }

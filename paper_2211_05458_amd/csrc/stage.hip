@@ -99,6 +99,15 @@ __device__ __forceinline__ void stage_update(const MeshView& m, const UT* __rest
   }
 }
 
+// local faces of an element that are not internal (wall, open, periodic,
+// mortar): their crossings cannot be repaired by following xi to a neighbour
+__device__ __forceinline__ unsigned boundary_faces(const FaceRec* __restrict__ Fe) {
+  unsigned b = 0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) b |= (Fe[f].bc != BC_INTERNAL ? 1u : 0u) << f;
+  return b;
+}
+
 struct Task { int32_t e, p0, cnt, pad; };
 
 struct Queues {
@@ -196,15 +205,16 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
                           (xe[2] - x[2]) * (xe[2] - x[2]);
         const double ds = m.dsafe[e];
         if (!(sp.refspace && L2 < ds * ds)) {
-          // the sampled reach bounds only drop faces of segments that cannot
-          // reach a wall, open or periodic face (certified distance dsafe):
-          // a crossing they miss is then an internal one, which the location
-          // step repairs exactly by following xi to the neighbour
-          reach = L2 < ds * ds ? reachable_faces(m, e, xi, L2) : 0x3Fu;
+          // the sampled reach bounds drop internal faces only: the faces that
+          // are not internal (wall, open, periodic) keep their bit and meet the
+          // box test, and a crossing of an internal face the bound misses is
+          // repaired exactly by the location step (xi followed to the neighbour)
+          const unsigned keep = boundary_faces(Fe);
+          reach = reachable_faces(m, e, xi, L2) | keep;
 #pragma unroll 1
           for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
-          if (kReach2<NG> && any && L2 < ds * ds) {
-            reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach);
+          if (kReach2<NG> && any) {
+            reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach) | keep;
             any = false;
 #pragma unroll 1
             for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
@@ -317,11 +327,12 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
           const double ds = m.dsafe[e];
           if (!(sp.refspace && L2 < ds * ds)) {
             const FaceRec* Fe = m.faces + (size_t)e * 6;
-            reach = L2 < ds * ds ? reachable_faces(m, e, xi, L2) : 0x3Fu;
+            const unsigned keep = boundary_faces(Fe);
+            reach = reachable_faces(m, e, xi, L2) | keep;
 #pragma unroll 1
             for (int f = 0; f < 6 && !trk; ++f) trk = ((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe);
-            if (kReach2<NG> && trk && L2 < ds * ds) {
-              reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach);
+            if (kReach2<NG> && trk) {
+              reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach) | keep;
               trk = false;
 #pragma unroll 1
               for (int f = 0; f < 6 && !trk; ++f) trk = ((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe);

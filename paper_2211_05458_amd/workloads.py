@@ -231,9 +231,10 @@ def _dg_state(cells, N, logical_to_phys, field):
                     kk.transpose(2, 1, 0).ravel()], axis=1)          # (n^3, 3)
     cnt = np.array([n1, n2, n3], dtype=np.float64)
     U = np.empty((E, 5, n ** 3))
-    chunk = max(1, 2_000_000 // (n ** 3))
+    chunk = max(1, 500_000 // (n ** 3))
     report = max(chunk, (E // 10) // chunk * chunk)
-    for s in range(0, E, chunk):
+
+    def fill(s):
         if s % report == 0:
             _progress("fluid state", s, E)
         cs = c[s:s + chunk]
@@ -241,7 +242,18 @@ def _dg_state(cells, N, logical_to_phys, field):
         xp = logical_to_phys(sl)
         cv = conservative(field(xp))                                     # (e, n^3, 5)
         U[s:s + chunk] = cv.transpose(0, 2, 1)
+    _chunked(fill, range(0, E, chunk))
     return U
+
+
+def _chunked(fn, starts):
+    """Run fn over independent chunks on a thread pool (numpy releases the GIL
+    in its array operations; every chunk writes its own slice)."""
+    import concurrent.futures as cf
+    import os
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fn, starts))
 
 
 def _particles(rng, cells, n_particles, logical_to_phys, field):
@@ -252,8 +264,14 @@ def _particles(rng, cells, n_particles, logical_to_phys, field):
     d = rng.lognormal(mean=-9.2, sigma=0.3, size=n_particles)
     c = np.stack([e % n1, (e // n1) % n2, e // (n1 * n2)], axis=1).astype(np.float64)
     sl = (c + 0.5 * (xi + 1.0)) / np.array([n1, n2, n3], dtype=np.float64)
-    x = logical_to_phys(sl)
-    v = field(x)
+    x = np.empty_like(sl)
+    v = np.empty_like(sl)
+    chunk = 500_000
+
+    def fill(s):
+        x[s:s + chunk] = logical_to_phys(sl[s:s + chunk])
+        v[s:s + chunk] = field(x[s:s + chunk])
+    _chunked(fill, range(0, n_particles, chunk))
     return x, v, d, e.astype(np.int32)
 
 
