@@ -227,7 +227,7 @@ int fp_read_particles(fp_ctx* ctx, int64_t* n, double* x, double* v, int32_t* el
  * out[9] particles recovered in a neighbour element after a crossing the face
  * intersection missed (see fp_step), out[10] (particle, DG node) pairs within
  * the shape-kernel radius evaluated by FP32 sources (the kernel's unit of
- * work).  Synchronises. */
+ * work), counted only while fp_set_timing's bit 1 is set.  Synchronises. */
 int fp_get_stats(fp_ctx* ctx, int64_t* out11);
 int fp_reset_stats(fp_ctx* ctx);
 
@@ -238,7 +238,10 @@ int fp_reset_stats(fp_ctx* ctx);
  * 3 nearest-DOF source, 4 shape-kernel source (all of its kernels), 5 per-lane
  * stage kernel, 6 tracking kernel, 7 the shape-kernel source's normalisation
  * pass, 8 its node-sum pass), out[2*k] = launches and out[2*k+1] = total
- * milliseconds since the last call; the counters are then cleared. */
+ * milliseconds since the last call; the counters are then cleared.
+ * enable: bit 0 the events, bit 1 the count of shape-kernel pairs within the
+ * radius (fp_get_stats out[10]), which costs the FP32 source's normalisation
+ * pass one more VALU operation per pair. */
 #define FP_TIMING_CLASSES 9
 int fp_set_timing(fp_ctx* ctx, int32_t enable);
 int fp_get_timing(fp_ctx* ctx, double* out /* [2*FP_TIMING_CLASSES] */);

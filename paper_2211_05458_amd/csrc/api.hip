@@ -73,6 +73,7 @@ struct fp_ctx {
   int64_t n_flagged = 0;
   // timing
   bool timing = false;
+  bool count_pairs = false;   // count the shape-kernel pairs within R (timing bit 1)
   std::vector<hipEvent_t> ev_pool;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -281,7 +282,8 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.sort_rank = take((size_t)std::max<int64_t>(cap, 1) * 4);
   L.sort_sums = take(((std::max<size_t>(E + 1, cap) + 1023) / 1024 + 2) * 4);
   L.scratch = take(64);
-  L.dep = take((size_t)std::max<int64_t>(cap, 1) * 5 * 8);
+  // F (4 doubles), validity flag, FP32 normalisation sum, FP32 local position (float4)
+  L.dep = take((size_t)std::max<int64_t>(cap, 1) * 7 * 8 + 16);
   L.mlp_rows = take((size_t)kMlpMaxBatch * kMlpRow * 4);
   L.mlp_grad = take((size_t)(kMlpWeights + 64) * 4);
   size_t pc1 = (size_t)std::max<int64_t>(cap, 1);
@@ -1010,7 +1012,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
       Timed tm(c, 4);
       HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
                                      c->node_pad, c->dep_buf, c->sort_start, c->dep_pad,
-                                     c->stats + ST_DEP_PAIRS * kStatSlots, c->dl_valid ? c->dl_start : nullptr,
+                                     c->count_pairs ? c->stats + ST_DEP_PAIRS * kStatSlots : nullptr, c->dl_valid ? c->dl_start : nullptr,
                                      c->dl_list, c->dl_pad, ev, c->stream));
     }
     if (c->timing && ev[0] && ev[1] && ev[2] && ev[3]) {
@@ -1102,7 +1104,8 @@ int fp_reset_stats(fp_ctx* c) {
 
 int fp_set_timing(fp_ctx* c, int32_t enable) {
   if (!c) return FP_EINVAL;
-  c->timing = enable != 0;
+  c->timing = (enable & 1) != 0;
+  c->count_pairs = (enable & 2) != 0;
   return FP_OK;
 }
 

@@ -574,26 +574,28 @@ __device__ __forceinline__ void for_candidates(const MeshView& m, const DepGeo& 
 // ---------------------------------------------------------------------------
 // FP32 source on the matrix cores.  With node and particle positions n, p
 // relative to the target element's centre in units of R,
-//   q = 1 - |n - p|^2 = a(p) . b(n),  a = (1 - |p|^2, 2p, 1),  b = (1, n, -|n|^2),
-// so the kernel argument of 16 particles x 16 nodes is one rank-5 product:
-// two v_mfma_f32_16x16x4f32 (the fifth feature in the second, zero-padded),
-// and K = max(q, 0)^2 leaves two VALU operations per pair.  Both passes are
-// node-major: a workgroup owns one target element, each of its four waves a
-// group of at most TPW 16-node tiles whose features stay in registers; the
-// candidate particles (from the background-mesh candidates of the target) are
-// culled once per workgroup against the target's node box, staged in LDS and
-// processed 16 at a time by every wave.  Pass 1 adds sum_n K V_n of every particle to
-// its normalisation with one float atomic per particle and wave; pass 2
-// accumulates sum_p K G_p per node in registers and adds it to S once.
-// MFMA 16x16x4 lane layout: A[row][k] and B[k][col] sit in lane
-// (row or col) + 16 k; D[row][col] in lane col + 16 (row / 4), register row % 4.
+//   q = 1 - |n - p|^2 = 2 p . n + alpha_p - |n|^2,   alpha_p = 1 - |p|^2,
+// so the kernel argument of 16 particles x 16 nodes is one rank-4 product plus
+// a term that depends on one side only, which enters as the accumulator input:
+// one v_mfma_f32_16x16x4f32 per tile.  Both passes are node-major: a workgroup
+// owns one target element, each of its waves a group of at most TPW 16-node
+// tiles whose features stay in registers; the candidate particles (from the
+// per-target candidate lists) are culled once per workgroup against the
+// target's node box, staged in LDS and processed 16 at a time by every wave.
+//  * Pass 1 (rows = nodes): the node features carry sqrt(V_n), so that
+//    max(q', 0)^2 = K V_n and the per-particle sum takes two VALU operations
+//    per pair; one float atomic per particle and wave adds it to the norm.
+//  * Pass 2 (rows = particles): K = max(q, 0)^2 (two VALU operations per
+//    pair), then sum_p K G_p per node on v_mfma_f32_4x4x1f32 (16 blocks of a
+//    4-node x 1-particle by 1-particle x 4-component product), the K tile
+//    being already in that instruction's A layout; S += once per node.
+// Lane layouts (gfx950): 16x16x4: A[row][k], B[k][col] in lane (row or col)
+// + 16 k, D[row][col] in lane col + 16 (row / 4), register row % 4.
+// 4x4x1 (16 blocks): A[b][row], B[b][col] in lane (row or col) + 4 b,
+// D[b][row][col] in lane col + 4 b, register row.
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Waves per target element: two (seven tiles each for N = 5, half a tile of
-// padding) up to N = 5, four for N = 7 (eight tiles each); each wave issues
-// the MFMAs of all its node tiles before their VALU work, so up to TPW
-// independent MFMA chains are in flight.
 template <int NN>
 struct NodeTiling {
   static constexpr int N3 = NN * NN * NN;
@@ -604,32 +606,34 @@ struct NodeTiling {
   static constexpr int CAP = TH + 16;                                // staged particles
 };
 
-struct __attribute__((aligned(16))) PStage {
-  float g[4];     // G_p (pass 2)
-  float a[5];     // particle features 1 - |p|^2, 2 p, 1
-  int32_t p;      // particle index, -1 for a padding row
-  float pad[2];
+// staged particles (structure of arrays in LDS)
+template <int CAP>
+struct PStage {
+  float4 f[CAP];    // 2 p, alpha_p = 1 - |p|^2 (padding rows: 0, 0, 0, -1)
+  float4 g[CAP];    // G_p (pass 2)
+  int32_t id[CAP];  // particle index, -1 for a padding row
 };
-static_assert(sizeof(PStage) == 48, "a staged particle is three float4");
 
-// One wave's node group: features (as A or B operand: k = lane / 16) and the
-// quadrature volumes of the nodes this lane holds in the node-row layout.
+// One wave's node group.  Pass 1: feature (lane / 16) of sqrt(V) (n, 1) of
+// node tile*16 + lane % 16, and the accumulator input -sqrt(V) |n|^2 of the
+// node rows 4 (lane / 16) + i.  Pass 2: feature (lane / 16) of (n, -|n|^2).
 template <int NN>
 struct NodeGroup {
   static constexpr int TPW = NodeTiling<NN>::TPW;
-  float b0[TPW], b1[TPW];   // features 0..3 (k = lane/16), feature 4 (lanes 0..15) of node tile*16 + lane%16
-  float vrow[TPW][4];       // V of nodes tile*16 + 4 (lane/16) + i (norm pass, node-row layout)
+  float b[TPW];
+  v4f c[TPW];
 };
 
-template <int NN>
+template <int NN, bool NORM>
 __device__ inline void load_node_group(const MeshView& m, int t, const double* ctr, double iR, int wave, int lane,
                                        NodeGroup<NN>& G) {
   using T = NodeTiling<NN>;
   const int t0 = wave * T::TPW;   // tiles past the element's nodes keep zero features (q = 0)
+  const int kq = lane >> 4;
 #pragma unroll
   for (int tt = 0; tt < T::TPW; ++tt) {
     const int q = (t0 + tt) * 16 + (lane & 15);
-    float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float f[4] = {0.f, 0.f, 0.f, 0.f};
     if (q < T::N3) {
       double r[3], rr = 0.0;
 #pragma unroll
@@ -637,40 +641,100 @@ __device__ inline void load_node_group(const MeshView& m, int t, const double* c
         r[k] = (m.xnode[((size_t)t * T::N3 + q) * 3 + k] - ctr[k]) * iR;
         rr += r[k] * r[k];
       }
-      f[0] = 1.f;
-      f[1] = (float)r[0];
-      f[2] = (float)r[1];
-      f[3] = (float)r[2];
-      f[4] = (float)(-rr);
+      const double s = NORM ? sqrt(m.vol[(size_t)t * T::N3 + q]) : 1.0;
+      f[0] = (float)(s * r[0]);
+      f[1] = (float)(s * r[1]);
+      f[2] = (float)(s * r[2]);
+      f[3] = NORM ? (float)s : (float)(-rr);
     }
-    // feature k = lane / 16 without indexing a private array (scratch)
-    const int kq = lane >> 4;
-    G.b0[tt] = kq == 0 ? f[0] : kq == 1 ? f[1] : kq == 2 ? f[2] : f[3];
-    G.b1[tt] = (kq == 0) ? f[4] : 0.f;
+    // feature kq without indexing a private array (scratch)
+    G.b[tt] = kq == 0 ? f[0] : kq == 1 ? f[1] : kq == 2 ? f[2] : f[3];
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+    if (NORM) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int qr = (t0 + tt) * 16 + 4 * kq + i;
-      G.vrow[tt][i] = (qr < T::N3) ? (float)m.vol[(size_t)t * T::N3 + qr] : 0.f;
+      for (int i = 0; i < 4; ++i) {
+        const int qr = (t0 + tt) * 16 + 4 * kq + i;
+        if (qr < T::N3) {
+          double rr = 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double d = (m.xnode[((size_t)t * T::N3 + qr) * 3 + k] - ctr[k]) * iR;
+            rr += d * d;
+          }
+          c[i] = (float)(-sqrt(m.vol[(size_t)t * T::N3 + qr]) * rr);
+        }
+      }
     }
+    G.c[tt] = c;
   }
 }
 
-// Stream the target's candidate particles through the workgroup: for every
-// window of candidate elements each thread takes one candidate particle at a
-// time, keeps it if its force is valid and it lies within R of the target's
-// node box, and the kept ones are appended (features in FP32, relative to the
-// target's centre, units of R) to the shared list s_c; then every wave runs
-// tile(first) on each full 16-particle tile of the list with its own node
-// tiles.  The last partial tile is padded (q = -1, so K = 0) and flushed.
-// All threads of the workgroup must call it.
+// exclusive prefix count of pred over the workgroup of TH threads; every
+// thread must call it
+template <int TH>
+__device__ inline int block_scan_bool(bool pred, int32_t* wsum, int& total) {
+  const unsigned long long b = __ballot(pred);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) wsum[w] = __popcll(b);
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < TH / 64; ++k) {
+    const int t = wsum[k];
+    base += (k < w) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + lane_rank(b);
+}
 
-template <int NN, class Tile>
-__device__ inline void stream_particles(const MeshView& m, const Particles& P, const int32_t* __restrict__ elem_start,
-                                        const DepGeo& g, const DepLists& dl, const int32_t* __restrict__ ok,
-                                        const float* __restrict__ Gp, int t, const double* ctr, double part_pad,
-                                        CandLds<NodeTiling<NN>::TH>& L, int32_t* s_pre, PStage* s_c, Tile&& tile) {
-  constexpr int TH = NodeTiling<NN>::TH;
+// FP32 position of every particle relative to the centre of its element's
+// node box, in units of R; w = 0 if the particle deposits (valid force), 1
+// if not.  The staging of the matrix-core passes reads it instead of the FP64
+// positions: a candidate element's offset to the target is added once per
+// element, in FP32.
+__global__ __launch_bounds__(256) void k_dep_local(MeshView m, Particles P, int64_t n, const int32_t* __restrict__ ok,
+                                                   double iR, float4* __restrict__ xl) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  if (!ok[p]) {
+    xl[p] = make_float4(0.f, 0.f, 0.f, 1.f);
+    return;
+  }
   const int64_t cap = P.cap;
+  const double* nb = m.nbox + (size_t)P.elem[p] * 6;
+  xl[p] = make_float4((float)((P.x[p] - 0.5 * (nb[0] + nb[3])) * iR),
+                      (float)((P.x[cap + p] - 0.5 * (nb[1] + nb[4])) * iR),
+                      (float)((P.x[2 * cap + p] - 0.5 * (nb[2] + nb[5])) * iR), 0.f);
+}
+
+constexpr int kSlotCap = 5120;   // particle slots of one candidate window mapped to their element
+
+// per-window staging tables in LDS
+struct WinLds {
+  float4 off[kDepCand];        // candidate element's node-box centre (image shifted) - target centre, units of R
+  int32_t base[kDepCand];      // first particle of the candidate minus its first slot
+  int32_t pre[kDepCand + 1];   // first slot of each candidate, pre[nc] = slots of the window
+  uint8_t slot[kSlotCap];      // candidate of each slot (windows of at most kSlotCap slots)
+};
+
+// Stream the target's candidate particles through the workgroup: for every
+// window of candidate elements the particles of the window are numbered
+// (slots) and each thread takes one slot at a time, keeps the particle if it
+// deposits and lies within R of the target's node box, and the kept ones are
+// appended (features in FP32, relative to the target's centre, units of R) to
+// the shared staging list; then every wave runs tile(first) on each full
+// 16-particle tile of the list with its own node tiles.  The last partial
+// tile is padded (q <= -1, so K = 0) and flushed.  All threads of the
+// workgroup must call it.
+template <int NN, class Tile>
+__device__ inline void stream_particles(const MeshView& m, const int32_t* __restrict__ elem_start, const DepGeo& g,
+                                        const DepLists& dl, const float4* __restrict__ xl,
+                                        const float* __restrict__ Gp, int t, const double* ctr, double part_pad,
+                                        CandLds<NodeTiling<NN>::TH>& L, WinLds& Wl,
+                                        PStage<NodeTiling<NN>::CAP>& s_c, Tile&& tile) {
+  constexpr int TH = NodeTiling<NN>::TH;
   const double* nb = m.nbox + (size_t)t * 6;
   const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
   float flo[3], fhi[3];
@@ -681,58 +745,79 @@ __device__ inline void stream_particles(const MeshView& m, const Particles& P, c
   }
   int n = 0;   // entries in s_c (uniform)
   for_candidates<TH>(m, g, dl, t, blo, bhi, part_pad, L, [&](int nc) {
+    // candidate tables: slot numbering, particle base and FP32 offset
     int T = 0;
     for (int cb = 0; cb < nc; cb += TH) {
       const int c = cb + threadIdx.x;
-      const int cntc = (c < nc) ? elem_start[L.e[c] + 1] - elem_start[L.e[c]] : 0;
+      int beg = 0, cntc = 0;
+      if (c < nc) {
+        const int e = L.e[c];
+        beg = elem_start[e];
+        cntc = elem_start[e + 1] - beg;
+      }
       int tot = 0;
       const int off = block_excl_scan<TH>(cntc, L.wsum, tot);
-      if (c < nc) s_pre[c] = T + off;
+      if (c < nc) {
+        const int e = L.e[c];
+        double sh[3];
+        image_shift(L.img[c], g.period, sh);
+        const double* eb = m.nbox + (size_t)e * 6;
+        Wl.off[c] = make_float4((float)((0.5 * (eb[0] + eb[3]) - sh[0] - ctr[0]) * g.iR),
+                                (float)((0.5 * (eb[1] + eb[4]) - sh[1] - ctr[1]) * g.iR),
+                                (float)((0.5 * (eb[2] + eb[5]) - sh[2] - ctr[2]) * g.iR), 0.f);
+        Wl.pre[c] = T + off;
+        Wl.base[c] = beg - (T + off);
+      }
       T += tot;
     }
+    if (threadIdx.x == 0) Wl.pre[nc] = T;
     __syncthreads();
+    const bool mapped = T <= kSlotCap;
+    if (mapped) {
+      for (int c = threadIdx.x; c < nc; c += TH)
+        for (int k = Wl.pre[c]; k < Wl.pre[c + 1]; ++k) Wl.slot[k] = (uint8_t)c;
+      __syncthreads();
+    }
     for (int jb = 0; jb < T; jb += TH) {
       const int j = jb + threadIdx.x;
       bool keep = false;
-      float r[3] = {0.f, 0.f, 0.f}, gg[4] = {0.f, 0.f, 0.f, 0.f};
+      float r[3] = {0.f, 0.f, 0.f};
+      float4 gg = make_float4(0.f, 0.f, 0.f, 0.f);
       int32_t pi = -1;
       if (j < T) {
-        int lo = 0, hi = nc - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[mid] <= j) lo = mid;
-          else hi = mid - 1;
+        int c;
+        if (mapped) {
+          c = Wl.slot[j];
+        } else {
+          int lo = 0, hi = nc - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (Wl.pre[mid] <= j) lo = mid;
+            else hi = mid - 1;
+          }
+          c = lo;
         }
-        const int64_t p = elem_start[L.e[lo]] + (j - s_pre[lo]);
-        if (ok[p]) {
-          double sh[3];
-          image_shift(L.img[lo], g.period, sh);
-          float d2 = 0.f;
+        pi = Wl.base[c] + j;
+        const float4 v = xl[pi];
+        const float4 o = Wl.off[c];
+        r[0] = v.x + o.x;
+        r[1] = v.y + o.y;
+        r[2] = v.z + o.z;
+        float d2 = 0.f;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            r[k] = (float)((P.x[k * cap + p] - sh[k] - ctr[k]) * g.iR);
-            const float dd = fmaxf(fmaxf(flo[k] - r[k], r[k] - fhi[k]), 0.f);
-            d2 = fmaf(dd, dd, d2);
-          }
-          keep = d2 < 1.f;
-          pi = (int32_t)p;
-          if (Gp) {
-            const float4 gv = *(const float4*)(Gp + p * 8);
-            gg[0] = gv.x; gg[1] = gv.y; gg[2] = gv.z; gg[3] = gv.w;
-          }
+        for (int k = 0; k < 3; ++k) {
+          const float dd = fmaxf(fmaxf(flo[k] - r[k], r[k] - fhi[k]), 0.f);
+          d2 = fmaf(dd, dd, d2);
         }
+        keep = v.w == 0.f && d2 < 1.f;
+        if (Gp && keep) gg = *(const float4*)(Gp + (int64_t)pi * 8);
       }
       int tot = 0;
-      const int off = block_excl_scan<TH>(keep ? 1 : 0, L.wsum, tot);
+      const int off = block_scan_bool<TH>(keep, L.wsum, tot);
       if (keep) {
-        PStage& S = s_c[n + off];
-        S.g[0] = gg[0]; S.g[1] = gg[1]; S.g[2] = gg[2]; S.g[3] = gg[3];
-        S.a[0] = 1.f - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-        S.a[1] = 2.f * r[0];
-        S.a[2] = 2.f * r[1];
-        S.a[3] = 2.f * r[2];
-        S.a[4] = 1.f;
-        S.p = pi;
+        s_c.f[n + off] = make_float4(2.f * r[0], 2.f * r[1], 2.f * r[2], 1.f - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+        s_c.g[n + off] = gg;
+        s_c.id[n + off] = pi;
       }
       n += tot;
       __syncthreads();
@@ -741,16 +826,19 @@ __device__ inline void stream_particles(const MeshView& m, const Particles& P, c
       if (first > 0) {
         // the remainder (< 16 entries) to the front
         const int rem = n - first;
-        float4 t0 = make_float4(0.f, 0.f, 0.f, 0.f), t1 = t0, t2 = t0;
+        float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), g0 = f0;
+        int32_t i0 = -1;
         __syncthreads();
         if ((int)threadIdx.x < rem) {
-          const float4* src = (const float4*)&s_c[first + threadIdx.x];
-          t0 = src[0]; t1 = src[1]; t2 = src[2];
+          f0 = s_c.f[first + threadIdx.x];
+          g0 = s_c.g[first + threadIdx.x];
+          i0 = s_c.id[first + threadIdx.x];
         }
         __syncthreads();
         if ((int)threadIdx.x < rem) {
-          float4* dst = (float4*)&s_c[threadIdx.x];
-          dst[0] = t0; dst[1] = t1; dst[2] = t2;
+          s_c.f[threadIdx.x] = f0;
+          s_c.g[threadIdx.x] = g0;
+          s_c.id[threadIdx.x] = i0;
         }
         n = rem;
       }
@@ -759,74 +847,73 @@ __device__ inline void stream_particles(const MeshView& m, const Particles& P, c
   });
   if (n > 0) {
     if ((int)threadIdx.x >= n && threadIdx.x < 16) {
-      PStage& S = s_c[threadIdx.x];
-      S.a[0] = -1.f;
-      S.a[1] = S.a[2] = S.a[3] = S.a[4] = 0.f;
-      S.g[0] = S.g[1] = S.g[2] = S.g[3] = 0.f;
-      S.p = -1;
+      s_c.f[threadIdx.x] = make_float4(0.f, 0.f, 0.f, -1.f);
+      s_c.g[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      s_c.id[threadIdx.x] = -1;
     }
     __syncthreads();
     tile(0);
   }
 }
 
-// pass 1: norm[p] += sum over the wave's nodes of K V (rows = nodes)
-template <int NN>
-__global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_norm_mfma(MeshView m, Particles P,
-                                                                     const int32_t* __restrict__ elem_start,
-                                                                     DepGeo g, DepLists dl,
-                                                                     const int32_t* __restrict__ ok,
-                                                                     const unsigned long long* __restrict__ povh,
-                                                                     float* norm, unsigned long long* pairs) {
+// max(x, 0) as one integer max: a float with the sign bit set is a negative
+// int (fmaxf would first quieten a signalling NaN, a second instruction)
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// pass 1: norm[p] += sum over the wave's nodes of K V (rows = nodes); with
+// COUNT, the (particle, node) pairs within R are counted as well
+template <int NN, bool COUNT>
+__global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_norm_mfma(
+    MeshView m, const int32_t* __restrict__ elem_start, DepGeo g, DepLists dl, const float4* __restrict__ xl,
+    const unsigned long long* __restrict__ povh, float* norm, unsigned long long* pairs) {
   using T = NodeTiling<NN>;
   const int t = xcd_element(blockIdx.x, m.E);
   if (t >= m.E) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ CandLds<T::TH> L;
-  __shared__ int32_t s_pre[kDepCand + 1];
-  __shared__ PStage s_c[T::CAP];
+  __shared__ WinLds Wl;
+  __shared__ PStage<T::CAP> s_c;
   const double* nb = m.nbox + (size_t)t * 6;
   const double ctr[3] = {0.5 * (nb[0] + nb[3]), 0.5 * (nb[1] + nb[4]), 0.5 * (nb[2] + nb[5])};
   NodeGroup<NN> NG;
-  load_node_group<NN>(m, t, ctr, g.iR, wave, lane, NG);
+  load_node_group<NN, true>(m, t, ctr, g.iR, wave, lane, NG);
   const double part_pad = __longlong_as_double((long long)*povh);
   unsigned long long npairs = 0;   // wave-uniform
-  const v4f zero = {0.f, 0.f, 0.f, 0.f};
   auto tile = [&](int first) {
-    // B operand: features (k = lane / 16) of particle first + lane % 16
-    const PStage& S = s_c[first + (lane & 15)];
-    const int kq = lane >> 4;
-    const float pb0 = S.a[kq];
-    const float pb1 = (kq == 0) ? S.a[4] : 0.f;
+    // B operand: feature (lane / 16) of particle first + lane % 16
+    const int pc = first + (lane & 15);
+    const float pb = ((const float*)&s_c.f[pc])[lane >> 4];
     float acc = 0.f;
-    // node tiles in groups of four: their MFMA chains are in flight together
+    v4f q[T::TPW];
 #pragma unroll
-    for (int t0 = 0; t0 < T::TPW; t0 += 4) {
-      constexpr int G4 = 4;
-      v4f q[G4];
+    for (int u = 0; u < T::TPW; ++u) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(NG.b[u], pb, NG.c[u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < G4; ++u)
-        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(NG.b0[t0 + u], pb0, zero, 0, 0, 0);
+    for (int u = 0; u < T::TPW; ++u)
 #pragma unroll
-      for (int u = 0; u < G4; ++u)
-        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(NG.b1[t0 + u], pb1, q[u], 0, 0, 0);
+      for (int i = 0; i < 4; ++i) {
+        const float w = relu(q[u][i]);
+        if (COUNT) npairs += __popcll(__ballot(w > 0.f));
+        acc = fmaf(w, w, acc);
+      }
+    if (!COUNT) {
+      // software pipeline: each tile's MFMA is issued two tiles ahead of the
+      // VALU work that reads it
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
 #pragma unroll
-      for (int u = 0; u < G4; ++u)
-        if (t0 + u < T::TPW)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float w = fmaxf(q[u][i], 0.f);
-            npairs += __popcll(__ballot(w > 0.f));
-            acc = fmaf(w * w, NG.vrow[t0 + u][i], acc);
-          }
+      for (int u = 0; u + 2 < T::TPW; ++u) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
     }
     // sum over the node rows held by the four lane groups
     acc += __shfl_xor(acc, 16, 64);
     acc += __shfl_xor(acc, 32, 64);
-    if (lane < 16 && S.p >= 0 && acc != 0.f) atomicAdd(norm + S.p, acc);
+    const int32_t id = s_c.id[pc];
+    if (lane < 16 && id >= 0 && acc != 0.f) atomicAdd(norm + id, acc);
   };
-  stream_particles<NN>(m, P, elem_start, g, dl, ok, nullptr, t, ctr, part_pad, L, s_pre, s_c, tile);
-  if (pairs && lane == 0 && npairs) atomicAdd(pairs + (blockIdx.x & (kStatSlots - 1)), npairs);
+  stream_particles<NN>(m, elem_start, g, dl, xl, nullptr, t, ctr, part_pad, L, Wl, s_c, tile);
+  if (COUNT && pairs && lane == 0 && npairs) atomicAdd(pairs + (blockIdx.x & (kStatSlots - 1)), npairs);
 }
 
 // G_p = -F_p / norm_p (FP32, written over F_p), zero for particles that
@@ -848,87 +935,89 @@ __global__ __launch_bounds__(256) void k_dep_scale(int64_t n, double* F, const i
 
 // pass 2: S[node] += sum_p K G_p (rows = particles)
 template <int NN>
-__global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_gather_mfma(MeshView m, Particles P,
-                                                                       const int32_t* __restrict__ elem_start,
-                                                                       DepGeo g, DepLists dl,
-                                                                       const int32_t* __restrict__ ok,
-                                                                       const float* __restrict__ Gp,
-                                                                       const unsigned long long* __restrict__ povh,
-                                                                       float* S) {
+__global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_gather_mfma(
+    MeshView m, const int32_t* __restrict__ elem_start, DepGeo g, DepLists dl, const float4* __restrict__ xl,
+    const float* __restrict__ Gp, const unsigned long long* __restrict__ povh, float* S) {
   using T = NodeTiling<NN>;
   const int t = xcd_element(blockIdx.x, m.E);
   if (t >= m.E) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ CandLds<T::TH> L;
-  __shared__ int32_t s_pre[kDepCand + 1];
-  __shared__ PStage s_c[T::CAP];
+  __shared__ WinLds Wl;
+  __shared__ PStage<T::CAP> s_c;
   const double* nb = m.nbox + (size_t)t * 6;
   const double ctr[3] = {0.5 * (nb[0] + nb[3]), 0.5 * (nb[1] + nb[4]), 0.5 * (nb[2] + nb[5])};
   NodeGroup<NN> NG;
-  load_node_group<NN>(m, t, ctr, g.iR, wave, lane, NG);
+  load_node_group<NN, false>(m, t, ctr, g.iR, wave, lane, NG);
   const double part_pad = __longlong_as_double((long long)*povh);
-  float acc[T::TPW][4];
+  // acc[tt]: block (node group 4 g, particle quarter kq) of node tile tt,
+  // register r = node 4 g + r, lane c + 4 g + 16 kq = component c
+  v4f acc[T::TPW];
 #pragma unroll
-  for (int tt = 0; tt < T::TPW; ++tt)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[tt][c] = 0.f;
-  const v4f zero = {0.f, 0.f, 0.f, 0.f};
+  for (int tt = 0; tt < T::TPW; ++tt) acc[tt] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const int kq = lane >> 4;
   auto tile = [&](int first) {
-    // A operand: features of particle first + lane % 16
-    const PStage& Sa = s_c[first + (lane & 15)];
-    const int kq = lane >> 4;
-    const float pa0 = Sa.a[kq];
-    const float pa1 = (kq == 0) ? Sa.a[4] : 0.f;
-    // G of the four particle rows this lane holds: first + 4 kq + i
-    float gr[4][4];
+    // A operand: feature kq of (2 p, 1) of particle first + lane % 16; the
+    // accumulator input alpha of the particle rows 4 kq + i
+    const float fk = ((const float*)&s_c.f[first + (lane & 15)])[kq];
+    const float pa = kq == 3 ? 1.f : fk;
+    v4f cin;
+    float gb[4];   // B of the 4x4x1 products: G_c of particle 4 kq + i, c = lane % 4
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float4 gv = *(const float4*)s_c[first + 4 * kq + i].g;
-      gr[i][0] = gv.x; gr[i][1] = gv.y; gr[i][2] = gv.z; gr[i][3] = gv.w;
+      cin[i] = s_c.f[first + 4 * kq + i].w;
+      gb[i] = ((const float*)&s_c.g[first + 4 * kq + i])[lane & 3];
     }
-    // node tiles in groups of four: their MFMA chains are in flight together
+    v4f q[T::TPW];
 #pragma unroll
-    for (int t0 = 0; t0 < T::TPW; t0 += 4) {
-      constexpr int G4 = 4;
-      v4f q[G4];
+    for (int u = 0; u < T::TPW; ++u) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, NG.b[u], cin, 0, 0, 0);
+    float kk[T::TPW][4];
 #pragma unroll
-      for (int u = 0; u < G4; ++u)
-        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa0, NG.b0[t0 + u], zero, 0, 0, 0);
+    for (int u = 0; u < T::TPW; ++u)
 #pragma unroll
-      for (int u = 0; u < G4; ++u)
-        if (t0 + u < T::TPW) q[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa1, NG.b1[t0 + u], q[u], 0, 0, 0);
+      for (int i = 0; i < 4; ++i) {
+        const float w = relu(q[u][i]);
+        kk[u][i] = w * w;
+      }
 #pragma unroll
-      for (int u = 0; u < G4; ++u)
-        if (t0 + u < T::TPW)
+    for (int u = 0; u < T::TPW; ++u)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            float w = fmaxf(q[u][i], 0.f);
-            w *= w;
+      for (int i = 0; i < 4; ++i) acc[u] = __builtin_amdgcn_mfma_f32_4x4x1f32(kk[u][i], gb[i], acc[u], 0, 0, 0);
+    // software pipeline: tile u's kernel-argument MFMA two tiles ahead of its
+    // VALU work, its four 4x4x1 products one tile behind
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[t0 + u][c] = fmaf(w, gr[i][c], acc[t0 + u][c]);
-          }
+    for (int u = 1; u < T::TPW; ++u) {
+      if (u + 1 < T::TPW) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // kernel argument of tile u + 1
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);                        // products of tile u - 1
+      __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);                        // K of tile u
     }
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
   };
-  stream_particles<NN>(m, P, elem_start, g, dl, ok, Gp, t, ctr, part_pad, L, s_pre, s_c, tile);
-  // sum over the particle rows held by the four lane groups, then one
-  // read-modify-write of each node's four components
+  stream_particles<NN>(m, elem_start, g, dl, xl, Gp, t, ctr, part_pad, L, Wl, s_c, tile);
+  // sum over the particle quarters, then one read-modify-write of each
+  // (node, component)
   const int t0 = wave * T::TPW;
 #pragma unroll
   for (int tt = 0; tt < T::TPW; ++tt) {
+    v4f v = acc[tt];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      float v = acc[tt][c];
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
-      acc[tt][c] = v;
+    for (int r = 0; r < 4; ++r) {
+      v[r] += __shfl_xor(v[r], 16, 64);
+      v[r] += __shfl_xor(v[r], 32, 64);
     }
-    const int q = (t0 + tt) * 16 + lane;
-    if (lane < 16 && q < T::N3)
+    if (lane < 16) {
+      const int c = lane & 3, g4 = lane >> 2;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float* dst = S + ((size_t)t * 4 + c) * T::N3 + q;
-        *dst += acc[tt][c];
+      for (int r = 0; r < 4; ++r) {
+        const int q = (t0 + tt) * 16 + 4 * g4 + r;
+        if (q < T::N3) {
+          float* dst = S + ((size_t)t * 4 + c) * T::N3 + q;
+          *dst += v[r];
+        }
       }
+    }
   }
 }
 
@@ -973,6 +1062,8 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
   // FP32 source: the normalisation sums of the matrix-core pass (float[cap],
   // after the validity flags)
   float* norm = (float*)(ok + P.cap);
+  // FP32 local positions (float4[cap], 16-byte aligned after the sums)
+  float4* xl = (float4*)(((uintptr_t)(norm + P.cap) + 15) & ~(uintptr_t)15);
   k_dep_reset<<<gp, 256, 0, s>>>(povh, norm, s_f32 ? n : 0);
 #define FP_L(A, B)                                                                                           \
   if (m.n == A && m.ng == B) {                                                                               \
@@ -980,11 +1071,15 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
     else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                         \
     if (s_f32) {                                                                                             \
       rec(0);                                                                                                \
-      k_dep_norm_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, P, elem_start, g, dl, ok, povh, norm, pairs);  \
+      k_dep_local<<<gp, 256, 0, s>>>(m, P, n, ok, g.iR, xl);                                                 \
+      if (pairs)                                                                                             \
+        k_dep_norm_mfma<A, true><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, povh, norm, pairs);   \
+      else                                                                                                   \
+        k_dep_norm_mfma<A, false><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, povh, norm, pairs);  \
       rec(1);                                                                                                \
       k_dep_scale<<<gp, 256, 0, s>>>(n, F, ok, norm);                                                        \
       rec(2);                                                                                                \
-      k_dep_gather_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, P, elem_start, g, dl, ok, (const float*)F,  \
+      k_dep_gather_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, (const float*)F,      \
                                                             povh, (float*)S);                                \
       rec(3);                                                                                                \
     } else {                                                                                                 \

@@ -262,8 +262,11 @@ class FlexiPart:
                     lost=int(s[4]), fallbacks=int(s[5]), sorts=int(s[6]), stragglers=int(s[7]),
                     track_queue=int(s[8]), recovered=int(s[9]), deposit_pairs=int(s[10]))
 
-    def set_timing(self, enable=True):
-        self._check(self.L.fp_set_timing(self.ctx, int(bool(enable))), "fp_set_timing")
+    def set_timing(self, enable=True, count_pairs=False):
+        """HIP-event timing of the step and source kernels; count_pairs also
+        counts the shape-kernel pairs within the radius (stats deposit_pairs)."""
+        flags = (1 if enable else 0) | (2 if count_pairs else 0)
+        self._check(self.L.fp_set_timing(self.ctx, flags), "fp_set_timing")
 
     def timing(self):
         """{class: (launches, total ms)} since the last call (synchronises)."""

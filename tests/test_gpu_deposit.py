@@ -129,6 +129,13 @@ def test_shape_fp32_matrix_core_path(N, n_geo, cells, n, R_cells):
     So = o.deposit(kind=1, radius=R, period=per)
     g.reset_stats()
     Sf = g.deposit(kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy().astype(np.float64)
+    assert g.stats()["deposit_pairs"] == 0          # counted only when asked for
+    g.set_timing(False, count_pairs=True)
+    Sc = g.deposit(kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy().astype(np.float64)
+    g.set_timing(False)
+    # the counting variant computes the same values (float atomics from the
+    # target workgroups add the normalisation sums in a run-dependent order)
+    np.testing.assert_allclose(Sc, Sf, rtol=2e-6, atol=1e-6 * np.abs(Sf).max())
     err = np.abs(Sf - So).max() / np.abs(So).max()
     print("N=%d R=%.2f h: max |S32 - S64| / max |S| = %.3g" % (N, R_cells, err))
     assert err <= 2e-5
