@@ -1249,24 +1249,45 @@ __device__ __forceinline__ bool outside_band(const double* q, double amin, doubl
   return hi < amin || lo > amax;
 }
 
-// Physical-space tracking of the straight stage segment xs -> xe (Sec. 3.2.3):
-// smallest alpha in (1e-12 h_e, remaining length] with (u, v) in [-1,1]^2,
-// ties to the lowest local face; hand-off, periodic shift, specular reflection
-// (Sec. 2.4) of the remaining displacement, v and the stage registers; open
-// boundaries end the particle.
+// Physical-space tracking of the queued straight stage segments xs -> xe
+// (Sec. 3.2.3): smallest alpha in (1e-12 h_e, remaining length] with (u, v) in
+// [-1,1]^2, ties to the lowest local face; hand-off, periodic shift, specular
+// reflection (Sec. 2.4) of the remaining displacement, v and the stage
+// registers; open boundaries end the particle.
 //
 // Written as a per-lane state machine: one loop iteration advances a lane by
 // one step of its own work (next candidate face, pop of a clipping box, one
 // Bezier-clipping iteration, end of a leg), so the lanes of a wavefront that
 // test different faces, need different iteration counts or cross different
-// numbers of faces all share the clipping iteration that dominates the cost,
-// instead of the wavefront running every face to the slowest lane.
+// numbers of faces all share the clipping iteration that dominates the cost.
+// A lane whose segment is done takes the next one from the queue (one atomic
+// per wavefront and iteration for all its idle lanes), so the lanes stay busy
+// until the queue is drained instead of each wavefront waiting for its
+// slowest segment.  The results do not depend on the order.
+__device__ __forceinline__ int lane_rank64(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
 template <int NG, bool MORT>
-__device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe, double* v, double* kx, double* kv,
-                      int max_cross, int8_t& status, int& hits, int& ncross, unsigned reach = 0x3Fu) {
+__device__ void track_queue(const MeshView& m, const Particles& P, const int32_t* __restrict__ trk_p,
+                            const double* __restrict__ trk_x, const uint8_t* __restrict__ trk_m, int32_t* head,
+                            int64_t nq, int max_cross, int& ncross, int& nhits) {
   constexpr double kBoxTol = 1e-7;
+  // Bezier clipping contracts a box around a simple root quadratically; once
+  // both sides are below kNewtonBox and the last iteration cut each of them to
+  // at most kQuadRatio, the box holds one transversal root and the 2-D Newton
+  // below reaches it in three steps (a double root, where the clipping only
+  // contracts linearly, keeps clipping down to kBoxTol)
+  constexpr double kNewtonBox = 1e-3, kQuadRatio = 0.25;
   enum { NEW_LEG, NEXT_FACE, POP, CLIP, LEG_END, MORT_FACE, MORT_END, DONE };
-  double xs[3] = {xs_in[0], xs_in[1], xs_in[2]};
+  const int64_t cap = P.cap;
+  // the lane's segment: particle, element at the start, wall hits, crossings
+  int64_t p = -1;
+  int e = 0, e0 = 0, hits = 0, nseg = 0;
+  int8_t status = ACTIVE;
+  unsigned reach = 0x3Fu;
+  double xe[3] = {0, 0, 0}, v[3] = {0, 0, 0}, kx[3] = {0, 0, 0}, kv[3] = {0, 0, 0};
+  double xs[3] = {0, 0, 0};
   // excl: planar face just entered through (no further root possible);
   // entry: non-planar face just entered through, whose root at the entry point
   // (alpha ~ 0, error growing like 1/sin(incidence)) is ignored below
@@ -1302,9 +1323,45 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
     if (!(tn > 0.0)) return;
     if (a < best) { best = a; bf = f; bu = uu; bv = vv; }
   };
-  int mode = NEW_LEG;
+  int mode = DONE;
+  bool drained = false;   // wave-uniform: the queue has no segment left
+  const int lane = threadIdx.x & 63;
 #pragma unroll 1
-  while (mode != DONE) {
+  while (true) {
+    if (!drained) {
+      const unsigned long long idle = __ballot(mode == DONE);
+      if (idle) {
+        const int nidle = __popcll(idle);
+        const int leader = __ffsll((long long)idle) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(head, nidle);
+        base = __shfl(base, leader, 64);
+        if ((int64_t)base + nidle >= nq) drained = true;
+        if (mode == DONE) {
+          const int64_t i = (int64_t)base + lane_rank64(idle);
+          if (i < nq) {
+            p = trk_p[i];
+            xs[0] = trk_x[i]; xs[1] = trk_x[cap + i]; xs[2] = trk_x[2 * cap + i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              xe[k] = P.x[k * cap + p];
+              v[k] = P.v[k * cap + p];
+              kx[k] = P.kx[k * cap + p];
+              kv[k] = P.kv[k * cap + p];
+            }
+            e = e0 = P.elem[p];
+            hits = nseg = 0;
+            status = ACTIVE;
+            reach = trk_m[i];
+            excl = entry = -1;
+            count = 0;
+            mort = -1;
+            mode = NEW_LEG;
+          }
+        }
+      }
+    }
+    if (__ballot(mode != DONE) == 0ull) break;
     if (mode == NEW_LEG) {
       t[0] = xe[0] - xs[0]; t[1] = xe[1] - xs[1]; t[2] = xe[2] - xs[2];
       L = sqrt(dot3(t, t));
@@ -1410,7 +1467,8 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         if (v0 != 0.0 || v1 != 1.0) patch_restrict<NG, 3>(q, 1, v0, v1);
         mode = CLIP;
       }
-    } else if (mode == CLIP) {
+    }
+    if (mode == CLIP) {
       // one Bezier-clipping iteration (Sec. 3.2.4) on the live box
       double a, b;
       mode = POP;
@@ -1427,7 +1485,8 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
           v0 = nv0; v1 = nv1;
           const double rv = b - a;
           const double wu = u1 - u0, wv = v1 - v0;
-          bool conv = (wu <= kBoxTol && wv <= kBoxTol);
+          bool conv = (wu <= kBoxTol && wv <= kBoxTol) ||
+                      (wu <= kNewtonBox && wv <= kNewtonBox && ru <= kQuadRatio && rv <= kQuadRatio);
           const bool su = (ru > 0.8 && wu > kBoxTol), sv = (rv > 0.8 && wv > kBoxTol);
           if (!conv && (su || sv) && sp + 2 > kClipStack) conv = true;
           if (conv) {
@@ -1474,7 +1533,7 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
         mode = DONE;
       } else {
         count++;
-        ncross++;
+        nseg++;
         double xh[3] = {xs[0] + best * t[0], xs[1] + best * t[1], xs[2] + best * t[2]};
         const int fid = e * 6 + bf;
         const FaceRec& F = m.faces[fid];
@@ -1549,6 +1608,24 @@ __device__ void track(const MeshView& m, int& e, const double* xs_in, double* xe
       mort = -1;
       mode = NEW_LEG;
       reach = 0x3Fu;
+    }
+    if (mode == DONE && p >= 0) {
+      // segment done: write back what changed
+      ncross += nseg;
+      nhits += hits;
+      if (nseg || status != ACTIVE) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          P.x[k * cap + p] = xe[k];
+          P.v[k * cap + p] = v[k];
+          P.kx[k * cap + p] = kx[k];
+          P.kv[k * cap + p] = kv[k];
+        }
+        if (e != e0) P.elem[p] = e;
+        if (hits) P.hits[p] += hits;
+        if (status != ACTIVE) P.status[p] = status;
+      }
+      p = -1;
     }
   }
 }

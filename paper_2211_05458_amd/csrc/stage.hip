@@ -111,7 +111,7 @@ __device__ __forceinline__ unsigned boundary_faces(const FaceRec* __restrict__ F
 struct Task { int32_t e, p0, cnt, pad; };
 
 struct Queues {
-  int32_t* counters;  // [0] stragglers, [1] tracking
+  int32_t* counters;  // [0] stragglers, [1] tracking, [2] next tracking entry
   int32_t* strag;     // [cap]
   int32_t* trk_p;     // [cap]
   double* trk_x;      // [3][cap] segment start
@@ -363,40 +363,14 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
 template <int NG, bool MORT>
 __global__ __launch_bounds__(256) void k_track(MeshView m, Particles P, Queues q, StepParams sp,
                                                unsigned long long* stats) {
-  const int64_t count = q.counters[1];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t cap = P.cap;
   int ncross = 0, nhits = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-    const int64_t p = q.trk_p[i];
-    double xs[3] = {q.trk_x[i], q.trk_x[cap + i], q.trk_x[2 * cap + i]};
-    double xe[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
-    double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
-    double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
-    double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
-    int e = P.elem[p], e0 = e, h = 0, nc = 0;
-    int8_t st = ACTIVE;
-    track<NG, MORT>(m, e, xs, xe, v, kx, kv, sp.max_cross, st, h, nc, q.trk_m[i]);
-    ncross += nc;
-    nhits += h;
-    if (nc || st != ACTIVE) {
-      for (int k = 0; k < 3; ++k) {
-        P.x[k * cap + p] = xe[k];
-        P.v[k * cap + p] = v[k];
-        P.kx[k * cap + p] = kx[k];
-        P.kv[k * cap + p] = kv[k];
-      }
-      if (e != e0) P.elem[p] = e;
-      if (h) P.hits[p] += h;
-      if (st != ACTIVE) P.status[p] = st;
-    }
-  }
+  track_queue<NG, MORT>(m, P, q.trk_p, q.trk_x, q.trk_m, q.counters + 2, q.counters[1], sp.max_cross, ncross, nhits);
   wave_add(stats + ST_CROSS * kStatSlots, ncross);
   wave_add(stats + ST_HITS * kStatSlots, nhits);
 }
 
 __global__ void k_reset_counters(int32_t* c) {
-  if (threadIdx.x < 2) c[threadIdx.x] = 0;
+  if (threadIdx.x < 3) c[threadIdx.x] = 0;   // stragglers, tracking queue, its head
 }
 
 // tasks of <= tp particles per element after the counting sort
