@@ -237,12 +237,13 @@ int fp_reset_stats(fp_ctx* ctx);
  * class (0 sort, 1 element-wise stage kernel, 2 final reference coordinates,
  * 3 nearest-DOF source, 4 shape-kernel source (all of its kernels), 5 per-lane
  * stage kernel, 6 tracking kernel, 7 the shape-kernel source's normalisation
- * pass, 8 its node-sum pass), out[2*k] = launches and out[2*k+1] = total
+ * pass, 8 its node-sum pass, 9 the learned guesses of a stage), out[2*k] =
+ * launches and out[2*k+1] = total
  * milliseconds since the last call; the counters are then cleared.
  * enable: bit 0 the events, bit 1 the count of shape-kernel pairs within the
  * radius (fp_get_stats out[10]), which costs the FP32 source's normalisation
  * pass one more VALU operation per pair. */
-#define FP_TIMING_CLASSES 9
+#define FP_TIMING_CLASSES 10
 int fp_set_timing(fp_ctx* ctx, int32_t enable);
 int fp_get_timing(fp_ctx* ctx, double* out /* [2*FP_TIMING_CLASSES] */);
 

@@ -70,6 +70,7 @@ struct fp_ctx {
   float* mlp_adam = nullptr;      // Adam moments m, v of fp_mlp_train [2][nw]
   int32_t* mlp_order = nullptr;   // row order of one epoch [cap]
   float* mlp_bloss = nullptr;     // batch losses of one epoch [cap]
+  float* mlp_guess = nullptr;     // learned guesses of a stage [3][cap]
   int64_t n_flagged = 0;
   // timing
   bool timing = false;
@@ -239,7 +240,7 @@ struct Layout {
   size_t X, faces, cp, hE, xnode, vol, elo, ehi, nbox, dsafe, gxi, mortar, nbr_elem, nbr_face, bc, shift, bstart, blist,
       mlp_flag, mlp_h1, mlp_ctr, mlp_w, mlp_adam, mlp_order, mlp_bloss, dl_count, dl_start, dl_list, stats,
       sort_count, sort_start, sort_rank, sort_sums, scratch, dep, mlp_rows, mlp_grad, tcount, tstart, tasks, qcnt,
-      strag, trk_p, trk_x, trk_m, part[2], total;
+      strag, trk_p, trk_x, trk_m, mlp_guess, part[2], total;
   size_t part_bytes;
 };
 
@@ -295,6 +296,7 @@ Layout layout(const fp_ctx* c, int64_t cap) {
   L.trk_p = take(pc1 * 4);
   L.trk_x = take(pc1 * 3 * 8);
   L.trk_m = take(pc1);
+  L.mlp_guess = take(pc1 * 3 * 4);
   {
     int64_t off[10];
     particle_offsets(cap, off, &L.part_bytes);
@@ -755,6 +757,7 @@ int fp_bind_workspace(fp_ctx* c, void* dev, size_t bytes) {
   c->mlp_adam = (float*)(b + L.mlp_adam);
   c->mlp_order = (int32_t*)(b + L.mlp_order);
   c->mlp_bloss = (float*)(b + L.mlp_bloss);
+  c->mlp_guess = (float*)(b + L.mlp_guess);
   c->mlp_w = nullptr;
   c->dl_count = (int32_t*)(b + L.dl_count);
   c->dl_start = (int32_t*)(b + L.dl_start);
@@ -888,6 +891,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   sp.use_mlp = (o->guess == 1 && c->mlp_w) ? 1 : 0;
   sp.refspace = o->tracking;
   sp.forces = o->forces;
+  sp.mlp_guess = (sp.use_mlp && c->n_flagged > 0) ? c->mlp_guess : nullptr;
   hipStream_t s = c->stream;
   for (int st = 0; st < n_steps; ++st) {
     if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
@@ -922,12 +926,13 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
       Lc.trk_m = c->trk_m;
       Lc.stats = c->stats;
       if (c->timing)
-        for (int k = 0; k < 6; ++k) Lc.ev[k] = take_event(c);
+        for (int k = 0; k < (sp.mlp_guess ? 8 : 6); ++k) Lc.ev[k] = take_event(c);
       HIPCHK(c, launch_stage(Lc, s));
       if (c->timing) {
         if (stage_uses_tasks(Lc) && Lc.ev[0] && Lc.ev[1]) c->recs.push_back({1, Lc.ev[0], Lc.ev[1]});
         if (Lc.ev[2] && Lc.ev[3]) c->recs.push_back({5, Lc.ev[2], Lc.ev[3]});
         if (Lc.ev[4] && Lc.ev[5]) c->recs.push_back({6, Lc.ev[4], Lc.ev[5]});
+        if (Lc.ev[6] && Lc.ev[7]) c->recs.push_back({9, Lc.ev[6], Lc.ev[7]});
       }
     }
     c->steps_done++;

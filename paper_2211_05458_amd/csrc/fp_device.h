@@ -327,59 +327,6 @@ __device__ void mlp_features(const MeshView& m, int e, const double* x, float* f
 
 __device__ __forceinline__ float fast_tanh(float s) { return tanhf(s); }
 
-// Layers 2..4 of the 84-64-64-64-3 network from the first layer's
-// pre-activation s1 (64 values).
-__device__ inline void mlp_forward_tail(const float* __restrict__ w, const float* s1, float* out) {
-  constexpr int H = 64, NI = kMlpIn;
-  const float* W2 = w + H * NI + H;
-  const float* b2 = W2 + H * H;
-  const float* W3 = b2 + H;
-  const float* b3 = W3 + H * H;
-  const float* W4 = b3 + H;
-  const float* b4 = W4 + 3 * H;
-  float h1[H], h2[H];
-#pragma unroll
-  for (int o = 0; o < H; ++o) h1[o] = fast_tanh(s1[o]);
-#pragma unroll 2
-  for (int o = 0; o < H; ++o) {
-    float s = b2[o];
-#pragma unroll
-    for (int i = 0; i < H; ++i) s += W2[o * H + i] * h1[i];
-    h2[o] = fast_tanh(s);
-  }
-#pragma unroll 2
-  for (int o = 0; o < H; ++o) {
-    float s = b3[o];
-#pragma unroll
-    for (int i = 0; i < H; ++i) s += W3[o * H + i] * h2[i];
-    h1[o] = fast_tanh(s);
-  }
-  for (int o = 0; o < 3; ++o) {
-    float s = b4[o];
-#pragma unroll
-    for (int i = 0; i < H; ++i) s += W4[o * H + i] * h1[i];
-    out[o] = s;
-  }
-}
-
-// The learned guess at x in element e: 81 of the 84 inputs depend on the
-// element only, so the first layer's element part is taken from the table
-// filled when the weights are set (mlp_h1) and only the point's three inputs
-// are added per particle.
-__device__ inline void mlp_guess(const MeshView& m, int e, const double* x, float* out) {
-  constexpr int H = 64, NI = kMlpIn;
-  const float* W1 = m.mlp_w;
-  const float* h1e = m.mlp_h1 + (size_t)e * H;
-  const double* c = m.mlp_ctr + (size_t)e * 4;
-  const float p0 = (float)((x[0] - c[0]) * c[3]), p1 = (float)((x[1] - c[1]) * c[3]),
-              p2 = (float)((x[2] - c[2]) * c[3]);
-  float s1[H];
-#pragma unroll
-  for (int o = 0; o < H; ++o)
-    s1[o] = h1e[o] + W1[o * NI + 81] * p0 + W1[o * NI + 82] * p1 + W1[o * NI + 83] * p2;
-  mlp_forward_tail(m.mlp_w, s1, out);
-}
-
 // 84-64-64-64-3 forward for one row; weights read through the scalar path
 // (uniform addresses).
 __device__ inline void mlp_forward_row(const float* __restrict__ w, const float* in, float* out) {
@@ -422,16 +369,16 @@ __device__ inline void mlp_forward_row(const float* __restrict__ w, const float*
   }
 }
 
-// Reference coordinates of x in element e: learned guess (flagged elements),
-// then the paper's guess, then the face-barycentre guess.
+// Reference coordinates of x in element e: learned guess (flagged elements;
+// gin, the stage's precomputed guess of this particle), then the paper's
+// guess, then the face-barycentre guess.
 template <int NN, int NG, bool MLP = false>
 __device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__ Xe, const double* __restrict__ XNe,
-                            const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks) {
+                            const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks,
+                            const float* gin = nullptr) {
   double g[3];
-  if (MLP && m.mlp_flag[e]) {
-    float o[3];
-    mlp_guess(m, e, x, o);
-    g[0] = o[0]; g[1] = o[1]; g[2] = o[2];
+  if (MLP && gin && m.mlp_flag[e]) {
+    g[0] = gin[0]; g[1] = gin[1]; g[2] = gin[2];
     calls++;
     if (newton_e<NG>(m, Xe, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
     fallbacks++;

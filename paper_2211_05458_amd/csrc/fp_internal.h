@@ -119,6 +119,7 @@ struct StepParams {
   int32_t drag, max_it, max_cross, use_mlp;
   int32_t refspace;     // reference-space localisation of segments that cannot reach a boundary face
   int32_t forces;       // kForce* terms beyond drag and gravity
+  const float* mlp_guess;   // [3][cap] learned guesses of the stage (flagged elements), or null
 };
 
 // force model of the two-way source (the fluid force of the equation of motion)

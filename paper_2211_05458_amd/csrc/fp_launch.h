@@ -34,7 +34,7 @@ struct StageLaunch {
   double* trk_x;            // [3][cap]
   uint8_t* trk_m;           // [cap] faces the first leg can reach
   unsigned long long* stats;
-  hipEvent_t ev[6];         // optional (start, end) pairs around the elem, lane and track kernels
+  hipEvent_t ev[8];         // optional (start, end) pairs around the elem, lane, track and learned-guess kernels
 };
 hipError_t launch_stage(const StageLaunch& L, hipStream_t s);
 bool stage_uses_tasks(const StageLaunch& L);   // k_stage_elem runs (else all particles go per lane)
@@ -67,6 +67,7 @@ hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem
 hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
                                int32_t* ids, int32_t* count, hipStream_t s);
 hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s);
+hipError_t launch_mlp_guess(const MeshView& m, const Particles& P, int64_t n, float* guess, hipStream_t s);
 hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,
                                 const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s);
 // device address of the fixed row buffer of fp_mlp_loss_grad_static on the

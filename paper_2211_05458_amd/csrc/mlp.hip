@@ -275,6 +275,186 @@ hipError_t launch_curved_flags(const MeshView& m, double thresh, uint8_t* flag, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Learned guesses of a stage on the matrix cores.  Each wavefront takes 64
+// particles at a time (persistent grid) and runs the network transposed, units
+// as rows and particles as columns: Z^T = W H^T on v_mfma_f32_16x16x16bf16_1k
+// (bf16 weights and activations, FP32 sums).  With that orientation the
+// 16x16 output tile of a layer (lane: particle lane % 16, four consecutive
+// units 4 (lane / 16) + i) is, after tanh and rounding to bf16, already the B
+// operand of the next layer, so no activation leaves the registers.  The first
+// layer takes the element's part from the table (W1 g_e + b1) and adds the
+// point's three inputs on the VALU.  The guess only starts Newton, which
+// converges to the same root from any guess in its basin; bf16 rounding of
+// the network moves the guess by about 1e-2 of the reference cell at most.
+// Lane layout (gfx950): A[m][k] in lane m + 16 (k / 4), element k % 4; B[k][n]
+// in lane n + 16 (k / 4), element k % 4; D[m][n] in lane n + 16 (m / 4),
+// register m % 4.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+
+// four floats -> four bf16 (round to nearest even, v_cvt_pk_bf16_f32)
+__device__ __forceinline__ v4s to_bf16(v4f x) { return __builtin_bit_cast(v4s, __builtin_convertvector(x, v4bf)); }
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1), exact at both saturations; relative error
+// of a few float ulps, far below the bf16 rounding that follows
+__device__ __forceinline__ float tanh_guess(float x) {
+  const float e = __expf(2.f * x);
+  return 1.f - __fdividef(2.f, e + 1.f);
+}
+
+// the weights as the A operands of each lane (lane-major, so that a
+// wavefront reads one fragment with one 8-byte LDS load per lane), and the
+// first layer's point weights and the biases of the units a lane holds in
+// the output layout (unit 16 mt + 4 (lane / 16) + i)
+struct GuessLds {
+  v4s a2[4][4][64], a3[4][4][64], a4[4][64];
+  float w1p[4][4][4][3];   // [lane / 16][mt][i][input 81 + k]
+  float b2[64], b3[64];
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_guess(MeshView m, Particles P, int64_t n, float* __restrict__ guess) {
+  __shared__ GuessLds S;
+  const int lane = threadIdx.x & 63, kq = lane >> 4, col = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t cap = P.cap;
+  const float* W1 = m.mlp_w;
+  const float* W2 = W1 + H * NI + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H * H;
+  const float* W4 = b3 + H;
+  const float* b4 = W4 + NO * H;
+  // A[m][k] = W[16 mt + m][16 st + k] in lane m + 16 (k / 4), element k % 4
+  for (int idx = threadIdx.x; idx < 16 * 64; idx += blockDim.x) {
+    const int l = idx & 63, mt = (idx >> 6) & 3, st = idx >> 8;
+    const int o = 16 * mt + (l & 15), i0 = 16 * st + 4 * (l >> 4);
+    v4f w2, w3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      w2[j] = W2[o * H + i0 + j];
+      w3[j] = W3[o * H + i0 + j];
+    }
+    S.a2[mt][st][l] = to_bf16(w2);
+    S.a3[mt][st][l] = to_bf16(w3);
+    if (mt == 0) {
+      v4f w4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w4[j] = (l & 15) < NO ? W4[(l & 15) * H + i0 + j] : 0.f;
+      S.a4[st][l] = to_bf16(w4);
+    }
+  }
+  for (int idx = threadIdx.x; idx < 64; idx += blockDim.x) {
+    S.b2[idx] = b2[idx];
+    S.b3[idx] = b3[idx];
+    const int q = idx >> 4, mt = (idx >> 2) & 3, i = idx & 3, o = 16 * mt + 4 * q + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S.w1p[q][mt][i][k] = W1[o * NI + 81 + k];
+  }
+  __syncthreads();
+  for (int64_t base = wave * 64; base < n; base += nwave * 64) {
+    int e[4];
+    bool use[4];
+    bool any = false;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t p = base + 16 * nt + col;
+      e[nt] = 0;
+      use[nt] = false;
+      if (p < n && P.status[p] == ACTIVE) {
+        e[nt] = P.elem[p];
+        use[nt] = m.mlp_flag[e[nt]] != 0;
+      }
+      any = any || use[nt];
+    }
+    if (!__ballot(any)) continue;   // no particle of these 64 is in a flagged element
+    // layer 1 on the VALU: particles base + 16 nt + lane % 16
+    v4s hb[4][4];   // B operands [input tile][particle tile]
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t p = base + 16 * nt + col;
+      const double* c = m.mlp_ctr + (size_t)e[nt] * 4;
+      float xh[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xh[k] = p < n ? (float)((P.x[k * cap + p] - c[k]) * c[3]) : 0.f;
+      const float* h1e = m.mlp_h1 + (size_t)e[nt] * H;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const float4 t = *(const float4*)(h1e + 16 * mt + 4 * kq);
+        const float tv[4] = {t.x, t.y, t.z, t.w};
+        v4f z;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float* w = S.w1p[kq][mt][i];
+          z[i] = tanh_guess(tv[i] + w[0] * xh[0] + w[1] * xh[1] + w[2] * xh[2]);
+        }
+        hb[mt][nt] = to_bf16(z);
+      }
+    }
+    // layers 2 and 3 on the matrix cores
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+      v4s nb[4][4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        v4f acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[nt][i] = layer == 0 ? S.b2[16 * mt + 4 * kq + i] : S.b3[16 * mt + 4 * kq + i];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const v4s a = layer == 0 ? S.a2[mt][st][lane] : S.a3[mt][st][lane];
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, hb[st][nt], acc[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          v4f z;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) z[i] = tanh_guess(acc[nt][i]);
+          nb[mt][nt] = to_bf16(z);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) hb[mt][nt] = nb[mt][nt];
+    }
+    // output layer: rows 0..2 of the tile (lanes 0..15) are the guess
+    v4f acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[nt][i] = (kq == 0 && i < NO) ? b4[i] : 0.f;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const v4s a = S.a4[st][lane];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, hb[st][nt], acc[nt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t p = base + 16 * nt + col;
+      if (kq == 0 && use[nt]) {
+#pragma unroll
+        for (int k = 0; k < NO; ++k) guess[k * cap + p] = acc[nt][k];
+      }
+    }
+  }
+}
+
+hipError_t launch_mlp_guess(const MeshView& m, const Particles& P, int64_t n, float* guess, hipStream_t s) {
+  if (n == 0 || !m.mlp_w) return hipSuccess;
+  // persistent: each wavefront converts the weights once
+  const int64_t waves = std::min<int64_t>((n + 63) / 64, 4096);
+  k_mlp_guess<<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(m, P, n, guess);
+  return hipGetLastError();
+}
+
 hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_mlp_forward<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(w, n, in, out);

@@ -188,7 +188,13 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
       const UT* Ue = kStageU ? sU[slot] : U + (size_t)e * 5 * NN3;
       double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
       double xi[3];
-      if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb) || !inside_ref(xi)) {
+      float gl[3] = {0.f, 0.f, 0.f};
+      if (MLP && sp.mlp_guess) {
+        gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
+      }
+      if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb,
+                                    (MLP && sp.mlp_guess) ? gl : nullptr) ||
+          !inside_ref(xi)) {
         strag = true;   // not located in its element: the per-lane kernel recovers it
       } else {
         double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
@@ -275,8 +281,12 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
         int e = P.elem[p];
         double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
         double xi[3];
+        float gl[3] = {0.f, 0.f, 0.f};
+        if (MLP && sp.mlp_guess) {
+          gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
+        }
         bool ok = locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi,
-                                           sp.max_it, it_sum, calls, fb);
+                                           sp.max_it, it_sum, calls, fb, (MLP && sp.mlp_guess) ? gl : nullptr);
         bool inside = ok && inside_ref(xi);
         if (!ok) {
           // Newton diverges in the recorded element: the point left it along a
@@ -427,6 +437,11 @@ static void run_stage(const StageLaunch& L, hipStream_t s) {
   k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   int64_t lane_blocks;
   auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
+  if (MLP && L.sp.mlp_guess) {
+    rec(6);
+    (void)launch_mlp_guess(m, L.P, L.n, const_cast<float*>(L.sp.mlp_guess), s);
+    rec(7);
+  }
   if (stage_uses_tasks(L)) {
     // at most E + cap / tp + 1 tasks, 64 / tp per wavefront
     constexpr int tp = task_particles(NN, NG, MIXED), nw = elem_waves(tp);

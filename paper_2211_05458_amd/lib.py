@@ -27,7 +27,7 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_set_timing", "fp_get_timing", "fp_node_volumes", "fp_bind_particles",
            "fp_particle_block_layout", "fp_mlp_train", "fp_mlp_loss_grad_static"]
 TIMING_CLASSES = ("sort", "stage_elem", "finalize", "deposit_nearest", "deposit_shape", "stage_lane", "track",
-                  "deposit_norm", "deposit_gather")
+                  "deposit_norm", "deposit_gather", "learned_guess")
 
 
 class FPError(RuntimeError):
