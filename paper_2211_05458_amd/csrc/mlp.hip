@@ -83,110 +83,253 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w
   for (int k = 0; k < 3; ++k) out[r * 3 + k] = o[k];
 }
 
-// per-row forward and backward; activations and deltas to buf[row][ROW]
-__global__ __launch_bounds__(128) void k_mlp_rows(const float* __restrict__ w, int64_t n, const float* __restrict__ in,
-                                                  const float* __restrict__ target, const int32_t* __restrict__ rows,
-                                                  float* buf, float* loss) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float lsum = 0.0f;
-  if (r < n) {
-    int64_t src = rows ? rows[r] : r;
-    const float* W1 = w;
-    const float* b1 = W1 + H * NI;
-    const float* W2 = b1 + H;
-    const float* b2 = W2 + H * H;
-    const float* W3 = b2 + H;
-    const float* b3 = W3 + H * H;
-    const float* W4 = b3 + H;
-    const float* b4 = W4 + NO * H;
-    float* B = buf + r * ROW;
-    float* x = B;
-    float* h1 = x + NI;
-    float* h2 = h1 + H;
-    float* h3 = h2 + H;
-    float* d1 = h3 + H;
-    float* d2 = d1 + H;
-    float* d3 = d2 + H;
-    float* dy = d3 + H;
-    float xr[NI];
-    for (int i = 0; i < NI; ++i) { xr[i] = in[src * NI + i]; x[i] = xr[i]; }
-    float a[H], b[H];
-    for (int o = 0; o < H; ++o) {
-      float s = b1[o];
-      for (int i = 0; i < NI; ++i) s += W1[o * NI + i] * xr[i];
-      a[o] = tanhf(s);
-      h1[o] = a[o];
+// ---------------------------------------------------------------------------
+// Training on the matrix cores (FP32, v_mfma_f32_16x16x4f32).  The network
+// runs transposed, units as rows and batch rows as columns: a layer's 16x16
+// output tile holds, in lane (row l % 16, group q = l / 16), units
+// 16 t + 4 q + i in register i.  Taking the k-steps of the next product as the
+// unit sets {16 t + 4 k + i : k = 0..3} (k = lane group), register i of that
+// tile is already the B operand, forward (W H^T) and backward (W^T dZ^T)
+// alike; the weights are the A operands, read from LDS.
+// Lane layout: A[m][k], B[k][n] in lane (m or n) + 16 k; D[m][n] in lane
+// n + 16 (m / 4), register m % 4.
+// ---------------------------------------------------------------------------
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+constexpr int FBT = 2;   // 16-row tiles per wavefront of the training pass
+
+// forward and backward of 16 FBT batch rows per wavefront (one per workgroup);
+// activations and deltas to buf[row][ROW] (x, h1, h2, h3, d1, d2, d3, dy), the
+// mean squared error to *loss
+__global__ __launch_bounds__(64) void k_mlp_fb(const float* __restrict__ w, int64_t n, const float* __restrict__ in,
+                                               const float* __restrict__ target, const int32_t* __restrict__ rows,
+                                               float* buf, float* loss) {
+  __shared__ float W[NW];
+  for (int i = threadIdx.x; i < NW; i += 64) W[i] = w[i];
+  __syncthreads();
+  const float* W1 = W;
+  const float* b1 = W1 + H * NI;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H * H;
+  const float* W4 = b3 + H;
+  const float* b4 = W4 + NO * H;
+  const int lane = threadIdx.x, kq = lane >> 4, col = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * (16 * FBT);
+  const float scale = 1.0f / (float)(n * NO);
+  int64_t src[FBT];
+  bool ok[FBT];
+#pragma unroll
+  for (int nt = 0; nt < FBT; ++nt) {
+    const int64_t r = r0 + 16 * nt + col;
+    ok[nt] = r < n;
+    src[nt] = ok[nt] ? (rows ? rows[r] : r) : 0;
+  }
+  // layer 1: k-steps of four consecutive inputs 4 s + k
+  v4f32 h1[4][FBT], h2[4][FBT], h3[4][FBT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < FBT; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h1[mt][nt][i] = b1[16 * mt + 4 * kq + i];
+#pragma unroll 3
+  for (int st = 0; st < NI / 4; ++st) {
+    float xb[FBT];
+#pragma unroll
+    for (int nt = 0; nt < FBT; ++nt) {
+      xb[nt] = ok[nt] ? in[src[nt] * NI + 4 * st + kq] : 0.f;
+      if (ok[nt]) buf[(r0 + 16 * nt + col) * ROW + 4 * st + kq] = xb[nt];
     }
-    for (int o = 0; o < H; ++o) {
-      float s = b2[o];
-      for (int i = 0; i < H; ++i) s += W2[o * H + i] * a[i];
-      b[o] = tanhf(s);
-      h2[o] = b[o];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const float a = W1[(16 * mt + col) * NI + 4 * st + kq];
+#pragma unroll
+      for (int nt = 0; nt < FBT; ++nt) h1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xb[nt], h1[mt][nt], 0, 0, 0);
     }
-    for (int o = 0; o < H; ++o) {
-      float s = b3[o];
-      for (int i = 0; i < H; ++i) s += W3[o * H + i] * b[i];
-      a[o] = tanhf(s);
-      h3[o] = a[o];
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < FBT; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h1[mt][nt][i] = tanhf(h1[mt][nt][i]);
+  // hidden layers: k-step (t, i) = units 16 t + 4 k + i
+  auto forward = [&](const float* Wl, const float* bl, v4f32 (*hin)[FBT], v4f32 (*hout)[FBT]) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int nt = 0; nt < FBT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hout[mt][nt][i] = bl[16 * mt + 4 * kq + i];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float a = Wl[(16 * mt + col) * H + 16 * t + 4 * kq + i];
+#pragma unroll
+          for (int nt = 0; nt < FBT; ++nt)
+            hout[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hin[t][nt][i], hout[mt][nt], 0, 0, 0);
+        }
+#pragma unroll
+      for (int nt = 0; nt < FBT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hout[mt][nt][i] = tanhf(hout[mt][nt][i]);
     }
-    const float scale = 1.0f / (float)(n * NO);
-    float g[NO];
-    for (int o = 0; o < NO; ++o) {
-      float s = b4[o];
-      for (int i = 0; i < H; ++i) s += W4[o * H + i] * a[i];
-      float diff = s - target[src * NO + o];
-      lsum += diff * diff * scale;
-      g[o] = 2.0f * diff * scale;
-      dy[o] = g[o];
+  };
+  forward(W2, b2, h1, h2);
+  forward(W3, b3, h2, h3);
+  // output rows 0..2 (lanes of group 0, register j), error and its gradient
+  float lsum = 0.f;
+  float dyv[FBT][NO];
+#pragma unroll
+  for (int nt = 0; nt < FBT; ++nt) {
+    v4f32 y;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = (kq == 0 && i < NO) ? b4[i] : 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float a = col < NO ? W4[col * H + 16 * t + 4 * kq + i] : 0.f;
+        y = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h3[t][nt][i], y, 0, 0, 0);
+      }
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      float g = 0.f;
+      if (kq == 0 && ok[nt]) {
+        const float diff = y[j] - target[src[nt] * NO + j];
+        lsum += diff * diff * scale;
+        g = 2.0f * diff * scale;
+      }
+      dyv[nt][j] = g;
     }
-    // deltas (pre-activation gradients)
-    for (int i = 0; i < H; ++i) {
-      float s = 0.0f;
-      for (int o = 0; o < NO; ++o) s += W4[o * H + i] * g[o];
-      b[i] = s * (1.0f - a[i] * a[i]);
-      d3[i] = b[i];
+  }
+  // d3 = W4^T dy (k = output j, one k-step) * (1 - h3^2)
+  v4f32 d3[4][FBT], d2[4][FBT], d1[4][FBT];
+#pragma unroll
+  for (int nt = 0; nt < FBT; ++nt) {
+    const float s0 = __shfl(dyv[nt][0], col, 64), s1 = __shfl(dyv[nt][1], col, 64), s2 = __shfl(dyv[nt][2], col, 64);
+    const float bdy = kq == 0 ? s0 : kq == 1 ? s1 : kq == 2 ? s2 : 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const float a = kq < NO ? W4[kq * H + 16 * mt + col] : 0.f;
+      v4f32 z = {0.f, 0.f, 0.f, 0.f};
+      z = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bdy, z, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) d3[mt][nt][i] = z[i] * (1.f - h3[mt][nt][i] * h3[mt][nt][i]);
     }
-    for (int i = 0; i < H; ++i) {
-      float s = 0.0f;
-      for (int o = 0; o < H; ++o) s += W3[o * H + i] * b[o];
-      float hv = h2[i];
-      a[i] = s * (1.0f - hv * hv);
-      d2[i] = a[i];
+    if (kq == 0 && ok[nt]) {
+#pragma unroll
+      for (int j = 0; j < NO; ++j) buf[(r0 + 16 * nt + col) * ROW + NI + 6 * H + j] = dyv[nt][j];
     }
-    for (int i = 0; i < H; ++i) {
-      float s = 0.0f;
-      for (int o = 0; o < H; ++o) s += W2[o * H + i] * a[o];
-      float hv = h1[i];
-      d1[i] = s * (1.0f - hv * hv);
+  }
+  // d_prev = W^T d (A[m = input unit][k = output unit]) * (1 - h_prev^2)
+  auto backward = [&](const float* Wl, v4f32 (*din)[FBT], v4f32 (*hprev)[FBT], v4f32 (*dout)[FBT]) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      v4f32 z[FBT];
+#pragma unroll
+      for (int nt = 0; nt < FBT; ++nt) z[nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float a = Wl[(16 * t + 4 * kq + i) * H + 16 * mt + col];
+#pragma unroll
+          for (int nt = 0; nt < FBT; ++nt) z[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, din[t][nt][i], z[nt], 0, 0, 0);
+        }
+#pragma unroll
+      for (int nt = 0; nt < FBT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dout[mt][nt][i] = z[nt][i] * (1.f - hprev[mt][nt][i] * hprev[mt][nt][i]);
+    }
+  };
+  backward(W3, d3, h2, d2);
+  backward(W2, d2, h1, d1);
+  // rows to the buffer: four consecutive units per lane and tile
+#pragma unroll
+  for (int nt = 0; nt < FBT; ++nt) {
+    if (!ok[nt]) continue;
+    float* B = buf + (r0 + 16 * nt + col) * ROW + NI;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int u = 16 * mt + 4 * kq;
+      *(float4*)(B + 0 * H + u) = make_float4(h1[mt][nt][0], h1[mt][nt][1], h1[mt][nt][2], h1[mt][nt][3]);
+      *(float4*)(B + 1 * H + u) = make_float4(h2[mt][nt][0], h2[mt][nt][1], h2[mt][nt][2], h2[mt][nt][3]);
+      *(float4*)(B + 2 * H + u) = make_float4(h3[mt][nt][0], h3[mt][nt][1], h3[mt][nt][2], h3[mt][nt][3]);
+      *(float4*)(B + 3 * H + u) = make_float4(d1[mt][nt][0], d1[mt][nt][1], d1[mt][nt][2], d1[mt][nt][3]);
+      *(float4*)(B + 4 * H + u) = make_float4(d2[mt][nt][0], d2[mt][nt][1], d2[mt][nt][2], d2[mt][nt][3]);
+      *(float4*)(B + 5 * H + u) = make_float4(d3[mt][nt][0], d3[mt][nt][1], d3[mt][nt][2], d3[mt][nt][3]);
     }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(loss, lsum);
+  if (lane == 0) atomicAdd(loss, lsum);
 }
 
-// weight gradients: block (o, layer), threads stride over the layer's inputs,
-// each summing over the rows
-__global__ __launch_bounds__(128) void k_mlp_wgrad(int64_t n, const float* __restrict__ buf, float* grad) {
-  int o = blockIdx.x, layer = blockIdx.y;
-  int nin = layer == 0 ? NI : H;
-  int nout = layer == 3 ? NO : H;
-  if (o >= nout) return;
-  int in_off = layer == 0 ? 0 : (layer == 1 ? NI : (layer == 2 ? NI + H : NI + 2 * H));
-  int d_off = layer == 0 ? NI + 3 * H : (layer == 1 ? NI + 4 * H : (layer == 2 ? NI + 5 * H : NI + 6 * H));
-  size_t wofs = layer == 0 ? 0 : (layer == 1 ? H * NI + H : (layer == 2 ? H * NI + H + H * H + H : H * NI + H + 2 * (H * H + H)));
-  for (int i = threadIdx.x; i < nin; i += blockDim.x) {
-    float g = 0.0f;
-    for (int64_t r = 0; r < n; ++r) {
-      const float* B = buf + r * ROW;
-      g += B[d_off + o] * B[in_off + i];
+// Weight and bias gradients on the matrix cores: one wavefront per 16x16
+// tile of a layer's gradient, summing over the batch rows (k-steps of four
+// rows): dW[o][i] = sum_r d[r][o] h_in[r][i]; the bias column is the tile whose
+// input is 1 in column 0.
+struct GradTile { int layer, mt, it; };   // it == -1: the bias tile
+__device__ inline GradTile grad_tile(int b) {
+  // layer 1: 4 x 6 tiles (84 inputs) + 4 bias tiles; layers 2, 3: 4 x 4 + 4;
+  // output layer: 1 x 4 + 1
+  if (b < 28) return {0, b / 7, b % 7 == 6 ? -1 : b % 7};
+  b -= 28;
+  if (b < 20) return {1, b / 5, b % 5 == 4 ? -1 : b % 5};
+  b -= 20;
+  if (b < 20) return {2, b / 5, b % 5 == 4 ? -1 : b % 5};
+  b -= 20;
+  return {3, 0, b == 4 ? -1 : b};
+}
+constexpr int kGradTiles = 28 + 20 + 20 + 5;
+
+// four wavefronts per tile, each summing every fourth group of four rows,
+// then the four partial tiles added in a fixed order
+__global__ __launch_bounds__(256) void k_mlp_wgrad_mfma(int64_t n, const float* __restrict__ buf, float* grad) {
+  __shared__ v4f32 part[3][64];
+  const GradTile T = grad_tile(blockIdx.x);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = lane >> 4, col = lane & 15;
+  const int nin = T.layer == 0 ? NI : H, nout = T.layer == 3 ? NO : H;
+  const int in_off = T.layer == 0 ? 0 : NI + (T.layer - 1) * H;
+  const int d_off = T.layer == 3 ? NI + 6 * H : NI + (3 + T.layer) * H;
+  const size_t wofs = T.layer == 0 ? 0 : (size_t)H * NI + H + (size_t)(T.layer - 1) * (H * H + H);
+  const int o = 16 * T.mt + col, i = 16 * T.it + col;
+  const bool ao = o < nout, bi = T.it >= 0 && i < nin;
+  v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+  constexpr int U = 4;   // k-steps in flight
+  for (int64_t r0 = 4 * (int64_t)wv; r0 < n; r0 += 16 * U) {
+    float a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + 16 * u + kq;
+      const bool live = r < n;
+      const float* B = buf + (live ? r : 0) * ROW;
+      a[u] = (ao && live) ? B[d_off + o] : 0.f;
+      b[u] = T.it >= 0 ? ((bi && live) ? B[in_off + i] : 0.f) : ((col == 0 && live) ? 1.f : 0.f);
     }
-    grad[wofs + (size_t)o * nin + i] = g;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
   }
-  if (threadIdx.x == 0) {
-    float gb = 0.0f;
-    for (int64_t r = 0; r < n; ++r) gb += buf[r * ROW + d_off + o];
-    grad[wofs + (size_t)nout * nin + o] = gb;
+  if (wv > 0) part[wv - 1][lane] = acc;
+  __syncthreads();
+  if (wv != 0) return;
+  acc += part[0][lane];
+  acc += part[1][lane];
+  acc += part[2][lane];
+  // D[m = output 16 mt + 4 kq + j][n = input col]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int oo = 16 * T.mt + 4 * kq + j;
+    if (oo >= nout) continue;
+    if (T.it >= 0) {
+      if (bi) grad[wofs + (size_t)oo * nin + i] = acc[j];
+    } else if (col == 0) {
+      grad[wofs + (size_t)nout * nin + oo] = acc[j];
+    }
   }
 }
 
@@ -496,8 +639,8 @@ hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, cons
                                 const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s) {
   if (n <= 0 || n > kMlpMaxBatch) return hipErrorInvalidValue;
   k_zero_f32<<<1, 64, 0, s>>>(loss, 1);
-  k_mlp_rows<<<dim3((unsigned)((n + 127) / 128)), 128, 0, s>>>(w, n, in, target, rows, rowbuf, loss);
-  k_mlp_wgrad<<<dim3(H, 4), 128, 0, s>>>(n, rowbuf, grad);
+  k_mlp_fb<<<dim3((unsigned)((n + 16 * FBT - 1) / (16 * FBT))), 64, 0, s>>>(w, n, in, target, rows, rowbuf, loss);
+  k_mlp_wgrad_mfma<<<dim3(kGradTiles), 256, 0, s>>>(n, rowbuf, grad);
   return hipGetLastError();
 }
 
