@@ -45,11 +45,7 @@ DEP_FLOPS_NORM = 13
 DEP_FLOPS_GATHER = 19
 TRAFFIC = {   # committed counter summaries: kernel -> (file, sources its hash covers)
     "k_dep_norm_mfma": ("profiles/k_dep_norm_mfma_twoway96_traffic.md",
-                        ["paper_2211_05458_amd/csrc/deposit.hip", "paper_2211_05458_amd/csrc/fp_internal.h",
-                         "paper_2211_05458_amd/build.py"]),
-    "k_stage_elem": ("profiles/k_stage_elem_fp64_curved32_traffic.md",
-                     ["paper_2211_05458_amd/csrc/fp_device.h", "paper_2211_05458_amd/csrc/stage.hip",
-                      "paper_2211_05458_amd/csrc/fp_internal.h", "paper_2211_05458_amd/build.py"]),
+                        ["paper_2211_05458_amd/csrc/deposit.hip", "paper_2211_05458_amd/build.py"]),
 }
 
 

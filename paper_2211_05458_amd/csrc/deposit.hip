@@ -611,6 +611,7 @@ template <int CAP>
 struct PStage {
   float4 f[CAP];    // 2 p, alpha_p = 1 - |p|^2 (padding rows: 0, 0, 0, -1)
   float4 g[CAP];    // G_p (pass 2)
+  float acc[CAP];   // normalisation sums of both wavefronts (pass 1), zero outside the processed tiles
   int32_t id[CAP];  // particle index, -1 for a padding row
 };
 
@@ -728,12 +729,12 @@ struct WinLds {
 // 16-particle tile of the list with its own node tiles.  The last partial
 // tile is padded (q <= -1, so K = 0) and flushed.  All threads of the
 // workgroup must call it.
-template <int NN, class Tile>
+template <int NN, class Tile, class Flush>
 __device__ inline void stream_particles(const MeshView& m, const int32_t* __restrict__ elem_start, const DepGeo& g,
                                         const DepLists& dl, const float4* __restrict__ xl,
                                         const float* __restrict__ Gp, int t, const double* ctr, double part_pad,
                                         CandLds<NodeTiling<NN>::TH>& L, WinLds& Wl,
-                                        PStage<NodeTiling<NN>::CAP>& s_c, Tile&& tile) {
+                                        PStage<NodeTiling<NN>::CAP>& s_c, Tile&& tile, Flush&& flush) {
   constexpr int TH = NodeTiling<NN>::TH;
   const double* nb = m.nbox + (size_t)t * 6;
   const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
@@ -824,11 +825,12 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
       int first = 0;
       for (; n - first >= 16; first += 16) tile(first);
       if (first > 0) {
-        // the remainder (< 16 entries) to the front
+        // the processed entries' sums out, the remainder (< 16 entries) to the front
         const int rem = n - first;
         float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), g0 = f0;
         int32_t i0 = -1;
         __syncthreads();
+        flush(first);
         if ((int)threadIdx.x < rem) {
           f0 = s_c.f[first + threadIdx.x];
           g0 = s_c.g[first + threadIdx.x];
@@ -853,6 +855,8 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
     }
     __syncthreads();
     tile(0);
+    __syncthreads();
+    flush(16);
   }
 }
 
@@ -906,13 +910,24 @@ __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per
       }
       __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
     }
-    // sum over the node rows held by the four lane groups
+    // sum over the node rows held by the four lane groups, then both
+    // wavefronts' sums in LDS (one global atomic per particle and target)
     acc += __shfl_xor(acc, 16, 64);
     acc += __shfl_xor(acc, 32, 64);
-    const int32_t id = s_c.id[pc];
-    if (lane < 16 && id >= 0 && acc != 0.f) atomicAdd(norm + id, acc);
+    if (lane < 16 && acc != 0.f) atomicAdd(&s_c.acc[pc], acc);
   };
-  stream_particles<NN>(m, elem_start, g, dl, xl, nullptr, t, ctr, part_pad, L, Wl, s_c, tile);
+  // entries [0, cnt) are processed: their sums to the particles, LDS cleared
+  auto flush = [&](int cnt) {
+    for (int k = threadIdx.x; k < cnt; k += T::TH) {
+      const float a = s_c.acc[k];
+      const int32_t id = s_c.id[k];
+      if (id >= 0 && a != 0.f) atomicAdd(norm + id, a);
+      s_c.acc[k] = 0.f;
+    }
+  };
+  for (int k = threadIdx.x; k < T::CAP; k += T::TH) s_c.acc[k] = 0.f;
+  __syncthreads();
+  stream_particles<NN>(m, elem_start, g, dl, xl, nullptr, t, ctr, part_pad, L, Wl, s_c, tile, flush);
   if (COUNT && pairs && lane == 0 && npairs) atomicAdd(pairs + (blockIdx.x & (kStatSlots - 1)), npairs);
 }
 
@@ -995,7 +1010,7 @@ __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per
     }
     __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
   };
-  stream_particles<NN>(m, elem_start, g, dl, xl, Gp, t, ctr, part_pad, L, Wl, s_c, tile);
+  stream_particles<NN>(m, elem_start, g, dl, xl, Gp, t, ctr, part_pad, L, Wl, s_c, tile, [](int) {});
   // sum over the particle quarters, then one read-modify-write of each
   // (node, component)
   const int t0 = wave * T::TPW;
