@@ -49,6 +49,12 @@ TRAFFIC = {   # committed counter summaries: kernel -> (file, sources its hash c
 }
 
 
+# guess bit 1 in every form: each particle is located from its reference
+# coordinates of the previous stage continued along its displacement first
+# (the paper's guess after a crossing or reflection); --no-warm turns it off
+WARM = 2
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -128,8 +134,8 @@ def run_gpu(w, U, precision, steps, warmup, guess=0, weights=None, deposit=None,
     st, nrej = g.push(x, v, d, h)
     n_active = int((st == 0).sum())
     n_flagged = g.mlp_set_weights(weights) if weights is not None else 0
-    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=sort_every, guess=guess, tracking=tracking,
-                forces=forces, gravity=gravity)
+    opts = dict(rk=w.rk, drag=w.drag, precision=precision, sort_every=sort_every, guess=guess | WARM,
+                tracking=tracking, forces=forces, gravity=gravity)
     for _ in range(warmup):
         g.step(w.dt, 1, **opts)
         if deposit:
@@ -408,7 +414,10 @@ def bench_composite(args):
         "config": {"workload": "two-way coupling at scale: curved sine box 96^3 Ngeo=4, DG N=5 random-Fourier "
                                "state, %d particles, Schiller-Naumann, 3-stage LSERK, dt=1e-3, shape-kernel source "
                                "R=1.5h after every step; FP32 + learned-guess form" % rv["n_active"],
-                   "elements": 884736, "particles": rv["n_active"], "N": 5, "n_geo": 4},
+                   "elements": 884736, "particles": rv["n_active"], "N": 5, "n_geo": 4,
+                   "newton_guess": ("continued reference coordinates of the previous stage first, then the "
+                                    "learned guess on flagged elements, then the paper's guess (both forms)")
+                   if WARM else "learned guess on flagged elements, then the paper's guess"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp32_learned": value,
@@ -554,9 +563,13 @@ def main():
     ap.add_argument("--err-every", type=int, default=10000, help="error subset: every k-th particle")
     ap.add_argument("--cpu-every", type=int, default=2500, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-warm", action="store_true",
+                    help="locate with the paper's initial guess only (no continued reference coordinates)")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: a plain device copy of known size, the calibration for HBM counters")
     args = ap.parse_args()
+    global WARM
+    WARM = 0 if args.no_warm else 2
     if args.mode == "copy":
         copy_calibration()
         return

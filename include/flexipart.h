@@ -91,7 +91,12 @@ typedef struct {
   int32_t rk;            /* 0: 5-stage 4th-order low-storage RK (Carpenter-Kennedy), 1: 3-stage 3rd-order (Williamson) */
   int32_t drag;          /* 0: Stokes (f_D = 1), 1: Schiller-Naumann, 2: no drag */
   int32_t precision;     /* 0: FP64 throughout; 1: mixed (FP32 interpolation/drag/RK, FP64 Newton tail and tracking) */
-  int32_t guess;         /* 0: the paper's initial guess; 1: learned guess on flagged elements, paper's guess as fallback */
+  int32_t guess;         /* bit 0: learned guess on flagged elements (the paper's guess as fallback);
+                            bit 1: first try each particle's reference coordinates of the previous
+                            stage continued along its displacement (xi + J^-1 dx, kept from the
+                            last Newton of that stage; not after a crossing or reflection);
+                            0: the paper's initial guess (Sec. 3.2.1).  The converged xi is the
+                            same from any guess in Newton's basin. */
   int32_t sort_every;    /* counting-sort particles by element every k steps (0: never) */
   int32_t max_newton_it; /* Newton iteration cap (50) */
   int32_t max_crossings; /* face crossings per stage before FP_MAX_CROSS (64) */

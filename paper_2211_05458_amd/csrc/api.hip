@@ -58,6 +58,7 @@ struct fp_ctx {
   int64_t np = 0;
   double d_min = 0.0;
   bool xi_dirty = false;
+  bool xi_warm = false;   // P.xi holds each particle's continued reference coordinates (or NaN)
   bool sorted_fresh = false;   // sorted by element, and no particle moved since
   int64_t steps_done = 0, sorts = 0;
   // caller-owned particle block (fp_bind_particles): P[0] then lives there and
@@ -888,7 +889,8 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   sp.drag = o->drag;
   sp.max_it = o->max_newton_it > 0 ? o->max_newton_it : 50;
   sp.max_cross = o->max_crossings > 0 ? o->max_crossings : 64;
-  sp.use_mlp = (o->guess == 1 && c->mlp_w) ? 1 : 0;
+  sp.use_mlp = ((o->guess & 1) && c->mlp_w) ? 1 : 0;
+  sp.warm = (o->guess & 2) ? 1 : 0;
   sp.refspace = o->tracking;
   sp.forces = o->forces;
   sp.mlp_guess = (sp.use_mlp && c->n_flagged > 0) ? c->mlp_guess : nullptr;
@@ -938,6 +940,7 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
     c->steps_done++;
   }
   c->xi_dirty = true;
+  c->xi_warm = sp.warm != 0;
   {
     int rc = sync_bound(c);
     if (rc) return rc;
@@ -971,7 +974,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   // crossing the face intersection missed, leaves the old element recorded)
   if (c->xi_dirty && c->np > 0) {
     Timed tm(c, 2);
-    HIPCHK(c, launch_finalize(c->mv, c->P[c->cur], c->np, c->stats, c->stream));
+    HIPCHK(c, launch_finalize(c->mv, c->P[c->cur], c->np, c->xi_warm ? 1 : 0, c->stats, c->stream));
     c->xi_dirty = false;
     c->sorted_fresh = false;
   }
@@ -1048,7 +1051,7 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
   const int64_t cap = P.cap;
   if (c->xi_dirty) {
     Timed tm(c, 2);
-    HIPCHK(c, launch_finalize(c->mv, P, n, c->stats, s));
+    HIPCHK(c, launch_finalize(c->mv, P, n, c->xi_warm ? 1 : 0, c->stats, s));
     c->xi_dirty = false;
     c->sorted_fresh = false;
   }

@@ -153,9 +153,12 @@ __device__ __forceinline__ void map_jac(const MeshView& m, const double* __restr
 
 // Newton for chi(xi) = x (Sec. 3.2.1): Cramer's rule, stop after an update with
 // max-norm <= 1e-10, divergence when |xi| > 2 after the third iteration.
+// Ji (may be null): on success, the inverse of the last Jacobian (row-major),
+// the Jacobian at the iterate before the final update, for continuing xi
+// along a short displacement
 template <int NG>
 __device__ bool newton_e(const MeshView& m, const double* __restrict__ X, const double* x, double* z, int max_it,
-                         int& iters) {
+                         int& iters, double* Ji = nullptr) {
   for (int it = 1; it <= max_it; ++it) {
     double F[3], J[3][3];
     map_jac<NG>(m, X, z, F, J);
@@ -173,7 +176,21 @@ __device__ bool newton_e(const MeshView& m, const double* __restrict__ X, const 
     z[0] += dz0; z[1] += dz1; z[2] += dz2;
     double dmax = fmax(fabs(dz0), fmax(fabs(dz1), fabs(dz2)));
     if (!isfinite(z[0]) || !isfinite(z[1]) || !isfinite(z[2])) { iters += it; return false; }
-    if (dmax <= kNewtonTol) { iters += it; return true; }
+    if (dmax <= kNewtonTol) {
+      iters += it;
+      if (Ji) {
+        Ji[0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * inv;
+        Ji[1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * inv;
+        Ji[2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * inv;
+        Ji[3] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * inv;
+        Ji[4] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * inv;
+        Ji[5] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * inv;
+        Ji[6] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * inv;
+        Ji[7] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * inv;
+        Ji[8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * inv;
+      }
+      return true;
+    }
     if (it >= 3 && fmax(fabs(z[0]), fmax(fabs(z[1]), fabs(z[2]))) > 2.0) { iters += it; return false; }
   }
   iters += max_it;
@@ -369,37 +386,84 @@ __device__ inline void mlp_forward_row(const float* __restrict__ w, const float*
   }
 }
 
-// Reference coordinates of x in element e: learned guess (flagged elements;
-// gin, the stage's precomputed guess of this particle), then the paper's
-// guess, then the face-barycentre guess.
+// Reference coordinates of x in element e: the continued coordinates of the
+// particle's previous position (gw, may be null), then the learned guess
+// (flagged elements; gin, the stage's precomputed guess of this particle),
+// then the paper's guess, then the face-barycentre guess.  Ji (may be null):
+// see newton_e.
+// (The guesses come as arrays with flags, not as pointers that may be null:
+// a pointer chosen at run time between an array and null keeps the array out
+// of registers.)
 template <int NN, int NG, bool MLP = false>
 __device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__ Xe, const double* __restrict__ XNe,
                             const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks,
-                            const float* gin = nullptr) {
+                            bool use_gin = false, const float* gin = nullptr, bool use_gw = false,
+                            const double* gw = nullptr, double* Ji = nullptr) {
   double g[3];
-  if (MLP && gin && m.mlp_flag[e]) {
+  // the first guess of each lane (continued coordinates, else the learned
+  // guess on a flagged element, else the paper's), then one Newton for all
+  // lanes of the wavefront together; the other guesses only on failure
+  const bool learned = MLP && use_gin && m.mlp_flag[e];
+  int first;
+  if (use_gw) {
+    first = 0;
+    g[0] = gw[0]; g[1] = gw[1]; g[2] = gw[2];
+  } else if (learned) {
+    first = 1;
+    g[0] = gin[0]; g[1] = gin[1]; g[2] = gin[2];
+  } else {
+    first = 2;
+    guess_paper_e<NN, NG>(m, Xe, XNe, x, g);
+  }
+  calls++;
+  if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+  fallbacks++;
+  if (first < 1 && learned) {
     g[0] = gin[0]; g[1] = gin[1]; g[2] = gin[2];
     calls++;
-    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
     fallbacks++;
   }
-  guess_paper_e<NN, NG>(m, Xe, XNe, x, g);
-  calls++;
-  if (newton_e<NG>(m, Xe, x, g, max_it, it_sum)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
-  fallbacks++;
+  if (first < 2) {
+    guess_paper_e<NN, NG>(m, Xe, XNe, x, g);
+    calls++;
+    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+    fallbacks++;
+  }
   guess_faces_e<NG>(Xe, x, g);
   calls++;
-  bool ok = newton_e<NG>(m, Xe, x, g, max_it, it_sum);
+  bool ok = newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji);
   xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2];
   return ok;
 }
 
+// the continued reference coordinates of a particle, if stored and plausible
+__device__ __forceinline__ bool warm_guess(const Particles& P, int64_t p, double* gw) {
+  const int64_t cap = P.cap;
+  gw[0] = P.xi[p];
+  gw[1] = P.xi[cap + p];
+  gw[2] = P.xi[2 * cap + p];
+  return fabs(gw[0]) <= 1.5 && fabs(gw[1]) <= 1.5 && fabs(gw[2]) <= 1.5;   // false for the NaN mark
+}
+
+// xi + Ji (xe - x): the reference coordinates of the end of a short step
+// from x, to first order, stored as the next location's guess
+__device__ __forceinline__ void store_warm(const Particles& P, int64_t p, const double* xi, const double* Ji,
+                                           const double* x, const double* xe) {
+  const int64_t cap = P.cap;
+  const double d[3] = {xe[0] - x[0], xe[1] - x[1], xe[2] - x[2]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.xi[k * cap + p] = xi[k] + Ji[3 * k] * d[0] + Ji[3 * k + 1] * d[1] + Ji[3 * k + 2] * d[2];
+}
+
 template <int NN, int NG>
 __device__ __forceinline__ bool locate_xi(const MeshView& m, int e, const double* x, double* xi, int max_it,
-                                          bool use_mlp, int& it_sum, int& calls, int& fallbacks) {
+                                          bool use_mlp, int& it_sum, int& calls, int& fallbacks,
+                                          bool use_gw = false, const double* gw = nullptr) {
   (void)use_mlp;
   return locate_xi_e<NN, NG, false>(m, e, m.X + (size_t)e * (NG * NG * NG * 3),
-                                    m.xnode + (size_t)e * (NN * NN * NN * 3), x, xi, max_it, it_sum, calls, fallbacks);
+                                    m.xnode + (size_t)e * (NN * NN * NN * 3), x, xi, max_it, it_sum, calls, fallbacks,
+                                    false, nullptr, use_gw, gw);
 }
 
 // A located particle lies outside its element: a crossing that was not traced
@@ -1571,6 +1635,7 @@ __device__ void track_queue(const MeshView& m, const Particles& P, const int32_t
         if (e != e0) P.elem[p] = e;
         if (hits) P.hits[p] += hits;
         if (status != ACTIVE) P.status[p] = status;
+        P.xi[p] = NAN;   // the continued reference coordinates no longer hold
       }
       p = -1;
     }

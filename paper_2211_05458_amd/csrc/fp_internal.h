@@ -120,6 +120,7 @@ struct StepParams {
   int32_t refspace;     // reference-space localisation of segments that cannot reach a boundary face
   int32_t forces;       // kForce* terms beyond drag and gravity
   const float* mlp_guess;   // [3][cap] learned guesses of the stage (flagged elements), or null
+  int32_t warm;             // locate from the particle's continued reference coordinates (P.xi) first
 };
 
 // force model of the two-way source (the fluid force of the equation of motion)

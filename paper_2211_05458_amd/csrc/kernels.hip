@@ -271,7 +271,8 @@ hipError_t launch_min_positive(const double* d, int64_t n, unsigned long long* i
 
 // reference coordinates of the current positions, with the inside check
 template <int NN, int NG>
-__global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, unsigned long long* stats) {
+__global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, int warm,
+                                                  unsigned long long* stats) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int nlost = 0, nrec = 0;
   if (p < n && P.status[p] == ACTIVE) {
@@ -279,7 +280,9 @@ __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64
     double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
     double xi[3];
     int it = 0, calls = 0, fb = 0, e = P.elem[p];
-    bool ok = locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb);
+    double gw[3];
+    const bool wv = warm && warm_guess(P, p, gw);
+    bool ok = locate_xi<NN, NG>(m, e, x, xi, 50, false, it, calls, fb, wv, gw);
     bool inside = ok && inside_ref(xi);
     if (!ok) {
       // as in the stage: the background-mesh candidates of the point
@@ -397,11 +400,14 @@ hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* h
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, unsigned long long* stats,
+hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, int warm, unsigned long long* stats,
                            hipStream_t s) {
   if (n == 0) return hipSuccess;
-#define FP_L(A, B) \
-  if (m.n == A && m.ng == B) { k_finalize<A, B><<<grid_for(n), 256, 0, s>>>(m, P, n, stats); return hipGetLastError(); }
+#define FP_L(A, B)                                                                    \
+  if (m.n == A && m.ng == B) {                                                        \
+    k_finalize<A, B><<<grid_for(n), 256, 0, s>>>(m, P, n, warm, stats);               \
+    return hipGetLastError();                                                         \
+  }
   FP_FOR_EACH_SHAPE(FP_L)
 #undef FP_L
   return hipErrorInvalidValue;

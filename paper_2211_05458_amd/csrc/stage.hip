@@ -192,11 +192,20 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
       if (MLP && sp.mlp_guess) {
         gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
       }
+      double gw[3], Ji[9];
+      const bool wv = sp.warm && warm_guess(P, p, gw);
       if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb,
-                                    (MLP && sp.mlp_guess) ? gl : nullptr) ||
+                                    MLP && sp.mlp_guess, gl, wv, gw, Ji) ||
           !inside_ref(xi)) {
         strag = true;   // not located in its element: the per-lane kernel recovers it
       } else {
+        if (sp.warm) {
+          // the stage moves x by B (A kx + dt v): continue xi along it
+          double xe1[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) xe1[k] = x[k] + sp.B * (sp.A * P.kx[k * cap + p] + sp.dt * P.v[k * cap + p]);
+          store_warm(P, p, xi, Ji, x, xe1);
+        }
         double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
         double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
         double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
@@ -285,9 +294,12 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
         if (MLP && sp.mlp_guess) {
           gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
         }
+        double gw[3], Ji[9];
+        const bool wv = sp.warm && warm_guess(P, p, gw);
         bool ok = locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi,
-                                           sp.max_it, it_sum, calls, fb, (MLP && sp.mlp_guess) ? gl : nullptr);
+                                           sp.max_it, it_sum, calls, fb, MLP && sp.mlp_guess, gl, wv, gw, Ji);
         bool inside = ok && inside_ref(xi);
+        const bool direct = inside;   // located in the recorded element (Ji belongs to this xi)
         if (!ok) {
           // Newton diverges in the recorded element: the point left it along a
           // segment that was not traced (reference-space localisation), and the
@@ -318,6 +330,16 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
           double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
           double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
           double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
+          if (sp.warm) {
+            if (direct) {
+              double xe1[3];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) xe1[k] = x[k] + sp.B * (sp.A * kx[k] + sp.dt * v[k]);
+              store_warm(P, p, xi, Ji, x, xe1);
+            } else {
+              P.xi[p] = NAN;   // located by a recovery: no Jacobian of this xi at hand
+            }
+          }
           double xe[3];
           const UT* Ue = (const UT*)fl.U + (size_t)e * 5 * NN3;
           const double* Xe = m.X + (size_t)e * NG3 * 3;
