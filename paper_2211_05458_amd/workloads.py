@@ -344,6 +344,28 @@ def curved_box(cells=32, N=5, n_particles=1_000_000, n_steps=500, seed=1002, nam
                     dt=1e-3, n_steps=n_steps, rk=1, drag=1, velocity=field)
 
 
+def peaked_box(displace=0.08, cells=3, N=3, n_geo=4):
+    """The sine box of curved_box with the centre geometry node of the central
+    element moved by -displace * h along x: the element stays valid (det J > 0)
+    but its map is compressed at the centre of its face xi_1 = +1, where
+    |grad xi_1| peaks far above its value at any point of a lattice that skips
+    xi = 0 (the face stays shared with the neighbour, which is untouched).
+    Returns the workload (no particles) and the element index."""
+    assert cells % 2 == 1 and n_geo % 2 == 0
+    mesh = sine_mesh(cells, n_geo)
+    c = cells // 2
+    e = c + cells * (c + cells * c)
+    ng = n_geo + 1
+    m = n_geo // 2
+    X = mesh.X.copy()
+    X[e, (m * ng + m) * ng + m, 0] -= displace * mesh.h
+    mesh = Mesh(mesh.n_geo, X, mesh.nbr_elem, mesh.nbr_face, mesh.bc, mesh.shift, mesh.h, mesh.cells)
+    U = uniform_state(mesh.n_elem, N, (0.0, 0.0, 0.0))
+    z = np.zeros((0, 3))
+    return Workload("peaked_box%d_N%d_Ng%d" % (cells, N, n_geo), mesh, N, U, z, z, np.zeros(0),
+                    np.zeros(0, np.int32), dt=1e-3, n_steps=1, rk=1, drag=2, velocity=None), e
+
+
 def config2(n_particles=1_000_000, cells=32, n_steps=500):
     return curved_box(cells, 5, n_particles, n_steps, seed=1002, name="config2")
 

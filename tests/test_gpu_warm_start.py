@@ -94,3 +94,4 @@ def test_warm_start_mixed_form_and_learned_bits():
     rb = g0.read()
     np.testing.assert_array_equal(ra["elem"], rb["elem"])
     assert np.abs(ra["x"] - rb["x"]).max() <= 1e-12
+

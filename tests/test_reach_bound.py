@@ -112,3 +112,27 @@ def test_hessian_bound_denser_lattice(kind):
         hs = _hess_xi_max(o, int(e), 2 * ng + 2)
         hd = _hess_xi_max(o, int(e), 3 * ng + 2)
         assert np.all(hd <= 1.25 * hs + 1e-12 * np.abs(hs).max()), (e, hs, hd)
+
+
+def test_sampled_bound_misses_a_peak_between_samples():
+    """A mesh built to peak between the lattice samples (workloads.peaked_box:
+    the centre geometry node of one element moved so that its map is
+    compressed at the centre of its face xi_1 = +1): the library's sampled
+    bound (the (2 n_g + 2)^3 lattice, which skips xi = 0, times 1.2) is far
+    below |grad xi_1| at xi = (1, 0, 0), while the element stays valid.  This
+    is why the sampled bounds only drop internal faces (a crossing of an
+    internal face that the bound misses is repaired by the location step;
+    tests/test_gpu_reach_repair.py checks that on this mesh against the oracle),
+    never a wall, open or periodic face."""
+    w, e = W.peaked_box()
+    o = O.Oracle(w.mesh, w.N, w.U)
+    ng = w.mesh.n_geo + 1
+    bound = MARGIN * _grad_xi_max(o, e, 2 * ng + 2)
+    _, J = o.map(e, np.array([1.0, 0.0, 0.0]))
+    peak = np.linalg.norm(np.linalg.inv(J), axis=1)
+    dense = _grad_xi_max(o, e, 4 * ng + 7)       # a lattice with xi = 0
+    print("sampled bound", bound, "at (1, 0, 0)", peak, "dense lattice", dense)
+    assert np.linalg.det(J) > 0.0 and min(np.linalg.det(o.map(e, np.array([a, b, c]))[1])
+                                          for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)) > 0.0
+    assert peak[0] > 2.0 * bound[0]
+    assert dense[0] >= peak[0]
