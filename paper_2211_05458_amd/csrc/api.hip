@@ -955,6 +955,18 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   return FP_OK;
 }
 
+// reference coordinates of every active particle's position: along the
+// element tasks of the step's sort when they still describe the particle
+// order (the stages do not reorder), the rest per lane
+static hipError_t finalize(fp_ctx* c, hipStream_t s) {
+  const int warm = c->xi_warm ? 1 : 0;
+  const Particles& P = c->P[c->cur];
+  if (c->tasks_valid)
+    return launch_finalize_elem(c->mv, P, c->tasks, c->qcnt + 4, c->task_tp, c->np, warm, c->qcnt, c->strag,
+                                c->stats, s);
+  return launch_finalize(c->mv, P, c->np, nullptr, nullptr, warm, c->stats, s);
+}
+
 int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radius, const double* period,
                       int32_t drag, int32_t forces, const double* gravity) {
   if (!c || !S || kind < 0 || kind > 1 || drag < 0 || drag > 2 || (forces & ~kForceAll) != 0) return FP_EINVAL;
@@ -974,7 +986,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
   // crossing the face intersection missed, leaves the old element recorded)
   if (c->xi_dirty && c->np > 0) {
     Timed tm(c, 2);
-    HIPCHK(c, launch_finalize(c->mv, c->P[c->cur], c->np, c->xi_warm ? 1 : 0, c->stats, c->stream));
+    HIPCHK(c, finalize(c, c->stream));
     c->xi_dirty = false;
     c->sorted_fresh = false;
   }
@@ -1051,7 +1063,7 @@ int fp_read_particles(fp_ctx* c, int64_t* n_out, double* x, double* v, int32_t* 
   const int64_t cap = P.cap;
   if (c->xi_dirty) {
     Timed tm(c, 2);
-    HIPCHK(c, launch_finalize(c->mv, P, n, c->xi_warm ? 1 : 0, c->stats, s));
+    HIPCHK(c, finalize(c, s));
     c->xi_dirty = false;
     c->sorted_fresh = false;
   }

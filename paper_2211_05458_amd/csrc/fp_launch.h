@@ -42,7 +42,11 @@ hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int t
                         int32_t* sums, void* tasks, int32_t* ntask, int64_t max_tasks, hipStream_t s);
 size_t task_bytes();
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s);
-hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, int warm, unsigned long long* stats,
+hipError_t launch_finalize_elem(const MeshView& m, const Particles& P, const void* tasks, const int32_t* ntask, int tp,
+                                int64_t n, int warm, int32_t* counters, int32_t* list, unsigned long long* stats,
+                                hipStream_t s);
+hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, const int32_t* list,
+                           const int32_t* count, int warm, unsigned long long* stats,
                            hipStream_t s);
 hipError_t launch_deposit_nearest(const MeshView& m, const Particles& P, const Fluid& fl, int64_t n, void* S,
                                   int s_f32, const ForceModel& fm, hipStream_t s);

@@ -269,13 +269,18 @@ hipError_t launch_min_positive(const double* d, int64_t n, unsigned long long* i
   return hipGetLastError();
 }
 
-// reference coordinates of the current positions, with the inside check
+// reference coordinates of the current positions, with the inside check:
+// all n particles, or the list[0 .. *count) the element pass left over
 template <int NN, int NG>
-__global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, int warm,
+__global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64_t n, const int32_t* __restrict__ list,
+                                                  const int32_t* __restrict__ count, int warm,
                                                   unsigned long long* stats) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cnt = list ? (int64_t)*count : n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int nlost = 0, nrec = 0;
-  if (p < n && P.status[p] == ACTIVE) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+  const int64_t p = list ? (int64_t)list[i] : i;
+  if (P.status[p] == ACTIVE) {
     const int64_t cap = P.cap;
     double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
     double xi[3];
@@ -301,6 +306,7 @@ __global__ __launch_bounds__(256) void k_finalize(MeshView m, Particles P, int64
     if (!ok) { P.status[p] = LOST_NEWTON; nlost++; }
     else if (!inside) { P.status[p] = LOST_TRACK; nlost++; }
     for (int k = 0; k < 3; ++k) P.xi[k * cap + p] = xi[k];
+  }
   }
   wave_add(stats + ST_LOST * kStatSlots, nlost);
   wave_add(stats + ST_RECOVER * kStatSlots, nrec);
@@ -400,12 +406,14 @@ hipError_t launch_locate(const MeshView& m, const Particles& P, const int32_t* h
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, int warm, unsigned long long* stats,
-                           hipStream_t s) {
+hipError_t launch_finalize(const MeshView& m, const Particles& P, int64_t n, const int32_t* list,
+                           const int32_t* count, int warm, unsigned long long* stats, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  // a list's length is on the device: a grid that strides over it
+  const dim3 g = list ? dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)) : grid_for(n);
 #define FP_L(A, B)                                                                    \
   if (m.n == A && m.ng == B) {                                                        \
-    k_finalize<A, B><<<grid_for(n), 256, 0, s>>>(m, P, n, warm, stats);               \
+    k_finalize<A, B><<<g, 256, 0, s>>>(m, P, n, list, count, warm, stats);            \
     return hipGetLastError();                                                         \
   }
   FP_FOR_EACH_SHAPE(FP_L)

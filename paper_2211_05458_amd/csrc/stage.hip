@@ -405,6 +405,64 @@ __global__ void k_reset_counters(int32_t* c) {
   if (threadIdx.x < 3) c[threadIdx.x] = 0;   // stragglers, tracking queue, its head
 }
 
+// Reference coordinates of the final positions along the element tasks of
+// the step's sort: the task element's geometry nodes staged in LDS as in the
+// stage kernel, one Newton per particle (from its continued coordinates when
+// the step kept them); particles that left the task's element, or are not
+// located inside it, go to the list that the per-lane pass finishes.
+template <int NN, int NG, int TP>
+__global__ __launch_bounds__(64 * elem_waves(TP)) void k_finalize_elem(MeshView m, const Task* __restrict__ tasks,
+                                                                        const int32_t* __restrict__ ntask,
+                                                                        Particles P, int warm, Queues q,
+                                                                        unsigned long long* stats) {
+  constexpr int NG3 = NG * NG * NG, NN3 = NN * NN * NN;
+  constexpr int kW = elem_waves(TP), PER = 64 / TP, SLOTS = kW * PER;
+  __shared__ double sX[SLOTS][NG3 * 3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int half = (TP == 64) ? 0 : lane / TP, tl = lane % TP, slot = w * PER + half;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kW + w));
+  const int ti = wid * PER + half;
+  const int nt = __builtin_amdgcn_readfirstlane(*ntask);
+  const int64_t cap = P.cap;
+  int it_sum = 0, calls = 0, fb = 0;
+  bool strag = false;
+  int64_t p = 0;
+  Task t{0, 0, 0, 0};
+  if (ti < nt) {
+    t = tasks[ti];
+    const int e = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.e) : t.e;
+    const double* Xg = m.X + (size_t)e * NG3 * 3;
+    for (int i = tl; i < NG3 * 3; i += TP) sX[slot][i] = Xg[i];
+  }
+  __syncthreads();
+  if (ti < nt && tl < t.cnt) {
+    const int e = t.e;
+    p = (int64_t)t.p0 + tl;
+    if (P.status[p] == ACTIVE) {
+      if (P.elem[p] != e) {
+        strag = true;
+      } else {
+        const double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
+        double xi[3], gw[3];
+        const bool wv = warm && warm_guess(P, p, gw);
+        if (locate_xi_e<NN, NG, false>(m, e, sX[slot], m.xnode + (size_t)e * NN3 * 3, x, xi, 50, it_sum, calls, fb,
+                                       false, nullptr, wv, gw) &&
+            inside_ref(xi)) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) P.xi[k * cap + p] = xi[k];
+        } else {
+          strag = true;
+        }
+      }
+    }
+  }
+  __shared__ int sh[kW + 1];
+  const int s1 = block_push<kW>(q.counters + 0, strag, sh);
+  if (strag) q.strag[s1] = (int32_t)p;
+}
+
+
+
 // tasks of <= tp particles per element after the counting sort
 __global__ void k_task_count(const int32_t* __restrict__ count, int E, int tp, int32_t* tcount) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -444,6 +502,32 @@ hipError_t launch_tasks(const int32_t* count, const int32_t* start, int E, int t
 size_t task_bytes() { return sizeof(Task); }
 
 #include "fp_shapes.h"
+
+hipError_t launch_finalize_elem(const MeshView& m, const Particles& P, const void* tasks, const int32_t* ntask, int tp,
+                                int64_t n, int warm, int32_t* counters, int32_t* list, unsigned long long* stats,
+                                hipStream_t s) {
+  Queues q{counters, list, nullptr, nullptr, nullptr};
+  k_reset_counters<<<1, 64, 0, s>>>(counters);
+  const int64_t max_tasks = (int64_t)m.E + P.cap / tp + 1;
+#define FP_L(A, B)                                                                                         \
+  if (m.n == A && m.ng == B) {                                                                             \
+    if (tp == 64) {                                                                                        \
+      const int64_t waves = max_tasks;                                                                     \
+      k_finalize_elem<A, B, 64><<<dim3((unsigned)((waves + elem_waves(64) - 1) / elem_waves(64))),         \
+                                  64 * elem_waves(64), 0, s>>>(m, (const Task*)tasks, ntask, P, warm, q, stats); \
+    } else if (tp == 32) {                                                                                 \
+      const int64_t waves = (max_tasks + 1) / 2;                                                           \
+      k_finalize_elem<A, B, 32><<<dim3((unsigned)((waves + elem_waves(32) - 1) / elem_waves(32))),         \
+                                  64 * elem_waves(32), 0, s>>>(m, (const Task*)tasks, ntask, P, warm, q, stats); \
+    } else {                                                                                               \
+      return hipErrorInvalidValue;                                                                         \
+    }                                                                                                      \
+    return launch_finalize(m, P, n, list, counters, warm, stats, s);                                       \
+  }
+  FP_FOR_EACH_SHAPE(FP_L)
+#undef FP_L
+  return hipErrorInvalidValue;
+}
 
 // the element kernel runs when tasks of its size exist (with the extra forces
 // it has an instantiation of its own, except together with the learned guess)
