@@ -279,13 +279,44 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t cap = P.cap;
   int it_sum = 0, calls = 0, fb = 0, nlost = 0, nrec = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < count; i += stride) {
+  // the workgroup's 256 queue entries of an iteration sorted by element in
+  // LDS (bitonic), so that the lanes of a wavefront that share an element
+  // read its geometry and fluid state at the same addresses
+  __shared__ int32_t skey[256], sval[256];
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+    const int64_t i = base + threadIdx.x;
     bool trk = false;
     int64_t p = 0;
     double xs0 = 0, xs1 = 0, xs2 = 0;
     unsigned reach = 0x3Fu;
-    if (i < count) {
-      p = list ? (int64_t)list[i] : i;
+    bool have = i < count;
+    if (list) {
+      const int32_t pl = have ? list[i] : -1;
+      skey[threadIdx.x] = have ? P.elem[pl] : 0x7fffffff;
+      sval[threadIdx.x] = pl;
+      __syncthreads();
+      for (int k = 2; k <= 256; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          const int t = threadIdx.x, o = t ^ j;
+          if (o > t) {
+            const bool up = (t & k) == 0;
+            const int32_t a = skey[t], b = skey[o];
+            if ((a > b) == up) {
+              skey[t] = b; skey[o] = a;
+              const int32_t va = sval[t];
+              sval[t] = sval[o]; sval[o] = va;
+            }
+          }
+          __syncthreads();
+        }
+      const int32_t ps = sval[threadIdx.x];
+      have = ps >= 0;
+      p = have ? ps : 0;
+      __syncthreads();   // skey / sval are rewritten in the next iteration
+    } else {
+      p = i;
+    }
+    if (have) {
       if (P.status[p] == ACTIVE) {
         int e = P.elem[p];
         double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
