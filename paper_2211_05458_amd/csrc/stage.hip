@@ -1,12 +1,13 @@
 // One low-storage RK stage (Sec. 3.2), split by the data each part touches:
 //
 //  k_stage_elem  one wavefront per (element, <= 64 particles) task built after
-//                the counting sort.  The element's geometry nodes, fluid state
-//                and face boxes are wave-uniform, so they stream through the
-//                scalar cache as SGPR operands of the FMAs.  Per particle:
-//                guess, Newton, inside check, interpolation, drag, stage
-//                update, and the bounding-box test of the element's faces
-//                (Sec. 3.2.4).  Particles whose segment touches a face box go
+//                the counting sort (or one per half for tasks of <= 32).  The
+//                element's geometry nodes and fluid state are staged in LDS
+//                once per task and read as broadcasts.  Per particle: guess,
+//                Newton, inside check, interpolation, drag, stage update, and
+//                the bounding-box test of the element's faces (Sec. 3.2.4);
+//                the mixed stage interpolates for the whole wavefront at once
+//                on the matrix cores.  Particles whose segment touches a face box go
 //                to the tracking queue; particles that left the task element
 //                in an earlier stage, or that Newton does not locate inside
 //                it, go to the straggler queue.
@@ -29,6 +30,36 @@ namespace fp {
 // 5 % slower).
 template <int NG>
 constexpr bool kReach2 = NG >= 7;
+
+// the low-storage update of the mixed stage (FP32) from the acceleration a
+__device__ __forceinline__ void mixed_lsrk(const float* a, const double* x, double* v, double* kx, double* kv,
+                                           const StepParams& sp, double* xe) {
+  const float A = (float)sp.A, B = (float)sp.B, dt = (float)sp.dt;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float vf = (float)v[k];
+    float kxf = A * (float)kx[k] + dt * vf;
+    float kvf = A * (float)kv[k] + dt * a[k];
+    kx[k] = kxf;
+    kv[k] = kvf;
+    xe[k] = x[k] + (double)(B * kxf);
+    v[k] = (double)(vf + B * kvf);
+  }
+}
+
+// drag (plus gravity) and the low-storage update of the mixed stage from the
+// interpolated density and momentum Uc (FP32)
+__device__ __forceinline__ void mixed_update(const float* Uc, const double* x, double* v, double* kx, double* kv,
+                                             double d, const Fluid& fl, const StepParams& sp, double* xe) {
+  float vf[3] = {(float)v[0], (float)v[1], (float)v[2]};
+  float ir = 1.0f / Uc[0];
+  float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+  float a[3], fD;
+  drag_accel<float>(sp.drag, Uc[0], u, vf, (float)d, (float)fl.mu, (float)fl.rho_p, a, fD);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a[k] += (float)sp.gravity[k];
+  mixed_lsrk(a, x, v, kx, kv, sp, xe);
+}
 
 // interpolation, drag and the low-storage update for one particle.  FORCES:
 // the extra terms of the equation of motion selected in sp.forces (they need
@@ -76,25 +107,53 @@ __device__ __forceinline__ void stage_update(const MeshView& m, const UT* __rest
       velocity_gradient<float>(Jg, val, dval, u, G);
       particle_accel<float>(sp.drag, sp.forces, val[0], u, G, vf, (float)d, (float)fl.mu, (float)fl.rho_p,
                             sp.gravity, a, nullptr);
+      mixed_lsrk(a, x, v, kx, kv, sp, xe);
     } else {
       float Uc[kInterpVars];
       interp_f32<NN, UT>(m, Ue, xi, Uc);
-      float ir = 1.0f / Uc[0];
-      float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
-      float fD;
-      drag_accel<float>(sp.drag, Uc[0], u, vf, (float)d, (float)fl.mu, (float)fl.rho_p, a, fD);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) a[k] += (float)sp.gravity[k];
+      mixed_update(Uc, x, v, kx, kv, d, fl, sp, xe);
     }
-    const float A = (float)sp.A, B = (float)sp.B, dt = (float)sp.dt;
+  }
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Interpolation of the drag law's variables (FP32) for the particles of a
+// whole wavefront at once, with the contraction over xi_1 on 4x4x1 FP32
+// matrix products.  Block b of the product's 16 takes the particles of lanes
+// 4b .. 4b+3 as its four columns (operand B: l_i(xi_1) of the lane's own
+// particle) and four consecutive rows R = (var, k, j) of the element's state
+// as its rows (operand A: lane 4b + r reads row R0 + r), so after the sum
+// over i register r of every lane holds sum_i U[var][k][j][i] l_i(xi_1) of
+// row R0 + r for its own particle; the weights l_j(xi_2) and l_k(xi_3) are
+// applied in the lane.  The four lanes of a block read the same element (U is
+// the lane's element's state, [var][k][j][i], in LDS).  Every lane of the
+// wavefront calls it, a lane without a particle with any finite xi.
+template <int NN>
+__device__ __forceinline__ void interp_f32_mfma(const MeshView& m, const float* __restrict__ U, const double* xi,
+                                                float* out) {
+  float l1[NN], l2[NN], l3[NN];
+  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[0], l1);
+  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[1], l2);
+  lagrange<NN, float>(m.xdgf, m.cdgf, (float)xi[2], l3);
+  const float* Ur = U + (threadIdx.x & 3) * NN;
+  constexpr int kRows = kInterpVars * NN * NN;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float kxf = A * (float)kx[k] + dt * vf[k];
-      float kvf = A * (float)kv[k] + dt * a[k];
-      kx[k] = kxf;
-      kv[k] = kvf;
-      xe[k] = x[k] + (double)(B * kxf);
-      v[k] = (double)(vf[k] + B * kvf);
+  for (int v = 0; v < kInterpVars; ++v) out[v] = 0.0f;
+  float s = 0.0f;
+#pragma unroll
+  for (int g = 0; g < kRows / 4; ++g) {
+    v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < NN; ++i) d = __builtin_amdgcn_mfma_f32_4x4x1f32(Ur[4 * g * NN + i], l1[i], d, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = 4 * g + r, j = R % NN, k = (R / NN) % NN, v = R / (NN * NN);
+      s += d[r] * l2[j];
+      if (j == NN - 1) {
+        out[v] += s * l3[k];
+        s = 0.0f;
+      }
     }
   }
 }
@@ -130,9 +189,23 @@ struct Queues {
 // slower, and so do FP32 elements of N = 7 or N_geo = 6.)
 constexpr int elem_waves(int tp) { return tp == 64 ? 4 : 2; }
 
+// the element kernel's wavefronts per SIMD: four for tasks of 64 particles
+// (three for two tasks of 32 per wavefront), fewer where the staged element
+// data of a workgroup leave room for fewer workgroups in a CU's 160 KB of LDS
+template <int NN, int NG, typename UT, bool MIXED>
+constexpr int elem_occupancy() {
+  constexpr int tp = task_particles(NN, NG, MIXED), slots = elem_waves(tp) * (64 / tp);
+  constexpr int ng3 = NG * NG * NG, nn3 = NN * NN * NN;
+  constexpr bool stage_u = ng3 * 3 * 8 + kInterpVars * nn3 * (int)sizeof(UT) <= 12 * 1024 && ng3 * 3 * 8 <= 4096;
+  constexpr int lds = slots * (ng3 * 3 * 8 + (stage_u ? kInterpVars * nn3 * (int)sizeof(UT) : 0)) + 64;
+  constexpr int by_lds = (160 * 1024 / lds) * elem_waves(tp) / 4;
+  constexpr int want = tp == 64 ? 4 : 3;
+  return by_lds < want ? (by_lds < 1 ? 1 : by_lds) : want;
+}
+
 template <int NN, int NG, typename UT, bool MIXED, bool MLP, bool FORCES>
 __global__ __launch_bounds__(64 * elem_waves(task_particles(NN, NG, MIXED)))
-__attribute__((amdgpu_waves_per_eu(task_particles(NN, NG, MIXED) == 64 ? 4 : 3)))
+__attribute__((amdgpu_waves_per_eu(elem_occupancy<NN, NG, UT, MIXED>())))
 void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __restrict__ XN, const UT* __restrict__ U,
                   const FaceRec* __restrict__ faces, const Task* __restrict__ tasks, const int32_t* __restrict__ ntask,
                   Particles P, Fluid fl, StepParams sp, Queues q, unsigned long long* stats) {
@@ -172,8 +245,14 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
     }
   }
   __syncthreads();
+  // the mixed stage interpolates on the matrix cores, all lanes together,
+  // between the location of the lanes' particles and their update
+  constexpr bool kMfmaInterp = MIXED && !FORCES && kStageU;
+  bool ok = false;
+  int e = 0;
+  double x[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
   if (ti < nt) {
-    const int e = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.e) : t.e;
+    e = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.e) : t.e;
     const int p0 = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.p0) : t.p0;
     const int cnt = (TP == 64) ? __builtin_amdgcn_readfirstlane(t.cnt) : t.cnt;
     p = (int64_t)p0 + tl;
@@ -183,22 +262,21 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
       act = false;
     }
     if (act) {
-      const double* Xe = sX[slot];
       const double* XNe = XN + (size_t)e * NN3 * 3;
-      const UT* Ue = kStageU ? sU[slot] : U + (size_t)e * 5 * NN3;
-      double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
-      double xi[3];
+      x[0] = P.x[p]; x[1] = P.x[cap + p]; x[2] = P.x[2 * cap + p];
       float gl[3] = {0.f, 0.f, 0.f};
       if (MLP && sp.mlp_guess) {
         gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
       }
       double gw[3], Ji[9];
       const bool wv = sp.warm && warm_guess(P, p, gw);
-      if (!locate_xi_e<NN, NG, MLP>(m, e, Xe, XNe, x, xi, sp.max_it, it_sum, calls, fb,
+      if (!locate_xi_e<NN, NG, MLP>(m, e, sX[slot], XNe, x, xi, sp.max_it, it_sum, calls, fb,
                                     MLP && sp.mlp_guess, gl, wv, gw, Ji) ||
           !inside_ref(xi)) {
         strag = true;   // not located in its element: the per-lane kernel recovers it
+        xi[0] = xi[1] = xi[2] = 0.0;
       } else {
+        ok = true;
         if (sp.warm) {
           // the stage moves x by B (A kx + dt v): continue xi along it
           double xe1[3];
@@ -206,47 +284,56 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
           for (int k = 0; k < 3; ++k) xe1[k] = x[k] + sp.B * (sp.A * P.kx[k * cap + p] + sp.dt * P.v[k * cap + p]);
           store_warm(P, p, xi, Ji, x, xe1);
         }
-        double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
-        double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
-        double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
-        double xe[3];
-        stage_update<NN, NG, UT, MIXED, FORCES>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
-        const FaceRec* Fe = faces + (size_t)e * 6;
-        bool any = false;
-        // reference-space localisation: a segment that cannot reach a
-        // boundary face is not traced (the next location step finds it); in
-        // either mode only the boxes of the faces the segment can reach count
-        const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
-                          (xe[2] - x[2]) * (xe[2] - x[2]);
-        const double ds = m.dsafe[e];
-        if (!(sp.refspace && L2 < ds * ds)) {
-          // the sampled reach bounds drop internal faces only: the faces that
-          // are not internal (wall, open, periodic) keep their bit and meet the
-          // box test, and a crossing of an internal face the bound misses is
-          // repaired exactly by the location step (xi followed to the neighbour)
-          const unsigned keep = boundary_faces(Fe);
-          reach = reachable_faces(m, e, xi, L2) | keep;
-#pragma unroll 1
-          for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
-          if (kReach2<NG> && any) {
-            reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach) | keep;
-            any = false;
-#pragma unroll 1
-            for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          P.x[k * cap + p] = xe[k];
-          P.v[k * cap + p] = v[k];
-          P.kx[k * cap + p] = kx[k];
-          P.kv[k * cap + p] = kv[k];
-        }
-        if (any) {
-          trk = true;
-          xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
-        }
       }
+    }
+  }
+  float Uc[kInterpVars];
+  if constexpr (kMfmaInterp) {
+    if (wid * PER < nt) interp_f32_mfma<NN>(m, sU[slot], xi, Uc);
+  }
+  if (ok) {
+    const double* Xe = sX[slot];
+    const UT* Ue = kStageU ? sU[slot] : U + (size_t)e * 5 * NN3;
+    double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
+    double kx[3] = {P.kx[p], P.kx[cap + p], P.kx[2 * cap + p]};
+    double kv[3] = {P.kv[p], P.kv[cap + p], P.kv[2 * cap + p]};
+    double xe[3];
+    if constexpr (kMfmaInterp) mixed_update(Uc, x, v, kx, kv, P.d[p], fl, sp, xe);
+    else stage_update<NN, NG, UT, MIXED, FORCES>(m, Ue, Xe, xi, x, v, kx, kv, P.d[p], fl, sp, xe);
+    const FaceRec* Fe = faces + (size_t)e * 6;
+    bool any = false;
+    // reference-space localisation: a segment that cannot reach a
+    // boundary face is not traced (the next location step finds it); in
+    // either mode only the boxes of the faces the segment can reach count
+    const double L2 = (xe[0] - x[0]) * (xe[0] - x[0]) + (xe[1] - x[1]) * (xe[1] - x[1]) +
+                      (xe[2] - x[2]) * (xe[2] - x[2]);
+    const double ds = m.dsafe[e];
+    if (!(sp.refspace && L2 < ds * ds)) {
+      // the sampled reach bounds drop internal faces only: the faces that
+      // are not internal (wall, open, periodic) keep their bit and meet the
+      // box test, and a crossing of an internal face the bound misses is
+      // repaired exactly by the location step (xi followed to the neighbour)
+      const unsigned keep = boundary_faces(Fe);
+      reach = reachable_faces(m, e, xi, L2) | keep;
+#pragma unroll 1
+      for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
+      if (kReach2<NG> && any) {
+        reach = reachable_faces_taylor<NG>(m, e, Xe, xi, x, xe, L2, reach) | keep;
+        any = false;
+#pragma unroll 1
+        for (int f = 0; f < 6; ++f) any = any || (((reach >> f) & 1u) && bbox_hit(Fe[f], x, xe));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      P.x[k * cap + p] = xe[k];
+      P.v[k * cap + p] = v[k];
+      P.kx[k * cap + p] = kx[k];
+      P.kv[k * cap + p] = kv[k];
+    }
+    if (any) {
+      trk = true;
+      xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
     }
   }
   __shared__ int sh[kElemWaves + 1];
