@@ -158,7 +158,7 @@ __device__ __forceinline__ void map_jac(const MeshView& m, const double* __restr
 // along a short displacement
 template <int NG>
 __device__ bool newton_e(const MeshView& m, const double* __restrict__ X, const double* x, double* z, int max_it,
-                         int& iters, double* Ji = nullptr) {
+                         int& iters, double* Ji = nullptr, double tol = kNewtonTol) {
   for (int it = 1; it <= max_it; ++it) {
     double F[3], J[3][3];
     map_jac<NG>(m, X, z, F, J);
@@ -176,7 +176,7 @@ __device__ bool newton_e(const MeshView& m, const double* __restrict__ X, const 
     z[0] += dz0; z[1] += dz1; z[2] += dz2;
     double dmax = fmax(fabs(dz0), fmax(fabs(dz1), fabs(dz2)));
     if (!isfinite(z[0]) || !isfinite(z[1]) || !isfinite(z[2])) { iters += it; return false; }
-    if (dmax <= kNewtonTol) {
+    if (dmax <= tol) {
       iters += it;
       if (Ji) {
         Ji[0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * inv;
@@ -398,7 +398,7 @@ template <int NN, int NG, bool MLP = false>
 __device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__ Xe, const double* __restrict__ XNe,
                             const double* x, double* xi, int max_it, int& it_sum, int& calls, int& fallbacks,
                             bool use_gin = false, const float* gin = nullptr, bool use_gw = false,
-                            const double* gw = nullptr, double* Ji = nullptr) {
+                            const double* gw = nullptr, double* Ji = nullptr, double tol = kNewtonTol) {
   double g[3];
   // the first guess of each lane (continued coordinates, else the learned
   // guess on a flagged element, else the paper's), then one Newton for all
@@ -416,23 +416,23 @@ __device__ bool locate_xi_e(const MeshView& m, int e, const double* __restrict__
     guess_paper_e<NN, NG>(m, Xe, XNe, x, g);
   }
   calls++;
-  if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+  if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji, tol)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
   fallbacks++;
   if (first < 1 && learned) {
     g[0] = gin[0]; g[1] = gin[1]; g[2] = gin[2];
     calls++;
-    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji, tol)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
     fallbacks++;
   }
   if (first < 2) {
     guess_paper_e<NN, NG>(m, Xe, XNe, x, g);
     calls++;
-    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
+    if (newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji, tol)) { xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2]; return true; }
     fallbacks++;
   }
   guess_faces_e<NG>(Xe, x, g);
   calls++;
-  bool ok = newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji);
+  bool ok = newton_e<NG>(m, Xe, x, g, max_it, it_sum, Ji, tol);
   xi[0] = g[0]; xi[1] = g[1]; xi[2] = g[2];
   return ok;
 }

@@ -16,6 +16,11 @@ constexpr int kMlpIn = 84;           // learned-guess inputs: corners, curvature
 constexpr int kMlpRow = kMlpIn + 6 * 64 + 3;  // activations and deltas kept per row
 constexpr int kMlpWeights = 64 * kMlpIn + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3;
 constexpr double kNewtonTol = 1e-10;
+// Newton's acceptance in the mixed stage, whose interpolation is FP32: a step
+// of at most 1e-5 in the quadratic regime leaves an error of about
+// (M / 2) 1e-10, M = |J^-1| |second derivatives of the map| (below 1 on the
+// workloads' elements), far below the FP32 interpolation's resolution
+constexpr double kNewtonTolMixed = 1e-5;
 constexpr double kInsideEps = 1e-10;
 constexpr double kUVEps = 1e-12;
 constexpr double kClipTol = 1e-12;

@@ -271,7 +271,7 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
       double gw[3], Ji[9];
       const bool wv = sp.warm && warm_guess(P, p, gw);
       if (!locate_xi_e<NN, NG, MLP>(m, e, sX[slot], XNe, x, xi, sp.max_it, it_sum, calls, fb,
-                                    MLP && sp.mlp_guess, gl, wv, gw, Ji) ||
+                                    MLP && sp.mlp_guess, gl, wv, gw, Ji, MIXED ? kNewtonTolMixed : kNewtonTol) ||
           !inside_ref(xi)) {
         strag = true;   // not located in its element: the per-lane kernel recovers it
         xi[0] = xi[1] = xi[2] = 0.0;
@@ -415,7 +415,8 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
         double gw[3], Ji[9];
         const bool wv = sp.warm && warm_guess(P, p, gw);
         bool ok = locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi,
-                                           sp.max_it, it_sum, calls, fb, MLP && sp.mlp_guess, gl, wv, gw, Ji);
+                                           sp.max_it, it_sum, calls, fb, MLP && sp.mlp_guess, gl, wv, gw, Ji,
+                                           MIXED ? kNewtonTolMixed : kNewtonTol);
         bool inside = ok && inside_ref(xi);
         const bool direct = inside;   // located in the recorded element (Ji belongs to this xi)
         if (!ok) {
