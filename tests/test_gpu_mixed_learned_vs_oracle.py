@@ -18,7 +18,8 @@ than TRAPPED_HITS wall hits in the oracle run) the fraction with a different
 hit count and the maximum and RMS position difference in element widths h;
 for the wall-trapped ones the largest position difference.  Both task sizes of the
 mixed element kernel run: 32-particle tasks (two elements per wavefront,
-N = 5 with geometry degree 4) and 64-particle tasks (N = 7)."""
+N = 5 with geometry degree 4) and 64-particle tasks (N = 7); both take the
+same bits as the per-lane kernel, whose FP32 interpolation is plain FMAs."""
 import numpy as np
 import pytest
 
@@ -117,10 +118,17 @@ def test_fp64_and_mixed_32_particle_tasks_after_500_steps():
 
 
 def test_mixed_64_particle_tasks_n7_after_200_steps():
+    """Mixed form with one 64-particle task per wavefront (N = 7): the element
+    kernel's interpolation runs on 4x4x1 FP32 matrix products in the same
+    summation order as the per-lane kernel's FMAs, so both give the same bits;
+    and the stated error against the oracle."""
     w = W.curved_box(cells=4, N=7, n_particles=3000, n_steps=200, seed=52)
     ro = _oracle(w, w.n_steps)
     rg, st = _gpu_run(w, w.n_steps, 1)
     assert st["lost"] == 0
+    r_lane, _ = _gpu_run(w, w.n_steps, 1, sort_every=0)
+    for k in ("x", "v", "elem", "hits", "status"):
+        np.testing.assert_array_equal(rg[k], r_lane[k])
     _check(error_statement(ro, rg, w.mesh.h), free_max_h=5e-3, free_rms_h=1e-4)
 
 
