@@ -127,8 +127,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // over i register r of every lane holds sum_i U[var][k][j][i] l_i(xi_1) of
 // row R0 + r for its own particle; the weights l_j(xi_2) and l_k(xi_3) are
 // applied in the lane.  The four lanes of a block read the same element (U is
-// the lane's element's state, [var][k][j][i], in LDS).  Every lane of the
-// wavefront calls it, a lane without a particle with any finite xi.
+// the lane's element's state, [var][k][j][i], in LDS or global memory).
+// Every lane of the wavefront calls it, a lane without a particle with any
+// finite xi.
 template <int NN>
 __device__ __forceinline__ void interp_f32_mfma(const MeshView& m, const float* __restrict__ U, const double* xi,
                                                 float* out) {
@@ -191,7 +192,11 @@ constexpr int elem_waves(int tp) { return tp == 64 ? 4 : 2; }
 
 // the element kernel's wavefronts per SIMD: four for tasks of 64 particles
 // (three for two tasks of 32 per wavefront), fewer where the staged element
-// data of a workgroup leave room for fewer workgroups in a CU's 160 KB of LDS
+// data of a workgroup leave room for fewer workgroups in a CU's 160 KB of LDS.
+// Geometry degree 6 takes three: the degree-6 map and its reach test spill
+// about 250 registers at the 128 of four wavefronts per SIMD, and three with
+// fewer spills measured faster on the annular passage (FP64 10.9 -> 9.8 ms,
+// mixed 8.8 -> 7.4 ms per stage; two: 12.4 and 8.7 ms)
 template <int NN, int NG, typename UT, bool MIXED>
 constexpr int elem_occupancy() {
   constexpr int tp = task_particles(NN, NG, MIXED), slots = elem_waves(tp) * (64 / tp);
@@ -199,7 +204,7 @@ constexpr int elem_occupancy() {
   constexpr bool stage_u = ng3 * 3 * 8 + kInterpVars * nn3 * (int)sizeof(UT) <= 12 * 1024 && ng3 * 3 * 8 <= 4096;
   constexpr int lds = slots * (ng3 * 3 * 8 + (stage_u ? kInterpVars * nn3 * (int)sizeof(UT) : 0)) + 64;
   constexpr int by_lds = (160 * 1024 / lds) * elem_waves(tp) / 4;
-  constexpr int want = tp == 64 ? 4 : 3;
+  constexpr int want = (tp == 64 && NG < 7) ? 4 : 3;
   return by_lds < want ? (by_lds < 1 ? 1 : by_lds) : want;
 }
 
@@ -246,8 +251,9 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
   }
   __syncthreads();
   // the mixed stage interpolates on the matrix cores, all lanes together,
-  // between the location of the lanes' particles and their update
-  constexpr bool kMfmaInterp = MIXED && !FORCES && kStageU;
+  // between the location of the lanes' particles and their update (the
+  // element's state from LDS, or from global memory where it is not staged)
+  constexpr bool kMfmaInterp = MIXED && !FORCES;
   bool ok = false;
   int e = 0;
   double x[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
@@ -289,7 +295,8 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
   }
   float Uc[kInterpVars];
   if constexpr (kMfmaInterp) {
-    if (wid * PER < nt) interp_f32_mfma<NN>(m, sU[slot], xi, Uc);
+    if (wid * PER < nt)
+      interp_f32_mfma<NN>(m, kStageU ? (const float*)sU[slot] : (const float*)U + (size_t)e * 5 * NN3, xi, Uc);
   }
   if (ok) {
     const double* Xe = sX[slot];
