@@ -49,6 +49,12 @@ TRAFFIC = {   # committed counter summaries: kernel -> (file, sources its hash c
 }
 
 
+# the annular passage's small, strongly curved elements: about a tenth of the
+# particles cross a face in each stage, so every form there sorts before every
+# stage and runs those particles in their new element's task (bitwise the same
+# results as the per-lane kernel)
+ANNULUS_SORT = -1
+
 # guess bit 1 in every form: each particle is located from its reference
 # coordinates of the previous stage continued along its displacement first
 # (the paper's guess after a crossing or reflection); --no-warm turns it off
@@ -446,9 +452,11 @@ def bench_annulus_leg(args):
     for name, U, prec, guess in [("fp64", U64, 0, 0), ("fp64_learned", U64, 0, 1), ("fp32", U32, 1, 0),
                                  ("fp32_learned", U32, 1, 1)]:
         log("annulus run", name)
-        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None)
+        runs[name] = run_gpu(w, U, prec, K, Wm, guess=guess, weights=wts if guess else None,
+                             sort_every=ANNULUS_SORT)
     out = {"config": {"workload": "annular passage 48x24x48 Ngeo=6, DG N=5, %d particles, Schiller-Naumann, "
-                                  "3-stage LSERK, dt=1e-3" % w.n_particles, "elements": w.mesh.n_elem},
+                                  "3-stage LSERK, dt=1e-3, sorted by element before every stage" % w.n_particles,
+                      "elements": w.mesh.n_elem},
            "steps": K, "warmup": Wm, "training": train}
     for k, r in runs.items():
         out[k] = summary(r, K)
@@ -510,6 +518,7 @@ def bench_single(args):
                 S["S"] = torch.zeros((g.E, 4, g.n3), dtype=torch.float32, device="cuda")
             S["S"].zero_()
             g.deposit(S["S"], kind=1, radius=R, period=per)
+    sort_every = args.sort_every if args.sort_every is not None else (ANNULUS_SORT if name == "annulus" else 1)
     forms = [("fp64", U64, 0, 0)] if name != "twoway" else []
     forms += [("fp32", U32, 1, 0)]
     if name == "mortar":
@@ -518,7 +527,7 @@ def bench_single(args):
     for fname, U, prec, guess in forms:
         log("run", fname)
         runs[fname] = run_gpu(w, U, prec, K, Wm, guess=guess, deposit=dep,
-                              tracking=1 if fname.endswith("refspace") else 0)
+                              tracking=1 if fname.endswith("refspace") else 0, sort_every=sort_every)
     out = {"metric": METRIC, "workload": name, "steps": K, "warmup": Wm, "particles": w.n_particles,
            "elements": w.mesh.n_elem}
     first = None
@@ -563,6 +572,9 @@ def main():
     ap.add_argument("--err-every", type=int, default=10000, help="error subset: every k-th particle")
     ap.add_argument("--cpu-every", type=int, default=2500, help="oracle sample: every k-th particle")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--sort-every", type=int, default=None,
+                    help="--workload runs: sort by element every k steps (negative: before every stage); "
+                         "default: before every stage on the annular passage, every step elsewhere")
     ap.add_argument("--no-warm", action="store_true",
                     help="locate with the paper's initial guess only (no continued reference coordinates)")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",

@@ -97,7 +97,9 @@ typedef struct {
                             last Newton of that stage; not after a crossing or reflection);
                             0: the paper's initial guess (Sec. 3.2.1).  The converged xi is the
                             same from any guess in Newton's basin. */
-  int32_t sort_every;    /* counting-sort particles by element every k steps (0: never) */
+  int32_t sort_every;    /* counting-sort particles by element every k steps (0: never;
+                            negative: before every stage, so that the particles that
+                            crossed a face run in their new element's task) */
   int32_t max_newton_it; /* Newton iteration cap (50) */
   int32_t max_crossings; /* face crossings per stage before FP_MAX_CROSS (64) */
   int32_t tracking;      /* 0: physical-space tracking of every segment (Sec. 3.2.3);

@@ -895,9 +895,9 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
   sp.forces = o->forces;
   sp.mlp_guess = (sp.use_mlp && c->n_flagged > 0) ? c->mlp_guess : nullptr;
   hipStream_t s = c->stream;
+  const int tp = task_particles(c->n, c->ng, o->precision == 1);
   for (int st = 0; st < n_steps; ++st) {
-    if (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0) {
-      const int tp = task_particles(c->n, c->ng, o->precision == 1);
+    if (o->sort_every < 0 || (o->sort_every > 0 && (c->steps_done % o->sort_every) == 0)) {
       // a sort since the particles last moved (the shape-kernel source sorts
       // after locating them) already holds the tasks of this step
       if (!(c->sorted_fresh && c->tasks_valid && c->task_tp == tp)) {
@@ -908,6 +908,13 @@ int fp_step(fp_ctx* c, double dt, int32_t n_steps, const fp_step_opts* o) {
     }
     c->sorted_fresh = false;
     for (int i = 0; i < S; ++i) {
+      if (o->sort_every < 0 && i > 0) {
+        // every stage: the particles that crossed a face in the last stage
+        // join their new element's task instead of the per-lane kernel
+        Timed tm(c, 0);
+        int rc = sort_particles(c, tp);
+        if (rc) return rc;
+      }
       sp.A = A[i];
       sp.B = B[i];
       StageLaunch Lc{};

@@ -121,12 +121,22 @@ def test_push_without_hint_uses_background_mesh():
 
 
 def test_sorting_does_not_change_results():
+    """Unsorted (per-lane kernel), sorted every step (element tasks, the
+    particles that crossed a face per lane) and sorted before every stage: the
+    same bits, in both precisions."""
     w = W.curved_box(cells=5, N=3, n_particles=1500, n_steps=1, seed=23)
     v = w.v * 10.0
-    _, r0 = run_gpu(w, 10, rk=1, drag=1, v=v, sort_every=0)
-    _, r1 = run_gpu(w, 10, rk=1, drag=1, v=v, sort_every=1)
-    for k in ("x", "v", "xi", "elem", "hits", "status"):
-        np.testing.assert_array_equal(r0[k], r1[k])
+    for prec, U in ((0, None), (1, torch_f32(w.U))):
+        _, r0 = run_gpu(w, 10, rk=1, drag=1, v=v, sort_every=0, precision=prec, U=U)
+        for se in (1, -1):
+            _, r1 = run_gpu(w, 10, rk=1, drag=1, v=v, sort_every=se, precision=prec, U=U)
+            for k in ("x", "v", "xi", "elem", "hits", "status"):
+                np.testing.assert_array_equal(r0[k], r1[k])
+
+
+def torch_f32(U):
+    import torch
+    return torch.from_numpy(U.astype(np.float32))
 
 
 def test_edge_cases_empty_ragged_rejected_nan():
