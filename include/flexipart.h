@@ -95,6 +95,9 @@ typedef struct {
                             bit 1: first try each particle's reference coordinates of the previous
                             stage continued along its displacement (xi + J^-1 dx, kept from the
                             last Newton of that stage; not after a crossing or reflection);
+                            with both bits, the learned guess is computed and used only for
+                            the particles without such coordinates (their failures fall back
+                            to the paper's guess);
                             0: the paper's initial guess (Sec. 3.2.1).  The converged xi is the
                             same from any guess in Newton's basin. */
   int32_t sort_every;    /* counting-sort particles by element every k steps (0: never;

@@ -71,7 +71,11 @@ hipError_t launch_mlp_features(const MeshView& m, int64_t n, const int32_t* elem
 hipError_t launch_newton_pairs(const MeshView& m, const Particles& P, int64_t n, float* feat, float* xi,
                                int32_t* ids, int32_t* count, hipStream_t s);
 hipError_t launch_mlp_forward(const float* w, int64_t n, const float* in, float* out, hipStream_t s);
-hipError_t launch_mlp_guess(const MeshView& m, const Particles& P, int64_t n, float* guess, hipStream_t s);
+// learned guesses of the active particles in flagged elements that have no
+// continued reference coordinates (all of them with warm == 0); list and
+// count (device, cap and one entries) are scratch that this call overwrites
+hipError_t launch_mlp_guess(const MeshView& m, const Particles& P, int64_t n, int warm, int32_t* list,
+                            int32_t* count, float* guess, hipStream_t s);
 hipError_t launch_mlp_loss_grad(const float* w, int64_t n, const float* in, const float* target,
                                 const int32_t* rows, float* grad, float* loss, float* rowbuf, hipStream_t s);
 // device address of the fixed row buffer of fp_mlp_loss_grad_static on the

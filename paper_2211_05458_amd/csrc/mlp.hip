@@ -458,7 +458,33 @@ struct GuessLds {
   float b2[64], b3[64];
 };
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_guess(MeshView m, Particles P, int64_t n, float* __restrict__ guess) {
+// the particles that take a learned guess this stage: active, in a flagged
+// element, and without continued reference coordinates (warm != 0: the first
+// guess of the others is their continued xi, and only a learned guess computed
+// here is ever read)
+// (one atomic per workgroup of 1024 particles: a counter that every wavefront
+// hits serialises 1e5 atomics, about 1.4 ms for 1e7 particles)
+constexpr int kSelectWaves = 16;
+__global__ __launch_bounds__(64 * kSelectWaves) void k_mlp_select(MeshView m, Particles P, int64_t n, int warm,
+                                                                  int32_t* __restrict__ list,
+                                                                  int32_t* __restrict__ count) {
+  __shared__ int sh[kSelectWaves + 1];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool use = false;
+  if (p < n && P.status[p] == ACTIVE && m.mlp_flag[P.elem[p]] != 0) {
+    double gw[3];
+    use = !(warm && warm_guess(P, p, gw));
+  }
+  const int slot = block_push<kSelectWaves>(count, use, sh);
+  if (use) list[slot] = (int32_t)p;
+}
+
+__global__ void k_set_i32(int32_t* a, int32_t v) { *a = v; }
+
+// guesses of the listed particles (*count entries)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_guess(
+    MeshView m, Particles P, const int32_t* __restrict__ list, const int32_t* __restrict__ count,
+    float* __restrict__ guess) {
   __shared__ GuessLds S;
   const int lane = threadIdx.x & 63, kq = lane >> 4, col = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -498,31 +524,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int k = 0; k < 3; ++k) S.w1p[q][mt][i][k] = W1[o * NI + 81 + k];
   }
   __syncthreads();
+  const int64_t n = *count;
   for (int64_t base = wave * 64; base < n; base += nwave * 64) {
     int e[4];
-    bool use[4];
-    bool any = false;
+    int64_t pp[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const int64_t p = base + 16 * nt + col;
-      e[nt] = 0;
-      use[nt] = false;
-      if (p < n && P.status[p] == ACTIVE) {
-        e[nt] = P.elem[p];
-        use[nt] = m.mlp_flag[e[nt]] != 0;
-      }
-      any = any || use[nt];
+      const int64_t i = base + 16 * nt + col;
+      pp[nt] = i < n ? (int64_t)list[i] : -1;
+      e[nt] = pp[nt] >= 0 ? P.elem[pp[nt]] : 0;
     }
-    if (!__ballot(any)) continue;   // no particle of these 64 is in a flagged element
-    // layer 1 on the VALU: particles base + 16 nt + lane % 16
+    // layer 1 on the VALU: listed particles base + 16 nt + lane % 16
     v4s hb[4][4];   // B operands [input tile][particle tile]
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const int64_t p = base + 16 * nt + col;
+      const int64_t p = pp[nt];
       const double* c = m.mlp_ctr + (size_t)e[nt] * 4;
       float xh[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) xh[k] = p < n ? (float)((P.x[k * cap + p] - c[k]) * c[3]) : 0.f;
+      for (int k = 0; k < 3; ++k) xh[k] = p >= 0 ? (float)((P.x[k * cap + p] - c[k]) * c[3]) : 0.f;
       const float* h1e = m.mlp_h1 + (size_t)e[nt] * H;
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
@@ -581,8 +601,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const int64_t p = base + 16 * nt + col;
-      if (kq == 0 && use[nt]) {
+      const int64_t p = pp[nt];
+      if (kq == 0 && p >= 0) {
 #pragma unroll
         for (int k = 0; k < NO; ++k) guess[k * cap + p] = acc[nt][k];
       }
@@ -590,11 +610,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
-hipError_t launch_mlp_guess(const MeshView& m, const Particles& P, int64_t n, float* guess, hipStream_t s) {
+hipError_t launch_mlp_guess(const MeshView& m, const Particles& P, int64_t n, int warm, int32_t* list,
+                            int32_t* count, float* guess, hipStream_t s) {
   if (n == 0 || !m.mlp_w) return hipSuccess;
+  k_set_i32<<<1, 1, 0, s>>>(count, 0);
+  k_mlp_select<<<dim3((unsigned)((n + 64 * kSelectWaves - 1) / (64 * kSelectWaves))), 64 * kSelectWaves, 0, s>>>(
+      m, P, n, warm, list, count);
   // persistent: each wavefront converts the weights once
   const int64_t waves = std::min<int64_t>((n + 63) / 64, 4096);
-  k_mlp_guess<<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(m, P, n, guess);
+  k_mlp_guess<<<dim3((unsigned)((waves + 3) / 4)), 256, 0, s>>>(m, P, list, count, guess);
   return hipGetLastError();
 }
 

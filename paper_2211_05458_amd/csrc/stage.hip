@@ -270,14 +270,17 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
     if (act) {
       const double* XNe = XN + (size_t)e * NN3 * 3;
       x[0] = P.x[p]; x[1] = P.x[cap + p]; x[2] = P.x[2 * cap + p];
-      float gl[3] = {0.f, 0.f, 0.f};
-      if (MLP && sp.mlp_guess) {
-        gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
-      }
       double gw[3], Ji[9];
       const bool wv = sp.warm && warm_guess(P, p, gw);
+      // the guess pass computed learned guesses only for particles without
+      // continued coordinates
+      const bool lg = MLP && sp.mlp_guess && !wv;
+      float gl[3] = {0.f, 0.f, 0.f};
+      if (lg) {
+        gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
+      }
       if (!locate_xi_e<NN, NG, MLP>(m, e, sX[slot], XNe, x, xi, sp.max_it, it_sum, calls, fb,
-                                    MLP && sp.mlp_guess, gl, wv, gw, Ji, MIXED ? kNewtonTolMixed : kNewtonTol) ||
+                                    lg, gl, wv, gw, Ji, MIXED ? kNewtonTolMixed : kNewtonTol) ||
           !inside_ref(xi)) {
         strag = true;   // not located in its element: the per-lane kernel recovers it
         xi[0] = xi[1] = xi[2] = 0.0;
@@ -415,14 +418,15 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
         int e = P.elem[p];
         double x[3] = {P.x[p], P.x[cap + p], P.x[2 * cap + p]};
         double xi[3];
-        float gl[3] = {0.f, 0.f, 0.f};
-        if (MLP && sp.mlp_guess) {
-          gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
-        }
         double gw[3], Ji[9];
         const bool wv = sp.warm && warm_guess(P, p, gw);
+        const bool lg = MLP && sp.mlp_guess && !wv;   // computed only without continued coordinates
+        float gl[3] = {0.f, 0.f, 0.f};
+        if (lg) {
+          gl[0] = sp.mlp_guess[p]; gl[1] = sp.mlp_guess[cap + p]; gl[2] = sp.mlp_guess[2 * cap + p];
+        }
         bool ok = locate_xi_e<NN, NG, MLP>(m, e, m.X + (size_t)e * NG3 * 3, m.xnode + (size_t)e * NN3 * 3, x, xi,
-                                           sp.max_it, it_sum, calls, fb, MLP && sp.mlp_guess, gl, wv, gw, Ji,
+                                           sp.max_it, it_sum, calls, fb, lg, gl, wv, gw, Ji,
                                            MIXED ? kNewtonTolMixed : kNewtonTol);
         bool inside = ok && inside_ref(xi);
         const bool direct = inside;   // located in the recorded element (Ji belongs to this xi)
@@ -666,14 +670,15 @@ template <int NN, int NG, typename UT, bool MIXED, bool MLP>
 static void run_stage(const StageLaunch& L, hipStream_t s) {
   const MeshView& m = L.m;
   Queues q{L.counters, L.strag, L.trk_p, L.trk_x, L.trk_m};
-  k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   int64_t lane_blocks;
   auto rec = [&](int i) { if (L.ev[i]) hipEventRecord(L.ev[i], s); };
   if (MLP && L.sp.mlp_guess) {
+    // the straggler list and its counter hold the guess list until the reset
     rec(6);
-    (void)launch_mlp_guess(m, L.P, L.n, const_cast<float*>(L.sp.mlp_guess), s);
+    (void)launch_mlp_guess(m, L.P, L.n, L.sp.warm, L.strag, L.counters, const_cast<float*>(L.sp.mlp_guess), s);
     rec(7);
   }
+  k_reset_counters<<<1, 64, 0, s>>>(L.counters);
   if (stage_uses_tasks(L)) {
     // at most E + cap / tp + 1 tasks, 64 / tp per wavefront
     constexpr int tp = task_particles(NN, NG, MIXED), nw = elem_waves(tp);
