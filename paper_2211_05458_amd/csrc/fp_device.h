@@ -1692,4 +1692,43 @@ __device__ __forceinline__ int block_push(int32_t* counter, bool pred, int* sh /
   return r;
 }
 
+// block_push for two queues whose counters are adjacent (counters[0] and
+// counters[1], 8-byte aligned): one 64-bit atomic per workgroup returns both
+// bases (each count stays below 2^31, so the low word never carries).  The
+// per-workgroup atomics of the element stage kernel are serialised on one
+// address and cost it measurably (four times as many: +23 % kernel time).
+template <int NW = 4>
+__device__ __forceinline__ void block_push2(int32_t* counters, bool p0, bool p1, int* sh /* [2 NW + 2] shared */,
+                                            int& s0, int& s1) {
+  const unsigned long long m0 = __ballot(p0), m1 = __ballot(p1);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    sh[wid] = (int)__popcll(m0);
+    sh[NW + wid] = (int)__popcll(m1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t0 = 0, t1 = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      t0 += (unsigned long long)sh[w];
+      t1 += (unsigned long long)sh[NW + w];
+    }
+    unsigned long long old = 0;
+    if (t0 | t1) old = atomicAdd((unsigned long long*)counters, t0 | (t1 << 32));
+    sh[2 * NW] = (int)(old & 0xffffffffull);
+    sh[2 * NW + 1] = (int)(old >> 32);
+  }
+  __syncthreads();
+  int b0 = sh[2 * NW], b1 = sh[2 * NW + 1];
+  for (int w = 0; w < wid; ++w) {
+    b0 += sh[w];
+    b1 += sh[NW + w];
+  }
+  const unsigned long long below = (1ull << lane) - 1ull;
+  s0 = p0 ? b0 + (int)__popcll(m0 & below) : -1;
+  s1 = p1 ? b1 + (int)__popcll(m1 & below) : -1;
+  __syncthreads();
+}
+
 }  // namespace fp

@@ -171,7 +171,7 @@ __device__ __forceinline__ unsigned boundary_faces(const FaceRec* __restrict__ F
 struct Task { int32_t e, p0, cnt, pad; };
 
 struct Queues {
-  int32_t* counters;  // [0] stragglers, [1] tracking, [2] next tracking entry
+  int32_t* counters;  // [0] stragglers, [1] tracking (one 8-byte aligned word), [2] next tracking entry
   int32_t* strag;     // [cap]
   int32_t* trk_p;     // [cap]
   double* trk_x;      // [3][cap] segment start
@@ -346,12 +346,12 @@ void k_stage_elem(MeshView m, const double* __restrict__ X, const double* __rest
       xs0 = x[0]; xs1 = x[1]; xs2 = x[2];
     }
   }
-  __shared__ int sh[kElemWaves + 1];
-  int s1 = block_push<kElemWaves>(q.counters + 0, strag, sh);
+  __shared__ int sh[2 * kElemWaves + 2];
+  int s1, s2;
+  block_push2<kElemWaves>(q.counters, strag, trk, sh, s1, s2);
   if (strag) q.strag[s1] = (int32_t)p;
   wave_add(stats + ST_STRAG * kStatSlots, strag ? 1 : 0);
   wave_add(stats + ST_TRACKQ * kStatSlots, trk ? 1 : 0);
-  int s2 = block_push<kElemWaves>(q.counters + 1, trk, sh);
   if (trk) {
     q.trk_p[s2] = (int32_t)p;
     q.trk_m[s2] = (uint8_t)reach;
@@ -380,6 +380,7 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
   // LDS (bitonic), so that the lanes of a wavefront that share an element
   // read its geometry and fluid state at the same addresses
   __shared__ int32_t skey[256], sval[256];
+  __shared__ int shq[5];
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
     const int64_t i = base + threadIdx.x;
     bool trk = false;
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(256) void k_stage_lane(MeshView m, const int32_t* _
         }
       }
     }
-    int s = wave_push(q.counters + 1, trk);
+    const int s = block_push<4>(q.counters + 1, trk, shq);   // the loop is uniform over the workgroup
     if (trk) {
       q.trk_p[s] = (int32_t)p;
       q.trk_m[s] = (uint8_t)reach;
