@@ -10,12 +10,32 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
   if (i < n) a[i] = v;
 }
 
-__global__ void k_sort_hist(const int8_t* __restrict__ status, const int32_t* __restrict__ elem, int64_t n, int E,
-                            int32_t* count, int32_t* rank) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int key = status[p] == ACTIVE ? elem[p] : E;
-  rank[p] = atomicAdd(count + key, 1);
+// rank of each particle within its bucket.  The particles are mostly in
+// element order already (sorted at the last step, few crossings since), so
+// neighbouring lanes share keys: one atomic per run of equal keys within a
+// wavefront instead of one per particle (atomics on one address serialise)
+__global__ __launch_bounds__(256) void k_sort_hist(const int8_t* __restrict__ status,
+                                                   const int32_t* __restrict__ elem, int64_t n, int E,
+                                                   int32_t* count, int32_t* rank) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = p < n;
+  const int key = valid ? (status[p] == ACTIVE ? elem[p] : E) : -1;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool head = valid && (lane == 0 || prev != key);
+  const unsigned long long heads = __ballot(head);
+  const int nvalid = (int)__popcll(__ballot(valid));   // the valid lanes are a prefix
+  int base = 0;
+  if (head) {
+    const unsigned long long above = lane == 63 ? 0ull : heads >> (lane + 1);
+    const int next = above ? lane + 1 + __builtin_ctzll(above) : nvalid;
+    base = atomicAdd(count + key, next - lane);
+  }
+  // the head of this lane's run: the highest head at or below the lane
+  const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull));
+  const int start = upto ? 63 - __builtin_clzll(upto) : 0;
+  const int b = __shfl(base, start, 64);
+  if (valid) rank[p] = b + (lane - start);
 }
 
 // exclusive scan of 1024-entry tiles (256 threads x 4), tile totals to sums
