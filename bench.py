@@ -300,6 +300,15 @@ def train_guess(w, U, n_pairs, epochs, batch=1024, lr=2e-3, seed=4):
                  "median_guess_error": med}
 
 
+def dep_list_rows(n_particles, n_elem, r):
+    """Rows per element of the FP32 source's reuse list: a target stages about
+    ppe (1 + 6 r + 3 pi r^2 + 4 pi r^3 / 3) particles (the element box grown by
+    R = r h), with a quarter more room."""
+    import math
+    est = n_particles / n_elem * (1 + 6 * r + 3 * math.pi * r * r + 4 * math.pi * r ** 3 / 3)
+    return int(math.ceil(1.25 * est / 64.0)) * 64
+
+
 # ---------------------------------------------------------------------------
 # the default line
 # ---------------------------------------------------------------------------
@@ -317,11 +326,15 @@ def bench_composite(args):
     per = np.array([1.0, 0.0, 1.0])
     S = {}
 
+    rows = dep_list_rows(w.n_particles, w.mesh.n_elem, 1.5)
+
     def depositor(dtype):
         def dep(g):
             if "S" not in S or S["S"].dtype != dtype:
                 S.clear()
                 S["S"] = torch.zeros((g.E, 4, g.n3), dtype=dtype, device="cuda")
+            if dtype == torch.float32 and getattr(g, "dep_list", None) is None:
+                g.bind_deposit_list(rows)
             S["S"].zero_()
             g.deposit(S["S"], kind=1, radius=R, period=per)
         return dep
@@ -513,9 +526,13 @@ def bench_single(args):
     if name == "twoway":
         R, per, S = 1.5 * w.mesh.h, np.array([1.0, 0.0, 1.0]), {}
 
+        rows = dep_list_rows(w.n_particles, w.mesh.n_elem, 1.5)
+
         def dep(g):
             if "S" not in S:
                 S["S"] = torch.zeros((g.E, 4, g.n3), dtype=torch.float32, device="cuda")
+            if getattr(g, "dep_list", None) is None:
+                g.bind_deposit_list(rows)
             S["S"].zero_()
             g.deposit(S["S"], kind=1, radius=R, period=per)
     sort_every = args.sort_every if args.sort_every is not None else (ANNULUS_SORT if name == "annulus" else 1)

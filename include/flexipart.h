@@ -216,6 +216,20 @@ int fp_step(fp_ctx* ctx, double dt, int32_t n_steps, const fp_step_opts* opts);
 int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, double radius,
                       const double* period, int32_t drag, int32_t forces, const double* gravity);
 
+/* Optional caller-allocated device memory (256-byte aligned) in which the FP32
+ * shape-kernel source (kind 1, FP_F32) keeps, per target element, the
+ * particles its normalisation pass staged, so that the node-sum pass reads
+ * them instead of staging them again (the same rows in the same order: the
+ * same result).  Each element gets cap = (bytes - align256(4 n_elem)) /
+ * (20 n_elem) rows (fp_deposit_list_bytes gives the bytes for a cap); a target
+ * with more staged particles than cap stages again.  About
+ * ppe (1 + 6 r + 3 pi r^2 + 4 pi r^3 / 3) particles are staged per target,
+ * ppe = particles per element, r = radius / element width.  dev = NULL
+ * unbinds.  FP_EINVAL if the memory holds fewer than 16 rows per element.
+ * Borrowed until replaced or the context is destroyed. */
+int fp_bind_deposit_list(fp_ctx* ctx, void* dev, size_t bytes);
+int fp_deposit_list_bytes(fp_ctx* ctx, int32_t cap, size_t* bytes);
+
 /* Copy the quadrature volumes V_ijk = w_i w_j w_k J(xi_ijk) of all DG nodes
  * (device output V[n_elem][(n_dg+1)^3], f64) -- the measure in which the
  * deposited source is conservative: sum_k S_k V_k = -sum_p F_p.  Async. */

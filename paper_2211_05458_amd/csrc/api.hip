@@ -41,6 +41,9 @@ struct fp_ctx {
   double* dep_buf = nullptr;   // per-particle force (4 doubles), then a validity flag (int32)
   // candidate lists of the FP32 shape-kernel source, valid for (dl_R, dl_per)
   int32_t *dl_count = nullptr, *dl_start = nullptr, *dl_list = nullptr;
+  // caller memory for the FP32 source's per-target staged particles (optional)
+  void* rl_buf = nullptr;
+  int32_t rl_cap = 0;
   bool dl_valid = false, dl_tried = false;
   double dl_R = 0.0, dl_per[3] = {0, 0, 0}, dl_pad = 0.0;
   unsigned long long* dep_pad = nullptr;   // largest distance of a particle outside its element box
@@ -650,6 +653,8 @@ int fp_init_mesh(fp_ctx* c, const fp_mesh_desc* d) {
   }
   boundary_distance(c);
   c->mesh_ok = true;
+  c->rl_buf = nullptr;   // sized for the previous mesh's elements
+  c->rl_cap = 0;
   c->ws = nullptr;
   c->np = 0;
   c->fluid_ok = false;
@@ -1040,7 +1045,7 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
       HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
                                      c->node_pad, c->dep_buf, c->sort_start, c->dep_pad,
                                      c->count_pairs ? c->stats + ST_DEP_PAIRS * kStatSlots : nullptr, c->dl_valid ? c->dl_start : nullptr,
-                                     c->dl_list, c->dl_pad, ev, c->stream));
+                                     c->dl_list, c->dl_pad, c->rl_buf, c->rl_cap, ev, c->stream));
     }
     if (c->timing && ev[0] && ev[1] && ev[2] && ev[3]) {
       c->recs.push_back({7, ev[0], ev[1]});
@@ -1316,6 +1321,30 @@ int fp_bind_particles(fp_ctx* c, int64_t capacity, fp_dtype dtype, void* soa) {
   c->np = 0;
   c->cur = 0;
   c->tasks_valid = false;
+  return FP_OK;
+}
+
+int fp_deposit_list_bytes(fp_ctx* c, int32_t cap, size_t* bytes) {
+  if (!c || !bytes || cap <= 0) return FP_EINVAL;
+  if (!c->mesh_ok) return fail(c, FP_ESTATE, "fp_deposit_list_bytes: no mesh");
+  *bytes = deposit_reuse_bytes(c->E, cap);
+  return FP_OK;
+}
+
+int fp_bind_deposit_list(fp_ctx* c, void* dev, size_t bytes) {
+  if (!c) return FP_EINVAL;
+  if (!c->mesh_ok) return fail(c, FP_ESTATE, "fp_bind_deposit_list: no mesh");
+  if (!dev) {
+    c->rl_buf = nullptr;
+    c->rl_cap = 0;
+    return FP_OK;
+  }
+  if (((uintptr_t)dev) & 255) return fail(c, FP_EINVAL, "fp_bind_deposit_list: memory not 256-byte aligned");
+  const size_t head = deposit_reuse_bytes(c->E, 0);
+  const size_t cap = bytes > head ? (bytes - head) / ((size_t)c->E * 20) : 0;
+  if (cap < 16) return fail(c, FP_EINVAL, "fp_bind_deposit_list: fewer than 16 rows per element");
+  c->rl_buf = dev;
+  c->rl_cap = (int32_t)std::min<size_t>(cap, (size_t)INT32_MAX / 2);
   return FP_OK;
 }
 

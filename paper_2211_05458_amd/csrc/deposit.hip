@@ -499,6 +499,17 @@ struct DepLists {
   int32_t valid;
 };
 
+// the normalisation pass's staged particles of each target, kept for the
+// node-sum pass (caller memory, optional): per target up to cap entries of
+// the staged row (2 p, alpha_p) and the particle index, and the number of
+// particles it staged (more than cap: the node-sum pass stages again)
+struct DepRec {
+  float4* f;       // [E][cap], null: nothing recorded
+  int32_t* id;     // [E][cap]
+  int32_t* cnt;    // [E]
+  int32_t cap;
+};
+
 __device__ __forceinline__ double box_box_dist2(const double* alo, const double* ahi, const double* blo,
                                                 const double* bhi) {
   double s = 0.0;
@@ -589,6 +600,8 @@ __device__ __forceinline__ void for_candidates(const MeshView& m, const DepGeo& 
 //    pair), then sum_p K G_p per node on v_mfma_f32_4x4x1f32 (16 blocks of a
 //    4-node x 1-particle by 1-particle x 4-component product), the K tile
 //    being already in that instruction's A layout; S += once per node.
+//    With caller memory bound for it, pass 1 records each target's staged
+//    rows and pass 2 reads them back instead of staging again.
 // Lane layouts (gfx950): 16x16x4: A[row][k], B[k][col] in lane (row or col)
 // + 16 k, D[row][col] in lane col + 16 (row / 4), register row % 4.
 // 4x4x1 (16 blocks): A[b][row], B[b][col] in lane (row or col) + 4 b,
@@ -734,7 +747,8 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
                                         const DepLists& dl, const float4* __restrict__ xl,
                                         const float* __restrict__ Gp, int t, const double* ctr, double part_pad,
                                         CandLds<NodeTiling<NN>::TH>& L, WinLds& Wl,
-                                        PStage<NodeTiling<NN>::CAP>& s_c, Tile&& tile, Flush&& flush) {
+                                        PStage<NodeTiling<NN>::CAP>& s_c, const DepRec& rec, Tile&& tile,
+                                        Flush&& flush) {
   constexpr int TH = NodeTiling<NN>::TH;
   const double* nb = m.nbox + (size_t)t * 6;
   const double blo[3] = {nb[0], nb[1], nb[2]}, bhi[3] = {nb[3], nb[4], nb[5]};
@@ -744,7 +758,10 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
     flo[k] = (float)((blo[k] - ctr[k]) * g.iR);
     fhi[k] = (float)((bhi[k] - ctr[k]) * g.iR);
   }
-  int n = 0;   // entries in s_c (uniform)
+  int n = 0;    // entries in s_c (uniform)
+  int nr = 0;   // particles staged so far (uniform), the recorded list's length
+  float4* rf = rec.f ? rec.f + (size_t)t * rec.cap : nullptr;
+  int32_t* ri = rec.f ? rec.id + (size_t)t * rec.cap : nullptr;
   for_candidates<TH>(m, g, dl, t, blo, bhi, part_pad, L, [&](int nc) {
     // candidate tables: slot numbering, particle base and FP32 offset
     int T = 0;
@@ -816,11 +833,18 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
       int tot = 0;
       const int off = block_scan_bool<TH>(keep, L.wsum, tot);
       if (keep) {
-        s_c.f[n + off] = make_float4(2.f * r[0], 2.f * r[1], 2.f * r[2], 1.f - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+        const float4 f4 =
+            make_float4(2.f * r[0], 2.f * r[1], 2.f * r[2], 1.f - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+        s_c.f[n + off] = f4;
         s_c.g[n + off] = gg;
         s_c.id[n + off] = pi;
+        if (rf && nr + off < rec.cap) {
+          rf[nr + off] = f4;
+          ri[nr + off] = pi;
+        }
       }
       n += tot;
+      nr += tot;
       __syncthreads();
       int first = 0;
       for (; n - first >= 16; first += 16) tile(first);
@@ -858,6 +882,43 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
     __syncthreads();
     flush(16);
   }
+  if (rf && threadIdx.x == 0) rec.cnt[t] = nr;
+}
+
+// the node-sum pass from the recorded list of the target's staged particles:
+// the same rows in the same order, so the same 16-particle tiles (the last
+// one padded) as staging them again
+template <int NN, class Tile>
+__device__ inline void stream_list(const DepRec& rec, int t, int cnt, const float* __restrict__ Gp,
+                                   PStage<NodeTiling<NN>::CAP>& s_c, Tile&& tile) {
+  constexpr int TH = NodeTiling<NN>::TH;
+  const float4* lf = rec.f + (size_t)t * rec.cap;
+  const int32_t* li = rec.id + (size_t)t * rec.cap;
+  // each thread's row of the next chunk is loaded while the tiles of the
+  // current one run
+  float4 f = make_float4(0.f, 0.f, 0.f, -1.f), g = make_float4(0.f, 0.f, 0.f, 0.f);
+  int32_t pi = -1;
+  auto fetch = [&](int j) {
+    f = make_float4(0.f, 0.f, 0.f, -1.f);   // padding row: alpha = -1, no kernel weight
+    g = make_float4(0.f, 0.f, 0.f, 0.f);
+    pi = -1;
+    if (j < cnt) {
+      pi = li[j];
+      f = lf[j];
+      g = *(const float4*)(Gp + (int64_t)pi * 8);
+    }
+  };
+  fetch(threadIdx.x);
+  for (int j0 = 0; j0 < cnt; j0 += TH) {
+    const int mlen = min(TH, cnt - j0);
+    s_c.f[threadIdx.x] = f;
+    s_c.g[threadIdx.x] = g;
+    s_c.id[threadIdx.x] = pi;
+    __syncthreads();
+    fetch(j0 + TH + threadIdx.x);
+    for (int first = 0; first < mlen; first += 16) tile(first);
+    __syncthreads();
+  }
 }
 
 // max(x, 0) as one integer max: a float with the sign bit set is a negative
@@ -869,7 +930,7 @@ __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__flo
 template <int NN, bool COUNT>
 __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_norm_mfma(
     MeshView m, const int32_t* __restrict__ elem_start, DepGeo g, DepLists dl, const float4* __restrict__ xl,
-    const unsigned long long* __restrict__ povh, float* norm, unsigned long long* pairs) {
+    const unsigned long long* __restrict__ povh, float* norm, unsigned long long* pairs, DepRec rec) {
   using T = NodeTiling<NN>;
   const int t = xcd_element(blockIdx.x, m.E);
   if (t >= m.E) return;
@@ -927,7 +988,7 @@ __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per
   };
   for (int k = threadIdx.x; k < T::CAP; k += T::TH) s_c.acc[k] = 0.f;
   __syncthreads();
-  stream_particles<NN>(m, elem_start, g, dl, xl, nullptr, t, ctr, part_pad, L, Wl, s_c, tile, flush);
+  stream_particles<NN>(m, elem_start, g, dl, xl, nullptr, t, ctr, part_pad, L, Wl, s_c, rec, tile, flush);
   if (COUNT && pairs && lane == 0 && npairs) atomicAdd(pairs + (blockIdx.x & (kStatSlots - 1)), npairs);
 }
 
@@ -952,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_dep_scale(int64_t n, double* F, const i
 template <int NN>
 __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per_eu(4))) void k_dep_gather_mfma(
     MeshView m, const int32_t* __restrict__ elem_start, DepGeo g, DepLists dl, const float4* __restrict__ xl,
-    const float* __restrict__ Gp, const unsigned long long* __restrict__ povh, float* S) {
+    const float* __restrict__ Gp, const unsigned long long* __restrict__ povh, float* S, DepRec rec) {
   using T = NodeTiling<NN>;
   const int t = xcd_element(blockIdx.x, m.E);
   if (t >= m.E) return;
@@ -1010,7 +1071,13 @@ __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per
     }
     __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
   };
-  stream_particles<NN>(m, elem_start, g, dl, xl, Gp, t, ctr, part_pad, L, Wl, s_c, tile, [](int) {});
+  const int rc = rec.f ? rec.cnt[t] : -1;
+  if (rc >= 0 && rc <= rec.cap) {
+    stream_list<NN>(rec, t, rc, Gp, s_c, tile);
+  } else {
+    const DepRec none{nullptr, nullptr, nullptr, 0};
+    stream_particles<NN>(m, elem_start, g, dl, xl, Gp, t, ctr, part_pad, L, Wl, s_c, none, tile, [](int) {});
+  }
   // sum over the particle quarters, then one read-modify-write of each
   // (node, component)
   const int t0 = wave * T::TPW;
@@ -1061,8 +1128,16 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
                                 double* dep, const int32_t* elem_start, unsigned long long* povh,
                                 unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
-                                double list_pad, hipEvent_t* ev, hipStream_t s) {
+                                double list_pad, void* reuse, int32_t reuse_cap, hipEvent_t* ev, hipStream_t s) {
   DepLists dl{list_start, list, list_pad, list_start != nullptr ? 1 : 0};
+  // the reuse list: counts [E], then rows float4 [E][cap] (16-byte aligned), then indices [E][cap]
+  DepRec rc{nullptr, nullptr, nullptr, 0};
+  if (reuse && reuse_cap > 0) {
+    rc.cnt = (int32_t*)reuse;
+    rc.f = (float4*)(((uintptr_t)(rc.cnt + m.E) + 255) & ~(uintptr_t)255);
+    rc.id = (int32_t*)(rc.f + (size_t)m.E * reuse_cap);
+    rc.cap = reuse_cap;
+  }
   auto rec = [&](int i) { if (ev && ev[i]) hipEventRecord(ev[i], s); };
   DepGeo g;
   g.R = R;
@@ -1088,14 +1163,16 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
       rec(0);                                                                                                \
       k_dep_local<<<gp, 256, 0, s>>>(m, P, n, ok, g.iR, xl);                                                 \
       if (pairs)                                                                                             \
-        k_dep_norm_mfma<A, true><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, povh, norm, pairs);   \
+        k_dep_norm_mfma<A, true><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, povh, norm, pairs,     \
+                                                                  rc);                                       \
       else                                                                                                   \
-        k_dep_norm_mfma<A, false><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, povh, norm, pairs);  \
+        k_dep_norm_mfma<A, false><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, povh, norm, pairs,    \
+                                                                   rc);                                      \
       rec(1);                                                                                                \
       k_dep_scale<<<gp, 256, 0, s>>>(n, F, ok, norm);                                                        \
       rec(2);                                                                                                \
       k_dep_gather_mfma<A><<<ge, NodeTiling<A>::TH, 0, s>>>(m, elem_start, g, dl, xl, (const float*)F,      \
-                                                            povh, (float*)S);                                \
+                                                            povh, (float*)S, rc);                            \
       rec(3);                                                                                                \
     } else {                                                                                                 \
       rec(0);                                                                                                \

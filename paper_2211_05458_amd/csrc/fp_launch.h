@@ -54,8 +54,12 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
                                 double* dep, const int32_t* elem_start, unsigned long long* povh,
                                 unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
-                                double list_pad, hipEvent_t* ev /* [4] or null: around the two node passes */,
-                                hipStream_t s);
+                                double list_pad, void* reuse /* or null */, int32_t reuse_cap,
+                                hipEvent_t* ev /* [4] or null: around the two node passes */, hipStream_t s);
+// bytes of a source reuse list with cap rows per target element
+inline size_t deposit_reuse_bytes(int E, int32_t cap) {
+  return (((size_t)E * 4 + 255) & ~(size_t)255) + (size_t)E * cap * 20;
+}
 // candidate lists of the FP32 shape-kernel source: pass 0 counts per target
 // (count[E + 1], last entry 0), pass 1 fills list at the scanned start[]
 hipError_t launch_dep_lists(const MeshView& m, double R, const double* period, double pad, int pass,

@@ -25,7 +25,8 @@ EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_init_mesh", "fp_works
            "fp_mlp_n_weights", "fp_mlp_features", "fp_newton_pairs", "fp_mlp_forward",
            "fp_mlp_loss_grad", "fp_mlp_train_epoch", "fp_mlp_set_weights", "fp_mlp_num_flagged",
            "fp_set_timing", "fp_get_timing", "fp_node_volumes", "fp_bind_particles",
-           "fp_particle_block_layout", "fp_mlp_train", "fp_mlp_loss_grad_static"]
+           "fp_particle_block_layout", "fp_mlp_train", "fp_mlp_loss_grad_static", "fp_bind_deposit_list",
+           "fp_deposit_list_bytes"]
 TIMING_CLASSES = ("sort", "stage_elem", "finalize", "deposit_nearest", "deposit_shape", "stage_lane", "track",
                   "deposit_norm", "deposit_gather", "learned_guess")
 
@@ -98,6 +99,8 @@ def load():
     L.fp_bind_particles.argtypes = [P, I64, C.c_int, P]
     L.fp_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, P, P]
     L.fp_mlp_loss_grad_static.argtypes = [P, P, I64, P, P, P, P]
+    L.fp_bind_deposit_list.argtypes = [P, P, C.c_size_t]
+    L.fp_deposit_list_bytes.argtypes = [P, I32, C.POINTER(C.c_size_t)]
     for name in EXPORTS:       # every documented entry point must resolve
         getattr(L, name)
     _lib = L
@@ -222,6 +225,20 @@ class FlexiPart:
         self.block = block
         self._check(self.L.fp_bind_particles(self.ctx, int(capacity), F64, _ptr(block)), "fp_bind_particles")
         self.np = 0
+
+    def bind_deposit_list(self, cap):
+        """Allocate (torch) and bind the FP32 source's per-target reuse list with
+        cap rows per element; cap = 0 unbinds."""
+        if cap <= 0:
+            self.dep_list = None
+            return self._check(self.L.fp_bind_deposit_list(self.ctx, None, 0), "fp_bind_deposit_list")
+        nb = C.c_size_t(0)
+        self._check(self.L.fp_deposit_list_bytes(self.ctx, int(cap), C.byref(nb)), "fp_deposit_list_bytes")
+        self.dep_list = self.torch.empty(nb.value + 256, dtype=self.torch.uint8, device=self.device)
+        base = self.dep_list.data_ptr()
+        off = (-base) % 256
+        return self._check(self.L.fp_bind_deposit_list(self.ctx, C.c_void_p(base + off), nb.value),
+                           "fp_bind_deposit_list")
 
     def step(self, dt, n_steps=1, rk=1, drag=1, precision=0, guess=0, sort_every=1, max_newton_it=50,
              max_crossings=64, gravity=(0.0, 0.0, 0.0), tracking=0, forces=0):

@@ -147,3 +147,30 @@ def test_shape_fp32_matrix_core_path(N, n_geo, cells, n, R_cells):
     ref_pairs = _pairs_within(o, w, R, per)
     print("pairs within R: gpu %d, brute force %d" % (pairs, ref_pairs))
     assert abs(pairs - ref_pairs) <= max(2, 1e-4 * ref_pairs)
+
+
+@pytest.mark.parametrize("N, n_geo, cells, n, R_cells", [(1, 1, 4, 900, 1.5), (5, 4, 4, 2500, 1.5),
+                                                         (7, 4, 3, 1200, 1.2)])
+def test_shape_fp32_reuse_list(N, n_geo, cells, n, R_cells):
+    """With a caller-bound reuse list the node-sum pass reads the particles the
+    normalisation pass staged for each target instead of staging them again:
+    the same source (to the run-to-run order of the normalisation's float
+    atomics) with room for every target, and with room for only 16 rows, where
+    most targets stage again; against the oracle to FP32 rounding."""
+    import torch
+    w = W.curved_box(cells=cells, N=N, n_particles=n, n_steps=1, seed=54 + N, n_geo=n_geo)
+    v = w.v + 0.25
+    o, g = _setup(w, v)
+    R = R_cells / cells
+    per = np.array([1.0, 0.0, 1.0])
+    So = o.deposit(kind=1, radius=R, period=per)
+    S0 = g.deposit(kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy().astype(np.float64)
+    for cap in (4096, 16):
+        g.bind_deposit_list(cap)
+        for _ in range(2):   # the list is rewritten by every call
+            S1 = g.deposit(kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy().astype(np.float64)
+            np.testing.assert_allclose(S1, S0, rtol=2e-6, atol=1e-6 * np.abs(S0).max())
+            assert np.abs(S1 - So).max() <= 2e-5 * np.abs(So).max()
+    g.bind_deposit_list(0)
+    S2 = g.deposit(kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(S2, S0, rtol=2e-6, atol=1e-6 * np.abs(S0).max())
