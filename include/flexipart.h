@@ -217,7 +217,8 @@ int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, do
                       const double* period, int32_t drag, int32_t forces, const double* gravity);
 
 /* Optional caller-allocated device memory (256-byte aligned) in which the FP32
- * shape-kernel source (kind 1, FP_F32) keeps, per target element, the
+ * shape-kernel source of fp_deposit_source (Sec. 2.3, kind 1, FP_F32) keeps,
+ * per target element, the
  * particles its normalisation pass staged, so that the node-sum pass reads
  * them instead of staging them again (the same rows in the same order: the
  * same result).  Each element gets cap = (bytes - align256(4 n_elem)) /
