@@ -174,3 +174,27 @@ def test_shape_fp32_reuse_list(N, n_geo, cells, n, R_cells):
     g.bind_deposit_list(0)
     S2 = g.deposit(kind=1, radius=R, period=per, dtype=torch.float32).cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(S2, S0, rtol=2e-6, atol=1e-6 * np.abs(S0).max())
+
+
+def test_reuse_list_binding_errors():
+    """The reuse list's memory must be 256-byte aligned and hold at least 16
+    rows per element; a rejected binding leaves the source working without it."""
+    import ctypes as C
+    import torch
+    from paper_2211_05458_amd.lib import FPError
+    w = W.curved_box(cells=3, N=3, n_particles=300, n_steps=1, seed=60)
+    o, g = _setup(w, w.v)
+    nb = C.c_size_t(0)
+    assert g.L.fp_deposit_list_bytes(g.ctx, 16, C.byref(nb)) == 0
+    buf = torch.empty(nb.value + 512, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr() + (-buf.data_ptr()) % 256
+    assert g.L.fp_bind_deposit_list(g.ctx, C.c_void_p(base + 4), nb.value) < 0          # misaligned
+    assert g.L.fp_bind_deposit_list(g.ctx, C.c_void_p(base), nb.value - 1) < 0          # 15 rows
+    assert g.L.fp_bind_deposit_list(g.ctx, C.c_void_p(base), nb.value) == 0
+    assert g.L.fp_bind_deposit_list(g.ctx, None, 0) == 0
+    with pytest.raises(FPError):
+        g._check(g.L.fp_deposit_list_bytes(g.ctx, 0, C.byref(nb)), "fp_deposit_list_bytes")   # no rows
+    R = 1.2 / 3
+    So = o.deposit(kind=1, radius=R, period=np.array([1.0, 0.0, 1.0]))
+    Sf = g.deposit(kind=1, radius=R, period=np.array([1.0, 0.0, 1.0]), dtype=torch.float32)
+    assert np.abs(Sf.cpu().numpy() - So).max() <= 2e-5 * np.abs(So).max()
