@@ -95,3 +95,40 @@ def test_warm_start_mixed_form_and_learned_bits():
     np.testing.assert_array_equal(ra["elem"], rb["elem"])
     assert np.abs(ra["x"] - rb["x"]).max() <= 1e-12
 
+
+
+def test_learned_guess_list_and_stage_sorts_on_the_annulus():
+    """guess = 3 (continued coordinates; the learned guess, computed for the
+    compacted list of particles without them, on flagged elements) in the
+    mixed form on the annular passage: sorting before every stage gives the
+    same bits as sorting once per step and as no sort (each particle's
+    guesses and arithmetic do not depend on where it sits), and the learned
+    guess takes part (the Newton iteration count differs from the run
+    without it)."""
+    import torch
+    FlexiPart = _gpu()
+    wt = W.config4(n_particles=20_000, cells=(12, 6, 12), seed=1044)
+    gt = FlexiPart(wt.mesh, wt.N, wt.n_particles)
+    gt.set_fluid_state(torch.from_numpy(wt.U))
+    gt.push(wt.x, wt.v, wt.d, wt.elem_hint)
+    feat, xi = gt.newton_pairs()
+    weights, _ = gt.mlp_train(feat, xi, epochs=6, batch=512, lr=2e-3, seed=4)
+    w = W.config4(n_particles=3000, cells=(12, 6, 12), seed=1045)
+    U32 = torch.from_numpy(w.U.astype(np.float32))
+    runs = {}
+    for name, guess, se in (("step", 3, 1), ("stage", 3, -1), ("none", 3, 0), ("warm_only", 2, 1)):
+        g = FlexiPart(w.mesh, w.N, w.n_particles)
+        g.set_fluid_state(U32)
+        g.push(w.x, w.v, w.d, w.elem_hint)
+        g.mlp_set_weights(weights, 0.05)
+        g.reset_stats()
+        g.step(w.dt, 12, rk=1, drag=1, guess=guess, precision=1, sort_every=se)
+        runs[name] = (g.read(), g.stats())
+    for name in ("stage", "none"):
+        for k in ("x", "v", "xi", "elem", "hits", "status"):
+            np.testing.assert_array_equal(runs[name][0][k], runs["step"][0][k])
+    st, s2 = runs["step"][1], runs["warm_only"][1]
+    print("iterations per solve: continued + learned %.4f, continued only %.4f" %
+          (st["newton_iters"] / st["newton_calls"], s2["newton_iters"] / s2["newton_calls"]))
+    assert st["newton_iters"] != s2["newton_iters"]   # the learned guesses were used
+    assert st["lost"] == 0 and s2["lost"] == 0
