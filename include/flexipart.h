@@ -222,7 +222,7 @@ int fp_deposit_source(fp_ctx* ctx, void* S_dev, fp_dtype dtype, int32_t kind, do
  * particles its normalisation pass staged, so that the node-sum pass reads
  * them instead of staging them again (the same rows in the same order: the
  * same result).  Each element gets cap = (bytes - align256(4 n_elem)) /
- * (20 n_elem) rows (fp_deposit_list_bytes gives the bytes for a cap); a target
+ * (16 n_elem) rows (fp_deposit_list_bytes gives the bytes for a cap); a target
  * with more staged particles than cap stages again.  About
  * ppe (1 + 6 r + 3 pi r^2 + 4 pi r^3 / 3) particles are staged per target,
  * ppe = particles per element, r = radius / element width.  dev = NULL

@@ -1341,7 +1341,7 @@ int fp_bind_deposit_list(fp_ctx* c, void* dev, size_t bytes) {
   }
   if (((uintptr_t)dev) & 255) return fail(c, FP_EINVAL, "fp_bind_deposit_list: memory not 256-byte aligned");
   const size_t head = deposit_reuse_bytes(c->E, 0);
-  const size_t cap = bytes > head ? (bytes - head) / ((size_t)c->E * 20) : 0;
+  const size_t cap = bytes > head ? (bytes - head) / ((size_t)c->E * 16) : 0;
   if (cap < 16) return fail(c, FP_EINVAL, "fp_bind_deposit_list: fewer than 16 rows per element");
   c->rl_buf = dev;
   c->rl_cap = (int32_t)std::min<size_t>(cap, (size_t)INT32_MAX / 2);

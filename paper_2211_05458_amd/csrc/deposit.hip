@@ -501,14 +501,21 @@ struct DepLists {
 
 // the normalisation pass's staged particles of each target, kept for the
 // node-sum pass (caller memory, optional): per target up to cap entries of
-// the staged row (2 p, alpha_p) and the particle index, and the number of
-// particles it staged (more than cap: the node-sum pass stages again)
+// 2 p and the particle index (its bits in the fourth float), and the number
+// of particles it staged (more than cap: the node-sum pass stages again)
 struct DepRec {
   float4* f;       // [E][cap], null: nothing recorded
-  int32_t* id;     // [E][cap]
   int32_t* cnt;    // [E]
   int32_t cap;
 };
+
+// a staged row (2 p, alpha_p = 1 - |p|^2) from the FP32 position p relative
+// to the target centre in units of R; the operations are spelled out so that
+// both passes round alpha_p alike from the same p
+__device__ __forceinline__ float4 staged_row(float p0, float p1, float p2) {
+  const float pp = __fmaf_rn(p2, p2, __fmaf_rn(p1, p1, __fmul_rn(p0, p0)));
+  return make_float4(2.f * p0, 2.f * p1, 2.f * p2, __fsub_rn(1.f, pp));
+}
 
 __device__ __forceinline__ double box_box_dist2(const double* alo, const double* ahi, const double* blo,
                                                 const double* bhi) {
@@ -761,7 +768,6 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
   int n = 0;    // entries in s_c (uniform)
   int nr = 0;   // particles staged so far (uniform), the recorded list's length
   float4* rf = rec.f ? rec.f + (size_t)t * rec.cap : nullptr;
-  int32_t* ri = rec.f ? rec.id + (size_t)t * rec.cap : nullptr;
   for_candidates<TH>(m, g, dl, t, blo, bhi, part_pad, L, [&](int nc) {
     // candidate tables: slot numbering, particle base and FP32 offset
     int T = 0;
@@ -833,14 +839,12 @@ __device__ inline void stream_particles(const MeshView& m, const int32_t* __rest
       int tot = 0;
       const int off = block_scan_bool<TH>(keep, L.wsum, tot);
       if (keep) {
-        const float4 f4 =
-            make_float4(2.f * r[0], 2.f * r[1], 2.f * r[2], 1.f - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+        const float4 f4 = staged_row(r[0], r[1], r[2]);
         s_c.f[n + off] = f4;
         s_c.g[n + off] = gg;
         s_c.id[n + off] = pi;
         if (rf && nr + off < rec.cap) {
-          rf[nr + off] = f4;
-          ri[nr + off] = pi;
+          rf[nr + off] = make_float4(f4.x, f4.y, f4.z, __int_as_float(pi));
         }
       }
       n += tot;
@@ -893,7 +897,6 @@ __device__ inline void stream_list(const DepRec& rec, int t, int cnt, const floa
                                    PStage<NodeTiling<NN>::CAP>& s_c, Tile&& tile) {
   constexpr int TH = NodeTiling<NN>::TH;
   const float4* lf = rec.f + (size_t)t * rec.cap;
-  const int32_t* li = rec.id + (size_t)t * rec.cap;
   // each thread's row of the next chunk is loaded while the tiles of the
   // current one run
   float4 f = make_float4(0.f, 0.f, 0.f, -1.f), g = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -903,8 +906,9 @@ __device__ inline void stream_list(const DepRec& rec, int t, int cnt, const floa
     g = make_float4(0.f, 0.f, 0.f, 0.f);
     pi = -1;
     if (j < cnt) {
-      pi = li[j];
-      f = lf[j];
+      const float4 e = lf[j];
+      pi = __float_as_int(e.w);
+      f = staged_row(0.5f * e.x, 0.5f * e.y, 0.5f * e.z);   // 2 p halved is p exactly
       g = *(const float4*)(Gp + (int64_t)pi * 8);
     }
   };
@@ -1075,7 +1079,7 @@ __global__ __launch_bounds__(NodeTiling<NN>::TH) __attribute__((amdgpu_waves_per
   if (rc >= 0 && rc <= rec.cap) {
     stream_list<NN>(rec, t, rc, Gp, s_c, tile);
   } else {
-    const DepRec none{nullptr, nullptr, nullptr, 0};
+    const DepRec none{nullptr, nullptr, 0};
     stream_particles<NN>(m, elem_start, g, dl, xl, Gp, t, ctr, part_pad, L, Wl, s_c, none, tile, [](int) {});
   }
   // sum over the particle quarters, then one read-modify-write of each
@@ -1130,12 +1134,11 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
                                 double list_pad, void* reuse, int32_t reuse_cap, hipEvent_t* ev, hipStream_t s) {
   DepLists dl{list_start, list, list_pad, list_start != nullptr ? 1 : 0};
-  // the reuse list: counts [E], then rows float4 [E][cap] (16-byte aligned), then indices [E][cap]
-  DepRec rc{nullptr, nullptr, nullptr, 0};
+  // the reuse list: counts [E], then rows float4 [E][cap] (256-byte aligned)
+  DepRec rc{nullptr, nullptr, 0};
   if (reuse && reuse_cap > 0) {
     rc.cnt = (int32_t*)reuse;
     rc.f = (float4*)(((uintptr_t)(rc.cnt + m.E) + 255) & ~(uintptr_t)255);
-    rc.id = (int32_t*)(rc.f + (size_t)m.E * reuse_cap);
     rc.cap = reuse_cap;
   }
   auto rec = [&](int i) { if (ev && ev[i]) hipEventRecord(ev[i], s); };

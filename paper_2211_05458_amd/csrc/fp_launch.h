@@ -58,7 +58,7 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 hipEvent_t* ev /* [4] or null: around the two node passes */, hipStream_t s);
 // bytes of a source reuse list with cap rows per target element
 inline size_t deposit_reuse_bytes(int E, int32_t cap) {
-  return (((size_t)E * 4 + 255) & ~(size_t)255) + (size_t)E * cap * 20;
+  return (((size_t)E * 4 + 255) & ~(size_t)255) + (size_t)E * cap * 16;
 }
 // candidate lists of the FP32 shape-kernel source: pass 0 counts per target
 // (count[E + 1], last entry 0), pass 1 fills list at the scanned start[]
