@@ -1045,7 +1045,8 @@ int fp_deposit_source(fp_ctx* c, void* S, fp_dtype dt, int32_t kind, double radi
       HIPCHK(c, launch_deposit_shape(c->mv, c->P[c->cur], c->fl, c->np, S, dt == FP_F32, fm, radius, per,
                                      c->node_pad, c->dep_buf, c->sort_start, c->dep_pad,
                                      c->count_pairs ? c->stats + ST_DEP_PAIRS * kStatSlots : nullptr, c->dl_valid ? c->dl_start : nullptr,
-                                     c->dl_list, c->dl_pad, c->rl_buf, c->rl_cap, ev, c->stream));
+                                     c->dl_list, c->dl_pad, c->rl_buf, c->rl_cap,
+                                     c->tasks_valid ? c->tasks : nullptr, c->qcnt + 4, c->task_tp, ev, c->stream));
     }
     if (c->timing && ev[0] && ev[1] && ev[2] && ev[3]) {
       c->recs.push_back({7, ev[0], ev[1]});

@@ -1132,7 +1132,8 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 int s_f32, const ForceModel& fm, double R, const double* period, double node_pad,
                                 double* dep, const int32_t* elem_start, unsigned long long* povh,
                                 unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
-                                double list_pad, void* reuse, int32_t reuse_cap, hipEvent_t* ev, hipStream_t s) {
+                                double list_pad, void* reuse, int32_t reuse_cap, const void* tasks,
+                                const int32_t* ntask, int task_tp, hipEvent_t* ev, hipStream_t s) {
   DepLists dl{list_start, list, list_pad, list_start != nullptr ? 1 : 0};
   // the reuse list: counts [E], then rows float4 [E][cap] (256-byte aligned)
   DepRec rc{nullptr, nullptr, 0};
@@ -1160,8 +1161,14 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
   k_dep_reset<<<gp, 256, 0, s>>>(povh, norm, s_f32 ? n : 0);
 #define FP_L(A, B)                                                                                           \
   if (m.n == A && m.ng == B) {                                                                               \
-    if (fl.f32) k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                   \
-    else k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                         \
+    if (s_f32 && fl.f32 && fm.forces == 0 && tasks) {                                                       \
+      const hipError_t fe = launch_dep_force_elem(m, P, fl, fm.drag, tasks, ntask, task_tp, n, F, ok, povh, s); \
+      if (fe != hipSuccess) return fe;                                                                       \
+    } else if (fl.f32) {                                                                                     \
+      k_dep_force<A, B, float><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                             \
+    } else {                                                                                                 \
+      k_dep_force<A, B, double><<<gp, 256, 0, s>>>(m, P, fl, n, fm, F, ok, povh);                            \
+    }                                                                                                        \
     if (s_f32) {                                                                                             \
       rec(0);                                                                                                \
       k_dep_local<<<gp, 256, 0, s>>>(m, P, n, ok, g.iR, xl);                                                 \

@@ -55,7 +55,14 @@ hipError_t launch_deposit_shape(const MeshView& m, const Particles& P, const Flu
                                 double* dep, const int32_t* elem_start, unsigned long long* povh,
                                 unsigned long long* pairs, const int32_t* list_start, const int32_t* list,
                                 double list_pad, void* reuse /* or null */, int32_t reuse_cap,
+                                const void* tasks /* element tasks of the particles' order, or null */,
+                                const int32_t* ntask, int task_tp,
                                 hipEvent_t* ev /* [4] or null: around the two node passes */, hipStream_t s);
+// fluid force (drag only) and validity of the FP32 shape-kernel source along
+// the element tasks of the sort that precedes it (FP32 state)
+hipError_t launch_dep_force_elem(const MeshView& m, const Particles& P, const Fluid& fl, int drag,
+                                 const void* tasks, const int32_t* ntask, int tp, int64_t n, double* F,
+                                 int32_t* ok, unsigned long long* povh, hipStream_t s);
 // bytes of a source reuse list with cap rows per target element
 inline size_t deposit_reuse_bytes(int E, int32_t cap) {
   return (((size_t)E * 4 + 255) & ~(size_t)255) + (size_t)E * cap * 16;

@@ -594,6 +594,86 @@ __global__ __launch_bounds__(64 * elem_waves(TP)) void k_finalize_elem(MeshView 
 
 
 
+// Fluid force of the FP32 shape-kernel source (drag only, FP32 state) along
+// the element tasks of the source's sort: the element's state staged in LDS,
+// the interpolation for the whole wavefront on the matrix cores, drag in FP32.
+// F and ok are cleared beforehand; particles outside their element's
+// reference cube (not located) deposit nothing, as in the per-lane kernel.
+template <int NN, int TP>
+__global__ __launch_bounds__(64 * elem_waves(TP)) void k_dep_force_elem(MeshView m, const Task* __restrict__ tasks,
+                                                                         const int32_t* __restrict__ ntask,
+                                                                         Particles P, Fluid fl, int drag,
+                                                                         double* __restrict__ F,
+                                                                         int32_t* __restrict__ ok,
+                                                                         unsigned long long* povh) {
+  constexpr int NN3 = NN * NN * NN;
+  constexpr int kW = elem_waves(TP), PER = 64 / TP, SLOTS = kW * PER;
+  __shared__ float sU[SLOTS][kInterpVars * NN3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int half = (TP == 64) ? 0 : lane / TP, tl = lane % TP, slot = w * PER + half;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kW + w));
+  const int ti = wid * PER + half;
+  const int nt = __builtin_amdgcn_readfirstlane(*ntask);
+  const int64_t cap = P.cap;
+  Task t{0, 0, 0, 0};
+  if (ti < nt) {
+    t = tasks[ti];
+    const float* Ug = (const float*)fl.U + (size_t)t.e * 5 * NN3;
+    for (int i = tl; i < kInterpVars * NN3; i += TP) sU[slot][i] = Ug[i];
+  }
+  __syncthreads();
+  bool act = false;
+  int64_t p = 0;
+  double xi[3] = {0.0, 0.0, 0.0};
+  if (ti < nt && tl < t.cnt) {
+    p = (int64_t)t.p0 + tl;
+    if (P.status[p] == ACTIVE) {
+      const int e = t.e;
+      double ov = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double xk = P.x[k * cap + p];
+        ov = fmax(ov, fmax(m.elo[e * 3 + k] - xk, xk - m.ehi[e * 3 + k]));
+      }
+      if (ov > 0.0) atomicMax(povh, (unsigned long long)__double_as_longlong(ov));
+      const double xq[3] = {P.xi[p], P.xi[cap + p], P.xi[2 * cap + p]};
+      act = inside_ref(xq);
+      if (act) {
+        xi[0] = xq[0]; xi[1] = xq[1]; xi[2] = xq[2];
+      }
+    }
+  }
+  float Uc[kInterpVars];
+  if (wid * PER < nt) interp_f32_mfma<NN>(m, sU[slot], xi, Uc);
+  if (act) {
+    const double v[3] = {P.v[p], P.v[cap + p], P.v[2 * cap + p]};
+    const float vf[3] = {(float)v[0], (float)v[1], (float)v[2]};
+    const float ir = 1.0f / Uc[0];
+    const float u[3] = {Uc[1] * ir, Uc[2] * ir, Uc[3] * ir};
+    const float d = (float)P.d[p], mu = (float)fl.mu;
+    float a[3], fD;
+    drag_accel<float>(drag, Uc[0], u, vf, d, mu, (float)fl.rho_p, a, fD);
+    const float c = 3.0f * (float)M_PI * mu * d * fD;
+    double* Fp = F + p * 4;
+    double Fq[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Fq[k] = (double)(c * (u[k] - vf[k]));
+    Fp[0] = Fq[0];
+    Fp[1] = Fq[1];
+    Fp[2] = Fq[2];
+    Fp[3] = Fq[0] * v[0] + Fq[1] * v[1] + Fq[2] * v[2];
+    ok[p] = 1;
+  }
+}
+
+__global__ void k_dep_clear(double* F, int32_t* ok, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) F[p * 4 + k] = 0.0;
+  ok[p] = 0;
+}
+
 // tasks of <= tp particles per element after the counting sort
 __global__ void k_task_count(const int32_t* __restrict__ count, int E, int tp, int32_t* tcount) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -654,6 +734,28 @@ hipError_t launch_finalize_elem(const MeshView& m, const Particles& P, const voi
       return hipErrorInvalidValue;                                                                         \
     }                                                                                                      \
     return launch_finalize(m, P, n, list, counters, warm, stats, s);                                       \
+  }
+  FP_FOR_EACH_SHAPE(FP_L)
+#undef FP_L
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dep_force_elem(const MeshView& m, const Particles& P, const Fluid& fl, int drag,
+                                 const void* tasks, const int32_t* ntask, int tp, int64_t n, double* F,
+                                 int32_t* ok, unsigned long long* povh, hipStream_t s) {
+  if (!fl.f32 || (tp != 32 && tp != 64)) return hipErrorInvalidValue;
+  k_dep_clear<<<dim3((unsigned)((std::max<int64_t>(n, 1) + 255) / 256)), 256, 0, s>>>(F, ok, n);
+  const int64_t max_tasks = (int64_t)m.E + P.cap / tp + 1;
+  const int64_t waves = tp == 64 ? max_tasks : (max_tasks + 1) / 2;
+  const int nw = elem_waves(tp);
+  const dim3 g((unsigned)((waves + nw - 1) / nw));
+#define FP_L(A, B)                                                                                             \
+  if (m.n == A && m.ng == B) {                                                                                 \
+    if (tp == 64)                                                                                              \
+      k_dep_force_elem<A, 64><<<g, 64 * nw, 0, s>>>(m, (const Task*)tasks, ntask, P, fl, drag, F, ok, povh);   \
+    else                                                                                                       \
+      k_dep_force_elem<A, 32><<<g, 64 * nw, 0, s>>>(m, (const Task*)tasks, ntask, P, fl, drag, F, ok, povh);   \
+    return hipGetLastError();                                                                                  \
   }
   FP_FOR_EACH_SHAPE(FP_L)
 #undef FP_L
